@@ -1,0 +1,286 @@
+/*
+ * redsum -- device-wide sum reduction for AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the shared library libredsum.so.  Every entry point takes plain
+ * pointers and sizes; no C++ type or exception crosses this boundary.
+ *
+ * The operation is the reduction case study of Zhang, Wahib, Zhang,
+ * Matsuoka, "A Study of Single and Multi-device Synchronization Methods in
+ * Nvidia GPUs" (arXiv 2004.05371), Section VII ("Case Study: Reduction
+ * Operator"): the sum of the elements of an array, computed by a per-thread
+ * grid-stride accumulation, a warp (here: 64-lane wavefront) combine, a block
+ * (workgroup) combine, and a device-wide synchronization before the final
+ * combine of the per-block partials -- either an implicit barrier between
+ * two kernel launches (Section VII-C, implicit variant) or a grid barrier
+ * inside one persistent cooperative kernel (Section VII-C, explicit
+ * variant).  The latency probes measure the synchronization levels studied
+ * in Sections IV and V with the methods of Section IX (Eq. 6, 7, 8).
+ *
+ * Conventions for every entry point
+ *   - Return value: RED_OK (0) or a negative red_status.  On error a
+ *     thread-local message is available from red_last_error().
+ *   - Arguments are validated before any HIP call is made.
+ *   - "device pointer" means memory of the current HIP device (hipMalloc or
+ *     torch CUDA tensors); the caller owns it.  The library never frees or
+ *     retains caller memory.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream).
+ *     Reductions are stream-ordered and asynchronous: results are valid once
+ *     the stream has been synchronized.  Probes are synchronous.
+ *   - The library owns one workspace per (device, stream) (per-workgroup
+ *     partials, barrier words, carry slots, error word), allocated on first
+ *     use outside of stream capture, freed by red_shutdown().  Calls that
+ *     overlap on the same stream are ordered by the stream; calls on
+ *     different streams use different workspaces.
+ */
+#ifndef REDSUM_H
+#define REDSUM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Input element types. */
+typedef enum {
+    RED_I32 = 0,  /* int32 in, int64 out (exact)                           */
+    RED_F32 = 1,  /* binary32 in, binary64 out                             */
+    RED_F16 = 2,  /* binary16 in, binary64 out                             */
+    RED_BF16 = 3  /* bfloat16 in, binary64 out                             */
+} red_dtype;
+
+/* Status codes. */
+typedef enum {
+    RED_OK = 0,
+    RED_EINVAL = -1,   /* invalid argument (null pointer, n < 0, bad dtype,
+                          misaligned pointer, plan out of range, oversized
+                          cooperative grid)                                  */
+    RED_ENOTSUP = -2,  /* valid request this build does not support        */
+    RED_EHIP = -3,     /* a HIP runtime call failed (message has details)   */
+    RED_ETIMEOUT = -4, /* a device-side grid-barrier watchdog fired         */
+    RED_ENOMEM = -5,   /* workspace allocation failed                       */
+    RED_ENODEV = -6    /* no usable gfx950 device                           */
+} red_status;
+
+/* Device-wide synchronization used between the per-workgroup partials and
+ * the final combine (Section VII-C). */
+typedef enum {
+    RED_VARIANT_AUTO = 0,       /* tuned plan if one is installed, else default */
+    RED_VARIANT_RELAUNCH = 1,   /* implicit barrier: partials kernel, then a
+                                   one-workgroup final kernel on the same stream */
+    RED_VARIANT_ATOMIC = 2,     /* one kernel; the last workgroup to take an
+                                   atomic ticket does the final combine        */
+    RED_VARIANT_PERSISTENT = 3  /* one cooperative kernel; grid barrier, then
+                                   workgroup 0 does the final combine          */
+} red_variant;
+
+/* In-register accumulation of floating-point inputs. */
+typedef enum {
+    RED_ACC_COMPENSATED = 0, /* fp32 (sum, error) pairs updated by TwoSum     */
+    RED_ACC_PLAIN = 1        /* plain fp32 accumulation                        */
+} red_acc;
+
+/* Cross-lane method of the wavefront combine (probe selection). */
+typedef enum {
+    RED_WAVE_DPP = 0,      /* DPP quad_perm / row_ror / row_bcast moves       */
+    RED_WAVE_SWIZZLE = 1,  /* ds_swizzle xor butterfly within 32 lanes        */
+    RED_WAVE_BPERMUTE = 2, /* ds_bpermute xor butterfly over 64 lanes         */
+    RED_WAVE_DPP_STEP = 3  /* a single DPP add step (latency of one move+add) */
+} red_wave_op;
+
+/* Launch plan of one reduction. */
+typedef struct {
+    int32_t variant; /* red_variant, not RED_VARIANT_AUTO when installed     */
+    int32_t wg;      /* workgroup size in threads: 64..1024, multiple of 64  */
+    int32_t ipt;     /* 16-byte loads per thread per loop iteration: 1,2,4,8 */
+    int32_t grid;    /* number of workgroups, 1..RED_MAX_GRID; 0 = automatic */
+} red_plan;
+
+#define RED_MAX_GRID 8192
+
+/* Options of red_sum_ex / red_sum_segmented_ex.  A zero-initialized struct
+ * means: automatic plan, compensated accumulation. */
+typedef struct {
+    red_plan plan;   /* plan.variant == RED_VARIANT_AUTO selects the installed
+                        plan (or the default) and ignores the other fields;
+                        with an explicit variant, wg / ipt left at 0 take
+                        the default values (grid 0 is automatic)            */
+    int32_t acc;     /* red_acc                                             */
+    int32_t flags;   /* bit 0: nontemporal loads; other bits must be zero   */
+} red_opts;
+
+/* ---------------------------------------------------------------------
+ * Initialization
+ * ------------------------------------------------------------------- */
+
+/* Select and check `device` (must be gfx950), query its properties and
+ * allocate the workspace of the null stream.  Idempotent.  Other entry
+ * points call it implicitly for the current device.
+ * Errors: RED_ENODEV (no device / not gfx950), RED_EHIP, RED_ENOMEM. */
+int red_init(int device);
+
+/* Free every workspace and cached graph.  Safe to call more than once. */
+void red_shutdown(void);
+
+/* Thread-local description of the last error of this thread ("" if none).
+ * The pointer stays valid until the next library call on this thread. */
+const char *red_last_error(void);
+
+/* Synchronize `stream`, then report a grid-barrier watchdog timeout raised
+ * by an earlier persistent kernel on that stream (RED_ETIMEOUT), clearing
+ * the flag and the barrier words.  RED_OK if none. */
+int red_check_error(void *stream);
+
+/* ---------------------------------------------------------------------
+ * Reductions (Section VII)
+ * ------------------------------------------------------------------- */
+
+/* out = sum of x[0..n).
+ *   dtype  red_dtype of x.
+ *   x      device pointer, n elements, aligned to the element size (any
+ *          16-byte misalignment is handled); may be NULL only if n == 0.
+ *   n      number of elements, 0 <= n < 2^40.
+ *   out    device pointer to one int64_t (RED_I32) or one double (float
+ *          dtypes), written exactly once, asynchronously.  n == 0 writes 0.
+ *   stream hipStream_t or NULL.
+ * int32 sums are exact.  Floating-point inputs are accumulated in fp32 with
+ * TwoSum compensation per thread and through the wavefront and workgroup
+ * combines; the per-workgroup partials are combined in binary64 in index
+ * order.  Results are bit-identical across repeated calls with the same plan.
+ * NaN propagates; +inf with -inf gives NaN.
+ * Errors: RED_EINVAL (validation), RED_EHIP, RED_ENOMEM. */
+int red_sum(int dtype, const void *x, int64_t n, void *out, void *stream);
+
+/* red_sum with explicit options (variant, plan, accumulation). */
+int red_sum_ex(int dtype, const void *x, int64_t n, void *out, void *stream, const red_opts *opts);
+
+/* Per-segment sums of a CSR batch: out[k] = sum of x[offsets[k] ..
+ * offsets[k+1]) for k in [0, nseg).
+ *   x       device pointer to binary32 values (aligned to 4 bytes).
+ *   offsets device pointer to nseg + 1 non-decreasing int64 offsets with
+ *           offsets[0] == 0 (not checked on the device).
+ *   nseg    number of segments, 0 <= nseg < 2^31.
+ *   out     device pointer to nseg doubles.  Empty segments give 0.
+ * One persistent launch: every workgroup owns an equal slice of the
+ * elements, sums the pieces of the segments that meet its slice, and the
+ * pieces of segments that cross slice boundaries are combined in slice order
+ * in binary64 by the last contributor.  The launch is captured in a hipGraph
+ * on the first call for a given (x, offsets, nseg, out, stream, plan) and
+ * replayed afterwards; when the stream is already being captured by the
+ * caller the kernel is simply launched into that capture.
+ * Errors: RED_EINVAL, RED_EHIP, RED_ENOMEM. */
+int red_sum_segmented(const float *x, const int64_t *offsets, int64_t nseg, double *out, void *stream);
+
+/* red_sum_segmented with explicit options.  opts->plan.variant selects the
+ * cross-slice fix-up: RED_VARIANT_ATOMIC (ticket, default) or
+ * RED_VARIANT_PERSISTENT (cooperative launch + grid barrier, no graph).
+ * flags bit 1 disables graph capture (direct launch). */
+int red_sum_segmented_ex(const float *x, const int64_t *offsets, int64_t nseg, double *out,
+                         void *stream, const red_opts *opts);
+
+/* Baseline for the segmented batch: one single-kernel reduction launch per
+ * segment.  host_offsets is a HOST pointer to nseg + 1 offsets. */
+int red_sum_segmented_loop(const float *x, const int64_t *host_offsets, int64_t nseg, double *out,
+                           void *stream);
+
+/* ---------------------------------------------------------------------
+ * Plans and autotuning (performance model of Section VII-A/B as prior)
+ * ------------------------------------------------------------------- */
+
+/* Install `plan` for reductions of `dtype` with `acc` whose element count
+ * has the same bit length as n (ceil(log2 n) bucket).  Plans are validated
+ * (RED_EINVAL otherwise). */
+int red_set_plan(int dtype, int acc, int64_t n, const red_plan *plan);
+
+/* Plan that red_sum would use for (dtype, acc, n): the installed one, else
+ * the default.  Writes *plan. */
+int red_get_plan(int dtype, int acc, int64_t n, red_plan *plan);
+
+/* Time candidate plans on the caller's data (x, n; out is overwritten) and
+ * install the fastest for the (dtype, acc, n) bucket; writes it to *best and
+ * its median time in microseconds to *best_us (either may be NULL).
+ * Synchronous.  `budget` bounds the number of candidates timed (0 = all). */
+int red_autotune(int dtype, int acc, const void *x, int64_t n, void *out, void *stream, int budget,
+                 red_plan *best, double *best_us);
+
+/* Autotune the segmented kernel on the caller's batch (synchronous) and
+ * install the best plan for batches of this nseg and total-size bucket. */
+int red_autotune_segmented(const float *x, const int64_t *offsets, int64_t nseg, double *out,
+                           void *stream, int budget, red_plan *best, double *best_us);
+
+/* ---------------------------------------------------------------------
+ * Latency probes (Sections IV, V, IX).  Synchronous; results on the host.
+ * Each fills ns (mean latency per operation, nanoseconds, by the host
+ * differential of Eq. 7 between kernels with r1 and r2 repetitions),
+ * sigma_ns (its uncertainty by Eq. 8 over `reps` timed pairs) and, if
+ * non-NULL, cycles (in-kernel shader-clock cycles per operation, the
+ * in-SM clock method of Section IX-C; wall-clock ns for the grid probe).
+ * reps >= 2.
+ * ------------------------------------------------------------------- */
+
+/* One wavefront-level operation (red_wave_op) in a dependent chain, run by
+ * every wave of one workgroup of wg_size threads. */
+int sync_bench_wave(int op, int wg_size, int reps, double *ns, double *sigma_ns, double *cycles,
+                    void *stream);
+
+/* One workgroup barrier (s_barrier) in a chain, n_wg workgroups of wg_size
+ * threads. */
+int sync_bench_block(int wg_size, int n_wg, int reps, double *ns, double *sigma_ns, double *cycles,
+                     void *stream);
+
+/* One grid barrier inside a cooperative kernel of n_wg workgroups of
+ * wg_size threads (n_wg must be co-resident: RED_EINVAL otherwise). */
+int sync_bench_grid(int n_wg, int wg_size, int reps, double *ns, double *sigma_ns, double *cycles,
+                    void *stream);
+
+/* Launch overhead of a kernel boundary (the implicit barrier) by kernel
+ * fusion, Eq. 6, with (i, j) = (8, 1) launches of n_wg x wg_size kernels
+ * that wait 5 us per unit.  cooperative != 0 uses the cooperative launch
+ * API.  null_kernel_ns (if non-NULL) receives the total latency of one null
+ * kernel in ns (Section IV formula, host clock around 1 and 5 launches). */
+int sync_bench_relaunch(int n_wg, int wg_size, int cooperative, int reps, double *ns,
+                        double *sigma_ns, double *null_kernel_ns, void *stream);
+
+/* Grid-barrier ordering check: every workgroup of a cooperative kernel
+ * records the 100 MHz wall clock before and after one grid barrier; writes
+ * max(before) and min(after) (in clock ticks) to host *max_before and
+ * *min_after.  A correct barrier gives max_before <= min_after. */
+int sync_check_grid_order(int n_wg, int wg_size, int64_t *max_before, int64_t *min_after,
+                          void *stream);
+
+/* Watchdog check: a cooperative kernel in which workgroup `skip_wg` never
+ * arrives at the grid barrier while the others wait with a spin limit of
+ * `spin_limit` polls; returns RED_ETIMEOUT when the watchdog fires (the
+ * expected outcome), RED_OK if not.  Every wave exits. */
+int sync_check_watchdog(int n_wg, int wg_size, int skip_wg, int spin_limit, void *stream);
+
+/* Largest number of co-resident workgroups of wg_size threads for the
+ * persistent reduction kernel (occupancy x compute units). */
+int red_max_coresident(int wg_size, int32_t *n_wg);
+
+/* Device facts: compute units, wall-clock rate (kHz), shader clock (kHz),
+ * L2 bytes, HBM bytes.  Any pointer may be NULL. */
+int red_device_info(int32_t *cus, int64_t *wallclock_khz, int64_t *clock_khz, int64_t *l2_bytes,
+                    int64_t *hbm_bytes);
+
+/* ---------------------------------------------------------------------
+ * Measurement helpers (not part of a reduction)
+ * ------------------------------------------------------------------- */
+
+/* Read-only bandwidth ceiling (Section VII-B bandwidth proxy): a
+ * grid-stride read of nbytes of x (16-byte aligned) with 16-byte loads
+ * and two integer adds per load, writing one word per workgroup to the
+ * workspace.  Asynchronous. */
+int red_bw_proxy(const void *x, int64_t nbytes, int n_wg, int wg_size, void *stream);
+
+/* Host-side probe formulas, exported so host logic can be tested without a
+ * GPU: Eq. 6, Eq. 7, Eq. 8 (from two sample arrays of length nsamp). */
+double red_eq6_overhead(double lat_ij, double lat_ji, int i, int j);
+double red_eq7_latency(double lat_k1, double lat_k2, int64_t r1, int64_t r2);
+double red_eq8_sigma(const double *k1, const double *k2, int nsamp, int64_t r1, int64_t r2);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REDSUM_H */

@@ -1,0 +1,431 @@
+// Device primitives of the sum reduction on gfx950 (CDNA4, wave64).
+//
+// Levels of the synchronization hierarchy used by the reduction case study
+// (Section VII-C of Zhang et al., arXiv 2004.05371):
+//   * lane          : per-thread accumulation of a grid-stride share
+//                     (the "summing" step), with 16-byte vector loads;
+//   * wavefront     : a 64-lane cross-lane combine (the paper's warp
+//                     shuffle reduction, Section VII-D) done with DPP moves,
+//                     ds_swizzle or ds_bpermute;
+//   * workgroup     : per-wave partials staged in LDS, one s_barrier, and a
+//                     second wavefront combine in wave 0 (the paper's
+//                     block_reduce);
+//   * grid          : a software grid barrier on device-scope atomics for a
+//                     cooperative (co-resident) launch (the paper's
+//                     grid.sync), bounded by a watchdog.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace redsum {
+
+constexpr int kWave = 64;
+constexpr int kMaxWavesPerWG = 16;  // 1024 threads
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Combine operations for the cross-lane trees.  Every T is a whole number of
+// 32-bit words; zero() is the identity.
+// ---------------------------------------------------------------------------
+struct OpI64 {
+  using T = long long;
+  __device__ static T zero() { return 0; }
+  __device__ static T add(T a, T b) { return a + b; }
+};
+struct OpF64 {
+  using T = double;
+  __device__ static T zero() { return 0.0; }
+  __device__ static T add(T a, T b) { return a + b; }
+};
+struct OpF32 {
+  using T = float;
+  __device__ static T zero() { return 0.0f; }
+  __device__ static T add(T a, T b) { return a + b; }
+};
+
+// Error-free transformation of a sum (Knuth's TwoSum, branch free):
+// s + e == a + b exactly, s = fl(a + b).  Needs round-to-nearest and no
+// reassociation (this file is never compiled with fast-math).
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  float bp = s - a;
+  float ap = s - bp;
+  e = (a - ap) + (b - bp);
+}
+
+// Compensated fp32 value: the represented number is s + c.
+struct CompF32 {
+  float s, c;
+};
+// binary64 value of a compensated pair.  Once s is infinite or NaN the
+// TwoSum error terms are NaN (inf - inf), so c is dropped: the sum of
+// finite inputs with +inf is +inf, and NaN / (+inf with -inf) stay NaN.
+__device__ __forceinline__ double comp_to_double(CompF32 a) {
+  return __builtin_isfinite(a.s) ? (double)a.s + (double)a.c : (double)a.s;
+}
+
+struct OpComp {
+  using T = CompF32;
+  __device__ static T zero() { return CompF32{0.0f, 0.0f}; }
+  __device__ static T add(T a, T b) {
+    CompF32 r;
+    float e;
+    two_sum(a.s, b.s, r.s, e);
+    r.c = (a.c + b.c) + e;
+    return r;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Word-wise cross-lane moves
+// ---------------------------------------------------------------------------
+template <class T>
+struct Words {
+  static_assert(sizeof(T) % 4 == 0, "cross-lane values are whole 32-bit words");
+  static constexpr int N = sizeof(T) / 4;
+};
+
+// DPP move of every word of v.  Lanes whose source is invalid or whose row
+// is masked off receive 0 (the identity of every Op above).
+template <int CTRL, int ROW_MASK, int BANK_MASK, class T>
+__device__ __forceinline__ T dpp_move(T v) {
+  int w[Words<T>::N];
+  __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+  for (int i = 0; i < Words<T>::N; ++i)
+    w[i] = __builtin_amdgcn_update_dpp(0, w[i], CTRL, ROW_MASK, BANK_MASK, true);
+  T r;
+  __builtin_memcpy(&r, w, sizeof(T));
+  return r;
+}
+
+template <class T>
+__device__ __forceinline__ T read_lane(T v, int lane) {
+  int w[Words<T>::N];
+  __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+  for (int i = 0; i < Words<T>::N; ++i) w[i] = __builtin_amdgcn_readlane(w[i], lane);
+  T r;
+  __builtin_memcpy(&r, w, sizeof(T));
+  return r;
+}
+
+template <int PATTERN, class T>
+__device__ __forceinline__ T swizzle_move(T v) {
+  int w[Words<T>::N];
+  __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+  for (int i = 0; i < Words<T>::N; ++i) w[i] = __builtin_amdgcn_ds_swizzle(w[i], PATTERN);
+  T r;
+  __builtin_memcpy(&r, w, sizeof(T));
+  return r;
+}
+
+template <class T>
+__device__ __forceinline__ T bpermute_move(T v, int src_lane) {
+  int w[Words<T>::N];
+  __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+  for (int i = 0; i < Words<T>::N; ++i) w[i] = __builtin_amdgcn_ds_bpermute(src_lane << 2, w[i]);
+  T r;
+  __builtin_memcpy(&r, w, sizeof(T));
+  return r;
+}
+
+// DPP control codes (GFX9 encoding).
+constexpr int kQuadPerm1032 = 0xB1;  // quad_perm:[1,0,3,2]  (lane ^ 1)
+constexpr int kQuadPerm2301 = 0x4E;  // quad_perm:[2,3,0,1]  (lane ^ 2)
+constexpr int kRowRor4 = 0x124;      // rotate right by 4 within a 16-lane row
+constexpr int kRowRor8 = 0x128;      // rotate right by 8 within a row
+constexpr int kRowShr1 = 0x111;      // shift right by 1 within a row
+constexpr int kRowBcast15 = 0x142;   // lane 15 of each row -> next row
+constexpr int kRowBcast31 = 0x143;   // lane 31 -> rows 2 and 3
+
+// ---------------------------------------------------------------------------
+// Wavefront combine: 64 lane values -> one value, returned uniformly (SGPR
+// broadcast) to every lane.  All 64 lanes must be active.  The order of the
+// combine is fixed, so results are deterministic.
+// ---------------------------------------------------------------------------
+// DPP: two quad_perm steps and two row rotations leave every lane of a
+// 16-lane row with the row total; row_bcast:15 then adds row r-1 into rows
+// 1 and 3, and row_bcast:31 adds rows 0+1 into row 3, so lane 63 holds the
+// wave total (6 steps = log2 64).
+template <class Op>
+__device__ __forceinline__ typename Op::T wave_reduce_dpp(typename Op::T v) {
+  v = Op::add(v, dpp_move<kQuadPerm1032, 0xF, 0xF>(v));
+  v = Op::add(v, dpp_move<kQuadPerm2301, 0xF, 0xF>(v));
+  v = Op::add(v, dpp_move<kRowRor4, 0xF, 0xF>(v));
+  v = Op::add(v, dpp_move<kRowRor8, 0xF, 0xF>(v));
+  v = Op::add(v, dpp_move<kRowBcast15, 0xA, 0xF>(v));
+  v = Op::add(v, dpp_move<kRowBcast31, 0xC, 0xF>(v));
+  return read_lane(v, 63);
+}
+
+// ds_swizzle: xor butterfly (masks 1, 2, 4, 8, 16) inside each 32-lane half
+// (bit-mode pattern: and_mask = 0x1F, xor_mask in bits 14:10), then the two
+// half totals.
+template <class Op>
+__device__ __forceinline__ typename Op::T wave_reduce_swizzle(typename Op::T v) {
+  v = Op::add(v, swizzle_move<0x1F | (1 << 10)>(v));
+  v = Op::add(v, swizzle_move<0x1F | (2 << 10)>(v));
+  v = Op::add(v, swizzle_move<0x1F | (4 << 10)>(v));
+  v = Op::add(v, swizzle_move<0x1F | (8 << 10)>(v));
+  v = Op::add(v, swizzle_move<0x1F | (16 << 10)>(v));
+  return Op::add(read_lane(v, 0), read_lane(v, 32));
+}
+
+// ds_bpermute: xor butterfly over all 64 lanes (6 steps).
+template <class Op>
+__device__ __forceinline__ typename Op::T wave_reduce_bpermute(typename Op::T v) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int k = 1; k < kWave; k <<= 1) v = Op::add(v, bpermute_move(v, lane ^ k));
+  return read_lane(v, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup combine: per-wave totals -> LDS -> s_barrier -> wave 0 combines.
+// Returns the workgroup total in every lane of wave 0 (other waves get
+// zero()).  `lds` holds at least kMaxWavesPerWG values.  The caller must
+// place a __syncthreads() before reusing `lds`.
+// ---------------------------------------------------------------------------
+template <class Op>
+__device__ __forceinline__ typename Op::T block_reduce(typename Op::T v, typename Op::T* lds) {
+  using T = typename Op::T;
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int nwaves = blockDim.x / kWave;
+  T w = wave_reduce_dpp<Op>(v);
+  if (lane == 0) lds[wave] = w;
+  __syncthreads();
+  T r = Op::zero();
+  if (wave == 0) {
+    T u = lane < nwaves ? lds[lane] : Op::zero();
+    r = wave_reduce_dpp<Op>(u);
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Element modes: input type, 16-byte vector, per-thread accumulator, the
+// Op of the cross-lane combine and the partial stored per workgroup.
+// ---------------------------------------------------------------------------
+// int32 -> int64, exact.
+struct ModeI32 {
+  using In = int32_t;
+  using Vec = v4i;
+  static constexpr int kVE = 4;
+  using Acc = long long;
+  using Op = OpI64;
+  using Part = long long;
+  __device__ static Acc zero() { return 0; }
+  __device__ static void add_elem(Acc& a, In x) { a += (long long)x; }
+  __device__ static void add_vec(Acc& a, Vec v) {
+    a += (long long)v.x;
+    a += (long long)v.y;
+    a += (long long)v.z;
+    a += (long long)v.w;
+  }
+  __device__ static Part to_part(Acc a) { return a; }
+};
+
+// fp32, plain fp32 accumulation.
+struct ModeF32Plain {
+  using In = float;
+  using Vec = v4f;
+  static constexpr int kVE = 4;
+  using Acc = float;
+  using Op = OpF32;
+  using Part = double;
+  __device__ static Acc zero() { return 0.0f; }
+  __device__ static void add_elem(Acc& a, In x) { a += x; }
+  __device__ static void add_vec(Acc& a, Vec v) {
+    a += v.x;
+    a += v.y;
+    a += v.z;
+    a += v.w;
+  }
+  __device__ static Part to_part(Acc a) { return (double)a; }
+};
+
+// fp32, TwoSum-compensated: every element enters the (s, c) pair through an
+// error-free TwoSum, the rounding errors accumulate in c.
+struct ModeF32Comp {
+  using In = float;
+  using Vec = v4f;
+  static constexpr int kVE = 4;
+  using Acc = CompF32;
+  using Op = OpComp;
+  using Part = double;
+  __device__ static Acc zero() { return CompF32{0.0f, 0.0f}; }
+  __device__ static void add_elem(Acc& a, In x) {
+    float e;
+    two_sum(a.s, x, a.s, e);
+    a.c += e;
+  }
+  __device__ static void add_vec(Acc& a, Vec v) {
+    add_elem(a, v.x);
+    add_elem(a, v.y);
+    add_elem(a, v.z);
+    add_elem(a, v.w);
+  }
+  // s and c are fp32, so their binary64 sum is exact unless c is far below
+  // ulp(s); the final combine is in binary64.
+  __device__ static Part to_part(Acc a) { return comp_to_double(a); }
+};
+
+// 16-bit inputs: exact widening to fp32.
+struct Bf16 {
+  __device__ static float lo(unsigned w) { return __uint_as_float(w << 16); }
+  __device__ static float hi(unsigned w) { return __uint_as_float(w & 0xFFFF0000u); }
+  __device__ static float one(uint16_t b) { return __uint_as_float((unsigned)b << 16); }
+};
+struct F16 {
+  __device__ static float lo(unsigned w) {
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)(w & 0xFFFFu));
+  }
+  __device__ static float hi(unsigned w) {
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)(w >> 16));
+  }
+  __device__ static float one(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
+};
+
+// 16-bit inputs, compensated: the two halves of each 32-bit word are added
+// in fp32 (exact unless their exponents differ by more than the fp32
+// significand can bridge; then the error is at most half an fp32 ulp of the
+// pair), and each pair sum enters the (s, c) pair through TwoSum.
+template <class H>
+struct ModeHalfComp {
+  using In = uint16_t;
+  using Vec = v4u;
+  static constexpr int kVE = 8;
+  using Acc = CompF32;
+  using Op = OpComp;
+  using Part = double;
+  __device__ static Acc zero() { return CompF32{0.0f, 0.0f}; }
+  __device__ static void add_f(Acc& a, float x) {
+    float e;
+    two_sum(a.s, x, a.s, e);
+    a.c += e;
+  }
+  __device__ static void add_elem(Acc& a, In x) { add_f(a, H::one(x)); }
+  __device__ static void add_vec(Acc& a, Vec v) {
+    add_f(a, H::lo(v.x) + H::hi(v.x));
+    add_f(a, H::lo(v.y) + H::hi(v.y));
+    add_f(a, H::lo(v.z) + H::hi(v.z));
+    add_f(a, H::lo(v.w) + H::hi(v.w));
+  }
+  __device__ static Part to_part(Acc a) { return comp_to_double(a); }
+};
+
+// 16-bit inputs, plain fp32 accumulation.
+template <class H>
+struct ModeHalfPlain {
+  using In = uint16_t;
+  using Vec = v4u;
+  static constexpr int kVE = 8;
+  using Acc = float;
+  using Op = OpF32;
+  using Part = double;
+  __device__ static Acc zero() { return 0.0f; }
+  __device__ static void add_elem(Acc& a, In x) { a += H::one(x); }
+  __device__ static void add_vec(Acc& a, Vec v) {
+    a += H::lo(v.x);
+    a += H::hi(v.x);
+    a += H::lo(v.y);
+    a += H::hi(v.y);
+    a += H::lo(v.z);
+    a += H::hi(v.z);
+    a += H::lo(v.w);
+    a += H::hi(v.w);
+  }
+  __device__ static Part to_part(Acc a) { return (double)a; }
+};
+
+// Op used to combine stored partials (binary64 for floats, int64 for ints).
+template <class Part>
+struct PartOp;
+template <>
+struct PartOp<long long> {
+  using type = OpI64;
+};
+template <>
+struct PartOp<double> {
+  using type = OpF64;
+};
+
+template <bool NT, class Vec>
+__device__ __forceinline__ Vec load_vec(const Vec* p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace words of one (device, stream).  Each word that is polled or hit
+// by atomics sits on its own 128-byte line.
+// ---------------------------------------------------------------------------
+struct alignas(128) Line {
+  unsigned v;
+  unsigned pad[31];
+};
+struct BarrierWords {
+  Line count;   // arrivals at the current grid barrier
+  Line gen;     // grid-barrier generation (incremented by the last arrival)
+  Line ticket;  // atomic-final variant: workgroups that have stored a partial
+  Line err;     // watchdog flag (nonzero after a timeout)
+  Line acc_lo;  // atomic-final int accumulator (int64 in acc_lo.v/acc_lo.pad[0])
+};
+
+__device__ __forceinline__ long long* acc_i64(BarrierWords* w) {
+  return reinterpret_cast<long long*>(&w->acc_lo.v);
+}
+
+// ---------------------------------------------------------------------------
+// Grid barrier for a cooperative launch of `nblocks` co-resident workgroups.
+//
+// Centralized sense-reversing barrier: thread 0 of each workgroup reads the
+// generation, then increments the arrival counter with an acquire-release
+// atomic at agent (device) scope; the last arrival resets the counter and
+// publishes the next generation with a release increment, the others poll
+// the generation with acquire loads (s_sleep between polls).  Release/acquire
+// at agent scope makes the workgroups' earlier global stores visible across
+// the XCDs' separate L2 caches.  The poll is bounded by `spin_limit`: on
+// expiry the workgroup sets the error word and leaves the barrier, so the
+// kernel always ends (the paper observed that a grid in which not every
+// block calls grid sync deadlocks, Section VIII-B).  Returns false on
+// timeout.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool grid_barrier(BarrierWords* w, unsigned nblocks, unsigned spin_limit) {
+  __shared__ int timed_out;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int to = 0;
+    unsigned g = __hip_atomic_load(&w->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned old = __hip_atomic_fetch_add(&w->count.v, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == nblocks - 1) {
+      __hip_atomic_store(&w->count.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&w->gen.v, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      unsigned spins = 0;
+      while (__hip_atomic_load(&w->gen.v, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        if (++spins > spin_limit) {
+          __hip_atomic_store(&w->err.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          to = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    timed_out = to;
+  }
+  __syncthreads();
+  return timed_out == 0;
+}
+
+}  // namespace redsum

@@ -1,0 +1,96 @@
+// Host-side shared declarations of libredsum (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/redsum.h"
+
+namespace redsum {
+
+struct BarrierWords;
+
+// One carry slot of the segmented reduction: the binary64 sum of the piece
+// of segment `seg` that falls in one workgroup's slice.
+struct SegCarry {
+  long long seg;
+  double val;
+};
+
+struct DeviceInfo {
+  int id = -1;
+  int cus = 0;
+  int64_t wallclock_khz = 0;
+  int64_t clock_khz = 0;
+  int64_t l2_bytes = 0;
+  int64_t hbm_bytes = 0;
+  bool coop = false;
+};
+
+// Library-owned device memory of one (device, stream).
+struct Workspace {
+  void* base = nullptr;
+  BarrierWords* words = nullptr;   // barrier / ticket / error words
+  void* partials = nullptr;        // RED_MAX_GRID x 8 bytes
+  SegCarry* carry_in = nullptr;    // RED_MAX_GRID slots
+  SegCarry* carry_out = nullptr;   // RED_MAX_GRID slots
+  unsigned* seg_tickets = nullptr; // RED_MAX_GRID counters
+  unsigned* sink = nullptr;        // RED_MAX_GRID words for probes
+  long long* stamps = nullptr;     // 2 x RED_MAX_GRID timestamps for probes
+};
+
+// Workspace layout sizes.
+constexpr size_t kWordsBytes = 4096;
+constexpr size_t kPartialBytes = (size_t)RED_MAX_GRID * 8;
+constexpr size_t kCarryBytes = (size_t)RED_MAX_GRID * sizeof(SegCarry);
+constexpr size_t kTicketBytes = (size_t)RED_MAX_GRID * 4;
+constexpr size_t kSinkBytes = (size_t)RED_MAX_GRID * 4;
+constexpr size_t kStampBytes = (size_t)RED_MAX_GRID * 16;
+constexpr size_t kWorkspaceBytes =
+    kWordsBytes + kPartialBytes + 2 * kCarryBytes + kTicketBytes + kSinkBytes + kStampBytes;
+
+// Errors ---------------------------------------------------------------
+int set_error(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+#define RED_HIP(call)                                   \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return ::redsum::hip_fail(e_, #call); \
+  } while (0)
+
+// Device / workspace ---------------------------------------------------------
+int ensure_device(const DeviceInfo** info);  // current device, initialized
+int get_workspace(hipStream_t s, Workspace** ws);  // allocates outside capture
+bool stream_capturing(hipStream_t s);
+unsigned watchdog_spins();
+
+// Kernel launch (uniform signature: one argument struct by value).
+int launch(const void* fn, int grid, int block, void** args, hipStream_t s, bool cooperative);
+
+// Reductions ---------------------------------------------------------------
+struct ReduceLaunch {
+  int dtype, acc;
+  red_plan plan;
+  bool nontemporal;
+};
+int validate_plan(const red_plan& p);
+red_plan default_plan(int dtype, int64_t n, const DeviceInfo& dev);
+int reduce_launch(const ReduceLaunch& rl, const void* x, int64_t n, void* out, Workspace* ws,
+                  hipStream_t s, const DeviceInfo& dev);
+int reduce_max_coresident(int dtype, int acc, int ipt, bool nt, int wg, const DeviceInfo& dev,
+                          int* n_wg);
+
+// Segmented ------------------------------------------------------------------
+struct SegLaunch {
+  red_plan plan;  // variant: RED_VARIANT_ATOMIC (ticket) or RED_VARIANT_PERSISTENT
+  bool nontemporal;
+};
+red_plan default_seg_plan(int64_t nseg, const DeviceInfo& dev);
+int seg_launch(const SegLaunch& sl, const float* x, const int64_t* offsets, int64_t nseg, double* out,
+               Workspace* ws, hipStream_t s, const DeviceInfo& dev);
+int seg_max_coresident(int ipt, int wg, const DeviceInfo& dev, int* n_wg);
+
+// Probes -------------------------------------------------------------------
+int bw_proxy_launch(const void* x, int64_t nbytes, int n_wg, int wg, Workspace* ws, hipStream_t s);
+
+}  // namespace redsum

@@ -1,0 +1,501 @@
+// Synchronization latency probes (Sections IV, V and IX of Zhang et al.).
+//
+// * wavefront level  -- a dependent chain of cross-lane operations (DPP,
+//   ds_swizzle, ds_bpermute wavefront combines, or one DPP add step), timed
+//   in-kernel with the shader clock (the in-SM clock method of Section
+//   IX-C) and by the host differential of Eq. 7 between chains of r1 and r2
+//   operations;
+// * workgroup level  -- a chain of s_barrier (__syncthreads) in n_wg
+//   workgroups;
+// * grid level       -- a chain of software grid barriers in one cooperative
+//   kernel;
+// * implicit barrier -- the launch overhead of a kernel boundary by kernel
+//   fusion (Eq. 6) with kernels that wait a fixed wall-clock time per unit
+//   (the paper's nanosleep null kernel, Section IV), and the total latency
+//   of a null kernel by the three-timestamp formula of Section IV.
+// Uncertainties follow Eq. 8.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "device_prims.h"
+#include "internal.h"
+
+namespace redsum {
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+template <int OP>
+__global__ __launch_bounds__(1024) void k_wave_chain(int r, float* sink, long long* cycles) {
+  const int lane = __lane_id();
+  float v = 0.25f * (float)lane;
+  const float d = (float)(lane & 7) * 0.125f;
+  __builtin_amdgcn_sched_barrier(0);
+  const long long t0 = __builtin_amdgcn_s_memtime();
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll 8
+  for (int i = 0; i < r; ++i) {
+    if constexpr (OP == RED_WAVE_DPP)
+      v = wave_reduce_dpp<OpF32>(v) * 0.0078125f + d;
+    else if constexpr (OP == RED_WAVE_SWIZZLE)
+      v = wave_reduce_swizzle<OpF32>(v) * 0.0078125f + d;
+    else if constexpr (OP == RED_WAVE_BPERMUTE)
+      v = wave_reduce_bpermute<OpF32>(v) * 0.0078125f + d;
+    else
+      v = v + dpp_move<kRowShr1, 0xF, 0xF>(v);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  const long long t1 = __builtin_amdgcn_s_memtime();
+  __builtin_amdgcn_sched_barrier(0);
+  if (threadIdx.x == 0) cycles[blockIdx.x] = t1 - t0;
+  if (v == -1.0f) sink[threadIdx.x] = v;  // keeps the chain live; never true
+}
+
+__global__ __launch_bounds__(1024) void k_block_chain(int r, long long* cycles) {
+  __builtin_amdgcn_sched_barrier(0);
+  const long long t0 = __builtin_amdgcn_s_memtime();
+  __builtin_amdgcn_sched_barrier(0);
+  for (int i = 0; i < r; ++i) __syncthreads();
+  __builtin_amdgcn_sched_barrier(0);
+  const long long t1 = __builtin_amdgcn_s_memtime();
+  if (threadIdx.x == 0) cycles[blockIdx.x] = t1 - t0;
+}
+
+__global__ __launch_bounds__(1024) void k_grid_chain(int r, BarrierWords* w, unsigned spin_limit,
+                                                    long long* stamps) {
+  __syncthreads();
+  const long long t0 = __builtin_amdgcn_s_memrealtime();
+  for (int i = 0; i < r; ++i) grid_barrier(w, gridDim.x, spin_limit);
+  const long long t1 = __builtin_amdgcn_s_memrealtime();
+  if (blockIdx.x == 0 && threadIdx.x == 0) stamps[0] = t1 - t0;
+}
+
+// Waits `ticks` of the 100 MHz wall clock (a "wait unit" kernel; the
+// paper's nanosleep kernel).  The loop ends because the clock advances.
+__global__ __launch_bounds__(1024) void k_spin(long long ticks) {
+  if (ticks <= 0) return;
+  const long long t0 = __builtin_amdgcn_s_memrealtime();
+  while (__builtin_amdgcn_s_memrealtime() - t0 < ticks) __builtin_amdgcn_s_sleep(2);
+}
+
+__global__ __launch_bounds__(1024) void k_grid_order(BarrierWords* w, unsigned spin_limit,
+                                                    long long* before, long long* after) {
+  __syncthreads();
+  if (threadIdx.x == 0) before[blockIdx.x] = __builtin_amdgcn_s_memrealtime();
+  grid_barrier(w, gridDim.x, spin_limit);
+  if (threadIdx.x == 0) after[blockIdx.x] = __builtin_amdgcn_s_memrealtime();
+}
+
+// Workgroup `skip` never arrives; the others leave through the watchdog.
+__global__ __launch_bounds__(1024) void k_watchdog(BarrierWords* w, int skip, unsigned spin_limit) {
+  if ((int)blockIdx.x == skip) return;
+  grid_barrier(w, gridDim.x, spin_limit);
+}
+
+__global__ void k_reset_words(BarrierWords* w) {
+  if (threadIdx.x == 0) {
+    w->count.v = 0;
+    w->gen.v = 0;
+    w->ticket.v = 0;
+    w->err.v = 0;
+    *acc_i64(w) = 0;
+  }
+}
+
+// Read-only bandwidth proxy (Section VII-B): grid-stride 16-byte loads, two
+// adds per load.
+template <int IPT>
+__global__ __launch_bounds__(1024) void k_bw_proxy(const v4u* x, int64_t nvec, unsigned* sink) {
+  const int64_t bs = blockDim.x;
+  const int64_t tile = bs * IPT;
+  const int64_t ntiles = nvec / tile;
+  unsigned acc = 0;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    v4u v[IPT];
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) v[u] = x[t * tile + u * bs + threadIdx.x];
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) acc += v[u].x + v[u].y;
+  }
+  for (int64_t i = ntiles * tile + blockIdx.x * bs + threadIdx.x; i < nvec; i += gridDim.x * bs)
+    acc += x[i].x + x[i].y;
+  if (acc == 0x9E3779B9u) sink[blockIdx.x] = acc;  // keeps the loads live
+}
+
+// ---------------------------------------------------------------------------
+// Host helpers
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Events {
+  hipEvent_t a = nullptr, b = nullptr;
+  ~Events() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+  int init() {
+    RED_HIP(hipEventCreate(&a));
+    RED_HIP(hipEventCreate(&b));
+    return RED_OK;
+  }
+};
+
+// Milliseconds between two events around `k` launches of one kernel.
+int time_launches(const void* fn, int grid, int block, void** args, bool coop, int k, hipStream_t s,
+                  Events& ev, double* ms) {
+  RED_HIP(hipEventRecord(ev.a, s));
+  for (int i = 0; i < k; ++i) {
+    int rc = launch(fn, grid, block, args, s, coop);
+    if (rc) return rc;
+  }
+  RED_HIP(hipEventRecord(ev.b, s));
+  RED_HIP(hipEventSynchronize(ev.b));
+  float f = 0.f;
+  RED_HIP(hipEventElapsedTime(&f, ev.a, ev.b));
+  *ms = f;
+  return RED_OK;
+}
+
+double mean(const std::vector<double>& v) {
+  double s = 0;
+  for (double x : v) s += x;
+  return s / v.size();
+}
+
+double sdev(const std::vector<double>& v) {
+  const double m = mean(v);
+  double s = 0;
+  for (double x : v) s += (x - m) * (x - m);
+  return v.size() > 1 ? std::sqrt(s / (v.size() - 1)) : 0.0;
+}
+
+// Runs the Eq. 7 / Eq. 8 differential between r1 and r2 repetitions.
+// `set_r` rewrites the repetition argument; `read_cycles` (optional)
+// returns the in-kernel counter of the last launch.
+template <class SetR, class ReadCycles>
+int differential(const void* fn, int grid, int block, void** args, bool coop, int reps, hipStream_t s,
+                 SetR set_r, ReadCycles read_cycles, double target_us, int64_t r_max, double* ns,
+                 double* sigma, double* per_op_counter) {
+  Events ev;
+  int rc = ev.init();
+  if (rc) return rc;
+  double ms = 0;
+  // Warm-up and calibration: choose r2 so that the r2 kernel runs about
+  // target_us beyond its fixed cost, r1 = 8 r2 (Section IX-B: kernels must
+  // be long enough to saturate the launch pipeline).
+  int64_t rc_small = 16, rc_big = 16 * 64;
+  set_r(rc_small);
+  if ((rc = time_launches(fn, grid, block, args, coop, 1, s, ev, &ms))) return rc;
+  double t_small = 0, t_big = 0;
+  set_r(rc_small);
+  if ((rc = time_launches(fn, grid, block, args, coop, 1, s, ev, &t_small))) return rc;
+  set_r(rc_big);
+  if ((rc = time_launches(fn, grid, block, args, coop, 1, s, ev, &t_big))) return rc;
+  double per = std::max(1e-6, (t_big - t_small) * 1e3 / (double)(rc_big - rc_small));  // us per op
+  int64_t r2 = (int64_t)std::ceil(target_us / per);
+  r2 = std::max<int64_t>(4, std::min<int64_t>(r2, r_max / 8));
+  const int64_t r1 = 8 * r2;
+  std::vector<double> l1, l2, c1, c2;
+  for (int i = 0; i < reps; ++i) {
+    set_r(r1);
+    if ((rc = time_launches(fn, grid, block, args, coop, 1, s, ev, &ms))) return rc;
+    l1.push_back(ms * 1e6);
+    c1.push_back(read_cycles());
+    set_r(r2);
+    if ((rc = time_launches(fn, grid, block, args, coop, 1, s, ev, &ms))) return rc;
+    l2.push_back(ms * 1e6);
+    c2.push_back(read_cycles());
+  }
+  *ns = red_eq7_latency(mean(l1), mean(l2), r1, r2);
+  *sigma = red_eq8_sigma(l1.data(), l2.data(), (int)l1.size(), r1, r2);
+  if (per_op_counter) *per_op_counter = (mean(c1) - mean(c2)) / (double)(r1 - r2);
+  return RED_OK;
+}
+
+int read_i64(const long long* dptr, long long* h) {
+  RED_HIP(hipMemcpy(h, dptr, sizeof(long long), hipMemcpyDeviceToHost));
+  return RED_OK;
+}
+
+int probe_prologue(hipStream_t s, const DeviceInfo** dev, Workspace** ws) {
+  int rc = ensure_device(dev);
+  if (rc) return rc;
+  if (stream_capturing(s)) return set_error(RED_EINVAL, "probes cannot run inside stream capture");
+  return get_workspace(s, ws);
+}
+
+int reset_words(Workspace* ws, hipStream_t s) {
+  void* args[] = {&ws->words};
+  int rc = launch(reinterpret_cast<const void*>(&k_reset_words), 1, 64, args, s, false);
+  if (rc) return rc;
+  RED_HIP(hipStreamSynchronize(s));
+  return RED_OK;
+}
+
+int coresident(const void* fn, int wg, const DeviceInfo& dev, int* n) {
+  int per_cu = 0;
+  RED_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, wg, 0));
+  *n = per_cu * dev.cus;
+  return RED_OK;
+}
+
+}  // namespace
+
+int bw_proxy_launch(const void* x, int64_t nbytes, int n_wg, int wg, Workspace* ws, hipStream_t s) {
+  const v4u* xv = static_cast<const v4u*>(x);
+  int64_t nvec = nbytes / 16;
+  unsigned* sink = ws->sink;
+  void* args[] = {&xv, &nvec, &sink};
+  return launch(reinterpret_cast<const void*>(&k_bw_proxy<4>), n_wg, wg, args, s, false);
+}
+
+}  // namespace redsum
+
+using namespace redsum;
+
+extern "C" {
+
+double red_eq6_overhead(double lat_ij, double lat_ji, int i, int j) {
+  return (lat_ij - lat_ji) / (double)(i - j);
+}
+
+double red_eq7_latency(double lat_k1, double lat_k2, int64_t r1, int64_t r2) {
+  return (lat_k1 - lat_k2) / (double)(r1 - r2);
+}
+
+double red_eq8_sigma(const double* k1, const double* k2, int nsamp, int64_t r1, int64_t r2) {
+  if (!k1 || !k2 || nsamp < 2 || r1 == r2) return NAN;
+  std::vector<double> a(k1, k1 + nsamp), b(k2, k2 + nsamp);
+  const double s1 = sdev(a), s2 = sdev(b);
+  return std::sqrt(s1 * s1 + s2 * s2) / std::fabs((double)(r1 - r2));
+}
+
+int sync_bench_wave(int op, int wg_size, int reps, double* ns, double* sigma_ns, double* cycles,
+                    void* stream) {
+  if (op < RED_WAVE_DPP || op > RED_WAVE_DPP_STEP) return set_error(RED_EINVAL, "bad wave op %d", op);
+  if (wg_size < 64 || wg_size > 1024 || wg_size % 64) return set_error(RED_EINVAL, "bad wg_size %d", wg_size);
+  if (reps < 2 || !ns || !sigma_ns) return set_error(RED_EINVAL, "reps >= 2 and non-null outputs required");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DeviceInfo* dev;
+  Workspace* ws;
+  int rc = probe_prologue(s, &dev, &ws);
+  if (rc) return rc;
+  const void* fns[] = {reinterpret_cast<const void*>(&k_wave_chain<RED_WAVE_DPP>),
+                       reinterpret_cast<const void*>(&k_wave_chain<RED_WAVE_SWIZZLE>),
+                       reinterpret_cast<const void*>(&k_wave_chain<RED_WAVE_BPERMUTE>),
+                       reinterpret_cast<const void*>(&k_wave_chain<RED_WAVE_DPP_STEP>)};
+  int r = 0;
+  float* sink = reinterpret_cast<float*>(ws->sink);
+  long long* cyc = ws->stamps;
+  void* args[] = {&r, &sink, &cyc};
+  return differential(
+      fns[op], 1, wg_size, args, false, reps, s, [&](int64_t v) { r = (int)v; },
+      [&]() {
+        long long h = 0;
+        read_i64(cyc, &h);
+        return (double)h;
+      },
+      20.0, 1 << 22, ns, sigma_ns, cycles);
+}
+
+int sync_bench_block(int wg_size, int n_wg, int reps, double* ns, double* sigma_ns, double* cycles,
+                     void* stream) {
+  if (wg_size < 64 || wg_size > 1024 || wg_size % 64) return set_error(RED_EINVAL, "bad wg_size %d", wg_size);
+  if (n_wg < 1 || n_wg > RED_MAX_GRID) return set_error(RED_EINVAL, "bad n_wg %d", n_wg);
+  if (reps < 2 || !ns || !sigma_ns) return set_error(RED_EINVAL, "reps >= 2 and non-null outputs required");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DeviceInfo* dev;
+  Workspace* ws;
+  int rc = probe_prologue(s, &dev, &ws);
+  if (rc) return rc;
+  int r = 0;
+  long long* cyc = ws->stamps;
+  void* args[] = {&r, &cyc};
+  return differential(
+      reinterpret_cast<const void*>(&k_block_chain), n_wg, wg_size, args, false, reps, s,
+      [&](int64_t v) { r = (int)v; },
+      [&]() {
+        long long h = 0;
+        read_i64(cyc, &h);
+        return (double)h;
+      },
+      20.0, 1 << 22, ns, sigma_ns, cycles);
+}
+
+int sync_bench_grid(int n_wg, int wg_size, int reps, double* ns, double* sigma_ns, double* cycles,
+                    void* stream) {
+  if (wg_size < 64 || wg_size > 1024 || wg_size % 64) return set_error(RED_EINVAL, "bad wg_size %d", wg_size);
+  if (n_wg < 1 || n_wg > RED_MAX_GRID) return set_error(RED_EINVAL, "bad n_wg %d", n_wg);
+  if (reps < 2 || !ns || !sigma_ns) return set_error(RED_EINVAL, "reps >= 2 and non-null outputs required");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DeviceInfo* dev;
+  Workspace* ws;
+  int rc = probe_prologue(s, &dev, &ws);
+  if (rc) return rc;
+  const void* fn = reinterpret_cast<const void*>(&k_grid_chain);
+  int maxg = 0;
+  if ((rc = coresident(fn, wg_size, *dev, &maxg))) return rc;
+  if (n_wg > maxg)
+    return set_error(RED_EINVAL, "grid probe: %d workgroups of %d threads are not co-resident (max %d)",
+                     n_wg, wg_size, maxg);
+  if ((rc = reset_words(ws, s))) return rc;
+  int r = 0;
+  BarrierWords* w = ws->words;
+  unsigned spin = watchdog_spins();
+  long long* st = ws->stamps;
+  void* args[] = {&r, &w, &spin, &st};
+  const double tick_ns = 1e6 / (double)dev->wallclock_khz;
+  rc = differential(
+      fn, n_wg, wg_size, args, true, reps, s, [&](int64_t v) { r = (int)v; },
+      [&]() {
+        long long h = 0;
+        read_i64(st, &h);
+        return (double)h * tick_ns;
+      },
+      50.0, 1 << 16, ns, sigma_ns, cycles);
+  if (rc) return rc;
+  unsigned err = 0;
+  RED_HIP(hipMemcpy(&err, &ws->words->err.v, 4, hipMemcpyDeviceToHost));
+  if (err) {
+    reset_words(ws, s);
+    return set_error(RED_ETIMEOUT, "grid probe: barrier watchdog fired");
+  }
+  return RED_OK;
+}
+
+int sync_bench_relaunch(int n_wg, int wg_size, int cooperative, int reps, double* ns, double* sigma_ns,
+                        double* null_kernel_ns, void* stream) {
+  if (wg_size < 64 || wg_size > 1024 || wg_size % 64) return set_error(RED_EINVAL, "bad wg_size %d", wg_size);
+  if (n_wg < 1 || n_wg > RED_MAX_GRID) return set_error(RED_EINVAL, "bad n_wg %d", n_wg);
+  if (reps < 2 || !ns || !sigma_ns) return set_error(RED_EINVAL, "reps >= 2 and non-null outputs required");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DeviceInfo* dev;
+  Workspace* ws;
+  int rc = probe_prologue(s, &dev, &ws);
+  if (rc) return rc;
+  const void* fn = reinterpret_cast<const void*>(&k_spin);
+  const bool coop = cooperative != 0;
+  if (coop) {
+    int maxg = 0;
+    if ((rc = coresident(fn, wg_size, *dev, &maxg))) return rc;
+    if (n_wg > maxg) return set_error(RED_EINVAL, "relaunch probe: cooperative grid too large (max %d)", maxg);
+  }
+  Events ev;
+  if ((rc = ev.init())) return rc;
+  long long ticks = 0;
+  void* args[] = {&ticks};
+  // 5 us wait unit (Section IX-B: about 5 us keeps one GPU's launch
+  // pipeline saturated).
+  const long long unit = std::max<long long>(1, dev->wallclock_khz * 5 / 1000);
+  const int i = 8, j = 1;
+  double ms = 0;
+  ticks = unit;  // warm-up
+  if ((rc = time_launches(fn, n_wg, wg_size, args, coop, 2, s, ev, &ms))) return rc;
+  std::vector<double> lij, lji;
+  for (int k = 0; k < reps; ++k) {
+    ticks = unit * j;
+    if ((rc = time_launches(fn, n_wg, wg_size, args, coop, i, s, ev, &ms))) return rc;
+    lij.push_back(ms * 1e6);
+    ticks = unit * i;
+    if ((rc = time_launches(fn, n_wg, wg_size, args, coop, j, s, ev, &ms))) return rc;
+    lji.push_back(ms * 1e6);
+  }
+  *ns = red_eq6_overhead(mean(lij), mean(lji), i, j);
+  *sigma_ns = red_eq8_sigma(lij.data(), lji.data(), (int)lij.size(), i, j);
+  if (null_kernel_ns) {
+    // Section IV: host clock around 1 launch and around 5 launches of a
+    // null kernel, each followed by a device synchronization.
+    ticks = 0;
+    std::vector<double> tot;
+    for (int k = 0; k < reps; ++k) {
+      auto t1 = std::chrono::steady_clock::now();
+      if ((rc = launch(fn, n_wg, wg_size, args, s, coop))) return rc;
+      RED_HIP(hipStreamSynchronize(s));
+      auto t2 = std::chrono::steady_clock::now();
+      for (int q = 0; q < 5; ++q)
+        if ((rc = launch(fn, n_wg, wg_size, args, s, coop))) return rc;
+      RED_HIP(hipStreamSynchronize(s));
+      auto t3 = std::chrono::steady_clock::now();
+      const double a = std::chrono::duration<double, std::nano>(t2 - t1).count();
+      const double b = std::chrono::duration<double, std::nano>(t3 - t2).count();
+      tot.push_back((b - a) / 4.0);
+    }
+    *null_kernel_ns = mean(tot);
+  }
+  return RED_OK;
+}
+
+int sync_check_grid_order(int n_wg, int wg_size, int64_t* max_before, int64_t* min_after, void* stream) {
+  if (wg_size < 64 || wg_size > 1024 || wg_size % 64) return set_error(RED_EINVAL, "bad wg_size %d", wg_size);
+  if (n_wg < 1 || n_wg > RED_MAX_GRID) return set_error(RED_EINVAL, "bad n_wg %d", n_wg);
+  if (!max_before || !min_after) return set_error(RED_EINVAL, "null output");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DeviceInfo* dev;
+  Workspace* ws;
+  int rc = probe_prologue(s, &dev, &ws);
+  if (rc) return rc;
+  const void* fn = reinterpret_cast<const void*>(&k_grid_order);
+  int maxg = 0;
+  if ((rc = coresident(fn, wg_size, *dev, &maxg))) return rc;
+  if (n_wg > maxg) return set_error(RED_EINVAL, "order check: grid too large (max %d)", maxg);
+  if ((rc = reset_words(ws, s))) return rc;
+  BarrierWords* w = ws->words;
+  unsigned spin = watchdog_spins();
+  long long* before = ws->stamps;
+  long long* after = ws->stamps + RED_MAX_GRID;
+  void* args[] = {&w, &spin, &before, &after};
+  if ((rc = launch(fn, n_wg, wg_size, args, s, true))) return rc;
+  RED_HIP(hipStreamSynchronize(s));
+  std::vector<long long> hb(n_wg), ha(n_wg);
+  RED_HIP(hipMemcpy(hb.data(), before, n_wg * sizeof(long long), hipMemcpyDeviceToHost));
+  RED_HIP(hipMemcpy(ha.data(), after, n_wg * sizeof(long long), hipMemcpyDeviceToHost));
+  unsigned err = 0;
+  RED_HIP(hipMemcpy(&err, &ws->words->err.v, 4, hipMemcpyDeviceToHost));
+  if (err) {
+    reset_words(ws, s);
+    return set_error(RED_ETIMEOUT, "order check: barrier watchdog fired");
+  }
+  *max_before = *std::max_element(hb.begin(), hb.end());
+  *min_after = *std::min_element(ha.begin(), ha.end());
+  return RED_OK;
+}
+
+int sync_check_watchdog(int n_wg, int wg_size, int skip_wg, int spin_limit, void* stream) {
+  if (wg_size < 64 || wg_size > 1024 || wg_size % 64) return set_error(RED_EINVAL, "bad wg_size %d", wg_size);
+  if (n_wg < 2 || n_wg > RED_MAX_GRID) return set_error(RED_EINVAL, "bad n_wg %d", n_wg);
+  if (skip_wg < 0 || skip_wg >= n_wg) return set_error(RED_EINVAL, "skip_wg out of range");
+  if (spin_limit < 1 || spin_limit > (1 << 24)) return set_error(RED_EINVAL, "spin_limit out of range");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DeviceInfo* dev;
+  Workspace* ws;
+  int rc = probe_prologue(s, &dev, &ws);
+  if (rc) return rc;
+  const void* fn = reinterpret_cast<const void*>(&k_watchdog);
+  int maxg = 0;
+  if ((rc = coresident(fn, wg_size, *dev, &maxg))) return rc;
+  if (n_wg > maxg) return set_error(RED_EINVAL, "watchdog check: grid too large (max %d)", maxg);
+  if ((rc = reset_words(ws, s))) return rc;
+  BarrierWords* w = ws->words;
+  unsigned spin = (unsigned)spin_limit;
+  void* args[] = {&w, &skip_wg, &spin};
+  if ((rc = launch(fn, n_wg, wg_size, args, s, true))) return rc;
+  return red_check_error(stream);
+}
+
+int red_bw_proxy(const void* x, int64_t nbytes, int n_wg, int wg_size, void* stream) {
+  if (!x || nbytes < 0) return set_error(RED_EINVAL, "bad buffer");
+  if (reinterpret_cast<uintptr_t>(x) & 15) return set_error(RED_EINVAL, "x must be 16-byte aligned");
+  if (wg_size < 64 || wg_size > 1024 || wg_size % 64) return set_error(RED_EINVAL, "bad wg_size %d", wg_size);
+  if (n_wg < 1 || n_wg > RED_MAX_GRID) return set_error(RED_EINVAL, "bad n_wg %d", n_wg);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DeviceInfo* dev;
+  int rc = ensure_device(&dev);
+  if (rc) return rc;
+  Workspace* ws;
+  if ((rc = get_workspace(s, &ws))) return rc;
+  return bw_proxy_launch(x, nbytes, n_wg, wg_size, ws, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,357 @@
+// Device-wide sum reduction kernels for gfx950 and their host dispatch.
+//
+// Section VII-C (single-GPU reduction) of Zhang et al. describes two ways of
+// synchronizing the device between the per-block partial sums and the final
+// combine: an implicit barrier between two kernels on one stream
+// (Kernel1/Kernel2), and an explicit grid barrier inside one persistent
+// cooperative kernel.  Both are built here, plus a third single-kernel form
+// in which the last workgroup to arrive (atomic ticket) does the final
+// combine, which needs no co-residency.
+//
+// Every variant shares the same per-thread accumulation (the paper's
+// `summing`, a grid-stride loop, here over 16-byte vectors with IPT loads in
+// flight per thread) and the same workgroup combine (the paper's
+// `block_reduce`, here a DPP wavefront combine, LDS staging and a second
+// wavefront combine in wave 0).  One partial per workgroup is stored (int64
+// for int32 input, binary64 for floating-point input), and the final
+// combine sums the partials in a fixed order, so a plan gives bit-identical
+// results on every call.
+#include <algorithm>
+
+#include "device_prims.h"
+#include "internal.h"
+
+namespace redsum {
+
+// Arguments of every reduction kernel (passed by value).
+struct ReduceArgs {
+  const void* x;
+  int64_t head;   // scalar elements before the first 16-byte boundary
+  int64_t nvec;   // full 16-byte vectors after the head
+  int64_t tail;   // scalar elements after the vectors
+  void* partials; // one Part per workgroup
+  BarrierWords* words;
+  void* out;      // one Part
+  unsigned spin_limit;
+};
+
+// Per-thread accumulation of this thread's grid-stride share.  The vector
+// body is cut into tiles of blockDim.x * IPT vectors; workgroup g takes
+// tiles g, g + G, ...; inside a tile, load u of thread t reads vector
+// u * blockDim.x + t, so each wavefront load instruction reads 1 KiB of
+// contiguous memory.  IPT independent accumulators keep IPT loads in flight.
+template <class M, int IPT, bool NT>
+__device__ __forceinline__ typename M::Acc thread_accumulate(const ReduceArgs& a) {
+  using In = typename M::In;
+  using Vec = typename M::Vec;
+  using Acc = typename M::Acc;
+  const In* x = static_cast<const In*>(a.x);
+  const Vec* xv = reinterpret_cast<const Vec*>(x + a.head);
+  const int64_t bs = blockDim.x;
+  const int64_t tile = bs * IPT;
+  const int64_t ntiles = a.nvec / tile;
+
+  Acc acc[IPT];
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) acc[u] = M::zero();
+
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const Vec* p = xv + t * tile + threadIdx.x;
+    Vec v[IPT];
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) v[u] = load_vec<NT>(p + u * bs);
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) M::add_vec(acc[u], v[u]);
+  }
+  // Vectors after the last full tile.
+  for (int64_t i = ntiles * tile + (int64_t)blockIdx.x * bs + threadIdx.x; i < a.nvec;
+       i += (int64_t)gridDim.x * bs)
+    M::add_vec(acc[0], load_vec<NT>(xv + i));
+  // Unaligned head and the tail: fewer than 16 bytes each, workgroup 0.
+  if (blockIdx.x == 0) {
+    const int64_t t = threadIdx.x;
+    if (t < a.head)
+      M::add_elem(acc[0], x[t]);
+    else if (t < a.head + a.tail)
+      M::add_elem(acc[0], x[a.head + a.nvec * M::kVE + (t - a.head)]);
+  }
+#pragma unroll
+  for (int u = 1; u < IPT; ++u) acc[0] = M::Op::add(acc[0], acc[u]);
+  return acc[0];
+}
+
+// Workgroup total of the thread accumulators, as the stored partial type
+// (valid in thread 0).
+template <class M, int IPT, bool NT>
+__device__ __forceinline__ typename M::Part workgroup_partial(const ReduceArgs& a) {
+  __shared__ typename M::Op::T lds[kMaxWavesPerWG];
+  typename M::Acc acc = thread_accumulate<M, IPT, NT>(a);
+  return M::to_part(block_reduce<typename M::Op>(acc, lds));
+}
+
+// Final combine of `count` partials by one workgroup: thread t sums
+// partials t, t + blockDim.x, ... in order, then the workgroup combine.
+// Deterministic for a fixed (count, blockDim.x).  Valid in thread 0.
+template <class Part>
+__device__ __forceinline__ Part combine_partials(const Part* partials, int count) {
+  using Op = typename PartOp<Part>::type;
+  __shared__ Part lds[kMaxWavesPerWG];
+  Part s = Op::zero();
+  for (int i = threadIdx.x; i < count; i += blockDim.x) s = Op::add(s, partials[i]);
+  return block_reduce<Op>(s, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Variant 1, implicit barrier: kernel 1 writes one partial per workgroup,
+// kernel 2 (one workgroup) combines them.
+// ---------------------------------------------------------------------------
+template <class M, int IPT, bool NT>
+__global__ __launch_bounds__(1024) void k_partials(ReduceArgs a) {
+  typename M::Part p = workgroup_partial<M, IPT, NT>(a);
+  if (threadIdx.x == 0) static_cast<typename M::Part*>(a.partials)[blockIdx.x] = p;
+}
+
+template <class Part>
+__global__ __launch_bounds__(1024) void k_final(const Part* partials, int count, Part* out) {
+  Part s = combine_partials<Part>(partials, count);
+  if (threadIdx.x == 0) *out = s;
+}
+
+// ---------------------------------------------------------------------------
+// Variant 2, one kernel with an atomic ticket: each workgroup publishes its
+// partial (int: atomic int64 add into one word; float: its partial slot),
+// then takes a ticket with an acquire-release atomic at device scope; the
+// workgroup that draws the last ticket does the final combine and resets
+// the ticket (and the int accumulator) for the next launch.
+// ---------------------------------------------------------------------------
+template <class M, int IPT, bool NT>
+__global__ __launch_bounds__(1024) void k_atomic(ReduceArgs a) {
+  using Part = typename M::Part;
+  __shared__ unsigned ticket;
+  Part p = workgroup_partial<M, IPT, NT>(a);
+  BarrierWords* w = a.words;
+  if (threadIdx.x == 0) {
+    if constexpr (__is_same(Part, long long))
+      __hip_atomic_fetch_add(acc_i64(w), p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+      static_cast<Part*>(a.partials)[blockIdx.x] = p;
+    ticket = __hip_atomic_fetch_add(&w->ticket.v, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (ticket != gridDim.x - 1) return;
+  // Last workgroup: every thread acquires before reading the others' data.
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if constexpr (__is_same(Part, long long)) {
+    if (threadIdx.x == 0) {
+      long long s = __hip_atomic_load(acc_i64(w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      *static_cast<Part*>(a.out) = s;
+      __hip_atomic_store(acc_i64(w), 0LL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&w->ticket.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else {
+    Part s = combine_partials<Part>(static_cast<const Part*>(a.partials), gridDim.x);
+    if (threadIdx.x == 0) {
+      *static_cast<Part*>(a.out) = s;
+      __hip_atomic_store(&w->ticket.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Variant 3, explicit barrier: one cooperative (co-resident) kernel; every
+// workgroup stores its partial, all meet at the grid barrier, workgroup 0
+// combines.
+// ---------------------------------------------------------------------------
+template <class M, int IPT, bool NT>
+__global__ __launch_bounds__(1024) void k_persistent(ReduceArgs a) {
+  using Part = typename M::Part;
+  Part p = workgroup_partial<M, IPT, NT>(a);
+  if (threadIdx.x == 0) static_cast<Part*>(a.partials)[blockIdx.x] = p;
+  grid_barrier(a.words, gridDim.x, a.spin_limit);
+  if (blockIdx.x != 0) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  Part s = combine_partials<Part>(static_cast<const Part*>(a.partials), gridDim.x);
+  if (threadIdx.x == 0) *static_cast<Part*>(a.out) = s;
+}
+
+template <class Part>
+__global__ void k_write_zero(Part* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = Part(0);
+}
+
+// ---------------------------------------------------------------------------
+// Host dispatch
+// ---------------------------------------------------------------------------
+namespace {
+
+// Element modes by (dtype, acc).
+enum ModeId { kI32 = 0, kF32C, kF32P, kF16C, kF16P, kBF16C, kBF16P, kNumModes };
+
+int mode_of(int dtype, int acc) {
+  switch (dtype) {
+    case RED_I32: return kI32;
+    case RED_F32: return acc == RED_ACC_PLAIN ? kF32P : kF32C;
+    case RED_F16: return acc == RED_ACC_PLAIN ? kF16P : kF16C;
+    case RED_BF16: return acc == RED_ACC_PLAIN ? kBF16P : kBF16C;
+  }
+  return -1;
+}
+
+int elem_size(int dtype) { return dtype == RED_I32 || dtype == RED_F32 ? 4 : 2; }
+
+constexpr int kIpts[4] = {1, 2, 4, 8};
+int ipt_index(int ipt) { return ipt == 1 ? 0 : ipt == 2 ? 1 : ipt == 4 ? 2 : ipt == 8 ? 3 : -1; }
+
+struct KernelSet {
+  const void* partials;
+  const void* atomic;
+  const void* persistent;
+};
+
+template <class M, int IPT, bool NT>
+KernelSet make_set() {
+  return KernelSet{reinterpret_cast<const void*>(&k_partials<M, IPT, NT>),
+                   reinterpret_cast<const void*>(&k_atomic<M, IPT, NT>),
+                   reinterpret_cast<const void*>(&k_persistent<M, IPT, NT>)};
+}
+
+template <class M, bool NT>
+void fill_ipts(KernelSet* row) {
+  row[0] = make_set<M, 1, NT>();
+  row[1] = make_set<M, 2, NT>();
+  row[2] = make_set<M, 4, NT>();
+  row[3] = make_set<M, 8, NT>();
+}
+
+struct Table {
+  KernelSet k[kNumModes][2][4];  // mode, nontemporal, ipt index
+  Table() {
+    fill_ipts<ModeI32, false>(k[kI32][0]);
+    fill_ipts<ModeI32, true>(k[kI32][1]);
+    fill_ipts<ModeF32Comp, false>(k[kF32C][0]);
+    fill_ipts<ModeF32Comp, true>(k[kF32C][1]);
+    fill_ipts<ModeF32Plain, false>(k[kF32P][0]);
+    fill_ipts<ModeF32Plain, true>(k[kF32P][1]);
+    fill_ipts<ModeHalfComp<F16>, false>(k[kF16C][0]);
+    fill_ipts<ModeHalfComp<F16>, true>(k[kF16C][1]);
+    fill_ipts<ModeHalfPlain<F16>, false>(k[kF16P][0]);
+    fill_ipts<ModeHalfPlain<F16>, true>(k[kF16P][1]);
+    fill_ipts<ModeHalfComp<Bf16>, false>(k[kBF16C][0]);
+    fill_ipts<ModeHalfComp<Bf16>, true>(k[kBF16C][1]);
+    fill_ipts<ModeHalfPlain<Bf16>, false>(k[kBF16P][0]);
+    fill_ipts<ModeHalfPlain<Bf16>, true>(k[kBF16P][1]);
+  }
+};
+
+const Table& table() {
+  static const Table t;
+  return t;
+}
+
+constexpr int kFinalWG = 256;
+
+}  // namespace
+
+int validate_plan(const red_plan& p) {
+  if (p.variant < RED_VARIANT_RELAUNCH || p.variant > RED_VARIANT_PERSISTENT)
+    return set_error(RED_EINVAL, "plan: variant %d out of range", p.variant);
+  if (p.wg < 64 || p.wg > 1024 || p.wg % 64 != 0)
+    return set_error(RED_EINVAL, "plan: workgroup size %d must be a multiple of 64 in [64, 1024]", p.wg);
+  if (ipt_index(p.ipt) < 0) return set_error(RED_EINVAL, "plan: ipt %d must be 1, 2, 4 or 8", p.ipt);
+  if (p.grid < 0 || p.grid > RED_MAX_GRID)
+    return set_error(RED_EINVAL, "plan: grid %d out of range [0, %d]", p.grid, RED_MAX_GRID);
+  return RED_OK;
+}
+
+red_plan default_plan(int dtype, int64_t n, const DeviceInfo& dev) {
+  (void)dtype;
+  (void)n;
+  red_plan p;
+  p.variant = RED_VARIANT_RELAUNCH;
+  p.wg = 512;
+  p.ipt = 4;
+  p.grid = 0;  // automatic: bounded by the work and by 4 workgroups per CU
+  (void)dev;
+  return p;
+}
+
+int reduce_max_coresident(int dtype, int acc, int ipt, bool nt, int wg, const DeviceInfo& dev,
+                          int* n_wg) {
+  int m = mode_of(dtype, acc);
+  int ii = ipt_index(ipt);
+  if (m < 0 || ii < 0) return set_error(RED_EINVAL, "bad dtype/ipt");
+  int per_cu = 0;
+  RED_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, table().k[m][nt ? 1 : 0][ii].persistent,
+                                                       wg, 0));
+  *n_wg = per_cu * dev.cus;
+  return RED_OK;
+}
+
+int reduce_launch(const ReduceLaunch& rl, const void* x, int64_t n, void* out, Workspace* ws,
+                  hipStream_t s, const DeviceInfo& dev) {
+  const int m = mode_of(rl.dtype, rl.acc);
+  const bool is_int = rl.dtype == RED_I32;
+  if (n == 0) {
+    void* zargs[] = {&out};
+    const void* fn = is_int ? reinterpret_cast<const void*>(&k_write_zero<long long>)
+                            : reinterpret_cast<const void*>(&k_write_zero<double>);
+    return launch(fn, 1, 64, zargs, s, false);
+  }
+  const int es = elem_size(rl.dtype);
+  const int ve = 16 / es;
+  ReduceArgs a;
+  a.x = x;
+  uintptr_t addr = reinterpret_cast<uintptr_t>(x);
+  int64_t head = (int64_t)(((16 - (addr & 15)) & 15) / es);
+  a.head = std::min<int64_t>(head, n);
+  a.nvec = (n - a.head) / ve;
+  a.tail = n - a.head - a.nvec * ve;
+  a.partials = ws->partials;
+  a.words = ws->words;
+  a.out = out;
+  a.spin_limit = watchdog_spins();
+
+  const red_plan& p = rl.plan;
+  const int ii = ipt_index(p.ipt);
+  const KernelSet& ks = table().k[m][rl.nontemporal ? 1 : 0][ii];
+  // Grid: the requested size, else enough workgroups for the work, capped
+  // at 4 per compute unit (and at the co-resident limit for the persistent
+  // variant).
+  const int64_t tile = (int64_t)p.wg * p.ipt;
+  int64_t want = std::max<int64_t>(1, (a.nvec + tile - 1) / tile);
+  int grid = p.grid > 0 ? p.grid : (int)std::min<int64_t>(want, 4LL * dev.cus);
+  grid = std::max(1, std::min(grid, RED_MAX_GRID));
+  void* args[] = {&a};
+  switch (p.variant) {
+    case RED_VARIANT_RELAUNCH: {
+      int rc = launch(ks.partials, grid, p.wg, args, s, false);
+      if (rc) return rc;
+      if (is_int) {
+        const long long* part = static_cast<const long long*>(ws->partials);
+        long long* o = static_cast<long long*>(out);
+        void* fargs[] = {&part, &grid, &o};
+        return launch(reinterpret_cast<const void*>(&k_final<long long>), 1, kFinalWG, fargs, s, false);
+      }
+      const double* part = static_cast<const double*>(ws->partials);
+      double* o = static_cast<double*>(out);
+      void* fargs[] = {&part, &grid, &o};
+      return launch(reinterpret_cast<const void*>(&k_final<double>), 1, kFinalWG, fargs, s, false);
+    }
+    case RED_VARIANT_ATOMIC:
+      return launch(ks.atomic, grid, p.wg, args, s, false);
+    case RED_VARIANT_PERSISTENT: {
+      int maxg = 0;
+      int rc = reduce_max_coresident(rl.dtype, rl.acc, p.ipt, rl.nontemporal, p.wg, dev, &maxg);
+      if (rc) return rc;
+      if (p.grid > 0 && p.grid > maxg)
+        return set_error(RED_EINVAL, "persistent plan: grid %d exceeds the %d co-resident workgroups",
+                         p.grid, maxg);
+      grid = std::min(grid, maxg);
+      if (grid < 1) return set_error(RED_EINVAL, "persistent kernel cannot be resident");
+      return launch(ks.persistent, grid, p.wg, args, s, true);
+    }
+  }
+  return set_error(RED_EINVAL, "unknown variant %d", p.variant);
+}
+
+}  // namespace redsum

@@ -1,0 +1,672 @@
+// C-ABI entry points of libredsum: validation, device and workspace
+// management, plan table, autotuner, segmented-batch graph cache.
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <list>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "device_prims.h"
+#include "internal.h"
+
+namespace redsum {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+static thread_local std::string t_err;
+
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  t_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return set_error(RED_EHIP, "%s failed: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+// ---------------------------------------------------------------------------
+// Global state
+// ---------------------------------------------------------------------------
+namespace {
+
+std::mutex g_mu;
+std::map<int, DeviceInfo> g_dev;
+std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+
+// Plan table: (kind, dtype, acc, bucket) -> plan.  kind 0 = red_sum,
+// 1 = segmented (dtype = nseg bucket, acc = total-size bucket).
+std::map<std::tuple<int, int, int, int>, red_plan> g_plans;
+
+struct GraphKey {
+  int dev;
+  hipStream_t s;
+  const void* x;
+  const void* off;
+  int64_t nseg;
+  void* out;
+  int variant, wg, ipt, grid, nt;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(dev, s, x, off, nseg, out, variant, wg, ipt, grid, nt) <
+           std::tie(o.dev, o.s, o.x, o.off, o.nseg, o.out, o.variant, o.wg, o.ipt, o.grid, o.nt);
+  }
+};
+struct GraphEntry {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t e = nullptr;
+};
+std::map<GraphKey, GraphEntry> g_graphs;
+std::list<GraphKey> g_graph_lru;
+constexpr size_t kMaxGraphs = 64;
+
+int bucket(int64_t n) {
+  int b = 0;
+  while (b < 63 && ((int64_t)1 << b) < n) ++b;
+  return b;  // ceil(log2 n)
+}
+
+}  // namespace
+
+unsigned watchdog_spins() {
+  static unsigned v = [] {
+    const char* e = getenv("REDSUM_WATCHDOG_SPINS");
+    long long x = e ? atoll(e) : 0;
+    if (x <= 0 || x > 0x7FFFFFFF) x = 1 << 22;
+    return (unsigned)x;
+  }();
+  return v;
+}
+
+bool stream_capturing(hipStream_t s) {
+  if (!s) return false;
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+  return st != hipStreamCaptureStatusNone;
+}
+
+int ensure_device(const DeviceInfo** info) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
+    (void)hipGetLastError();
+    return set_error(RED_ENODEV, "no HIP device is available");
+  }
+  int dev = 0;
+  RED_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_dev.find(dev);
+  if (it != g_dev.end()) {
+    *info = &it->second;
+    return RED_OK;
+  }
+  hipDeviceProp_t prop;
+  RED_HIP(hipGetDeviceProperties(&prop, dev));
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return set_error(RED_ENODEV, "device %d is %s, this library is built for gfx950", dev, prop.gcnArchName);
+  DeviceInfo d;
+  d.id = dev;
+  d.cus = prop.multiProcessorCount;
+  int wc = 0;
+  if (hipDeviceGetAttribute(&wc, hipDeviceAttributeWallClockRate, dev) != hipSuccess || wc <= 0) wc = 100000;
+  d.wallclock_khz = wc;
+  d.clock_khz = prop.clockRate;
+  d.l2_bytes = prop.l2CacheSize;
+  d.hbm_bytes = (int64_t)prop.totalGlobalMem;
+  d.coop = prop.cooperativeLaunch != 0;
+  auto r = g_dev.emplace(dev, d);
+  *info = &r.first->second;
+  return RED_OK;
+}
+
+int get_workspace(hipStream_t s, Workspace** out) {
+  int dev = 0;
+  RED_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_pair(dev, s);
+  auto it = g_ws.find(key);
+  if (it != g_ws.end()) {
+    *out = &it->second;
+    return RED_OK;
+  }
+  if (stream_capturing(s))
+    return set_error(RED_EINVAL,
+                     "the first call on a stream allocates its workspace and cannot be captured; "
+                     "call once before capturing");
+  Workspace w;
+  hipError_t e = hipMalloc(&w.base, kWorkspaceBytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(RED_ENOMEM, "workspace allocation of %zu bytes failed: %s", kWorkspaceBytes,
+                     hipGetErrorString(e));
+  }
+  e = hipMemset(w.base, 0, kWorkspaceBytes);
+  if (e != hipSuccess) {
+    (void)hipFree(w.base);
+    return hip_fail(e, "hipMemset(workspace)");
+  }
+  char* p = static_cast<char*>(w.base);
+  w.words = reinterpret_cast<BarrierWords*>(p);
+  p += kWordsBytes;
+  w.partials = p;
+  p += kPartialBytes;
+  w.carry_in = reinterpret_cast<SegCarry*>(p);
+  p += kCarryBytes;
+  w.carry_out = reinterpret_cast<SegCarry*>(p);
+  p += kCarryBytes;
+  w.seg_tickets = reinterpret_cast<unsigned*>(p);
+  p += kTicketBytes;
+  w.sink = reinterpret_cast<unsigned*>(p);
+  p += kSinkBytes;
+  w.stamps = reinterpret_cast<long long*>(p);
+  auto r = g_ws.emplace(key, w);
+  *out = &r.first->second;
+  return RED_OK;
+}
+
+int launch(const void* fn, int grid, int block, void** args, hipStream_t s, bool cooperative) {
+  hipError_t e;
+  if (cooperative)
+    e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, 0, s);
+  else
+    e = hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, s);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    if (e == hipErrorCooperativeLaunchTooLarge)
+      return set_error(RED_EINVAL, "cooperative launch of %d x %d is too large", grid, block);
+    return hip_fail(e, cooperative ? "hipLaunchCooperativeKernel" : "hipLaunchKernel");
+  }
+  return RED_OK;
+}
+
+}  // namespace redsum
+
+using namespace redsum;
+
+namespace {
+
+int check_dtype(int dtype) {
+  if (dtype < RED_I32 || dtype > RED_BF16) return set_error(RED_EINVAL, "unknown dtype %d", dtype);
+  return RED_OK;
+}
+
+int esize(int dtype) { return dtype == RED_I32 || dtype == RED_F32 ? 4 : 2; }
+
+int validate_sum_args(int dtype, const void* x, int64_t n, void* out, const red_opts* opts) {
+  int rc = check_dtype(dtype);
+  if (rc) return rc;
+  if (n < 0 || n >= ((int64_t)1 << 40)) return set_error(RED_EINVAL, "n = %lld out of range", (long long)n);
+  if (!x && n > 0) return set_error(RED_EINVAL, "x is NULL");
+  if (!out) return set_error(RED_EINVAL, "out is NULL");
+  if (reinterpret_cast<uintptr_t>(x) % esize(dtype))
+    return set_error(RED_EINVAL, "x is not aligned to its element size");
+  if (reinterpret_cast<uintptr_t>(out) % 8) return set_error(RED_EINVAL, "out is not 8-byte aligned");
+  if (opts) {
+    if (opts->acc != RED_ACC_COMPENSATED && opts->acc != RED_ACC_PLAIN)
+      return set_error(RED_EINVAL, "unknown accumulation %d", opts->acc);
+    if (opts->flags & ~1) return set_error(RED_EINVAL, "unknown flags 0x%x", opts->flags);
+    if (opts->plan.variant != RED_VARIANT_AUTO) {
+      red_plan p = opts->plan;
+      if (p.wg == 0) p.wg = 512;
+      if (p.ipt == 0) p.ipt = 4;
+      return validate_plan(p);
+    }
+  }
+  return RED_OK;
+}
+
+// An explicit plan takes the default workgroup size / items per thread for
+// fields left at 0.
+red_plan complete_plan(red_plan p, const red_plan& dflt) {
+  if (p.wg == 0) p.wg = dflt.wg;
+  if (p.ipt == 0) p.ipt = dflt.ipt;
+  return p;
+}
+
+red_plan lookup_plan(int dtype, int acc, int64_t n, const DeviceInfo& dev) {
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_plans.find(std::make_tuple(0, dtype, dtype == RED_I32 ? 0 : acc, bucket(n)));
+    if (it != g_plans.end()) return it->second;
+  }
+  return default_plan(dtype, n, dev);
+}
+
+
+int validate_seg_args(const float* x, const int64_t* offsets, int64_t nseg, double* out, const red_opts* opts) {
+  if (nseg < 0 || nseg >= ((int64_t)1 << 31)) return set_error(RED_EINVAL, "nseg out of range");
+  if (!offsets) return set_error(RED_EINVAL, "offsets is NULL");
+  if (nseg > 0 && (!x || !out)) return set_error(RED_EINVAL, "x or out is NULL");
+  if (reinterpret_cast<uintptr_t>(x) % 4) return set_error(RED_EINVAL, "x is not 4-byte aligned");
+  if (reinterpret_cast<uintptr_t>(offsets) % 8) return set_error(RED_EINVAL, "offsets is not 8-byte aligned");
+  if (reinterpret_cast<uintptr_t>(out) % 8) return set_error(RED_EINVAL, "out is not 8-byte aligned");
+  if (opts) {
+    if (opts->flags & ~3) return set_error(RED_EINVAL, "unknown flags 0x%x", opts->flags);
+    if (opts->plan.variant != RED_VARIANT_AUTO) {
+      red_plan p = opts->plan;
+      if (p.wg == 0) p.wg = 512;
+      if (p.ipt == 0) p.ipt = 4;
+      int rc = validate_plan(p);
+      if (rc) return rc;
+      if (opts->plan.variant != RED_VARIANT_ATOMIC && opts->plan.variant != RED_VARIANT_PERSISTENT)
+        return set_error(RED_EINVAL, "segmented: variant must be ATOMIC or PERSISTENT");
+    }
+  }
+  return RED_OK;
+}
+
+// Median of a small vector.
+double median(std::vector<double> v) {
+  std::sort(v.begin(), v.end());
+  const size_t n = v.size();
+  return n % 2 ? v[n / 2] : 0.5 * (v[n / 2 - 1] + v[n / 2]);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* red_last_error(void) { return t_err.c_str(); }
+
+int red_init(int device) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
+    (void)hipGetLastError();
+    return set_error(RED_ENODEV, "no HIP device is available");
+  }
+  if (device < 0 || device >= count) return set_error(RED_ENODEV, "device %d does not exist", device);
+  RED_HIP(hipSetDevice(device));
+  const DeviceInfo* d;
+  int rc = ensure_device(&d);
+  if (rc) return rc;
+  Workspace* ws;
+  return get_workspace(nullptr, &ws);
+}
+
+void red_shutdown(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& kv : g_graphs) {
+    if (kv.second.e) (void)hipGraphExecDestroy(kv.second.e);
+    if (kv.second.g) (void)hipGraphDestroy(kv.second.g);
+  }
+  g_graphs.clear();
+  g_graph_lru.clear();
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (auto& kv : g_ws) {
+    (void)hipSetDevice(kv.first.first);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(kv.second.base);
+  }
+  if (!g_ws.empty()) (void)hipSetDevice(cur);
+  g_ws.clear();
+}
+
+int red_check_error(void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DeviceInfo* dev;
+  int rc = ensure_device(&dev);
+  if (rc) return rc;
+  Workspace* ws;
+  if ((rc = get_workspace(s, &ws))) return rc;
+  RED_HIP(hipStreamSynchronize(s));
+  unsigned err = 0;
+  RED_HIP(hipMemcpy(&err, &ws->words->err.v, 4, hipMemcpyDeviceToHost));
+  if (!err) return RED_OK;
+  // Clear the error and every barrier word (the barrier was abandoned).
+  RED_HIP(hipMemset(ws->words, 0, kWordsBytes));
+  RED_HIP(hipMemset(ws->seg_tickets, 0, kTicketBytes));
+  return set_error(RED_ETIMEOUT, "a grid-barrier watchdog fired on this stream");
+}
+
+int red_sum_ex(int dtype, const void* x, int64_t n, void* out, void* stream, const red_opts* opts) {
+  int rc = validate_sum_args(dtype, x, n, out, opts);
+  if (rc) return rc;
+  const DeviceInfo* dev;
+  if ((rc = ensure_device(&dev))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace* ws;
+  if ((rc = get_workspace(s, &ws))) return rc;
+  ReduceLaunch rl;
+  rl.dtype = dtype;
+  rl.acc = opts ? opts->acc : RED_ACC_COMPENSATED;
+  rl.nontemporal = opts ? (opts->flags & 1) != 0 : false;
+  rl.plan = (opts && opts->plan.variant != RED_VARIANT_AUTO)
+                ? complete_plan(opts->plan, default_plan(dtype, n, *dev))
+                : lookup_plan(dtype, rl.acc, n, *dev);
+  return reduce_launch(rl, x, n, out, ws, s, *dev);
+}
+
+int red_sum(int dtype, const void* x, int64_t n, void* out, void* stream) {
+  return red_sum_ex(dtype, x, n, out, stream, nullptr);
+}
+
+int red_set_plan(int dtype, int acc, int64_t n, const red_plan* plan) {
+  int rc = check_dtype(dtype);
+  if (rc) return rc;
+  if (acc != RED_ACC_COMPENSATED && acc != RED_ACC_PLAIN) return set_error(RED_EINVAL, "bad acc");
+  if (!plan || n < 0) return set_error(RED_EINVAL, "bad plan or n");
+  if ((rc = validate_plan(*plan))) return rc;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_plans[std::make_tuple(0, dtype, dtype == RED_I32 ? 0 : acc, bucket(n))] = *plan;
+  return RED_OK;
+}
+
+int red_get_plan(int dtype, int acc, int64_t n, red_plan* plan) {
+  int rc = check_dtype(dtype);
+  if (rc) return rc;
+  if (acc != RED_ACC_COMPENSATED && acc != RED_ACC_PLAIN) return set_error(RED_EINVAL, "bad acc");
+  if (!plan || n < 0) return set_error(RED_EINVAL, "bad plan or n");
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_plans.find(std::make_tuple(0, dtype, dtype == RED_I32 ? 0 : acc, bucket(n)));
+    if (it != g_plans.end()) {
+      *plan = it->second;
+      return RED_OK;
+    }
+  }
+  const DeviceInfo* dev;
+  if ((rc = ensure_device(&dev))) {
+    // Without a device the default plan is still defined (grid automatic).
+    DeviceInfo none;
+    none.cus = 256;
+    *plan = default_plan(dtype, n, none);
+    return RED_OK;
+  }
+  *plan = default_plan(dtype, n, *dev);
+  return RED_OK;
+}
+
+int red_max_coresident(int wg_size, int32_t* n_wg) {
+  if (!n_wg || wg_size < 64 || wg_size > 1024 || wg_size % 64) return set_error(RED_EINVAL, "bad arguments");
+  const DeviceInfo* dev;
+  int rc = ensure_device(&dev);
+  if (rc) return rc;
+  int n = 0;
+  if ((rc = reduce_max_coresident(RED_F32, RED_ACC_COMPENSATED, 4, false, wg_size, *dev, &n))) return rc;
+  *n_wg = n;
+  return RED_OK;
+}
+
+int red_device_info(int32_t* cus, int64_t* wallclock_khz, int64_t* clock_khz, int64_t* l2_bytes,
+                    int64_t* hbm_bytes) {
+  const DeviceInfo* dev;
+  int rc = ensure_device(&dev);
+  if (rc) return rc;
+  if (cus) *cus = dev->cus;
+  if (wallclock_khz) *wallclock_khz = dev->wallclock_khz;
+  if (clock_khz) *clock_khz = dev->clock_khz;
+  if (l2_bytes) *l2_bytes = dev->l2_bytes;
+  if (hbm_bytes) *hbm_bytes = dev->hbm_bytes;
+  return RED_OK;
+}
+
+// Times `plan` on the caller's data: 2 warm-up calls, then the median of 5
+// calls bracketed by events.
+static int time_plan(int dtype, int acc, const red_plan& plan, const void* x, int64_t n, void* out,
+                     hipStream_t s, double* us) {
+  red_opts o;
+  memset(&o, 0, sizeof o);
+  o.plan = plan;
+  o.acc = acc;
+  hipEvent_t a, b;
+  RED_HIP(hipEventCreate(&a));
+  RED_HIP(hipEventCreate(&b));
+  std::vector<double> t;
+  int rc = RED_OK;
+  for (int i = 0; i < 7 && rc == RED_OK; ++i) {
+    if (hipEventRecord(a, s) != hipSuccess) rc = set_error(RED_EHIP, "hipEventRecord");
+    if (!rc) rc = red_sum_ex(dtype, x, n, out, s, &o);
+    if (!rc && hipEventRecord(b, s) != hipSuccess) rc = set_error(RED_EHIP, "hipEventRecord");
+    if (!rc && hipEventSynchronize(b) != hipSuccess) rc = set_error(RED_EHIP, "hipEventSynchronize");
+    float ms = 0;
+    if (!rc && hipEventElapsedTime(&ms, a, b) != hipSuccess) rc = set_error(RED_EHIP, "hipEventElapsedTime");
+    if (!rc && i >= 2) t.push_back(ms * 1e3);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc) return rc;
+  *us = median(t);
+  return RED_OK;
+}
+
+int red_autotune(int dtype, int acc, const void* x, int64_t n, void* out, void* stream, int budget,
+                 red_plan* best, double* best_us) {
+  red_opts vo;
+  memset(&vo, 0, sizeof vo);
+  vo.acc = acc;
+  int rc = validate_sum_args(dtype, x, n, out, &vo);
+  if (rc) return rc;
+  const DeviceInfo* dev;
+  if ((rc = ensure_device(&dev))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (stream_capturing(s)) return set_error(RED_EINVAL, "autotuning cannot run inside stream capture");
+  // Coordinate search: (wg, ipt) with the relaunch variant and automatic
+  // grid, then the grid size, then the variant.  `budget` caps the number
+  // of timed candidates (0 = no cap).
+  int timed = 0;
+  red_plan cur = default_plan(dtype, n, *dev);
+  double cur_us = 1e300;
+  auto consider = [&](red_plan p) -> int {
+    if (budget > 0 && timed >= budget) return RED_OK;
+    if (p.variant == RED_VARIANT_PERSISTENT && p.grid > 0) {
+      int maxg = 0;
+      int r = reduce_max_coresident(dtype, acc, p.ipt, false, p.wg, *dev, &maxg);
+      if (r) return r;
+      if (p.grid > maxg) return RED_OK;
+    }
+    double us = 0;
+    int r = time_plan(dtype, acc, p, x, n, out, s, &us);
+    ++timed;
+    if (r) return r;
+    if (us < cur_us) {
+      cur_us = us;
+      cur = p;
+    }
+    return RED_OK;
+  };
+  const int wgs[] = {256, 512, 1024};
+  const int ipts[] = {1, 2, 4, 8};
+  for (int wg : wgs)
+    for (int ipt : ipts) {
+      red_plan p{RED_VARIANT_RELAUNCH, wg, ipt, 0};
+      if ((rc = consider(p))) return rc;
+    }
+  const int64_t tile = (int64_t)cur.wg * cur.ipt;
+  const int64_t nvec = n / (16 / esize(dtype));
+  const int64_t want = std::max<int64_t>(1, (nvec + tile - 1) / tile);
+  const int mults[] = {1, 2, 3, 4, 6, 8, 12, 16};
+  const red_plan base = cur;
+  for (int m : mults) {
+    red_plan p = base;
+    p.grid = (int)std::min<int64_t>({(int64_t)m * dev->cus, want, (int64_t)RED_MAX_GRID});
+    if ((rc = consider(p))) return rc;
+    if ((int64_t)m * dev->cus >= want) break;
+  }
+  const red_plan base2 = cur;
+  for (int v : {RED_VARIANT_ATOMIC, RED_VARIANT_PERSISTENT}) {
+    red_plan p = base2;
+    p.variant = v;
+    if (v == RED_VARIANT_PERSISTENT && p.grid == 0) {
+      int maxg = 0;
+      if ((rc = reduce_max_coresident(dtype, acc, p.ipt, false, p.wg, *dev, &maxg))) return rc;
+      p.grid = (int)std::min<int64_t>({(int64_t)maxg, want, (int64_t)4 * dev->cus});
+    }
+    if ((rc = consider(p))) return rc;
+  }
+  if ((rc = red_set_plan(dtype, acc, n, &cur))) return rc;
+  if (best) *best = cur;
+  if (best_us) *best_us = cur_us;
+  return RED_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Segmented batches
+// ---------------------------------------------------------------------------
+static int seg_direct(const SegLaunch& sl, const float* x, const int64_t* offsets, int64_t nseg, double* out,
+                      Workspace* ws, hipStream_t s, const DeviceInfo& dev) {
+  return seg_launch(sl, x, offsets, nseg, out, ws, s, dev);
+}
+
+int red_sum_segmented_ex(const float* x, const int64_t* offsets, int64_t nseg, double* out, void* stream,
+                         const red_opts* opts) {
+  int rc = validate_seg_args(x, offsets, nseg, out, opts);
+  if (rc) return rc;
+  const DeviceInfo* dev;
+  if ((rc = ensure_device(&dev))) return rc;
+  if (nseg == 0) return RED_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace* ws;
+  if ((rc = get_workspace(s, &ws))) return rc;
+  SegLaunch sl;
+  sl.nontemporal = opts ? (opts->flags & 1) != 0 : false;
+  const bool no_graph = opts ? (opts->flags & 2) != 0 : false;
+  if (opts && opts->plan.variant != RED_VARIANT_AUTO) {
+    sl.plan = complete_plan(opts->plan, default_seg_plan(nseg, *dev));
+  } else {
+    sl.plan = default_seg_plan(nseg, *dev);
+    std::lock_guard<std::mutex> lk(g_mu);
+    // Installed plans are keyed by the nseg bucket only on this path (the
+    // total size lives on the device).
+    auto it = g_plans.find(std::make_tuple(1, bucket(nseg), 0, 0));
+    if (it != g_plans.end()) sl.plan = it->second;
+  }
+  // Cooperative launches, the null stream and a caller's own capture launch
+  // directly; otherwise the launch is replayed from a cached graph.
+  if (no_graph || !s || sl.plan.variant == RED_VARIANT_PERSISTENT || stream_capturing(s))
+    return seg_direct(sl, x, offsets, nseg, out, ws, s, *dev);
+  GraphKey key{dev->id, s, x, offsets, nseg, out, sl.plan.variant, sl.plan.wg, sl.plan.ipt, sl.plan.grid,
+               sl.nontemporal ? 1 : 0};
+  hipGraphExec_t exec = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_graphs.find(key);
+    if (it != g_graphs.end()) exec = it->second.e;
+  }
+  if (!exec) {
+    // Capture the one launch on this stream into a graph.
+    RED_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    rc = seg_launch(sl, x, offsets, nseg, out, ws, s, *dev);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_graphs.size() >= kMaxGraphs && !g_graph_lru.empty()) {
+      auto old = g_graphs.find(g_graph_lru.front());
+      if (old != g_graphs.end()) {
+        (void)hipGraphExecDestroy(old->second.e);
+        (void)hipGraphDestroy(old->second.g);
+        g_graphs.erase(old);
+      }
+      g_graph_lru.pop_front();
+    }
+    g_graphs[key] = GraphEntry{g, exec};
+    g_graph_lru.push_back(key);
+  }
+  RED_HIP(hipGraphLaunch(exec, s));
+  return RED_OK;
+}
+
+int red_sum_segmented(const float* x, const int64_t* offsets, int64_t nseg, double* out, void* stream) {
+  return red_sum_segmented_ex(x, offsets, nseg, out, stream, nullptr);
+}
+
+int red_sum_segmented_loop(const float* x, const int64_t* host_offsets, int64_t nseg, double* out,
+                           void* stream) {
+  if (nseg < 0 || !host_offsets) return set_error(RED_EINVAL, "bad offsets / nseg");
+  if (nseg > 0 && (!x || !out)) return set_error(RED_EINVAL, "x or out is NULL");
+  if (host_offsets[0] != 0) return set_error(RED_EINVAL, "offsets[0] must be 0");
+  for (int64_t k = 0; k < nseg; ++k)
+    if (host_offsets[k + 1] < host_offsets[k]) return set_error(RED_EINVAL, "offsets decrease at %lld", (long long)k);
+  red_opts o;
+  memset(&o, 0, sizeof o);
+  o.acc = RED_ACC_COMPENSATED;
+  o.plan = red_plan{RED_VARIANT_ATOMIC, 512, 4, 0};
+  for (int64_t k = 0; k < nseg; ++k) {
+    int rc = red_sum_ex(RED_F32, x + host_offsets[k], host_offsets[k + 1] - host_offsets[k], out + k, stream, &o);
+    if (rc) return rc;
+  }
+  return RED_OK;
+}
+
+int red_autotune_segmented(const float* x, const int64_t* offsets, int64_t nseg, double* out, void* stream,
+                           int budget, red_plan* best, double* best_us) {
+  int rc = validate_seg_args(x, offsets, nseg, out, nullptr);
+  if (rc) return rc;
+  const DeviceInfo* dev;
+  if ((rc = ensure_device(&dev))) return rc;
+  if (nseg == 0) return set_error(RED_EINVAL, "nothing to tune");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (stream_capturing(s)) return set_error(RED_EINVAL, "autotuning cannot run inside stream capture");
+  Workspace* ws;
+  if ((rc = get_workspace(s, &ws))) return rc;
+  hipEvent_t a, b;
+  RED_HIP(hipEventCreate(&a));
+  RED_HIP(hipEventCreate(&b));
+  red_plan cur = default_seg_plan(nseg, *dev);
+  double cur_us = 1e300;
+  int timed = 0;
+  auto consider = [&](red_plan p) -> int {
+    if (budget > 0 && timed >= budget) return RED_OK;
+    SegLaunch sl{p, false};
+    std::vector<double> t;
+    for (int i = 0; i < 6; ++i) {
+      RED_HIP(hipEventRecord(a, s));
+      int r = seg_launch(sl, x, offsets, nseg, out, ws, s, *dev);
+      if (r) return r;
+      RED_HIP(hipEventRecord(b, s));
+      RED_HIP(hipEventSynchronize(b));
+      float ms = 0;
+      RED_HIP(hipEventElapsedTime(&ms, a, b));
+      if (i >= 1) t.push_back(ms * 1e3);
+    }
+    ++timed;
+    const double us = median(t);
+    if (us < cur_us) {
+      cur_us = us;
+      cur = p;
+    }
+    return RED_OK;
+  };
+  for (int wg : {256, 512, 1024})
+    for (int ipt : {2, 4, 8})
+      if ((rc = consider(red_plan{RED_VARIANT_ATOMIC, wg, ipt, 4 * dev->cus}))) break;
+  const red_plan base = cur;
+  if (!rc)
+    for (int m : {1, 2, 3, 6, 8, 12, 16}) {
+      red_plan p = base;
+      p.grid = std::min(m * dev->cus, RED_MAX_GRID);
+      if ((rc = consider(p))) break;
+    }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_plans[std::make_tuple(1, bucket(nseg), 0, 0)] = cur;
+  }
+  if (best) *best = cur;
+  if (best_us) *best_us = cur_us;
+  return RED_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+"""Performance model of Section VII-A/B (Eq. 1-5): when should a reduction
+use fewer workers?
+
+A "basic" configuration (one thread, one wavefront, one workgroup, ...) is
+compared with a "more" configuration that has higher throughput but pays a
+synchronization latency T_sync (Eq. 3: T_more = T + T_sync).  Concurrency
+follows Little's law (Eq. 1: C = T * Thr).  With N bytes of input the basic
+configuration wins when Eq. 2 holds:
+
+    T_basic + max(0, N - C_basic) / Thr_basic < T_more + max(0, N - C_more) / Thr_more
+
+which gives two switch points: N_m (Eq. 4) when N lies between the two
+concurrencies, and N_l (Eq. 5) when N exceeds both.  All quantities share
+one time unit (cycles in the paper) and bytes.
+
+The autotuner uses the same reasoning as its prior (never launch more
+workgroups than the work keeps busy); ``mi355x_switch_points`` evaluates
+the model with latencies measured by the library's probes.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+
+def concurrency(latency: float, throughput: float) -> float:
+    """Eq. 1, Little's law: bytes in flight C = T * Thr."""
+    return latency * throughput
+
+
+def latency_more(t_basic: float, t_sync: float) -> float:
+    """Eq. 3: the 'more' configuration pays the synchronization latency."""
+    return t_basic + t_sync
+
+
+def time_to_finish(n: float, latency: float, throughput: float, conc: float) -> float:
+    """One side of Eq. 2: latency plus the bytes beyond the concurrency at
+    the configuration's throughput."""
+    return latency + max(0.0, n - conc) / throughput
+
+
+def prefer_basic(n: float, t: float, t_sync: float, thr_basic: float, thr_more: float) -> bool:
+    """Eq. 2: True when the basic configuration finishes first for n bytes."""
+    c_basic = concurrency(t, thr_basic)
+    t_m = latency_more(t, t_sync)
+    c_more = concurrency(t, thr_more)  # concurrency is taken at the basic latency T
+    return time_to_finish(n, t, thr_basic, c_basic) < time_to_finish(n, t_m, thr_more, c_more)
+
+
+def switch_point_m(t: float, t_sync: float, thr_basic: float) -> float:
+    """Eq. 4: N_m = (T + T_sync) * Thr_basic (n between the concurrencies)."""
+    return (t + t_sync) * thr_basic
+
+
+def switch_point_l(t_sync: float, thr_more: float, thr_basic: float) -> float:
+    """Eq. 5: N_l = T_sync * Thr_more * Thr_basic / (Thr_more - Thr_basic)
+    (n beyond both concurrencies)."""
+    return t_sync * thr_more * thr_basic / (thr_more - thr_basic)
+
+
+@dataclass
+class Scenario:
+    """One row pair of Tables III/IV: basic vs more."""
+    name: str
+    latency: float      # T (cycles)
+    thr_basic: float    # bytes / cycle
+    thr_more: float     # bytes / cycle
+    t_sync: float       # cycles (the synchronization steps the 'more' side pays)
+
+    def concurrency_basic(self) -> float:
+        return concurrency(self.latency, self.thr_basic)
+
+    def concurrency_more(self) -> float:
+        return concurrency(self.latency, self.thr_more)
+
+    def n_l(self) -> float:
+        return switch_point_l(self.t_sync, self.thr_more, self.thr_basic)
+
+    def n_m(self) -> float:
+        return switch_point_m(self.latency, self.t_sync, self.thr_basic)
+
+    def use_basic(self, n_bytes: float) -> bool:
+        """Scenario rule of Section VII-A: (1) n within the basic
+        concurrency -> basic; (2) n between the concurrencies -> compare
+        with N_m; (3) beyond both -> compare with N_l."""
+        if n_bytes <= self.concurrency_basic():
+            return True
+        if n_bytes <= self.concurrency_more():
+            return n_bytes < self.n_m()
+        return n_bytes < self.n_l()
+
+
+def mi355x_switch_points(wave_reduce_ns: float, block_barrier_ns: float, lds_bytes_per_ns: float,
+                         clock_ghz: float = 2.4):
+    """Switch points for MI355X from probe measurements, in bytes.
+
+    Scenario 1: one lane vs one wavefront (64 lanes) reading LDS; the
+    wavefront pays one full wavefront combine.  Scenario 2: one wavefront vs
+    a 1024-thread workgroup; the workgroup pays a barrier plus a combine.
+    ``lds_bytes_per_ns`` is the single-lane LDS streaming rate."""
+    cyc = clock_ghz
+    thr1 = lds_bytes_per_ns / cyc                  # bytes / cycle, one lane
+    s1 = Scenario("1 lane vs 1 wave", latency=64.0, thr_basic=thr1, thr_more=64 * thr1,
+                  t_sync=wave_reduce_ns * cyc)
+    s2 = Scenario("1 wave vs 1024 threads", latency=64.0, thr_basic=64 * thr1, thr_more=1024 * thr1,
+                  t_sync=(block_barrier_ns + wave_reduce_ns) * cyc)
+    return {s.name: {"n_l_bytes": s.n_l(), "n_m_bytes": s.n_m()} for s in (s1, s2)}

@@ -1,0 +1,99 @@
+"""C-ABI library checks that need no GPU: the library loads, exports every
+symbol that include/redsum.h declares, validates arguments before touching
+HIP, reports RED_ENODEV without a device, and its host-side probe formulas
+agree with the oracle's (Eq. 6, 7, 8)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+from paper_2004_05371_amd import redsum as R
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "redsum.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|double|const char\s*\*)\s*\**\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return R.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = header_functions()
+    assert len(names) >= 20
+    assert sorted(R.EXPORTS) == names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def has_gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def test_validation_before_hip(lib):
+    # Each of these must fail validation without any HIP call.
+    assert lib.red_sum(99, None, 0, None, None) == R.RED_EINVAL
+    assert lib.red_sum(R.RED_F32, None, 10, ctypes.c_void_p(64), None) == R.RED_EINVAL
+    assert lib.red_sum(R.RED_F32, ctypes.c_void_p(64), -1, ctypes.c_void_p(64), None) == R.RED_EINVAL
+    assert lib.red_sum(R.RED_F32, ctypes.c_void_p(64), 1 << 40, ctypes.c_void_p(64), None) == R.RED_EINVAL
+    assert lib.red_sum(R.RED_F32, ctypes.c_void_p(66), 4, ctypes.c_void_p(64), None) == R.RED_EINVAL  # misaligned
+    assert lib.red_sum(R.RED_F32, ctypes.c_void_p(64), 4, None, None) == R.RED_EINVAL
+    assert "out" in R.last_error()
+    bad = R.make_opts(variant=R.RED_VARIANT_RELAUNCH, wg=100, ipt=4)
+    assert lib.red_sum_ex(R.RED_F32, ctypes.c_void_p(64), 4, ctypes.c_void_p(64), None, ctypes.byref(bad)) == R.RED_EINVAL
+    bad = R.make_opts(variant=R.RED_VARIANT_RELAUNCH, wg=256, ipt=3)
+    assert lib.red_sum_ex(R.RED_F32, ctypes.c_void_p(64), 4, ctypes.c_void_p(64), None, ctypes.byref(bad)) == R.RED_EINVAL
+    bad = R.make_opts(acc=7)
+    assert lib.red_sum_ex(R.RED_F32, ctypes.c_void_p(64), 4, ctypes.c_void_p(64), None, ctypes.byref(bad)) == R.RED_EINVAL
+    bad = R.make_opts(flags=8)
+    assert lib.red_sum_ex(R.RED_F32, ctypes.c_void_p(64), 4, ctypes.c_void_p(64), None, ctypes.byref(bad)) == R.RED_EINVAL
+    assert lib.red_sum_segmented(None, None, 3, None, None) == R.RED_EINVAL
+    assert lib.red_sum_segmented(ctypes.c_void_p(64), ctypes.c_void_p(64), -1, ctypes.c_void_p(64), None) == R.RED_EINVAL
+    assert lib.red_sum_segmented(ctypes.c_void_p(64), ctypes.c_void_p(68), 2, ctypes.c_void_p(64), None) == R.RED_EINVAL
+    seg = R.make_opts(variant=R.RED_VARIANT_RELAUNCH, wg=256, ipt=4)
+    assert lib.red_sum_segmented_ex(ctypes.c_void_p(64), ctypes.c_void_p(64), 2, ctypes.c_void_p(64), None,
+                                    ctypes.byref(seg)) == R.RED_EINVAL
+    assert lib.sync_bench_wave(9, 64, 10, None, None, None, None) == R.RED_EINVAL
+    assert lib.sync_bench_grid(0, 256, 10, None, None, None, None) == R.RED_EINVAL
+    assert lib.sync_check_watchdog(4, 64, 9, 100, None) == R.RED_EINVAL
+    p = R.Plan(R.RED_VARIANT_PERSISTENT, 256, 16, 0)
+    assert lib.red_set_plan(R.RED_F32, 0, 100, ctypes.byref(p)) == R.RED_EINVAL
+    # host-side loop baseline validates host offsets
+    off = (ctypes.c_int64 * 3)(0, 5, 2)
+    assert lib.red_sum_segmented_loop(ctypes.c_void_p(64), off, 2, ctypes.c_void_p(64), None) == R.RED_EINVAL
+
+
+@pytest.mark.skipif(has_gpu(), reason="checks the no-device path")
+def test_no_device_reports_enodev(lib):
+    assert lib.red_init(0) == R.RED_ENODEV
+    assert lib.red_sum(R.RED_F32, ctypes.c_void_p(64), 4, ctypes.c_void_p(64), None) == R.RED_ENODEV
+    assert "device" in R.last_error()
+
+
+def test_plan_table_roundtrip(lib):
+    p = R.Plan(R.RED_VARIANT_ATOMIC, 256, 2, 512)
+    R.red_set_plan(R.RED_BF16, R.RED_ACC_COMPENSATED, 1 << 20, p)
+    q = R.red_get_plan(R.RED_BF16, R.RED_ACC_COMPENSATED, (1 << 20) - 5)  # same ceil(log2) bucket
+    assert (q.variant, q.wg, q.ipt, q.grid) == (2, 256, 2, 512)
+    d = R.red_get_plan(R.RED_BF16, R.RED_ACC_PLAIN, 1 << 20)  # other bucket key -> default
+    assert d.variant in (1, 2, 3) and d.wg % 64 == 0
+
+
+def test_host_probe_formulas_match_oracle(lib):
+    assert R.red_eq6_overhead(9000.0, 2000.0, 8, 1) == pytest.approx(oracle.launch_overhead_eq6(9000.0, 2000.0, 8, 1))
+    assert R.red_eq7_latency(5000.0, 1000.0, 4096, 512) == pytest.approx(oracle.per_op_latency_eq7(5000.0, 1000.0, 4096, 512))
+    a = [10.0, 12.0, 11.0, 13.0, 9.0, 10.5]
+    b = [5.0, 5.5, 4.5, 5.0, 6.0, 5.25]
+    assert R.red_eq8_sigma(a, b, 64, 8) == pytest.approx(oracle.sigma_eq8(a, b, 64, 8), rel=1e-12)

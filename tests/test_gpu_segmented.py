@@ -1,0 +1,122 @@
+"""GPU parity of the segmented batch (red_sum_segmented) against the
+oracle's exact per-segment sums, through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2004_05371_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+BOUND = 1e-6
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run(lib, x, off, variant=0, wg=0, ipt=0, grid=0, flags=0):
+    xt = torch.from_numpy(x).to("cuda") if x.size else torch.zeros(1, dtype=torch.float32, device="cuda")
+    ot = torch.from_numpy(off).to("cuda")
+    nseg = off.size - 1
+    out = torch.full((max(nseg, 1),), float("nan"), dtype=torch.float64, device="cuda")
+    opts = lib.make_opts(variant=variant, wg=wg, ipt=ipt, grid=grid, flags=flags)
+    lib.red_sum_segmented_ex(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), lib.current_stream(), opts)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()[:nseg]
+
+
+def check(res, x, off):
+    sums = oracle.segmented_sums(x, off)
+    for k, ex in enumerate(sums):
+        if ex.fraction == 0:
+            a = float(oracle.exact_abs_sum(x[off[k]:off[k + 1]], "f32").fraction)
+            assert abs(res[k]) <= 1e-6 * a, (k, res[k])
+        else:
+            e = oracle.rel_err(float(res[k]), ex)
+            assert e <= BOUND, (k, res[k], ex.value, e)
+
+
+PLANS = [dict(), dict(variant=2, wg=256, ipt=1, grid=7), dict(variant=2, wg=1024, ipt=8, grid=1),
+         dict(variant=2, wg=64, ipt=2, grid=300), dict(variant=3, wg=256, ipt=4, grid=64),
+         dict(variant=2, wg=512, ipt=4, grid=0, flags=2)]
+
+
+@pytest.mark.parametrize("plan", range(len(PLANS)))
+def test_small_batches(lib, plan):
+    p = PLANS[plan]
+    r = np.random.default_rng(100 + plan)
+    lens = np.concatenate([r.integers(0, 3, 40), r.integers(0, 5000, 40), [0, 0, 70001, 0, 1, 1]])
+    r.shuffle(lens)
+    off = inputs.offsets_from_lengths(lens.astype(np.int64))
+    x = inputs.mixed_f32(int(off[-1]), sub=9)
+    check(run(lib, x, off, **p), x, off)
+
+
+def test_edge_batches(lib):
+    # empty total, leading / trailing empties, a single segment, all length-1
+    for lens in ([0], [0, 0, 0], [0, 5, 0], [1], [12345], [3, 0, 0], [1] * 3000, [0] * 10 + [100] + [0] * 10):
+        off = inputs.offsets_from_lengths(np.array(lens, dtype=np.int64))
+        x = inputs.normal_f32(int(off[-1]), sub=10)
+        for p in PLANS:
+            check(run(lib, x, off, **p), x, off)
+
+
+def test_single_segment_equals_red_sum(lib):
+    x = inputs.normal_f32(3000017, sub=11)
+    off = np.array([0, x.size], dtype=np.int64)
+    seg = run(lib, x, off)
+    xt = torch.from_numpy(x).to("cuda")
+    tot = lib.sum(xt).item()
+    ex = oracle.exact_sum(x, "f32")
+    assert oracle.rel_err(float(seg[0]), ex) <= BOUND
+    assert oracle.rel_err(tot, ex) <= BOUND
+
+
+def test_length_one_segments_return_values(lib):
+    x = inputs.mixed_f32(10007, sub=12)
+    off = np.arange(x.size + 1, dtype=np.int64)
+    res = run(lib, x, off)
+    assert np.array_equal(res, x.astype(np.float64))
+
+
+def test_repeat_bit_identical_and_graph_replay(lib):
+    lens = inputs.segment_lengths(500, max_len=1 << 14)
+    off = inputs.offsets_from_lengths(lens)
+    x = inputs.normal_f32(int(off[-1]), sub=13)
+    xt = torch.from_numpy(x).to("cuda")
+    ot = torch.from_numpy(off).to("cuda")
+    out = torch.empty(500, dtype=torch.float64, device="cuda")
+    first = None
+    for i in range(5):  # first call captures a graph, later calls replay it
+        out.fill_(float("nan"))
+        lib.red_sum_segmented(xt.data_ptr(), ot.data_ptr(), 500, out.data_ptr(), lib.current_stream())
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        if first is None:
+            first = got.copy()
+            check(got, x, off)
+        assert np.array_equal(got, first), i
+
+
+def test_loop_baseline_matches(lib):
+    lens = inputs.segment_lengths(200, max_len=1 << 12)
+    off = inputs.offsets_from_lengths(lens)
+    x = inputs.normal_f32(int(off[-1]), sub=14)
+    xt = torch.from_numpy(x).to("cuda")
+    out = torch.empty(200, dtype=torch.float64, device="cuda")
+    lib.red_sum_segmented_loop(xt.data_ptr(), off, 200, out.data_ptr(), lib.current_stream())
+    torch.cuda.synchronize()
+    check(out.cpu().numpy(), x, off)
+
+
+def test_full_batch_config(lib):
+    """10,000 log-uniform segments in [1, 2^20] (about 7.4e8 values)."""
+    x, off = inputs.segments(10000)
+    say("segments total", int(off[-1]))
+    for p in (dict(), dict(variant=3, wg=512, ipt=4, grid=256)):
+        res = run(lib, x, off, **p)
+        check(res, x, off)

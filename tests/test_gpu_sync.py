@@ -1,0 +1,104 @@
+"""Grid barrier and latency probes on the GPU (through the C ABI).
+
+* ordering: every workgroup's clock stamp before the barrier precedes every
+  stamp after it (the paper's timer check of a barrier, Section VIII-A,
+  applied to the grid level);
+* watchdog: a grid in which one workgroup never arrives (the partial
+  participation that deadlocks in Section VIII-B) ends with RED_ETIMEOUT
+  from a small spin limit, and the next reduction is correct;
+* stress: many persistent reductions with random grids stay bit-exact;
+* probes: positive latencies, stable under repetition (Section IX-D).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2004_05371_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.mark.parametrize("n_wg,wg", [(2, 64), (256, 256), (1024, 256), (512, 1024)])
+def test_grid_barrier_ordering(lib, n_wg, wg):
+    n_wg = min(n_wg, lib.red_max_coresident(wg))
+    for _ in range(5):
+        before, after = lib.sync_check_grid_order(n_wg, wg)
+        assert before <= after, (n_wg, wg, before, after)
+
+
+def test_watchdog_fires_and_recovers(lib):
+    rc = lib.sync_check_watchdog(8, 64, skip_wg=3, spin_limit=2000)
+    assert rc == lib.RED_ETIMEOUT
+    assert lib.red_check_error(lib.current_stream()) == lib.RED_OK  # cleared
+    x = inputs.uniform_i32(1 << 20)
+    t = torch.from_numpy(x).to("cuda")
+    out = lib.sum(t, opts=lib.make_opts(variant=3, wg=256, ipt=4, grid=64))
+    torch.cuda.synchronize()
+    assert out.item() == oracle.sum_i32(x)
+
+
+def test_persistent_stress_random_grids(lib):
+    x = inputs.uniform_i32(5_000_011, lo=-2**31, hi=2**31 - 1, sub=9)
+    ref = oracle.sum_i32(x)
+    t = torch.from_numpy(x).to("cuda")
+    r = np.random.default_rng(4)
+    maxg = lib.red_max_coresident(256)
+    outs = torch.empty(300, dtype=torch.int64, device="cuda")
+    for i in range(300):
+        g = int(r.integers(1, maxg + 1))
+        lib.red_sum_ex(lib.RED_I32, t.data_ptr(), t.numel(), outs[i].data_ptr(), lib.current_stream(),
+                       lib.make_opts(variant=3, wg=256, ipt=int(r.choice([1, 2, 4, 8])), grid=g))
+    torch.cuda.synchronize()
+    assert lib.red_check_error(lib.current_stream()) == lib.RED_OK
+    assert all(v == ref for v in outs.cpu().tolist())
+
+
+def test_atomic_stress_random_grids(lib):
+    x = inputs.normal_f32(3_000_001, sub=15)
+    t = torch.from_numpy(x).to("cuda")
+    ex = oracle.exact_sum(x, "f32")
+    r = np.random.default_rng(5)
+    for i in range(100):
+        g = int(r.integers(1, 4097))
+        out = lib.sum(t, opts=lib.make_opts(variant=2, wg=512, ipt=4, grid=g))
+        torch.cuda.synchronize()
+        assert oracle.rel_err(out.item(), ex) <= 1e-6
+
+
+@pytest.mark.parametrize("op", [0, 1, 2, 3])
+def test_wave_probe(lib, op):
+    ns, sigma, cyc = lib.sync_bench_wave(op, 64, reps=10)
+    say("wave op %d: %.2f ns (sigma %.2f), %.1f cycles" % (op, ns, sigma, cyc))
+    assert 0 < ns < 10000 and cyc > 0
+
+
+@pytest.mark.parametrize("wg", [64, 256, 1024])
+def test_block_probe(lib, wg):
+    ns, sigma, cyc = lib.sync_bench_block(wg, 1, reps=10)
+    say("block wg %d: %.2f ns (sigma %.2f), %.1f cycles" % (wg, ns, sigma, cyc))
+    assert 0 < ns < 100000 and cyc > 0
+
+
+@pytest.mark.parametrize("n_wg", [1, 16, 256, 1024])
+def test_grid_probe(lib, n_wg):
+    n_wg = min(n_wg, lib.red_max_coresident(256))
+    ns, sigma, wall = lib.sync_bench_grid(n_wg, 256, reps=10)
+    say("grid %d WGs: %.1f ns (sigma %.1f), in-kernel %.1f ns" % (n_wg, ns, sigma, wall))
+    assert 0 < ns < 1e6
+    # repeat-count invariance (Section IX-D): a second measurement agrees
+    ns2, _, _ = lib.sync_bench_grid(n_wg, 256, reps=10)
+    assert abs(ns2 - ns) <= 0.5 * max(ns, ns2) + 200
+
+
+@pytest.mark.parametrize("coop", [False, True])
+def test_relaunch_probe(lib, coop):
+    ns, sigma, null_ns = lib.sync_bench_relaunch(256, 256, cooperative=coop, reps=10)
+    say("relaunch coop=%s: overhead %.1f ns (sigma %.1f), null kernel %.1f ns" % (coop, ns, sigma, null_ns))
+    assert -2000 < ns < 1e5 and null_ns > 0
