@@ -76,6 +76,215 @@ def time_steps(fn, steps, stream):
     return [s.elapsed_time(e) for s, e in zip(starts, ends)], wall
 
 
+def variant_table(R, plan, dtype, xt, n, out, sh, stream, dev, reps=50, flush=None):
+    """GB/s (median of `reps` event-timed calls) of every synchronization
+    variant with the plan's workgroup size, loads per thread and flags."""
+    import statistics
+    nbytes = xt.numel() * xt.element_size()
+    nt = plan.flags & R.FLAG_NONTEMPORAL
+    coresident = R.red_max_coresident(plan.wg)
+    g = plan.grid or min(4 * dev["cus"], coresident)
+    cands = {
+        "relaunch": R.make_opts(variant=1, wg=plan.wg, ipt=plan.ipt, grid=plan.grid, flags=nt),
+        "atomic": R.make_opts(variant=2, wg=plan.wg, ipt=plan.ipt, grid=plan.grid, flags=nt),
+        "persistent_cooperative": R.make_opts(variant=3, wg=plan.wg, ipt=plan.ipt, grid=min(g, coresident), flags=nt),
+        "persistent_plain_launch": R.make_opts(variant=3, wg=plan.wg, ipt=plan.ipt, grid=coresident,
+                                               flags=nt | R.FLAG_PLAIN_LAUNCH),
+    }
+    res = {}
+    for name, o in cands.items():
+        fn = (lambda o=o: R.red_sum_ex(dtype, xt.data_ptr(), n, out.data_ptr(), sh, o))
+        for _ in range(3):
+            fn()
+        if flush is None:
+            tt, _ = time_steps(fn, reps, stream)
+        else:
+            tt = time_flushed(fn, reps, stream, flush)
+        res[name] = round(nbytes / (statistics.median(tt) * 1e-3) / 1e9, 1)
+    return res
+
+
+def time_flushed(fn, reps, stream, flush):
+    """Event time (ms) of each call after overwriting a 512 MiB buffer, so
+    that the 256 MB memory-side cache holds none of the input."""
+    import torch
+    out = []
+    for _ in range(reps):
+        flush.fill_(1.0)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        b.synchronize()
+        out.append(a.elapsed_time(b))
+    return out
+
+
+def gbps(nbytes, ms):
+    return round(nbytes / (ms * 1e-3) / 1e9, 1)
+
+
+def run_configs(R, dev, stream, path):
+    """Every workload of the study, one JSON record per measurement, written
+    to `path` (JSONL).  Timed regions hold only library calls; the oracle
+    timings and errors are the CPU-baseline leg of each record."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2004_05371_amd import inputs
+
+    sh = stream.cuda_stream
+    recs = []
+
+    def emit(rec):
+        recs.append(rec)
+        log(json.dumps(rec))
+        with open(path, "a") as fh:
+            fh.write(json.dumps(rec) + "\n")
+
+    flush = torch.empty(1 << 27, dtype=torch.float32, device="cuda")  # 512 MiB
+
+    def timed(fn, reps, flushed=False):
+        for _ in range(3):
+            fn()
+        if flushed:
+            return statistics.median(time_flushed(fn, reps, stream, flush))
+        tt, _ = time_steps(fn, reps, stream)
+        return statistics.median(tt)
+
+    def cpu_exact(x, kind):
+        c0 = time.perf_counter()
+        ex = oracle.exact_sum(x, kind) if kind != "i32" else oracle.sum_i32(x)
+        return ex, time.perf_counter() - c0
+
+    # -- small: 2^20 fp32 U[-1,1] and int32 U[-1000,1000], two-launch variant
+    for kind, x in (("f32", inputs.uniform_f32(1 << 20)), ("i32", inputs.uniform_i32(1 << 20))):
+        t = torch.from_numpy(x).to("cuda")
+        code = R.RED_F32 if kind == "f32" else R.RED_I32
+        out = torch.empty((), dtype=torch.float64 if kind == "f32" else torch.int64, device="cuda")
+        o = R.make_opts(variant=R.RED_VARIANT_RELAUNCH)
+        fn = lambda: R.red_sum_ex(code, t.data_ptr(), t.numel(), out.data_ptr(), sh, o)
+        warm, cold = timed(fn, 200), timed(fn, 50, flushed=True)
+        fn()
+        torch.cuda.synchronize()
+        ex, tc = cpu_exact(x, kind)
+        ok = (out.item() == ex) if kind == "i32" else (oracle.rel_err(out.item(), ex) <= 1e-6)
+        emit({"config": "small", "dtype": kind, "n": x.size, "variant": "relaunch", "us_warm": round(warm * 1e3, 2),
+              "us_flushed": round(cold * 1e3, 2), "GBps_warm": gbps(x.nbytes, warm), "matches_oracle": bool(ok),
+              "cpu_oracle_s": round(tc, 4)})
+
+    # -- int: 2^26 int32, three synchronization variants, flushed and warm
+    x = inputs.uniform_i32(1 << 26)
+    t = torch.from_numpy(x).to("cuda")
+    out = torch.empty((), dtype=torch.int64, device="cuda")
+    plan, us = R.red_autotune(R.RED_I32, 0, t.data_ptr(), t.numel(), out.data_ptr(), sh)
+    warm = variant_table(R, plan, R.RED_I32, t, t.numel(), out, sh, stream, dev)
+    cold = variant_table(R, plan, R.RED_I32, t, t.numel(), out, sh, stream, dev, reps=30, flush=flush)
+    exact, tc = cpu_exact(x, "i32")
+    bit_exact = {}
+    for v in (1, 2, 3):
+        R.red_sum_ex(R.RED_I32, t.data_ptr(), t.numel(), out.data_ptr(), sh,
+                     R.make_opts(variant=v, wg=plan.wg, ipt=plan.ipt,
+                                 grid=min(plan.grid or 1024, R.red_max_coresident(plan.wg))))
+        torch.cuda.synchronize()
+        bit_exact[R.VARIANT_NAMES[v]] = out.item() == exact
+    emit({"config": "int", "dtype": "i32", "n": x.size, "tuned_plan": plan.as_dict(), "GBps_warm": warm,
+          "GBps_flushed": cold, "bit_exact": bit_exact, "cpu_oracle_s": round(tc, 4)})
+    del t
+
+    # -- f32: 2^28 in two distributions, plain vs compensated
+    for gen in ("normal", "mixed"):
+        x = inputs.normal_f32(1 << 28) if gen == "normal" else inputs.mixed_f32(1 << 28)
+        t = torch.from_numpy(x).to("cuda")
+        out = torch.empty((), dtype=torch.float64, device="cuda")
+        ex, tc = cpu_exact(x, "f32")
+        absx = float(oracle.exact_abs_sum(x, "f32").fraction)
+        for acc, name in ((0, "compensated"), (1, "plain")):
+            plan, us = R.red_autotune(R.RED_F32, acc, t.data_ptr(), t.numel(), out.data_ptr(), sh)
+            o = R.opts_from_plan(plan, acc=acc)
+            ms = timed(lambda: R.red_sum_ex(R.RED_F32, t.data_ptr(), t.numel(), out.data_ptr(), sh, o), 50)
+            torch.cuda.synchronize()
+            r = out.item()
+            emit({"config": "f32", "dist": gen, "acc": name, "n": x.size, "plan": plan.as_dict(),
+                  "GBps": gbps(x.nbytes, ms), "rel_err": oracle.rel_err(r, ex),
+                  "err_over_sum_abs": abs(float(ex.fraction) - r) / absx, "cpu_oracle_s": round(tc, 3)})
+        del t
+
+    # -- half: bf16 / fp16 2^29 N(0,1), compensated
+    for kind in ("bf16", "f16"):
+        bits = inputs.normal_half_bits(1 << 29, kind)
+        tdt = torch.bfloat16 if kind == "bf16" else torch.float16
+        t = torch.from_numpy(bits.view(np.int16)).view(tdt).to("cuda")
+        code = R.RED_BF16 if kind == "bf16" else R.RED_F16
+        out = torch.empty((), dtype=torch.float64, device="cuda")
+        ex, tc = cpu_exact(bits, kind)
+        res = {}
+        for acc, name in ((0, "compensated"), (1, "plain")):
+            plan, us = R.red_autotune(code, acc, t.data_ptr(), t.numel(), out.data_ptr(), sh)
+            o = R.opts_from_plan(plan, acc=acc)
+            ms = timed(lambda: R.red_sum_ex(code, t.data_ptr(), t.numel(), out.data_ptr(), sh, o), 50)
+            torch.cuda.synchronize()
+            res[name] = {"plan": plan.as_dict(), "GBps": gbps(bits.nbytes, ms),
+                         "Gelem_per_s": round(bits.size / (ms * 1e-3) / 1e9, 1),
+                         "rel_err": oracle.rel_err(out.item(), ex)}
+        emit({"config": "half", "dtype": kind, "n": bits.size, **res, "cpu_oracle_s": round(tc, 3)})
+        del t
+        torch.cuda.empty_cache()
+
+    # -- segmented: 10,000 log-uniform segments, one graph launch vs a loop
+    x, off = inputs.segments(10000)
+    xt = torch.from_numpy(x).to("cuda")
+    ot = torch.from_numpy(off).to("cuda")
+    nseg = off.size - 1
+    out = torch.empty(nseg, dtype=torch.float64, device="cuda")
+    plan, us = R.red_autotune_segmented(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh)
+    nbytes = x.nbytes + off.nbytes + out.numel() * 8
+    ms_graph = timed(lambda: R.red_sum_segmented(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh), 30)
+    o = R.make_opts(variant=R.RED_VARIANT_PERSISTENT, wg=plan.wg, ipt=plan.ipt,
+                    grid=min(plan.grid, R.red_max_coresident(plan.wg)), flags=R.FLAG_PLAIN_LAUNCH)
+    ms_barrier = timed(lambda: R.red_sum_segmented_ex(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh, o), 30)
+    ms_loop = timed(lambda: R.red_sum_segmented_loop(xt.data_ptr(), off, nseg, out.data_ptr(), sh), 3)
+    R.red_sum_segmented(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    c0 = time.perf_counter()
+    sums = oracle.segmented_sums(x, off)
+    tc = time.perf_counter() - c0
+    worst = max(oracle.rel_err(float(got[k]), e) if e.fraction != 0 else abs(got[k]) for k, e in enumerate(sums))
+    emit({"config": "segments", "nseg": nseg, "total_elems": int(off[-1]), "bytes": nbytes, "plan": plan.as_dict(),
+          "graph_us": round(ms_graph * 1e3, 1), "graph_GBps": gbps(nbytes, ms_graph),
+          "grid_barrier_fixup_us": round(ms_barrier * 1e3, 1),
+          "loop_per_segment_us": round(ms_loop * 1e3, 1), "speedup_vs_loop": round(ms_loop / ms_graph, 1),
+          "max_rel_err": worst, "cpu_oracle_s": round(tc, 2)})
+    del xt, ot
+    torch.cuda.empty_cache()
+
+    # -- probes
+    for op, name in ((0, "dpp_reduce"), (1, "swizzle_reduce"), (2, "bpermute_reduce"), (3, "dpp_step")):
+        ns, sg, cyc = R.sync_bench_wave(op, 64, reps=20)
+        emit({"probe": "wave", "op": name, "ns": round(ns, 2), "sigma_ns": round(sg, 2), "cycles": round(cyc, 1)})
+    for wg in (64, 128, 256, 512, 1024):
+        for n_wg in (1, dev["cus"], 4 * dev["cus"]):
+            ns, sg, cyc = R.sync_bench_block(wg, n_wg, reps=20)
+            emit({"probe": "block", "wg": wg, "n_wg": n_wg, "waves_per_wg": wg // 64, "ns": round(ns, 2),
+                  "sigma_ns": round(sg, 2), "cycles": round(cyc, 1)})
+    for wg in (64, 256, 1024):
+        cores = R.red_max_coresident(wg)
+        n = 1
+        while n <= min(1024, cores):
+            ns, sg, wall = R.sync_bench_grid(n, wg, reps=20)
+            emit({"probe": "grid", "wg": wg, "n_wg": n, "wg_per_cu": round(n / dev["cus"], 3), "ns": round(ns, 1),
+                  "sigma_ns": round(sg, 1), "in_kernel_ns": round(wall, 1)})
+            n *= 2
+    for coop in (False, True):
+        ns, sg, null_ns = R.sync_bench_relaunch(dev["cus"], 256, cooperative=coop, reps=30)
+        emit({"probe": "relaunch", "cooperative": coop, "overhead_ns": round(ns, 1), "sigma_ns": round(sg, 1),
+              "null_kernel_total_ns": round(null_ns, 1)})
+    return recs
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +292,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probes", action="store_true")
+    ap.add_argument("--configs", metavar="JSONL", help="also measure every workload and probe sweep into JSONL")
+    ap.add_argument("--only-configs", action="store_true", help="skip the headline (with --configs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -102,6 +313,11 @@ def main():
     sh = stream.cuda_stream
     log("device", dev)
 
+    if args.configs:
+        run_configs(R, dev, stream, args.configs)
+        if args.only_configs:
+            return
+
     # ---- input, resident in HBM before timing
     t0 = time.time()
     x = inputs.normal_f32(N)
@@ -114,8 +330,7 @@ def main():
     # ---- autotune the plan for this workload
     plan, tuned_us = R.red_autotune(R.RED_F32, R.RED_ACC_COMPENSATED, xt.data_ptr(), N, out.data_ptr(), sh)
     log("tuned plan", plan.as_dict(), "%.1f us" % tuned_us)
-    opts = R.make_opts(variant=plan.variant, wg=plan.wg, ipt=plan.ipt, grid=plan.grid,
-                       acc=R.RED_ACC_COMPENSATED)
+    opts = R.opts_from_plan(plan, acc=R.RED_ACC_COMPENSATED)
 
     def step():
         R.red_sum_ex(R.RED_F32, xt.data_ptr(), N, out.data_ptr(), sh, opts)
@@ -134,17 +349,8 @@ def main():
 
     extra = {}
     # ---- other variants / accumulation (a few steps each)
-    variants = {}
-    for v, name in ((1, "relaunch"), (2, "atomic"), (3, "persistent")):
-        o = R.make_opts(variant=v, wg=plan.wg, ipt=plan.ipt, grid=plan.grid if v != 3 else min(
-            plan.grid or 4 * dev["cus"], R.red_max_coresident(plan.wg)))
-        fn = (lambda o=o: R.red_sum_ex(R.RED_F32, xt.data_ptr(), N, out.data_ptr(), sh, o))
-        for _ in range(5):
-            fn()
-        tt, _ = time_steps(fn, 50, stream)
-        variants[name] = round(nbytes / (statistics.median(tt) * 1e-3) / 1e9, 1)
-    extra["variants_GBps"] = variants
-    o = R.make_opts(variant=plan.variant, wg=plan.wg, ipt=plan.ipt, grid=plan.grid, acc=R.RED_ACC_PLAIN)
+    extra["variants_GBps"] = variant_table(R, plan, R.RED_F32, xt, N, out, sh, stream, dev)
+    o = R.opts_from_plan(plan, acc=R.RED_ACC_PLAIN)
     tt, _ = time_steps(lambda: R.red_sum_ex(R.RED_F32, xt.data_ptr(), N, out.data_ptr(), sh, o), 50, stream)
     extra["plain_fp32_GBps"] = round(nbytes / (statistics.median(tt) * 1e-3) / 1e9, 1)
     # read-only ceiling (bandwidth proxy)

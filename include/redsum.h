@@ -88,12 +88,23 @@ typedef enum {
     RED_WAVE_DPP_STEP = 3  /* a single DPP add step (latency of one move+add) */
 } red_wave_op;
 
+/* Plan / option flags. */
+#define RED_FLAG_NONTEMPORAL 1  /* streaming loads with the nontemporal hint  */
+#define RED_FLAG_NO_GRAPH 2     /* segmented: launch directly, no hipGraph    */
+#define RED_FLAG_PLAIN_LAUNCH 4 /* persistent variants: ordinary launch of a
+                                   grid capped at the co-resident limit
+                                   (occupancy x CUs) instead of the
+                                   cooperative launch API; the barrier
+                                   watchdog guards against a grid that is
+                                   not fully resident                       */
+
 /* Launch plan of one reduction. */
 typedef struct {
     int32_t variant; /* red_variant, not RED_VARIANT_AUTO when installed     */
     int32_t wg;      /* workgroup size in threads: 64..1024, multiple of 64  */
     int32_t ipt;     /* 16-byte loads per thread per loop iteration: 1,2,4,8 */
     int32_t grid;    /* number of workgroups, 1..RED_MAX_GRID; 0 = automatic */
+    int32_t flags;   /* RED_FLAG_NONTEMPORAL | RED_FLAG_PLAIN_LAUNCH         */
 } red_plan;
 
 #define RED_MAX_GRID 8192
@@ -106,7 +117,8 @@ typedef struct {
                         with an explicit variant, wg / ipt left at 0 take
                         the default values (grid 0 is automatic)            */
     int32_t acc;     /* red_acc                                             */
-    int32_t flags;   /* bit 0: nontemporal loads; other bits must be zero   */
+    int32_t flags;   /* RED_FLAG_* (OR-ed with plan.flags); other bits must
+                        be zero                                             */
 } red_opts;
 
 /* ---------------------------------------------------------------------
@@ -173,8 +185,8 @@ int red_sum_segmented(const float *x, const int64_t *offsets, int64_t nseg, doub
 
 /* red_sum_segmented with explicit options.  opts->plan.variant selects the
  * cross-slice fix-up: RED_VARIANT_ATOMIC (ticket, default) or
- * RED_VARIANT_PERSISTENT (cooperative launch + grid barrier, no graph).
- * flags bit 1 disables graph capture (direct launch). */
+ * RED_VARIANT_PERSISTENT (co-resident grid + grid barrier, launched
+ * directly, not from a graph).  RED_FLAG_NO_GRAPH disables graph capture. */
 int red_sum_segmented_ex(const float *x, const int64_t *offsets, int64_t nseg, double *out,
                          void *stream, const red_opts *opts);
 

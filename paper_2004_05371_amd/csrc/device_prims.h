@@ -387,33 +387,41 @@ __device__ __forceinline__ long long* acc_i64(BarrierWords* w) {
 }
 
 // ---------------------------------------------------------------------------
-// Grid barrier for a cooperative launch of `nblocks` co-resident workgroups.
+// Grid barrier for a launch of `nblocks` co-resident workgroups.
 //
-// Centralized sense-reversing barrier: thread 0 of each workgroup reads the
-// generation, then increments the arrival counter with an acquire-release
-// atomic at agent (device) scope; the last arrival resets the counter and
-// publishes the next generation with a release increment, the others poll
-// the generation with acquire loads (s_sleep between polls).  Release/acquire
-// at agent scope makes the workgroups' earlier global stores visible across
-// the XCDs' separate L2 caches.  The poll is bounded by `spin_limit`: on
-// expiry the workgroup sets the error word and leaves the barrier, so the
-// kernel always ends (the paper observed that a grid in which not every
-// block calls grid sync deadlocks, Section VIII-B).  Returns false on
-// timeout.
+// Centralized sense-reversing barrier.  Thread 0 of each workgroup:
+//   1. reads the generation g (relaxed);
+//   2. release fence at agent (device) scope -- one L2 write-back that makes
+//      the workgroup's earlier global stores visible across the XCDs'
+//      separate L2 caches -- then a relaxed atomic increment of the arrival
+//      counter;
+//   3. the last arrival resets the counter, fences (release) and bumps the
+//      generation; the others poll the generation with relaxed device-scope
+//      loads (s_sleep between polls, so polling neither invalidates the L2
+//      nor floods the memory-side atomic unit);
+//   4. one acquire fence after the wait.
+// Fence-to-fence synchronization through the relaxed counter / generation
+// operations orders every workgroup's stores before every workgroup's loads
+// after the barrier.  The poll is bounded by `spin_limit`: on expiry the
+// workgroup sets the error word and leaves, so the kernel always ends (a grid
+// in which not every block arrives deadlocks, Section VIII-B of the paper).
+// Returns false on timeout.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool grid_barrier(BarrierWords* w, unsigned nblocks, unsigned spin_limit) {
   __shared__ int timed_out;
   __syncthreads();
   if (threadIdx.x == 0) {
     int to = 0;
-    unsigned g = __hip_atomic_load(&w->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned old = __hip_atomic_fetch_add(&w->count.v, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned g = __hip_atomic_load(&w->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned old = __hip_atomic_fetch_add(&w->count.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (old == nblocks - 1) {
       __hip_atomic_store(&w->count.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&w->gen.v, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_fetch_add(&w->gen.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       unsigned spins = 0;
-      while (__hip_atomic_load(&w->gen.v, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+      while (__hip_atomic_load(&w->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
         if (++spins > spin_limit) {
           __hip_atomic_store(&w->err.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           to = 1;
@@ -422,6 +430,7 @@ __device__ __forceinline__ bool grid_barrier(BarrierWords* w, unsigned nblocks, 
         __builtin_amdgcn_s_sleep(1);
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     timed_out = to;
   }
   __syncthreads();

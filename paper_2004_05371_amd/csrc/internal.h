@@ -70,8 +70,7 @@ int launch(const void* fn, int grid, int block, void** args, hipStream_t s, bool
 // Reductions ---------------------------------------------------------------
 struct ReduceLaunch {
   int dtype, acc;
-  red_plan plan;
-  bool nontemporal;
+  red_plan plan;  // plan.flags: RED_FLAG_NONTEMPORAL | RED_FLAG_PLAIN_LAUNCH
 };
 int validate_plan(const red_plan& p);
 red_plan default_plan(int dtype, int64_t n, const DeviceInfo& dev);
@@ -83,7 +82,6 @@ int reduce_max_coresident(int dtype, int acc, int ipt, bool nt, int wg, const De
 // Segmented ------------------------------------------------------------------
 struct SegLaunch {
   red_plan plan;  // variant: RED_VARIANT_ATOMIC (ticket) or RED_VARIANT_PERSISTENT
-  bool nontemporal;
 };
 red_plan default_seg_plan(int64_t nseg, const DeviceInfo& dev);
 int seg_launch(const SegLaunch& sl, const float* x, const int64_t* offsets, int64_t nseg, double* out,

@@ -120,9 +120,10 @@ __global__ __launch_bounds__(1024) void k_final(const Part* partials, int count,
 // ---------------------------------------------------------------------------
 // Variant 2, one kernel with an atomic ticket: each workgroup publishes its
 // partial (int: atomic int64 add into one word; float: its partial slot),
-// then takes a ticket with an acquire-release atomic at device scope; the
-// workgroup that draws the last ticket does the final combine and resets
-// the ticket (and the int accumulator) for the next launch.
+// then, after a device-scope release fence, takes a ticket with a relaxed
+// atomic; the workgroup that draws the last ticket acquires, does the final
+// combine and resets the ticket (and the int accumulator) for the next
+// launch.
 // ---------------------------------------------------------------------------
 template <class M, int IPT, bool NT>
 __global__ __launch_bounds__(1024) void k_atomic(ReduceArgs a) {
@@ -135,7 +136,10 @@ __global__ __launch_bounds__(1024) void k_atomic(ReduceArgs a) {
       __hip_atomic_fetch_add(acc_i64(w), p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else
       static_cast<Part*>(a.partials)[blockIdx.x] = p;
-    ticket = __hip_atomic_fetch_add(&w->ticket.v, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    // Release (one L2 write-back) publishes the partial; the ticket itself
+    // is relaxed, and only the last workgroup pays an acquire.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    ticket = __hip_atomic_fetch_add(&w->ticket.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
   if (ticket != gridDim.x - 1) return;
@@ -260,6 +264,8 @@ int validate_plan(const red_plan& p) {
   if (ipt_index(p.ipt) < 0) return set_error(RED_EINVAL, "plan: ipt %d must be 1, 2, 4 or 8", p.ipt);
   if (p.grid < 0 || p.grid > RED_MAX_GRID)
     return set_error(RED_EINVAL, "plan: grid %d out of range [0, %d]", p.grid, RED_MAX_GRID);
+  if (p.flags & ~(RED_FLAG_NONTEMPORAL | RED_FLAG_PLAIN_LAUNCH))
+    return set_error(RED_EINVAL, "plan: unknown flags 0x%x", p.flags);
   return RED_OK;
 }
 
@@ -271,6 +277,7 @@ red_plan default_plan(int dtype, int64_t n, const DeviceInfo& dev) {
   p.wg = 512;
   p.ipt = 4;
   p.grid = 0;  // automatic: bounded by the work and by 4 workgroups per CU
+  p.flags = 0;
   (void)dev;
   return p;
 }
@@ -313,7 +320,8 @@ int reduce_launch(const ReduceLaunch& rl, const void* x, int64_t n, void* out, W
 
   const red_plan& p = rl.plan;
   const int ii = ipt_index(p.ipt);
-  const KernelSet& ks = table().k[m][rl.nontemporal ? 1 : 0][ii];
+  const bool nt = (p.flags & RED_FLAG_NONTEMPORAL) != 0;
+  const KernelSet& ks = table().k[m][nt ? 1 : 0][ii];
   // Grid: the requested size, else enough workgroups for the work, capped
   // at 4 per compute unit (and at the co-resident limit for the persistent
   // variant).
@@ -341,14 +349,14 @@ int reduce_launch(const ReduceLaunch& rl, const void* x, int64_t n, void* out, W
       return launch(ks.atomic, grid, p.wg, args, s, false);
     case RED_VARIANT_PERSISTENT: {
       int maxg = 0;
-      int rc = reduce_max_coresident(rl.dtype, rl.acc, p.ipt, rl.nontemporal, p.wg, dev, &maxg);
+      int rc = reduce_max_coresident(rl.dtype, rl.acc, p.ipt, nt, p.wg, dev, &maxg);
       if (rc) return rc;
       if (p.grid > 0 && p.grid > maxg)
         return set_error(RED_EINVAL, "persistent plan: grid %d exceeds the %d co-resident workgroups",
                          p.grid, maxg);
       grid = std::min(grid, maxg);
       if (grid < 1) return set_error(RED_EINVAL, "persistent kernel cannot be resident");
-      return launch(ks.persistent, grid, p.wg, args, s, true);
+      return launch(ks.persistent, grid, p.wg, args, s, (p.flags & RED_FLAG_PLAIN_LAUNCH) == 0);
     }
   }
   return set_error(RED_EINVAL, "unknown variant %d", p.variant);

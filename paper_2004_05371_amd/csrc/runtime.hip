@@ -214,7 +214,8 @@ int validate_sum_args(int dtype, const void* x, int64_t n, void* out, const red_
   if (opts) {
     if (opts->acc != RED_ACC_COMPENSATED && opts->acc != RED_ACC_PLAIN)
       return set_error(RED_EINVAL, "unknown accumulation %d", opts->acc);
-    if (opts->flags & ~1) return set_error(RED_EINVAL, "unknown flags 0x%x", opts->flags);
+    if (opts->flags & ~(RED_FLAG_NONTEMPORAL | RED_FLAG_PLAIN_LAUNCH))
+      return set_error(RED_EINVAL, "unknown flags 0x%x", opts->flags);
     if (opts->plan.variant != RED_VARIANT_AUTO) {
       red_plan p = opts->plan;
       if (p.wg == 0) p.wg = 512;
@@ -251,7 +252,8 @@ int validate_seg_args(const float* x, const int64_t* offsets, int64_t nseg, doub
   if (reinterpret_cast<uintptr_t>(offsets) % 8) return set_error(RED_EINVAL, "offsets is not 8-byte aligned");
   if (reinterpret_cast<uintptr_t>(out) % 8) return set_error(RED_EINVAL, "out is not 8-byte aligned");
   if (opts) {
-    if (opts->flags & ~3) return set_error(RED_EINVAL, "unknown flags 0x%x", opts->flags);
+    if (opts->flags & ~(RED_FLAG_NONTEMPORAL | RED_FLAG_NO_GRAPH | RED_FLAG_PLAIN_LAUNCH))
+      return set_error(RED_EINVAL, "unknown flags 0x%x", opts->flags);
     if (opts->plan.variant != RED_VARIANT_AUTO) {
       red_plan p = opts->plan;
       if (p.wg == 0) p.wg = 512;
@@ -340,10 +342,10 @@ int red_sum_ex(int dtype, const void* x, int64_t n, void* out, void* stream, con
   ReduceLaunch rl;
   rl.dtype = dtype;
   rl.acc = opts ? opts->acc : RED_ACC_COMPENSATED;
-  rl.nontemporal = opts ? (opts->flags & 1) != 0 : false;
   rl.plan = (opts && opts->plan.variant != RED_VARIANT_AUTO)
                 ? complete_plan(opts->plan, default_plan(dtype, n, *dev))
                 : lookup_plan(dtype, rl.acc, n, *dev);
+  if (opts) rl.plan.flags |= opts->flags & (RED_FLAG_NONTEMPORAL | RED_FLAG_PLAIN_LAUNCH);
   return reduce_launch(rl, x, n, out, ws, s, *dev);
 }
 
@@ -479,7 +481,7 @@ int red_autotune(int dtype, int acc, const void* x, int64_t n, void* out, void* 
   const int ipts[] = {1, 2, 4, 8};
   for (int wg : wgs)
     for (int ipt : ipts) {
-      red_plan p{RED_VARIANT_RELAUNCH, wg, ipt, 0};
+      red_plan p{RED_VARIANT_RELAUNCH, wg, ipt, 0, 0};
       if ((rc = consider(p))) return rc;
     }
   const int64_t tile = (int64_t)cur.wg * cur.ipt;
@@ -503,6 +505,22 @@ int red_autotune(int dtype, int acc, const void* x, int64_t n, void* out, void* 
       p.grid = (int)std::min<int64_t>({(int64_t)maxg, want, (int64_t)4 * dev->cus});
     }
     if ((rc = consider(p))) return rc;
+  }
+  // Nontemporal loads, and for the persistent variant the ordinary launch
+  // of an occupancy-capped grid (no cooperative-launch overhead).
+  {
+    red_plan p = cur;
+    p.flags |= RED_FLAG_NONTEMPORAL;
+    if ((rc = consider(p))) return rc;
+    red_plan q = base2;
+    q.variant = RED_VARIANT_PERSISTENT;
+    int maxg = 0;
+    if ((rc = reduce_max_coresident(dtype, acc, q.ipt, false, q.wg, *dev, &maxg))) return rc;
+    q.grid = (int)std::min<int64_t>({(int64_t)maxg, want, (int64_t)RED_MAX_GRID});
+    q.flags = RED_FLAG_PLAIN_LAUNCH;
+    if ((rc = consider(q))) return rc;
+    q.flags |= RED_FLAG_NONTEMPORAL;
+    if ((rc = consider(q))) return rc;
   }
   if ((rc = red_set_plan(dtype, acc, n, &cur))) return rc;
   if (best) *best = cur;
@@ -529,8 +547,7 @@ int red_sum_segmented_ex(const float* x, const int64_t* offsets, int64_t nseg, d
   Workspace* ws;
   if ((rc = get_workspace(s, &ws))) return rc;
   SegLaunch sl;
-  sl.nontemporal = opts ? (opts->flags & 1) != 0 : false;
-  const bool no_graph = opts ? (opts->flags & 2) != 0 : false;
+  const bool no_graph = opts ? (opts->flags & RED_FLAG_NO_GRAPH) != 0 : false;
   if (opts && opts->plan.variant != RED_VARIANT_AUTO) {
     sl.plan = complete_plan(opts->plan, default_seg_plan(nseg, *dev));
   } else {
@@ -541,12 +558,14 @@ int red_sum_segmented_ex(const float* x, const int64_t* offsets, int64_t nseg, d
     auto it = g_plans.find(std::make_tuple(1, bucket(nseg), 0, 0));
     if (it != g_plans.end()) sl.plan = it->second;
   }
-  // Cooperative launches, the null stream and a caller's own capture launch
-  // directly; otherwise the launch is replayed from a cached graph.
+  if (opts) sl.plan.flags |= opts->flags & (RED_FLAG_NONTEMPORAL | RED_FLAG_PLAIN_LAUNCH);
+  // Persistent (co-resident) launches, the null stream and a caller's own
+  // capture launch directly; otherwise the launch is replayed from a cached
+  // graph.
   if (no_graph || !s || sl.plan.variant == RED_VARIANT_PERSISTENT || stream_capturing(s))
     return seg_direct(sl, x, offsets, nseg, out, ws, s, *dev);
   GraphKey key{dev->id, s, x, offsets, nseg, out, sl.plan.variant, sl.plan.wg, sl.plan.ipt, sl.plan.grid,
-               sl.nontemporal ? 1 : 0};
+               sl.plan.flags};
   hipGraphExec_t exec = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -600,7 +619,7 @@ int red_sum_segmented_loop(const float* x, const int64_t* host_offsets, int64_t 
   red_opts o;
   memset(&o, 0, sizeof o);
   o.acc = RED_ACC_COMPENSATED;
-  o.plan = red_plan{RED_VARIANT_ATOMIC, 512, 4, 0};
+  o.plan = red_plan{RED_VARIANT_ATOMIC, 512, 4, 0, 0};
   for (int64_t k = 0; k < nseg; ++k) {
     int rc = red_sum_ex(RED_F32, x + host_offsets[k], host_offsets[k + 1] - host_offsets[k], out + k, stream, &o);
     if (rc) return rc;
@@ -627,7 +646,7 @@ int red_autotune_segmented(const float* x, const int64_t* offsets, int64_t nseg,
   int timed = 0;
   auto consider = [&](red_plan p) -> int {
     if (budget > 0 && timed >= budget) return RED_OK;
-    SegLaunch sl{p, false};
+    SegLaunch sl{p};
     std::vector<double> t;
     for (int i = 0; i < 6; ++i) {
       RED_HIP(hipEventRecord(a, s));
@@ -649,7 +668,7 @@ int red_autotune_segmented(const float* x, const int64_t* offsets, int64_t nseg,
   };
   for (int wg : {256, 512, 1024})
     for (int ipt : {2, 4, 8})
-      if ((rc = consider(red_plan{RED_VARIANT_ATOMIC, wg, ipt, 4 * dev->cus}))) break;
+      if ((rc = consider(red_plan{RED_VARIANT_ATOMIC, wg, ipt, 4 * dev->cus, 0}))) break;
   const red_plan base = cur;
   if (!rc)
     for (int m : {1, 2, 3, 6, 8, 12, 16}) {

@@ -136,9 +136,11 @@ __global__ __launch_bounds__(1024) void k_segmented(SegArgs a) {
         const int64_t o = sa / chunk;
         const int64_t np = (sb - 1) / chunk - o + 1;
         if constexpr (!BARRIER) {
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
           const unsigned tk =
-              __hip_atomic_fetch_add(&a.tickets[o], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+              __hip_atomic_fetch_add(&a.tickets[o], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           if (tk == (unsigned)(np - 1)) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             a.out[s] = combine_pieces(a, o, np);
             __hip_atomic_store(&a.tickets[o], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
@@ -196,6 +198,7 @@ red_plan default_seg_plan(int64_t nseg, const DeviceInfo& dev) {
   p.wg = 512;
   p.ipt = 4;
   p.grid = 4 * dev.cus;
+  p.flags = 0;
   return p;
 }
 
@@ -237,7 +240,9 @@ int seg_launch(const SegLaunch& sl, const float* x, const int64_t* offsets, int6
   a.words = ws->words;
   a.spin_limit = watchdog_spins();
   void* args[] = {&a};
-  return launch(seg_table().k[barrier ? 1 : 0][sl.nontemporal ? 1 : 0][ii], grid, p.wg, args, s, barrier);
+  const bool nt = (p.flags & RED_FLAG_NONTEMPORAL) != 0;
+  const bool coop = barrier && (p.flags & RED_FLAG_PLAIN_LAUNCH) == 0;
+  return launch(seg_table().k[barrier ? 1 : 0][nt ? 1 : 0][ii], grid, p.wg, args, s, coop);
 }
 
 }  // namespace redsum

@@ -28,6 +28,7 @@ RED_WAVE_DPP, RED_WAVE_SWIZZLE, RED_WAVE_BPERMUTE, RED_WAVE_DPP_STEP = 0, 1, 2, 
 RED_MAX_GRID = 8192
 FLAG_NONTEMPORAL = 1
 FLAG_NO_GRAPH = 2
+FLAG_PLAIN_LAUNCH = 4
 
 STATUS_NAMES = {0: "RED_OK", -1: "RED_EINVAL", -2: "RED_ENOTSUP", -3: "RED_EHIP",
                 -4: "RED_ETIMEOUT", -5: "RED_ENOMEM", -6: "RED_ENODEV"}
@@ -47,11 +48,11 @@ EXPORTS = [
 
 class Plan(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("wg", ctypes.c_int32),
-                ("ipt", ctypes.c_int32), ("grid", ctypes.c_int32)]
+                ("ipt", ctypes.c_int32), ("grid", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
     def as_dict(self):
         return {"variant": VARIANT_NAMES.get(self.variant, self.variant), "wg": self.wg,
-                "ipt": self.ipt, "grid": self.grid}
+                "ipt": self.ipt, "grid": self.grid, "flags": self.flags}
 
 
 class Opts(ctypes.Structure):
@@ -145,7 +146,11 @@ def red_sum(dtype: int, x: int, n: int, out: int, stream: int = 0) -> int:
 
 def make_opts(variant: int = RED_VARIANT_AUTO, wg: int = 0, ipt: int = 0, grid: int = 0,
               acc: int = RED_ACC_COMPENSATED, flags: int = 0) -> Opts:
-    return Opts(Plan(variant, wg, ipt, grid), acc, flags)
+    return Opts(Plan(variant, wg, ipt, grid, 0), acc, flags)
+
+
+def opts_from_plan(plan: Plan, acc: int = RED_ACC_COMPENSATED, flags: int = 0) -> Opts:
+    return Opts(Plan(plan.variant, plan.wg, plan.ipt, plan.grid, plan.flags), acc, flags)
 
 
 def red_sum_ex(dtype: int, x: int, n: int, out: int, stream: int = 0, opts: Optional[Opts] = None) -> int:

@@ -57,7 +57,7 @@ def test_validation_before_hip(lib):
     assert lib.red_sum_ex(R.RED_F32, ctypes.c_void_p(64), 4, ctypes.c_void_p(64), None, ctypes.byref(bad)) == R.RED_EINVAL
     bad = R.make_opts(acc=7)
     assert lib.red_sum_ex(R.RED_F32, ctypes.c_void_p(64), 4, ctypes.c_void_p(64), None, ctypes.byref(bad)) == R.RED_EINVAL
-    bad = R.make_opts(flags=8)
+    bad = R.make_opts(flags=16)
     assert lib.red_sum_ex(R.RED_F32, ctypes.c_void_p(64), 4, ctypes.c_void_p(64), None, ctypes.byref(bad)) == R.RED_EINVAL
     assert lib.red_sum_segmented(None, None, 3, None, None) == R.RED_EINVAL
     assert lib.red_sum_segmented(ctypes.c_void_p(64), ctypes.c_void_p(64), -1, ctypes.c_void_p(64), None) == R.RED_EINVAL
@@ -68,7 +68,7 @@ def test_validation_before_hip(lib):
     assert lib.sync_bench_wave(9, 64, 10, None, None, None, None) == R.RED_EINVAL
     assert lib.sync_bench_grid(0, 256, 10, None, None, None, None) == R.RED_EINVAL
     assert lib.sync_check_watchdog(4, 64, 9, 100, None) == R.RED_EINVAL
-    p = R.Plan(R.RED_VARIANT_PERSISTENT, 256, 16, 0)
+    p = R.Plan(R.RED_VARIANT_PERSISTENT, 256, 16, 0, 0)
     assert lib.red_set_plan(R.RED_F32, 0, 100, ctypes.byref(p)) == R.RED_EINVAL
     # host-side loop baseline validates host offsets
     off = (ctypes.c_int64 * 3)(0, 5, 2)
@@ -83,10 +83,10 @@ def test_no_device_reports_enodev(lib):
 
 
 def test_plan_table_roundtrip(lib):
-    p = R.Plan(R.RED_VARIANT_ATOMIC, 256, 2, 512)
+    p = R.Plan(R.RED_VARIANT_ATOMIC, 256, 2, 512, 1)
     R.red_set_plan(R.RED_BF16, R.RED_ACC_COMPENSATED, 1 << 20, p)
     q = R.red_get_plan(R.RED_BF16, R.RED_ACC_COMPENSATED, (1 << 20) - 5)  # same ceil(log2) bucket
-    assert (q.variant, q.wg, q.ipt, q.grid) == (2, 256, 2, 512)
+    assert (q.variant, q.wg, q.ipt, q.grid, q.flags) == (2, 256, 2, 512, 1)
     d = R.red_get_plan(R.RED_BF16, R.RED_ACC_PLAIN, 1 << 20)  # other bucket key -> default
     assert d.variant in (1, 2, 3) and d.wg % 64 == 0
 
