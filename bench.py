@@ -3,16 +3,21 @@
 
 Workload: the sum of 2^28 fp32 values drawn N(0,1) (1 GiB, resident in HBM
 before timing starts), TwoSum-compensated fp32 accumulation with a binary64
-final combine, launched with the autotuned plan.  One step = one call of
-red_sum over the whole array (per-thread accumulation, wavefront and
-workgroup combines, device-wide synchronization, final combine).
+final combine, launched with the tuned plan (from the committed plan cache,
+or tuned on the spot).  One step = one call of red_sum over the whole array
+(per-thread accumulation, wavefront and workgroup combines, device-wide
+synchronization, final combine).
 
-Prints ONE JSON line: GB/s (= 2^30 bytes / time per step) and the fraction
-of the 8 TB/s HBM peak, plus the grid-barrier and relaunch latencies, the
-other synchronization variants, the bandwidth-proxy ceiling, the error of
-the result against the exact CPU oracle, and the oracle's own CPU time.
+Prints ONE JSON line: GB/s (= 2^30 bytes / wall time per step) and the
+fraction of the 8 TB/s HBM peak; the roofline of the dominant (streaming)
+kernel from its own HIP-event durations; the grid-barrier and relaunch
+latencies, the other synchronization variants and the bandwidth-proxy
+ceiling; the error of the result against the exact CPU oracle and the
+oracle's own CPU time.
 
     python bench.py [--gpus 1] [--steps 200] [--warmup 20]
+    python bench.py --configs out.jsonl [--only-configs]   # every workload + probe sweeps
+    python bench.py --retune --save-plans plans.json        # re-run the autotuner
 """
 from __future__ import annotations
 
@@ -46,22 +51,27 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_per_launch():
+def traffic_per_launch(plan_dict):
     """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 counter summary, or None if it is absent or was taken on a
-    different kernel source."""
+    rocprofv3 counter summary, or None if it is absent, was taken on a
+    different kernel source, or on a different plan."""
     try:
         with open(TRAFFIC_FILE) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("plan") != plan_dict:
         return None
     return d.get("bytes_per_launch")
 
 
+def gbps(nbytes, ms):
+    return round(nbytes / (ms * 1e-3) / 1e9, 1)
+
+
 def time_steps(fn, steps, stream):
-    """Per-step HIP event times (ms) on `stream` over `steps` calls."""
+    """Per-step HIP event times (ms) on `stream` over `steps` calls, and
+    the wall time of the whole loop (s)."""
     import torch
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
@@ -76,10 +86,38 @@ def time_steps(fn, steps, stream):
     return [s.elapsed_time(e) for s, e in zip(starts, ends)], wall
 
 
+class Flusher:
+    """Read-only pass over a 1 GiB buffer before a timed call, so the 256 MB
+    memory-side cache holds none of the input (reads leave clean lines, so
+    no write-back competes with the timed call)."""
+
+    def __init__(self, R, sh):
+        import torch
+        self.R, self.sh = R, sh
+        self.buf = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+
+    def __call__(self):
+        self.R.red_bw_proxy(self.buf.data_ptr(), self.buf.numel() * 4, 1024, 512, self.sh)
+
+
+def time_flushed(fn, reps, stream, flush):
+    import torch
+    out = []
+    for _ in range(reps):
+        flush()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        b.synchronize()
+        out.append(a.elapsed_time(b))
+    return out
+
+
 def variant_table(R, plan, dtype, xt, n, out, sh, stream, dev, reps=50, flush=None):
     """GB/s (median of `reps` event-timed calls) of every synchronization
     variant with the plan's workgroup size, loads per thread and flags."""
-    import statistics
     nbytes = xt.numel() * xt.element_size()
     nt = plan.flags & R.FLAG_NONTEMPORAL
     coresident = R.red_max_coresident(plan.wg)
@@ -87,8 +125,9 @@ def variant_table(R, plan, dtype, xt, n, out, sh, stream, dev, reps=50, flush=No
     cands = {
         "relaunch": R.make_opts(variant=1, wg=plan.wg, ipt=plan.ipt, grid=plan.grid, flags=nt),
         "atomic": R.make_opts(variant=2, wg=plan.wg, ipt=plan.ipt, grid=plan.grid, flags=nt),
-        "persistent_cooperative": R.make_opts(variant=3, wg=plan.wg, ipt=plan.ipt, grid=min(g, coresident), flags=nt),
-        "persistent_plain_launch": R.make_opts(variant=3, wg=plan.wg, ipt=plan.ipt, grid=coresident,
+        "persistent_cooperative": R.make_opts(variant=3, wg=plan.wg, ipt=plan.ipt, grid=min(g, coresident),
+                                              flags=nt),
+        "persistent_plain_launch": R.make_opts(variant=3, wg=plan.wg, ipt=plan.ipt, grid=min(g, coresident),
                                                flags=nt | R.FLAG_PLAIN_LAUNCH),
     }
     res = {}
@@ -100,35 +139,44 @@ def variant_table(R, plan, dtype, xt, n, out, sh, stream, dev, reps=50, flush=No
             tt, _ = time_steps(fn, reps, stream)
         else:
             tt = time_flushed(fn, reps, stream, flush)
-        res[name] = round(nbytes / (statistics.median(tt) * 1e-3) / 1e9, 1)
+        res[name] = gbps(nbytes, statistics.median(tt))
     return res
 
 
-def time_flushed(fn, reps, stream, flush):
-    """Event time (ms) of each call after overwriting a 512 MiB buffer, so
-    that the 256 MB memory-side cache holds none of the input."""
-    import torch
-    out = []
-    for _ in range(reps):
-        flush.fill_(1.0)
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        fn()
-        b.record(stream)
-        b.synchronize()
-        out.append(a.elapsed_time(b))
-    return out
+class Plans:
+    """Plans from the committed cache, or tuned now (and recorded)."""
+
+    def __init__(self, R, retune: bool):
+        from paper_2004_05371_amd import autotune
+        self.R, self.at, self.retune = R, autotune, retune
+        self.keys = set() if retune else autotune.cached_keys()
+        self.installed = 0 if retune else autotune.load()
+        self.recorded = []
+
+    def sum_plan(self, t, out, acc, sh):
+        R, at = self.R, self.at
+        code = R.dtype_code(t)
+        inv = {v: k for k, v in at.DTYPES.items()}
+        key = ("sum", inv[code], "plain" if acc == R.RED_ACC_PLAIN else "compensated", at.bucket(t.numel()))
+        if key not in self.keys:
+            self.recorded.append(at.tune_sum(t, out, acc, sh))
+            self.keys.add(key)
+        return R.red_get_plan(code, acc, t.numel())
+
+    def seg_plan(self, xt, ot, out, sh):
+        R, at = self.R, self.at
+        nseg = ot.numel() - 1
+        key = ("segmented", at.bucket(nseg))
+        if key not in self.keys:
+            self.recorded.append(at.tune_segmented(xt, ot, out, sh))
+            self.keys.add(key)
+        return R.red_get_segmented_plan(nseg)
 
 
-def gbps(nbytes, ms):
-    return round(nbytes / (ms * 1e-3) / 1e9, 1)
-
-
-def run_configs(R, dev, stream, path):
-    """Every workload of the study, one JSON record per measurement, written
-    to `path` (JSONL).  Timed regions hold only library calls; the oracle
-    timings and errors are the CPU-baseline leg of each record."""
+def run_configs(R, dev, stream, path, plans):
+    """Every workload of the study, one JSON record per measurement,
+    appended to `path` (JSONL).  Timed regions hold only library calls; the
+    oracle timings and errors are the CPU-baseline leg of each record."""
     import numpy as np
     import torch
 
@@ -136,15 +184,12 @@ def run_configs(R, dev, stream, path):
     from paper_2004_05371_amd import inputs
 
     sh = stream.cuda_stream
-    recs = []
+    flush = Flusher(R, sh)
 
     def emit(rec):
-        recs.append(rec)
         log(json.dumps(rec))
         with open(path, "a") as fh:
             fh.write(json.dumps(rec) + "\n")
-
-    flush = torch.empty(1 << 27, dtype=torch.float32, device="cuda")  # 512 MiB
 
     def timed(fn, reps, flushed=False):
         for _ in range(3):
@@ -159,7 +204,8 @@ def run_configs(R, dev, stream, path):
         ex = oracle.exact_sum(x, kind) if kind != "i32" else oracle.sum_i32(x)
         return ex, time.perf_counter() - c0
 
-    # -- small: 2^20 fp32 U[-1,1] and int32 U[-1000,1000], two-launch variant
+    # -- small: 2^20 fp32 U[-1,1] and int32 U[-1000,1000]; the two-launch
+    #    variant, and the tuned plan
     for kind, x in (("f32", inputs.uniform_f32(1 << 20)), ("i32", inputs.uniform_i32(1 << 20))):
         t = torch.from_numpy(x).to("cuda")
         code = R.RED_F32 if kind == "f32" else R.RED_I32
@@ -167,19 +213,22 @@ def run_configs(R, dev, stream, path):
         o = R.make_opts(variant=R.RED_VARIANT_RELAUNCH)
         fn = lambda: R.red_sum_ex(code, t.data_ptr(), t.numel(), out.data_ptr(), sh, o)
         warm, cold = timed(fn, 200), timed(fn, 50, flushed=True)
+        plan = plans.sum_plan(t, out, R.RED_ACC_COMPENSATED, sh)
+        ot = R.opts_from_plan(plan)
+        tuned = timed(lambda: R.red_sum_ex(code, t.data_ptr(), t.numel(), out.data_ptr(), sh, ot), 200)
         fn()
         torch.cuda.synchronize()
         ex, tc = cpu_exact(x, kind)
         ok = (out.item() == ex) if kind == "i32" else (oracle.rel_err(out.item(), ex) <= 1e-6)
         emit({"config": "small", "dtype": kind, "n": x.size, "variant": "relaunch", "us_warm": round(warm * 1e3, 2),
-              "us_flushed": round(cold * 1e3, 2), "GBps_warm": gbps(x.nbytes, warm), "matches_oracle": bool(ok),
-              "cpu_oracle_s": round(tc, 4)})
+              "us_flushed": round(cold * 1e3, 2), "tuned_plan": plan.as_dict(), "us_tuned": round(tuned * 1e3, 2),
+              "matches_oracle": bool(ok), "cpu_oracle_s": round(tc, 4)})
 
     # -- int: 2^26 int32, three synchronization variants, flushed and warm
     x = inputs.uniform_i32(1 << 26)
     t = torch.from_numpy(x).to("cuda")
     out = torch.empty((), dtype=torch.int64, device="cuda")
-    plan, us = R.red_autotune(R.RED_I32, 0, t.data_ptr(), t.numel(), out.data_ptr(), sh)
+    plan = plans.sum_plan(t, out, R.RED_ACC_COMPENSATED, sh)
     warm = variant_table(R, plan, R.RED_I32, t, t.numel(), out, sh, stream, dev)
     cold = variant_table(R, plan, R.RED_I32, t, t.numel(), out, sh, stream, dev, reps=30, flush=flush)
     exact, tc = cpu_exact(x, "i32")
@@ -190,7 +239,7 @@ def run_configs(R, dev, stream, path):
                                  grid=min(plan.grid or 1024, R.red_max_coresident(plan.wg))))
         torch.cuda.synchronize()
         bit_exact[R.VARIANT_NAMES[v]] = out.item() == exact
-    emit({"config": "int", "dtype": "i32", "n": x.size, "tuned_plan": plan.as_dict(), "GBps_warm": warm,
+    emit({"config": "int", "dtype": "i32", "n": x.size, "plan": plan.as_dict(), "GBps_warm": warm,
           "GBps_flushed": cold, "bit_exact": bit_exact, "cpu_oracle_s": round(tc, 4)})
     del t
 
@@ -202,7 +251,7 @@ def run_configs(R, dev, stream, path):
         ex, tc = cpu_exact(x, "f32")
         absx = float(oracle.exact_abs_sum(x, "f32").fraction)
         for acc, name in ((0, "compensated"), (1, "plain")):
-            plan, us = R.red_autotune(R.RED_F32, acc, t.data_ptr(), t.numel(), out.data_ptr(), sh)
+            plan = plans.sum_plan(t, out, acc, sh)
             o = R.opts_from_plan(plan, acc=acc)
             ms = timed(lambda: R.red_sum_ex(R.RED_F32, t.data_ptr(), t.numel(), out.data_ptr(), sh, o), 50)
             torch.cuda.synchronize()
@@ -212,7 +261,7 @@ def run_configs(R, dev, stream, path):
                   "err_over_sum_abs": abs(float(ex.fraction) - r) / absx, "cpu_oracle_s": round(tc, 3)})
         del t
 
-    # -- half: bf16 / fp16 2^29 N(0,1), compensated
+    # -- half: bf16 / fp16 2^29 N(0,1), compensated (and plain for contrast)
     for kind in ("bf16", "f16"):
         bits = inputs.normal_half_bits(1 << 29, kind)
         tdt = torch.bfloat16 if kind == "bf16" else torch.float16
@@ -222,7 +271,7 @@ def run_configs(R, dev, stream, path):
         ex, tc = cpu_exact(bits, kind)
         res = {}
         for acc, name in ((0, "compensated"), (1, "plain")):
-            plan, us = R.red_autotune(code, acc, t.data_ptr(), t.numel(), out.data_ptr(), sh)
+            plan = plans.sum_plan(t, out, acc, sh)
             o = R.opts_from_plan(plan, acc=acc)
             ms = timed(lambda: R.red_sum_ex(code, t.data_ptr(), t.numel(), out.data_ptr(), sh, o), 50)
             torch.cuda.synchronize()
@@ -239,11 +288,12 @@ def run_configs(R, dev, stream, path):
     ot = torch.from_numpy(off).to("cuda")
     nseg = off.size - 1
     out = torch.empty(nseg, dtype=torch.float64, device="cuda")
-    plan, us = R.red_autotune_segmented(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh)
+    plan = plans.seg_plan(xt, ot, out, sh)
     nbytes = x.nbytes + off.nbytes + out.numel() * 8
     ms_graph = timed(lambda: R.red_sum_segmented(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh), 30)
     o = R.make_opts(variant=R.RED_VARIANT_PERSISTENT, wg=plan.wg, ipt=plan.ipt,
-                    grid=min(plan.grid, R.red_max_coresident(plan.wg)), flags=R.FLAG_PLAIN_LAUNCH)
+                    grid=min(plan.grid, R.red_max_coresident(plan.wg)),
+                    flags=R.FLAG_PLAIN_LAUNCH | (plan.flags & R.FLAG_NONTEMPORAL))
     ms_barrier = timed(lambda: R.red_sum_segmented_ex(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh, o), 30)
     ms_loop = timed(lambda: R.red_sum_segmented_loop(xt.data_ptr(), off, nseg, out.data_ptr(), sh), 3)
     R.red_sum_segmented(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh)
@@ -273,16 +323,17 @@ def run_configs(R, dev, stream, path):
     for wg in (64, 256, 1024):
         cores = R.red_max_coresident(wg)
         n = 1
-        while n <= min(1024, cores):
-            ns, sg, wall = R.sync_bench_grid(n, wg, reps=20)
-            emit({"probe": "grid", "wg": wg, "n_wg": n, "wg_per_cu": round(n / dev["cus"], 3), "ns": round(ns, 1),
-                  "sigma_ns": round(sg, 1), "in_kernel_ns": round(wall, 1)})
+        while n <= min(2048, cores):
+            for groups in ((1, 8, 0) if n >= 64 else (1,)):
+                ns, sg, wall = R.sync_bench_grid_ex(n, wg, groups, reps=20)
+                emit({"probe": "grid", "wg": wg, "n_wg": n, "wg_per_cu": round(n / dev["cus"], 3),
+                      "groups": groups or "default", "ns": round(ns, 1), "sigma_ns": round(sg, 1),
+                      "in_kernel_ns": round(wall, 1)})
             n *= 2
     for coop in (False, True):
         ns, sg, null_ns = R.sync_bench_relaunch(dev["cus"], 256, cooperative=coop, reps=30)
         emit({"probe": "relaunch", "cooperative": coop, "overhead_ns": round(ns, 1), "sigma_ns": round(sg, 1),
               "null_kernel_total_ns": round(null_ns, 1)})
-    return recs
 
 
 def main():
@@ -294,16 +345,19 @@ def main():
     ap.add_argument("--no-probes", action="store_true")
     ap.add_argument("--configs", metavar="JSONL", help="also measure every workload and probe sweep into JSONL")
     ap.add_argument("--only-configs", action="store_true", help="skip the headline (with --configs)")
+    ap.add_argument("--retune", action="store_true", help="ignore the plan cache and autotune")
+    ap.add_argument("--save-plans", metavar="JSON", help="write the plans tuned in this run")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the headline, copy the 1 GiB input 3 times (byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
-    from paper_2004_05371_amd import inputs, redsum as R
+    from paper_2004_05371_amd import autotune, inputs, redsum as R
 
     R.load()
     torch.cuda.set_device(0)
@@ -311,12 +365,20 @@ def main():
     dev = R.red_device_info()
     stream = torch.cuda.current_stream()
     sh = stream.cuda_stream
-    log("device", dev)
+    plans = Plans(R, args.retune)
+    log("device", dev, "cached plans installed:", plans.installed)
 
     if args.configs:
-        run_configs(R, dev, stream, args.configs)
-        if args.only_configs:
-            return
+        run_configs(R, dev, stream, args.configs, plans)
+    if not args.only_configs:
+        headline(args, R, dev, stream, sh, plans, inputs)
+    if args.save_plans and plans.recorded:
+        autotune.save(plans.recorded, args.save_plans, cus=dev["cus"])
+        log("saved %d plans to %s" % (len(plans.recorded), args.save_plans))
+
+
+def headline(args, R, dev, stream, sh, plans, inputs):
+    import torch
 
     # ---- input, resident in HBM before timing
     t0 = time.time()
@@ -327,9 +389,8 @@ def main():
     log("input ready in %.1f s" % (time.time() - t0))
     nbytes = N * 4
 
-    # ---- autotune the plan for this workload
-    plan, tuned_us = R.red_autotune(R.RED_F32, R.RED_ACC_COMPENSATED, xt.data_ptr(), N, out.data_ptr(), sh)
-    log("tuned plan", plan.as_dict(), "%.1f us" % tuned_us)
+    plan = plans.sum_plan(xt, out, R.RED_ACC_COMPENSATED, sh)
+    log("plan", plan.as_dict())
     opts = R.opts_from_plan(plan, acc=R.RED_ACC_COMPENSATED)
 
     def step():
@@ -337,34 +398,55 @@ def main():
 
     for _ in range(args.warmup):
         step()
+    # Timed region: K steps between two synchronizations, with the library
+    # recording HIP events around the dominant kernel of every step (on the
+    # stream it runs on) for the roofline.
     torch.cuda.synchronize()
-    times, wall = time_steps(step, args.steps, stream)
+    R.red_kernel_timer(sh, True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    k_mean_us, k_min_us, k_count = R.red_kernel_timer_read(sh)
+    R.red_kernel_timer(sh, False)
     ms_per_step = wall * 1e3 / args.steps
-    mean_ms = statistics.fmean(times)
-    gbps = nbytes / (ms_per_step * 1e-3) / 1e9
-    kernel_gbps = nbytes / (mean_ms * 1e-3) / 1e9
+    value = nbytes / (ms_per_step * 1e-3) / 1e9
     result = out.item()
-    log("steps: wall %.3f ms/step, event mean %.3f ms, median %.3f ms" %
-        (ms_per_step, mean_ms, statistics.median(times)))
+    kernel_gbps = nbytes / (k_mean_us * 1e-6) / 1e9
+    # The same loop without the dominant-kernel events, and with per-step
+    # events (for reference only).
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall_plain = time.perf_counter() - t0
+    times, _ = time_steps(step, args.steps, stream)
+    log("steps: wall %.4f ms/step (%.4f without kernel events), step events mean %.4f ms; "
+        "dominant kernel mean %.2f us (min %.2f, %d launches)" %
+        (ms_per_step, wall_plain * 1e3 / args.steps, statistics.fmean(times), k_mean_us, k_min_us, k_count))
 
-    extra = {}
-    # ---- other variants / accumulation (a few steps each)
+    extra = {"GBps_without_kernel_events": round(nbytes / (wall_plain / args.steps) / 1e9, 1),
+             "step_event_mean_us": round(statistics.fmean(times) * 1e3, 2),
+             "dominant_kernel_mean_us": round(k_mean_us, 2), "dominant_kernel_min_us": round(k_min_us, 2)}
     extra["variants_GBps"] = variant_table(R, plan, R.RED_F32, xt, N, out, sh, stream, dev)
     o = R.opts_from_plan(plan, acc=R.RED_ACC_PLAIN)
     tt, _ = time_steps(lambda: R.red_sum_ex(R.RED_F32, xt.data_ptr(), N, out.data_ptr(), sh, o), 50, stream)
-    extra["plain_fp32_GBps"] = round(nbytes / (statistics.median(tt) * 1e-3) / 1e9, 1)
-    # read-only ceiling (bandwidth proxy)
-    g = 4 * dev["cus"]
-    tt, _ = time_steps(lambda: R.red_bw_proxy(xt.data_ptr(), nbytes, g, 512, sh), 50, stream)
-    extra["bw_proxy_GBps"] = round(nbytes / (statistics.median(tt) * 1e-3) / 1e9, 1)
+    extra["plain_fp32_GBps"] = gbps(nbytes, statistics.median(tt))
+    tt, _ = time_steps(lambda: R.red_bw_proxy(xt.data_ptr(), nbytes, 1024, 512, sh), 50, stream)
+    extra["bw_proxy_GBps"] = gbps(nbytes, statistics.median(tt))
 
     # ---- synchronization latencies (ns)
     if not args.no_probes:
         cus = dev["cus"]
         gb = {}
-        for n_wg in (cus, 2 * cus):
-            ns, sg, wall_ns = R.sync_bench_grid(min(n_wg, R.red_max_coresident(256)), 256, reps=20)
-            gb[str(n_wg)] = {"ns": round(ns, 1), "sigma_ns": round(sg, 1), "in_kernel_ns": round(wall_ns, 1)}
+        for n_wg in (cus, 4 * cus):
+            n = min(n_wg, R.red_max_coresident(256))
+            for groups, name in ((1, "flat"), (0, "two_level")):
+                ns, sg, wall_ns = R.sync_bench_grid_ex(n, 256, groups, reps=20)
+                gb["%d_wg_%s" % (n, name)] = {"ns": round(ns, 1), "sigma_ns": round(sg, 1),
+                                              "in_kernel_ns": round(wall_ns, 1)}
         ro, ro_sg, null_ns = R.sync_bench_relaunch(cus, 256, cooperative=False, reps=20)
         rc, rc_sg, null_c = R.sync_bench_relaunch(cus, 256, cooperative=True, reps=20)
         extra["grid_barrier_ns"] = gb
@@ -373,7 +455,7 @@ def main():
                                          "null_kernel_total_ns": round(null_ns, 1),
                                          "null_kernel_total_coop_ns": round(null_c, 1)}
 
-    # ---- correctness of the timed result and the CPU oracle baseline
+    # ---- CPU baseline: the oracle on the same input (and the result's error)
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -386,14 +468,14 @@ def main():
         t_cpu = statistics.median(ts)
         extra["rel_err_vs_exact"] = oracle.rel_err(result, ex)
         cpu = {"value": round(nbytes / t_cpu / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": "the full 2^28-element fp32 input, exact exponent-binned sum (median of 3 runs, "
-                         "%.2f s each)" % t_cpu}
+               "sample": "the full 2^28-element fp32 input (1 GiB), exact exponent-binned sum, "
+                         "single thread, median of 3 runs of %.2f s" % t_cpu}
 
     roof = {"bound": "hbm", "achieved": round(kernel_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": round(kernel_gbps / HBM_PEAK_GBPS, 4), "traffic": traffic_per_launch()}
+            "frac": round(kernel_gbps / HBM_PEAK_GBPS, 4), "traffic": traffic_per_launch(plan.as_dict())}
     rec = {
         "metric": METRIC,
-        "value": round(gbps, 1),
+        "value": round(value, 1),
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -406,12 +488,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": "fp32 sum of 2^28 N(0,1) values (1 GiB), compensated fp32 + fp64 final combine",
                    "n": N, "bytes": nbytes, "plan": plan.as_dict()},
-        "pct_hbm_peak": round(100.0 * gbps / HBM_PEAK_GBPS, 2),
+        "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBPS, 2),
         "roofline": roof,
         "cpu_baseline": cpu,
         "extra": extra,
     }
     print(json.dumps(rec), flush=True)
+    if args.calibrate_copy:
+        y = torch.empty_like(xt)
+        for _ in range(3):
+            y.copy_(xt)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

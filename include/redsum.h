@@ -215,8 +215,13 @@ int red_get_plan(int dtype, int acc, int64_t n, red_plan *plan);
 int red_autotune(int dtype, int acc, const void *x, int64_t n, void *out, void *stream, int budget,
                  red_plan *best, double *best_us);
 
+/* Install / read the plan of segmented batches whose nseg has the same
+ * bit length as `nseg` (variant RED_VARIANT_ATOMIC or _PERSISTENT). */
+int red_set_segmented_plan(int64_t nseg, const red_plan *plan);
+int red_get_segmented_plan(int64_t nseg, red_plan *plan);
+
 /* Autotune the segmented kernel on the caller's batch (synchronous) and
- * install the best plan for batches of this nseg and total-size bucket. */
+ * install the best plan for batches with the same nseg bit length. */
 int red_autotune_segmented(const float *x, const int64_t *offsets, int64_t nseg, double *out,
                            void *stream, int budget, red_plan *best, double *best_us);
 
@@ -244,6 +249,13 @@ int sync_bench_block(int wg_size, int n_wg, int reps, double *ns, double *sigma_
  * wg_size threads (n_wg must be co-resident: RED_EINVAL otherwise). */
 int sync_bench_grid(int n_wg, int wg_size, int reps, double *ns, double *sigma_ns, double *cycles,
                     void *stream);
+
+/* sync_bench_grid with an explicit barrier shape: groups = 1 is the flat
+ * centralized barrier, groups = 2..32 the two-level barrier whose first
+ * level counts the workgroups with blockIdx % groups equal, 0 the default
+ * policy (flat below 64 workgroups, else about 64 members per group). */
+int sync_bench_grid_ex(int n_wg, int wg_size, int groups, int reps, double *ns, double *sigma_ns,
+                       double *cycles, void *stream);
 
 /* Launch overhead of a kernel boundary (the implicit barrier) by kernel
  * fusion, Eq. 6, with (i, j) = (8, 1) launches of n_wg x wg_size kernels
@@ -278,6 +290,16 @@ int red_device_info(int32_t *cus, int64_t *wallclock_khz, int64_t *clock_khz, in
 /* ---------------------------------------------------------------------
  * Measurement helpers (not part of a reduction)
  * ------------------------------------------------------------------- */
+
+/* While enabled on `stream`, every reduction / segmented launch on it
+ * records a pair of HIP events around its dominant streaming kernel (the
+ * partials kernel of the relaunch variant, the single kernel otherwise).
+ * Enabling clears earlier records.  Not recorded inside stream capture. */
+int red_kernel_timer(void *stream, int enable);
+
+/* Synchronize `stream` and report the timed launches: mean and minimum
+ * duration in microseconds and their number (any pointer may be NULL). */
+int red_kernel_timer_read(void *stream, double *mean_us, double *min_us, int64_t *count);
 
 /* Read-only bandwidth ceiling (Section VII-B bandwidth proxy): a
  * grid-stride read of nbytes of x (16-byte aligned) with 16-byte loads

@@ -370,55 +370,83 @@ __device__ __forceinline__ Vec load_vec(const Vec* p) {
 // Workspace words of one (device, stream).  Each word that is polled or hit
 // by atomics sits on its own 128-byte line.
 // ---------------------------------------------------------------------------
+constexpr int kMaxBarrierGroups = 32;
+
 struct alignas(128) Line {
   unsigned v;
   unsigned pad[31];
 };
 struct BarrierWords {
-  Line count;   // arrivals at the current grid barrier
+  Line count;   // arrivals at the current grid barrier (top level)
   Line gen;     // grid-barrier generation (incremented by the last arrival)
   Line ticket;  // atomic-final variant: workgroups that have stored a partial
   Line err;     // watchdog flag (nonzero after a timeout)
   Line acc_lo;  // atomic-final int accumulator (int64 in acc_lo.v/acc_lo.pad[0])
+  Line group[kMaxBarrierGroups];  // arrivals per group (two-level barrier)
 };
 
 __device__ __forceinline__ long long* acc_i64(BarrierWords* w) {
   return reinterpret_cast<long long*>(&w->acc_lo.v);
 }
 
+__device__ __forceinline__ unsigned relaxed_add(unsigned* p, unsigned v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---------------------------------------------------------------------------
 // Grid barrier for a launch of `nblocks` co-resident workgroups.
 //
-// Centralized sense-reversing barrier.  Thread 0 of each workgroup:
+// Sense-reversing barrier with an optional second level.  Thread 0 of each
+// workgroup:
 //   1. reads the generation g (relaxed);
 //   2. release fence at agent (device) scope -- one L2 write-back that makes
 //      the workgroup's earlier global stores visible across the XCDs'
-//      separate L2 caches -- then a relaxed atomic increment of the arrival
-//      counter;
-//   3. the last arrival resets the counter, fences (release) and bumps the
-//      generation; the others poll the generation with relaxed device-scope
-//      loads (s_sleep between polls, so polling neither invalidates the L2
-//      nor floods the memory-side atomic unit);
+//      separate L2 caches -- then a relaxed increment of an arrival counter:
+//        groups <= 1 : the single counter (flat, centralized barrier);
+//        groups  > 1 : the counter of group (blockIdx.x % groups); the last
+//                      arrival of a group acquires its members' releases,
+//                      releases them onward and increments the top counter
+//                      (so at most nblocks / groups arrivals serialize on
+//                      one counter; with groups a multiple of 8 every group
+//                      lies on one XCD under round-robin dispatch);
+//   3. the last top-level arrival resets the counter, acquires, releases and
+//      bumps the generation; the others poll the generation with relaxed
+//      device-scope loads (s_sleep between polls, so polling neither
+//      invalidates the L2 nor floods the atomic unit);
 //   4. one acquire fence after the wait.
-// Fence-to-fence synchronization through the relaxed counter / generation
-// operations orders every workgroup's stores before every workgroup's loads
-// after the barrier.  The poll is bounded by `spin_limit`: on expiry the
-// workgroup sets the error word and leaves, so the kernel always ends (a grid
-// in which not every block arrives deadlocks, Section VIII-B of the paper).
-// Returns false on timeout.
+// Each hop is a release fence / relaxed RMW / acquire fence chain, so every
+// workgroup's stores happen before every workgroup's loads after the
+// barrier.  The poll is bounded by `spin_limit`: on expiry the workgroup sets
+// the error word and leaves, so the kernel always ends (a grid in which not
+// every block arrives deadlocks, Section VIII-B of the paper).  Counters are
+// back at zero after every completed barrier.  Returns false on timeout.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool grid_barrier(BarrierWords* w, unsigned nblocks, unsigned spin_limit) {
+__device__ __forceinline__ bool grid_barrier(BarrierWords* w, unsigned nblocks, unsigned groups,
+                                             unsigned spin_limit) {
   __shared__ int timed_out;
   __syncthreads();
   if (threadIdx.x == 0) {
     int to = 0;
     const unsigned g = __hip_atomic_load(&w->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const unsigned old = __hip_atomic_fetch_add(&w->count.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (old == nblocks - 1) {
+    bool last;
+    if (groups <= 1) {
+      last = relaxed_add(&w->count.v, 1u) == nblocks - 1;
+    } else {
+      const unsigned grp = blockIdx.x % groups;
+      const unsigned members = (nblocks - grp + groups - 1) / groups;
+      const unsigned active = nblocks < groups ? nblocks : groups;
+      last = false;
+      if (relaxed_add(&w->group[grp].v, 1u) == members - 1) {
+        __hip_atomic_store(&w->group[grp].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        last = relaxed_add(&w->count.v, 1u) == active - 1;
+      }
+    }
+    if (last) {
       __hip_atomic_store(&w->count.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      __hip_atomic_fetch_add(&w->gen.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+      relaxed_add(&w->gen.v, 1u);
     } else {
       unsigned spins = 0;
       while (__hip_atomic_load(&w->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
@@ -435,6 +463,15 @@ __device__ __forceinline__ bool grid_barrier(BarrierWords* w, unsigned nblocks, 
   }
   __syncthreads();
   return timed_out == 0;
+}
+
+// Default number of barrier groups for a grid of n workgroups: flat below
+// 64 workgroups, else a multiple of 8 (whole XCDs) giving about 64 members
+// per group, between 8 and kMaxBarrierGroups.
+__host__ __device__ inline unsigned default_barrier_groups(unsigned n) {
+  if (n < 64) return 1u;
+  unsigned g = ((n / 64 + 7) / 8) * 8;  // about 64 members per group
+  return g < 8u ? 8u : (g > (unsigned)kMaxBarrierGroups ? (unsigned)kMaxBarrierGroups : g);
 }
 
 }  // namespace redsum

@@ -32,18 +32,22 @@ struct Workspace {
   void* base = nullptr;
   BarrierWords* words = nullptr;   // barrier / ticket / error words
   void* partials = nullptr;        // RED_MAX_GRID x 8 bytes
-  SegCarry* carry_in = nullptr;    // RED_MAX_GRID slots
-  SegCarry* carry_out = nullptr;   // RED_MAX_GRID slots
-  unsigned* seg_tickets = nullptr; // RED_MAX_GRID counters
+  SegCarry* carry_in = nullptr;    // kMaxChunks slots
+  SegCarry* carry_out = nullptr;   // kMaxChunks slots
+  unsigned* seg_tickets = nullptr; // kMaxChunks counters
   unsigned* sink = nullptr;        // RED_MAX_GRID words for probes
   long long* stamps = nullptr;     // 2 x RED_MAX_GRID timestamps for probes
 };
 
+// Segmented batches are cut into at most this many chunks (carry slots and
+// tickets per chunk).
+constexpr int64_t kMaxChunks = 65536;
+
 // Workspace layout sizes.
-constexpr size_t kWordsBytes = 4096;
+constexpr size_t kWordsBytes = 8192;
 constexpr size_t kPartialBytes = (size_t)RED_MAX_GRID * 8;
-constexpr size_t kCarryBytes = (size_t)RED_MAX_GRID * sizeof(SegCarry);
-constexpr size_t kTicketBytes = (size_t)RED_MAX_GRID * 4;
+constexpr size_t kCarryBytes = (size_t)kMaxChunks * sizeof(SegCarry);
+constexpr size_t kTicketBytes = (size_t)kMaxChunks * 4;
 constexpr size_t kSinkBytes = (size_t)RED_MAX_GRID * 4;
 constexpr size_t kStampBytes = (size_t)RED_MAX_GRID * 16;
 constexpr size_t kWorkspaceBytes =
@@ -63,6 +67,12 @@ int ensure_device(const DeviceInfo** info);  // current device, initialized
 int get_workspace(hipStream_t s, Workspace** ws);  // allocates outside capture
 bool stream_capturing(hipStream_t s);
 unsigned watchdog_spins();
+unsigned barrier_groups(int grid);  // REDSUM_BARRIER_GROUPS, else the default policy
+
+// Dominant-kernel timer: timer_begin returns a slot (or -1 when the timer
+// is off / the stream is capturing), timer_end closes it.
+int timer_begin(hipStream_t s);
+void timer_end(hipStream_t s, int slot);
 
 // Kernel launch (uniform signature: one argument struct by value).
 int launch(const void* fn, int grid, int block, void** args, hipStream_t s, bool cooperative);

@@ -63,11 +63,11 @@ __global__ __launch_bounds__(1024) void k_block_chain(int r, long long* cycles) 
   if (threadIdx.x == 0) cycles[blockIdx.x] = t1 - t0;
 }
 
-__global__ __launch_bounds__(1024) void k_grid_chain(int r, BarrierWords* w, unsigned spin_limit,
-                                                    long long* stamps) {
+__global__ __launch_bounds__(1024) void k_grid_chain(int r, BarrierWords* w, unsigned groups,
+                                                    unsigned spin_limit, long long* stamps) {
   __syncthreads();
   const long long t0 = __builtin_amdgcn_s_memrealtime();
-  for (int i = 0; i < r; ++i) grid_barrier(w, gridDim.x, spin_limit);
+  for (int i = 0; i < r; ++i) grid_barrier(w, gridDim.x, groups, spin_limit);
   const long long t1 = __builtin_amdgcn_s_memrealtime();
   if (blockIdx.x == 0 && threadIdx.x == 0) stamps[0] = t1 - t0;
 }
@@ -80,18 +80,19 @@ __global__ __launch_bounds__(1024) void k_spin(long long ticks) {
   while (__builtin_amdgcn_s_memrealtime() - t0 < ticks) __builtin_amdgcn_s_sleep(2);
 }
 
-__global__ __launch_bounds__(1024) void k_grid_order(BarrierWords* w, unsigned spin_limit,
+__global__ __launch_bounds__(1024) void k_grid_order(BarrierWords* w, unsigned groups, unsigned spin_limit,
                                                     long long* before, long long* after) {
   __syncthreads();
   if (threadIdx.x == 0) before[blockIdx.x] = __builtin_amdgcn_s_memrealtime();
-  grid_barrier(w, gridDim.x, spin_limit);
+  grid_barrier(w, gridDim.x, groups, spin_limit);
   if (threadIdx.x == 0) after[blockIdx.x] = __builtin_amdgcn_s_memrealtime();
 }
 
 // Workgroup `skip` never arrives; the others leave through the watchdog.
-__global__ __launch_bounds__(1024) void k_watchdog(BarrierWords* w, int skip, unsigned spin_limit) {
+__global__ __launch_bounds__(1024) void k_watchdog(BarrierWords* w, int skip, unsigned groups,
+                                                  unsigned spin_limit) {
   if ((int)blockIdx.x == skip) return;
-  grid_barrier(w, gridDim.x, spin_limit);
+  grid_barrier(w, gridDim.x, groups, spin_limit);
 }
 
 __global__ void k_reset_words(BarrierWords* w) {
@@ -101,6 +102,7 @@ __global__ void k_reset_words(BarrierWords* w) {
     w->ticket.v = 0;
     w->err.v = 0;
     *acc_i64(w) = 0;
+    for (int i = 0; i < kMaxBarrierGroups; ++i) w->group[i].v = 0;
   }
 }
 
@@ -136,8 +138,8 @@ struct Events {
     if (b) (void)hipEventDestroy(b);
   }
   int init() {
-    RED_HIP(hipEventCreate(&a));
-    RED_HIP(hipEventCreate(&b));
+    RED_HIP(hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
+    RED_HIP(hipEventCreateWithFlags(&b, hipEventDisableSystemFence));
     return RED_OK;
   }
 };
@@ -324,10 +326,11 @@ int sync_bench_block(int wg_size, int n_wg, int reps, double* ns, double* sigma_
       20.0, 1 << 22, ns, sigma_ns, cycles);
 }
 
-int sync_bench_grid(int n_wg, int wg_size, int reps, double* ns, double* sigma_ns, double* cycles,
-                    void* stream) {
+int sync_bench_grid_ex(int n_wg, int wg_size, int groups, int reps, double* ns, double* sigma_ns,
+                       double* cycles, void* stream) {
   if (wg_size < 64 || wg_size > 1024 || wg_size % 64) return set_error(RED_EINVAL, "bad wg_size %d", wg_size);
   if (n_wg < 1 || n_wg > RED_MAX_GRID) return set_error(RED_EINVAL, "bad n_wg %d", n_wg);
+  if (groups < 0 || groups > kMaxBarrierGroups) return set_error(RED_EINVAL, "bad groups %d", groups);
   if (reps < 2 || !ns || !sigma_ns) return set_error(RED_EINVAL, "reps >= 2 and non-null outputs required");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const DeviceInfo* dev;
@@ -343,9 +346,10 @@ int sync_bench_grid(int n_wg, int wg_size, int reps, double* ns, double* sigma_n
   if ((rc = reset_words(ws, s))) return rc;
   int r = 0;
   BarrierWords* w = ws->words;
+  unsigned grp = groups > 0 ? (unsigned)groups : barrier_groups(n_wg);
   unsigned spin = watchdog_spins();
   long long* st = ws->stamps;
-  void* args[] = {&r, &w, &spin, &st};
+  void* args[] = {&r, &w, &grp, &spin, &st};
   const double tick_ns = 1e6 / (double)dev->wallclock_khz;
   rc = differential(
       fn, n_wg, wg_size, args, true, reps, s, [&](int64_t v) { r = (int)v; },
@@ -363,6 +367,11 @@ int sync_bench_grid(int n_wg, int wg_size, int reps, double* ns, double* sigma_n
     return set_error(RED_ETIMEOUT, "grid probe: barrier watchdog fired");
   }
   return RED_OK;
+}
+
+int sync_bench_grid(int n_wg, int wg_size, int reps, double* ns, double* sigma_ns, double* cycles,
+                    void* stream) {
+  return sync_bench_grid_ex(n_wg, wg_size, 0, reps, ns, sigma_ns, cycles, stream);
 }
 
 int sync_bench_relaunch(int n_wg, int wg_size, int cooperative, int reps, double* ns, double* sigma_ns,
@@ -442,10 +451,11 @@ int sync_check_grid_order(int n_wg, int wg_size, int64_t* max_before, int64_t* m
   if (n_wg > maxg) return set_error(RED_EINVAL, "order check: grid too large (max %d)", maxg);
   if ((rc = reset_words(ws, s))) return rc;
   BarrierWords* w = ws->words;
+  unsigned grp = barrier_groups(n_wg);
   unsigned spin = watchdog_spins();
   long long* before = ws->stamps;
   long long* after = ws->stamps + RED_MAX_GRID;
-  void* args[] = {&w, &spin, &before, &after};
+  void* args[] = {&w, &grp, &spin, &before, &after};
   if ((rc = launch(fn, n_wg, wg_size, args, s, true))) return rc;
   RED_HIP(hipStreamSynchronize(s));
   std::vector<long long> hb(n_wg), ha(n_wg);
@@ -478,8 +488,9 @@ int sync_check_watchdog(int n_wg, int wg_size, int skip_wg, int spin_limit, void
   if (n_wg > maxg) return set_error(RED_EINVAL, "watchdog check: grid too large (max %d)", maxg);
   if ((rc = reset_words(ws, s))) return rc;
   BarrierWords* w = ws->words;
+  unsigned grp = barrier_groups(n_wg);
   unsigned spin = (unsigned)spin_limit;
-  void* args[] = {&w, &skip_wg, &spin};
+  void* args[] = {&w, &skip_wg, &grp, &spin};
   if ((rc = launch(fn, n_wg, wg_size, args, s, true))) return rc;
   return red_check_error(stream);
 }

@@ -33,6 +33,7 @@ struct ReduceArgs {
   BarrierWords* words;
   void* out;      // one Part
   unsigned spin_limit;
+  unsigned bar_groups;  // grid-barrier groups (persistent variant)
 };
 
 // Per-thread accumulation of this thread's grid-stride share.  The vector
@@ -117,6 +118,18 @@ __global__ __launch_bounds__(1024) void k_final(const Part* partials, int count,
   if (threadIdx.x == 0) *out = s;
 }
 
+// One-wavefront final combine (no LDS, no barrier): lane l sums partials
+// l, l + 64, ... in order, then the DPP wavefront combine.
+template <class Part>
+__global__ __launch_bounds__(64) void k_final_wave(const Part* partials, int count, Part* out) {
+  using Op = typename PartOp<Part>::type;
+  Part s = Op::zero();
+#pragma unroll 8
+  for (int i = threadIdx.x; i < count; i += kWave) s = Op::add(s, partials[i]);
+  s = wave_reduce_dpp<Op>(s);
+  if (threadIdx.x == 0) *out = s;
+}
+
 // ---------------------------------------------------------------------------
 // Variant 2, one kernel with an atomic ticket: each workgroup publishes its
 // partial (int: atomic int64 add into one word; float: its partial slot),
@@ -171,7 +184,7 @@ __global__ __launch_bounds__(1024) void k_persistent(ReduceArgs a) {
   using Part = typename M::Part;
   Part p = workgroup_partial<M, IPT, NT>(a);
   if (threadIdx.x == 0) static_cast<Part*>(a.partials)[blockIdx.x] = p;
-  grid_barrier(a.words, gridDim.x, a.spin_limit);
+  grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit);
   if (blockIdx.x != 0) return;
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   Part s = combine_partials<Part>(static_cast<const Part*>(a.partials), gridDim.x);
@@ -269,16 +282,17 @@ int validate_plan(const red_plan& p) {
   return RED_OK;
 }
 
+// Default shape (measured on MI355X): 256 threads x 4 loads of 16 bytes,
+// two workgroups per CU (32 KiB in flight per CU), nontemporal loads.
 red_plan default_plan(int dtype, int64_t n, const DeviceInfo& dev) {
   (void)dtype;
   (void)n;
   red_plan p;
   p.variant = RED_VARIANT_RELAUNCH;
-  p.wg = 512;
+  p.wg = 256;
   p.ipt = 4;
-  p.grid = 0;  // automatic: bounded by the work and by 4 workgroups per CU
-  p.flags = 0;
-  (void)dev;
+  p.grid = 2 * dev.cus;  // capped by the work at launch
+  p.flags = RED_FLAG_NONTEMPORAL;
   return p;
 }
 
@@ -317,6 +331,7 @@ int reduce_launch(const ReduceLaunch& rl, const void* x, int64_t n, void* out, W
   a.words = ws->words;
   a.out = out;
   a.spin_limit = watchdog_spins();
+  a.bar_groups = 1;
 
   const red_plan& p = rl.plan;
   const int ii = ipt_index(p.ipt);
@@ -327,26 +342,32 @@ int reduce_launch(const ReduceLaunch& rl, const void* x, int64_t n, void* out, W
   // variant).
   const int64_t tile = (int64_t)p.wg * p.ipt;
   int64_t want = std::max<int64_t>(1, (a.nvec + tile - 1) / tile);
-  int grid = p.grid > 0 ? p.grid : (int)std::min<int64_t>(want, 4LL * dev.cus);
+  int grid = (int)std::min<int64_t>(want, p.grid > 0 ? (int64_t)p.grid : 4LL * dev.cus);
   grid = std::max(1, std::min(grid, RED_MAX_GRID));
   void* args[] = {&a};
   switch (p.variant) {
     case RED_VARIANT_RELAUNCH: {
+      const int slot = timer_begin(s);
       int rc = launch(ks.partials, grid, p.wg, args, s, false);
+      timer_end(s, slot);
       if (rc) return rc;
-      if (is_int) {
-        const long long* part = static_cast<const long long*>(ws->partials);
-        long long* o = static_cast<long long*>(out);
-        void* fargs[] = {&part, &grid, &o};
-        return launch(reinterpret_cast<const void*>(&k_final<long long>), 1, kFinalWG, fargs, s, false);
-      }
-      const double* part = static_cast<const double*>(ws->partials);
-      double* o = static_cast<double*>(out);
-      void* fargs[] = {&part, &grid, &o};
-      return launch(reinterpret_cast<const void*>(&k_final<double>), 1, kFinalWG, fargs, s, false);
+      // Up to 1024 partials: one wavefront (at most 16 loads per lane);
+      // beyond: one 256-thread workgroup.
+      const bool wave = grid <= 1024;
+      void* part = ws->partials;
+      void* fargs[] = {&part, &grid, &out};
+      const void* fn = is_int ? (wave ? reinterpret_cast<const void*>(&k_final_wave<long long>)
+                                      : reinterpret_cast<const void*>(&k_final<long long>))
+                              : (wave ? reinterpret_cast<const void*>(&k_final_wave<double>)
+                                      : reinterpret_cast<const void*>(&k_final<double>));
+      return launch(fn, 1, wave ? kWave : kFinalWG, fargs, s, false);
     }
-    case RED_VARIANT_ATOMIC:
-      return launch(ks.atomic, grid, p.wg, args, s, false);
+    case RED_VARIANT_ATOMIC: {
+      const int slot = timer_begin(s);
+      int rc = launch(ks.atomic, grid, p.wg, args, s, false);
+      timer_end(s, slot);
+      return rc;
+    }
     case RED_VARIANT_PERSISTENT: {
       int maxg = 0;
       int rc = reduce_max_coresident(rl.dtype, rl.acc, p.ipt, nt, p.wg, dev, &maxg);
@@ -356,7 +377,11 @@ int reduce_launch(const ReduceLaunch& rl, const void* x, int64_t n, void* out, W
                          p.grid, maxg);
       grid = std::min(grid, maxg);
       if (grid < 1) return set_error(RED_EINVAL, "persistent kernel cannot be resident");
-      return launch(ks.persistent, grid, p.wg, args, s, (p.flags & RED_FLAG_PLAIN_LAUNCH) == 0);
+      a.bar_groups = barrier_groups(grid);
+      const int slot = timer_begin(s);
+      rc = launch(ks.persistent, grid, p.wg, args, s, (p.flags & RED_FLAG_PLAIN_LAUNCH) == 0);
+      timer_end(s, slot);
+      return rc;
     }
   }
   return set_error(RED_EINVAL, "unknown variant %d", p.variant);

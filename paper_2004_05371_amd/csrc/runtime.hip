@@ -89,6 +89,15 @@ unsigned watchdog_spins() {
   return v;
 }
 
+unsigned barrier_groups(int grid) {
+  static int forced = [] {
+    const char* e = getenv("REDSUM_BARRIER_GROUPS");
+    int x = e ? atoi(e) : 0;
+    return (x >= 1 && x <= kMaxBarrierGroups) ? x : 0;
+  }();
+  return forced ? (unsigned)forced : default_barrier_groups((unsigned)grid);
+}
+
 bool stream_capturing(hipStream_t s) {
   if (!s) return false;
   hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
@@ -172,6 +181,53 @@ int get_workspace(hipStream_t s, Workspace** out) {
   auto r = g_ws.emplace(key, w);
   *out = &r.first->second;
   return RED_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Dominant-kernel timer
+// ---------------------------------------------------------------------------
+namespace {
+struct KernelTimer {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  size_t used = 0;
+};
+std::map<std::pair<int, hipStream_t>, KernelTimer> g_timers;
+}  // namespace
+
+int timer_begin(hipStream_t s) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_timers.find(std::make_pair(dev, s));
+  if (it == g_timers.end() || !it->second.on) return -1;
+  if (stream_capturing(s)) return -1;
+  KernelTimer& t = it->second;
+  if (t.used == t.ev.size()) {
+    hipEvent_t a, b;
+    if (hipEventCreateWithFlags(&a, hipEventDisableSystemFence) != hipSuccess) return -1;
+    if (hipEventCreateWithFlags(&b, hipEventDisableSystemFence) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return -1;
+    }
+    t.ev.emplace_back(a, b);
+  }
+  const int slot = (int)t.used++;
+  if (hipEventRecord(t.ev[slot].first, s) != hipSuccess) {
+    --t.used;
+    return -1;
+  }
+  return slot;
+}
+
+void timer_end(hipStream_t s, int slot) {
+  if (slot < 0) return;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_timers.find(std::make_pair(dev, s));
+  if (it == g_timers.end() || (size_t)slot >= it->second.ev.size()) return;
+  (void)hipEventRecord(it->second.ev[slot].second, s);
 }
 
 int launch(const void* fn, int grid, int block, void** args, hipStream_t s, bool cooperative) {
@@ -413,7 +469,7 @@ int red_device_info(int32_t* cus, int64_t* wallclock_khz, int64_t* clock_khz, in
   return RED_OK;
 }
 
-// Times `plan` on the caller's data: 2 warm-up calls, then the median of 5
+// Times `plan` on the caller's data: 3 warm-up calls, then the median of 10
 // calls bracketed by events.
 static int time_plan(int dtype, int acc, const red_plan& plan, const void* x, int64_t n, void* out,
                      hipStream_t s, double* us) {
@@ -422,18 +478,18 @@ static int time_plan(int dtype, int acc, const red_plan& plan, const void* x, in
   o.plan = plan;
   o.acc = acc;
   hipEvent_t a, b;
-  RED_HIP(hipEventCreate(&a));
-  RED_HIP(hipEventCreate(&b));
+  RED_HIP(hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
+  RED_HIP(hipEventCreateWithFlags(&b, hipEventDisableSystemFence));
   std::vector<double> t;
   int rc = RED_OK;
-  for (int i = 0; i < 7 && rc == RED_OK; ++i) {
+  for (int i = 0; i < 13 && rc == RED_OK; ++i) {
     if (hipEventRecord(a, s) != hipSuccess) rc = set_error(RED_EHIP, "hipEventRecord");
     if (!rc) rc = red_sum_ex(dtype, x, n, out, s, &o);
     if (!rc && hipEventRecord(b, s) != hipSuccess) rc = set_error(RED_EHIP, "hipEventRecord");
     if (!rc && hipEventSynchronize(b) != hipSuccess) rc = set_error(RED_EHIP, "hipEventSynchronize");
     float ms = 0;
     if (!rc && hipEventElapsedTime(&ms, a, b) != hipSuccess) rc = set_error(RED_EHIP, "hipEventElapsedTime");
-    if (!rc && i >= 2) t.push_back(ms * 1e3);
+    if (!rc && i >= 3) t.push_back(ms * 1e3);
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
@@ -453,19 +509,22 @@ int red_autotune(int dtype, int acc, const void* x, int64_t n, void* out, void* 
   if ((rc = ensure_device(&dev))) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (stream_capturing(s)) return set_error(RED_EINVAL, "autotuning cannot run inside stream capture");
-  // Coordinate search: (wg, ipt) with the relaunch variant and automatic
-  // grid, then the grid size, then the variant.  `budget` caps the number
-  // of timed candidates (0 = no cap).
+  // Search: (1) nontemporal hint on the default shape; (2) every
+  // (wg, ipt, grid) of the relaunch variant with that hint; (3) the other
+  // synchronization variants on the best shape.  `budget` caps the number
+  // of timed candidates (0 = no cap).  The grid candidates start at one
+  // workgroup per CU; the in-flight bytes per CU (wg * ipt * 16 * grid /
+  // CUs) is what the shapes trade off.
   int timed = 0;
   red_plan cur = default_plan(dtype, n, *dev);
   double cur_us = 1e300;
   auto consider = [&](red_plan p) -> int {
     if (budget > 0 && timed >= budget) return RED_OK;
-    if (p.variant == RED_VARIANT_PERSISTENT && p.grid > 0) {
+    if (p.variant == RED_VARIANT_PERSISTENT) {
       int maxg = 0;
-      int r = reduce_max_coresident(dtype, acc, p.ipt, false, p.wg, *dev, &maxg);
+      int r = reduce_max_coresident(dtype, acc, p.ipt, (p.flags & RED_FLAG_NONTEMPORAL) != 0, p.wg, *dev, &maxg);
       if (r) return r;
-      if (p.grid > maxg) return RED_OK;
+      if (p.grid == 0 || p.grid > maxg) p.grid = maxg;
     }
     double us = 0;
     int r = time_plan(dtype, acc, p, x, n, out, s, &us);
@@ -477,50 +536,35 @@ int red_autotune(int dtype, int acc, const void* x, int64_t n, void* out, void* 
     }
     return RED_OK;
   };
-  const int wgs[] = {256, 512, 1024};
-  const int ipts[] = {1, 2, 4, 8};
-  for (int wg : wgs)
-    for (int ipt : ipts) {
-      red_plan p{RED_VARIANT_RELAUNCH, wg, ipt, 0, 0};
-      if ((rc = consider(p))) return rc;
-    }
-  const int64_t tile = (int64_t)cur.wg * cur.ipt;
-  const int64_t nvec = n / (16 / esize(dtype));
-  const int64_t want = std::max<int64_t>(1, (nvec + tile - 1) / tile);
-  const int mults[] = {1, 2, 3, 4, 6, 8, 12, 16};
-  const red_plan base = cur;
-  for (int m : mults) {
-    red_plan p = base;
-    p.grid = (int)std::min<int64_t>({(int64_t)m * dev->cus, want, (int64_t)RED_MAX_GRID});
-    if ((rc = consider(p))) return rc;
-    if ((int64_t)m * dev->cus >= want) break;
-  }
-  const red_plan base2 = cur;
-  for (int v : {RED_VARIANT_ATOMIC, RED_VARIANT_PERSISTENT}) {
-    red_plan p = base2;
-    p.variant = v;
-    if (v == RED_VARIANT_PERSISTENT && p.grid == 0) {
-      int maxg = 0;
-      if ((rc = reduce_max_coresident(dtype, acc, p.ipt, false, p.wg, *dev, &maxg))) return rc;
-      p.grid = (int)std::min<int64_t>({(int64_t)maxg, want, (int64_t)4 * dev->cus});
-    }
-    if ((rc = consider(p))) return rc;
-  }
-  // Nontemporal loads, and for the persistent variant the ordinary launch
-  // of an occupancy-capped grid (no cooperative-launch overhead).
   {
     red_plan p = cur;
+    p.flags &= ~RED_FLAG_NONTEMPORAL;
+    if ((rc = consider(p))) return rc;
     p.flags |= RED_FLAG_NONTEMPORAL;
     if ((rc = consider(p))) return rc;
-    red_plan q = base2;
-    q.variant = RED_VARIANT_PERSISTENT;
-    int maxg = 0;
-    if ((rc = reduce_max_coresident(dtype, acc, q.ipt, false, q.wg, *dev, &maxg))) return rc;
-    q.grid = (int)std::min<int64_t>({(int64_t)maxg, want, (int64_t)RED_MAX_GRID});
-    q.flags = RED_FLAG_PLAIN_LAUNCH;
-    if ((rc = consider(q))) return rc;
-    q.flags |= RED_FLAG_NONTEMPORAL;
-    if ((rc = consider(q))) return rc;
+  }
+  const int nt_flag = cur.flags & RED_FLAG_NONTEMPORAL;
+  const int64_t nvec = n / (16 / esize(dtype));
+  const int mults[] = {1, 2, 3, 4, 6, 8, 12, 16};
+  for (int wg : {128, 256, 512, 1024})
+    for (int ipt : {1, 2, 4, 8}) {
+      const int64_t tile = (int64_t)wg * ipt;
+      const int64_t want = std::max<int64_t>(1, (nvec + tile - 1) / tile);
+      for (int m : mults) {
+        const int64_t g = std::min<int64_t>({(int64_t)m * dev->cus, want, (int64_t)RED_MAX_GRID});
+        if ((rc = consider(red_plan{RED_VARIANT_RELAUNCH, wg, ipt, (int)g, nt_flag}))) return rc;
+        if (g == want) break;
+      }
+    }
+  const red_plan shape = cur;
+  for (int v : {RED_VARIANT_ATOMIC, RED_VARIANT_PERSISTENT}) {
+    red_plan p = shape;
+    p.variant = v;
+    if ((rc = consider(p))) return rc;
+    if (v == RED_VARIANT_PERSISTENT) {
+      p.flags |= RED_FLAG_PLAIN_LAUNCH;
+      if ((rc = consider(p))) return rc;
+    }
   }
   if ((rc = red_set_plan(dtype, acc, n, &cur))) return rc;
   if (best) *best = cur;
@@ -605,6 +649,76 @@ int red_sum_segmented_ex(const float* x, const int64_t* offsets, int64_t nseg, d
   return RED_OK;
 }
 
+int red_kernel_timer(void* stream, int enable) {
+  const DeviceInfo* dev;
+  int rc = ensure_device(&dev);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(g_mu);
+  KernelTimer& t = g_timers[std::make_pair(dev->id, s)];
+  t.on = enable != 0;
+  t.used = 0;
+  return RED_OK;
+}
+
+int red_kernel_timer_read(void* stream, double* mean_us, double* min_us, int64_t* count) {
+  const DeviceInfo* dev;
+  int rc = ensure_device(&dev);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  RED_HIP(hipStreamSynchronize(s));
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_timers.find(std::make_pair(dev->id, s));
+  double sum = 0, mn = 1e300;
+  int64_t n = 0;
+  if (it != g_timers.end()) {
+    KernelTimer& t = it->second;
+    for (size_t i = 0; i < t.used; ++i) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, t.ev[i].first, t.ev[i].second) != hipSuccess) {
+        (void)hipGetLastError();
+        continue;
+      }
+      sum += ms * 1e3;
+      mn = std::min(mn, (double)ms * 1e3);
+      ++n;
+    }
+    t.used = 0;
+  }
+  if (mean_us) *mean_us = n ? sum / n : 0.0;
+  if (min_us) *min_us = n ? mn : 0.0;
+  if (count) *count = n;
+  return RED_OK;
+}
+
+int red_set_segmented_plan(int64_t nseg, const red_plan* plan) {
+  if (!plan || nseg < 0) return set_error(RED_EINVAL, "bad plan or nseg");
+  int rc = validate_plan(*plan);
+  if (rc) return rc;
+  if (plan->variant != RED_VARIANT_ATOMIC && plan->variant != RED_VARIANT_PERSISTENT)
+    return set_error(RED_EINVAL, "segmented: variant must be ATOMIC or PERSISTENT");
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_plans[std::make_tuple(1, bucket(nseg), 0, 0)] = *plan;
+  return RED_OK;
+}
+
+int red_get_segmented_plan(int64_t nseg, red_plan* plan) {
+  if (!plan || nseg < 0) return set_error(RED_EINVAL, "bad plan or nseg");
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_plans.find(std::make_tuple(1, bucket(nseg), 0, 0));
+    if (it != g_plans.end()) {
+      *plan = it->second;
+      return RED_OK;
+    }
+  }
+  const DeviceInfo* dev;
+  DeviceInfo none;
+  none.cus = 256;
+  *plan = default_seg_plan(nseg, ensure_device(&dev) == RED_OK ? *dev : none);
+  return RED_OK;
+}
+
 int red_sum_segmented(const float* x, const int64_t* offsets, int64_t nseg, double* out, void* stream) {
   return red_sum_segmented_ex(x, offsets, nseg, out, stream, nullptr);
 }
@@ -639,8 +753,8 @@ int red_autotune_segmented(const float* x, const int64_t* offsets, int64_t nseg,
   Workspace* ws;
   if ((rc = get_workspace(s, &ws))) return rc;
   hipEvent_t a, b;
-  RED_HIP(hipEventCreate(&a));
-  RED_HIP(hipEventCreate(&b));
+  RED_HIP(hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
+  RED_HIP(hipEventCreateWithFlags(&b, hipEventDisableSystemFence));
   red_plan cur = default_seg_plan(nseg, *dev);
   double cur_us = 1e300;
   int timed = 0;
@@ -666,16 +780,18 @@ int red_autotune_segmented(const float* x, const int64_t* offsets, int64_t nseg,
     }
     return RED_OK;
   };
-  for (int wg : {256, 512, 1024})
+  {
+    red_plan p = cur;
+    p.flags &= ~RED_FLAG_NONTEMPORAL;
+    rc = consider(p);
+    p.flags |= RED_FLAG_NONTEMPORAL;
+    if (!rc) rc = consider(p);
+  }
+  const int nt_flag = cur.flags & RED_FLAG_NONTEMPORAL;
+  for (int wg : {128, 256, 512, 1024})
     for (int ipt : {2, 4, 8})
-      if ((rc = consider(red_plan{RED_VARIANT_ATOMIC, wg, ipt, 4 * dev->cus, 0}))) break;
-  const red_plan base = cur;
-  if (!rc)
-    for (int m : {1, 2, 3, 6, 8, 12, 16}) {
-      red_plan p = base;
-      p.grid = std::min(m * dev->cus, RED_MAX_GRID);
-      if ((rc = consider(p))) break;
-    }
+      for (int m : {1, 2, 3, 4, 6, 8})
+        if (!rc) rc = consider(red_plan{RED_VARIANT_ATOMIC, wg, ipt, std::min(m * dev->cus, RED_MAX_GRID), nt_flag});
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (rc) return rc;

@@ -37,6 +37,7 @@ struct SegArgs {
   unsigned* tickets;    // per owning slice: pieces published so far
   BarrierWords* words;
   unsigned spin_limit;
+  unsigned bar_groups;
 };
 
 // Per-thread compensated sum of x[a, b) with the whole workgroup: scalar
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(1024) void k_segmented(SegArgs a) {
     __syncthreads();  // lds is reused by the next piece
   }
   if constexpr (BARRIER) {
-    grid_barrier(a.words, gridDim.x, a.spin_limit);
+    grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit);
     if (threadIdx.x == 0 && own_seg >= 0) {
       const int64_t sa = a.offsets[own_seg];
       const int64_t sb = a.offsets[own_seg + 1];
@@ -195,10 +196,10 @@ red_plan default_seg_plan(int64_t nseg, const DeviceInfo& dev) {
   (void)nseg;
   red_plan p;
   p.variant = RED_VARIANT_ATOMIC;
-  p.wg = 512;
-  p.ipt = 4;
-  p.grid = 4 * dev.cus;
-  p.flags = 0;
+  p.wg = 256;
+  p.ipt = 8;
+  p.grid = 3 * dev.cus;
+  p.flags = RED_FLAG_NONTEMPORAL;
   return p;
 }
 
@@ -239,10 +240,14 @@ int seg_launch(const SegLaunch& sl, const float* x, const int64_t* offsets, int6
   a.tickets = ws->seg_tickets;
   a.words = ws->words;
   a.spin_limit = watchdog_spins();
+  a.bar_groups = barrier_groups(grid);
   void* args[] = {&a};
   const bool nt = (p.flags & RED_FLAG_NONTEMPORAL) != 0;
   const bool coop = barrier && (p.flags & RED_FLAG_PLAIN_LAUNCH) == 0;
-  return launch(seg_table().k[barrier ? 1 : 0][nt ? 1 : 0][ii], grid, p.wg, args, s, coop);
+  const int slot = timer_begin(s);
+  int rc = launch(seg_table().k[barrier ? 1 : 0][nt ? 1 : 0][ii], grid, p.wg, args, s, coop);
+  timer_end(s, slot);
+  return rc;
 }
 
 }  // namespace redsum

@@ -39,8 +39,9 @@ EXPORTS = [
     "red_init", "red_shutdown", "red_last_error", "red_check_error",
     "red_sum", "red_sum_ex", "red_sum_segmented", "red_sum_segmented_ex",
     "red_sum_segmented_loop", "red_set_plan", "red_get_plan", "red_autotune",
-    "red_autotune_segmented", "sync_bench_wave", "sync_bench_block",
-    "sync_bench_grid", "sync_bench_relaunch", "sync_check_grid_order",
+    "red_autotune_segmented", "red_set_segmented_plan", "red_get_segmented_plan",
+    "red_kernel_timer", "red_kernel_timer_read", "sync_bench_wave", "sync_bench_block",
+    "sync_bench_grid", "sync_bench_grid_ex", "sync_bench_relaunch", "sync_check_grid_order",
     "sync_check_watchdog", "red_max_coresident", "red_device_info",
     "red_bw_proxy", "red_eq6_overhead", "red_eq7_latency", "red_eq8_sigma",
 ]
@@ -86,9 +87,14 @@ _SIGS = {
     "red_get_plan": ([_i32, _i32, _i64, ctypes.POINTER(Plan)], _i32),
     "red_autotune": ([_i32, _i32, _vp, _i64, _vp, _vp, _i32, ctypes.POINTER(Plan), _dp], _i32),
     "red_autotune_segmented": ([_vp, _vp, _i64, _vp, _vp, _i32, ctypes.POINTER(Plan), _dp], _i32),
+    "red_set_segmented_plan": ([_i64, ctypes.POINTER(Plan)], _i32),
+    "red_get_segmented_plan": ([_i64, ctypes.POINTER(Plan)], _i32),
+    "red_kernel_timer": ([_vp, _i32], _i32),
+    "red_kernel_timer_read": ([_vp, _dp, _dp, _i64p], _i32),
     "sync_bench_wave": ([_i32, _i32, _i32, _dp, _dp, _dp, _vp], _i32),
     "sync_bench_block": ([_i32, _i32, _i32, _dp, _dp, _dp, _vp], _i32),
     "sync_bench_grid": ([_i32, _i32, _i32, _dp, _dp, _dp, _vp], _i32),
+    "sync_bench_grid_ex": ([_i32, _i32, _i32, _i32, _dp, _dp, _dp, _vp], _i32),
     "sync_bench_relaunch": ([_i32, _i32, _i32, _i32, _dp, _dp, _dp, _vp], _i32),
     "sync_check_grid_order": ([_i32, _i32, _i64p, _i64p, _vp], _i32),
     "sync_check_watchdog": ([_i32, _i32, _i32, _i32, _vp], _i32),
@@ -202,6 +208,28 @@ def red_autotune_segmented(x: int, offsets: int, nseg: int, out: int, stream: in
     return p, us.value
 
 
+def red_set_segmented_plan(nseg: int, plan: Plan) -> int:
+    return _check(load().red_set_segmented_plan(nseg, ctypes.byref(plan)), "red_set_segmented_plan")
+
+
+def red_get_segmented_plan(nseg: int) -> Plan:
+    p = Plan()
+    _check(load().red_get_segmented_plan(nseg, ctypes.byref(p)), "red_get_segmented_plan")
+    return p
+
+
+def red_kernel_timer(stream: int = 0, enable: bool = True) -> int:
+    return _check(load().red_kernel_timer(stream, int(bool(enable))), "red_kernel_timer")
+
+
+def red_kernel_timer_read(stream: int = 0):
+    """-> (mean us, min us, launches timed) of the dominant kernel."""
+    m, mn, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+    _check(load().red_kernel_timer_read(stream, ctypes.byref(m), ctypes.byref(mn), ctypes.byref(n)),
+           "red_kernel_timer_read")
+    return m.value, mn.value, n.value
+
+
 def _probe3(name, *args, stream=0):
     ns, sg, cy = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     _check(getattr(load(), name)(*args, ctypes.byref(ns), ctypes.byref(sg), ctypes.byref(cy), stream), name)
@@ -221,6 +249,11 @@ def sync_bench_block(wg_size: int, n_wg: int = 1, reps: int = 20, stream: int = 
 def sync_bench_grid(n_wg: int, wg_size: int = 256, reps: int = 20, stream: int = 0):
     """-> (ns per grid barrier by Eq. 7, sigma ns by Eq. 8, in-kernel wall-clock ns per barrier)"""
     return _probe3("sync_bench_grid", n_wg, wg_size, reps, stream=stream)
+
+
+def sync_bench_grid_ex(n_wg: int, wg_size: int = 256, groups: int = 0, reps: int = 20, stream: int = 0):
+    """Grid barrier with an explicit shape (groups = 1 flat, > 1 two-level)."""
+    return _probe3("sync_bench_grid_ex", n_wg, wg_size, groups, reps, stream=stream)
 
 
 def sync_bench_relaunch(n_wg: int = 256, wg_size: int = 256, cooperative: bool = False, reps: int = 20,

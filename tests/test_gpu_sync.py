@@ -102,3 +102,40 @@ def test_relaunch_probe(lib, coop):
     ns, sigma, null_ns = lib.sync_bench_relaunch(256, 256, cooperative=coop, reps=10)
     say("relaunch coop=%s: overhead %.1f ns (sigma %.1f), null kernel %.1f ns" % (coop, ns, sigma, null_ns))
     assert -2000 < ns < 1e5 and null_ns > 0
+
+
+@pytest.mark.parametrize("groups", [1, 2, 8, 32])
+def test_barrier_shapes_probe(lib, groups):
+    """Flat and two-level barriers through the probe."""
+    n_wg = min(1024, lib.red_max_coresident(256))
+    ns, sigma, wall = lib.sync_bench_grid_ex(n_wg, 256, groups, reps=5)
+    say("grid %d WGs, %d groups: %.1f ns" % (n_wg, groups, ns))
+    assert 0 < ns < 1e6
+    assert lib.red_check_error(lib.current_stream()) == lib.RED_OK
+
+
+def test_two_level_barrier_in_persistent_sums(lib):
+    """The two-level barrier (grids of 64 and more) inside persistent
+    reductions, bit-exact."""
+    n_wg = min(1024, lib.red_max_coresident(256))
+    x = inputs.uniform_i32(4_000_037, lo=-2**31, hi=2**31 - 1, sub=16)
+    t = torch.from_numpy(x).to("cuda")
+    ref = oracle.sum_i32(x)
+    for g in (64, 100, 513, n_wg):
+        out = lib.sum(t, opts=lib.make_opts(variant=3, wg=256, ipt=2, grid=min(g, n_wg)))
+        torch.cuda.synchronize()
+        assert out.item() == ref, g
+    assert lib.red_check_error(lib.current_stream()) == lib.RED_OK
+
+
+def test_kernel_timer(lib):
+    x = torch.ones(1 << 24, dtype=torch.float32, device="cuda")
+    s = lib.current_stream()
+    lib.red_kernel_timer(s, True)
+    for v in (1, 2, 3):
+        lib.sum(x, opts=lib.make_opts(variant=v))
+    mean_us, min_us, count = lib.red_kernel_timer_read(s)
+    lib.red_kernel_timer(s, False)
+    assert count == 3 and 0 < min_us <= mean_us < 1e5
+    lib.sum(x)
+    assert lib.red_kernel_timer_read(s)[2] == 0  # off: nothing recorded
