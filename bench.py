@@ -119,7 +119,7 @@ def variant_table(R, plan, dtype, xt, n, out, sh, stream, dev, reps=50, flush=No
     """GB/s (median of `reps` event-timed calls) of every synchronization
     variant with the plan's workgroup size, loads per thread and flags."""
     nbytes = xt.numel() * xt.element_size()
-    nt = plan.flags & R.FLAG_NONTEMPORAL
+    nt = plan.flags & (R.FLAG_NONTEMPORAL | R.FLAG_PIPELINE)
     coresident = R.red_max_coresident(plan.wg)
     g = plan.grid or min(4 * dev["cus"], coresident)
     cands = {

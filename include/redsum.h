@@ -97,6 +97,18 @@ typedef enum {
                                    cooperative launch API; the barrier
                                    watchdog guards against a grid that is
                                    not fully resident                       */
+#define RED_FLAG_PIPELINE 8     /* reductions: double-buffered loop that
+                                   issues the next tile's loads before the
+                                   current tile's arithmetic                */
+#define RED_FLAG_XCD 16         /* atomic / persistent variants: publish the
+                                   partials with one L2 write-back per XCD
+                                   (the last workgroup of each XCD releases
+                                   for all of them) instead of one per
+                                   workgroup.  Relies on the round-robin
+                                   dispatch of workgroups over the XCDs,
+                                   which every workgroup checks against its
+                                   XCC_ID register; a mismatch is reported
+                                   by red_check_error as RED_ENOTSUP        */
 
 /* Launch plan of one reduction. */
 typedef struct {
@@ -104,7 +116,8 @@ typedef struct {
     int32_t wg;      /* workgroup size in threads: 64..1024, multiple of 64  */
     int32_t ipt;     /* 16-byte loads per thread per loop iteration: 1,2,4,8 */
     int32_t grid;    /* number of workgroups, 1..RED_MAX_GRID; 0 = automatic */
-    int32_t flags;   /* RED_FLAG_NONTEMPORAL | RED_FLAG_PLAIN_LAUNCH         */
+    int32_t flags;   /* RED_FLAG_NONTEMPORAL | RED_FLAG_PLAIN_LAUNCH |
+                        RED_FLAG_PIPELINE | RED_FLAG_XCD                    */
 } red_plan;
 
 #define RED_MAX_GRID 8192
@@ -139,8 +152,10 @@ void red_shutdown(void);
 const char *red_last_error(void);
 
 /* Synchronize `stream`, then report a grid-barrier watchdog timeout raised
- * by an earlier persistent kernel on that stream (RED_ETIMEOUT), clearing
- * the flag and the barrier words.  RED_OK if none. */
+ * by an earlier persistent kernel on that stream (RED_ETIMEOUT), or a
+ * workgroup that ran on another XCD than round-robin dispatch implies under
+ * RED_FLAG_XCD (RED_ENOTSUP), clearing the flag and the barrier words.
+ * RED_OK if none. */
 int red_check_error(void *stream);
 
 /* ---------------------------------------------------------------------
@@ -252,8 +267,9 @@ int sync_bench_grid(int n_wg, int wg_size, int reps, double *ns, double *sigma_n
 
 /* sync_bench_grid with an explicit barrier shape: groups = 1 is the flat
  * centralized barrier, groups = 2..32 the two-level barrier whose first
- * level counts the workgroups with blockIdx % groups equal, 0 the default
- * policy (flat below 64 workgroups, else about 64 members per group). */
+ * level counts the workgroups with blockIdx % groups equal, -1 the
+ * XCD-aggregated barrier (first level per XCD with one L2 write-back per
+ * XCD, see RED_FLAG_XCD), 0 the default policy. */
 int sync_bench_grid_ex(int n_wg, int wg_size, int groups, int reps, double *ns, double *sigma_ns,
                        double *cycles, void *stream);
 
@@ -283,9 +299,13 @@ int sync_check_watchdog(int n_wg, int wg_size, int skip_wg, int spin_limit, void
 int red_max_coresident(int wg_size, int32_t *n_wg);
 
 /* Device facts: compute units, wall-clock rate (kHz), shader clock (kHz),
- * L2 bytes, HBM bytes.  Any pointer may be NULL. */
+ * L2 bytes (per XCD), HBM bytes, number of XCDs.  Any pointer may be NULL. */
 int red_device_info(int32_t *cus, int64_t *wallclock_khz, int64_t *clock_khz, int64_t *l2_bytes,
-                    int64_t *hbm_bytes);
+                    int64_t *hbm_bytes, int32_t *nxcc);
+
+/* XCD (hardware XCC_ID) on which each of n_wg workgroups of an ordinary
+ * launch ran; host_xcc receives n_wg ints.  Synchronous. */
+int sync_xcc_map(int n_wg, int wg_size, int32_t *host_xcc, void *stream);
 
 /* ---------------------------------------------------------------------
  * Measurement helpers (not part of a reduction)

@@ -366,6 +366,12 @@ __device__ __forceinline__ Vec load_vec(const Vec* p) {
     return *p;
 }
 
+// Hardware id of the XCD (accelerator complex die) the calling wave runs on
+// (the 4-bit XCC_ID hardware register of gfx94x / gfx950).
+__device__ __forceinline__ unsigned xcc_id() {
+  return (unsigned)__builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)) & 0xFu;
+}
+
 // ---------------------------------------------------------------------------
 // Workspace words of one (device, stream).  Each word that is polled or hit
 // by atomics sits on its own 128-byte line.
@@ -394,53 +400,95 @@ __device__ __forceinline__ unsigned relaxed_add(unsigned* p, unsigned v) {
 }
 
 // ---------------------------------------------------------------------------
+// XCD-aggregated publication.
+//
+// Workgroups are dispatched to the XCDs round-robin (workgroup g runs on XCD
+// g mod nxcc; the library checks this with the XCC_ID register).  All
+// workgroups of one XCD share that XCD's L2, and a store is in that L2 once
+// the issuing wave's vector-memory counter has drained.  So instead of one
+// L2 write-back per workgroup (an agent-scope release fence), each
+// workgroup drains its stores and counts itself on its XCD's counter; the
+// last arrival of the XCD performs ONE agent-scope release (write-back of
+// that L2, which holds every member's stores) before it signals onward.  A
+// workgroup that finds itself on an unexpected XCD publishes with its own
+// release fence and sets err = kErrDispatch, so a violated assumption is
+// reported instead of silently trusted.
+// ---------------------------------------------------------------------------
+constexpr unsigned kErrTimeout = 1u;
+constexpr unsigned kErrDispatch = 2u;
+constexpr unsigned kBarrierXcd = 0x100u;  // groups value: XCD-aggregated barrier (| nxcc)
+
+// Makes this workgroup's earlier global stores visible to the members of
+// its XCD group and counts it there; returns true for the last member of
+// the group (which must then release agent-wide before signalling).
+// Thread 0 only; every wave of the workgroup must have drained its stores
+// (s_waitcnt) before the workgroup barrier that precedes this call.
+__device__ __forceinline__ bool xcd_arrive(BarrierWords* w, unsigned nblocks, unsigned nxcc) {
+  const unsigned grp = blockIdx.x % nxcc;
+  const unsigned members = (nblocks - grp + nxcc - 1) / nxcc;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0);
+  if (xcc_id() != grp) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(&w->err.v, kErrDispatch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (relaxed_add(&w->group[grp].v, 1u) != members - 1) return false;
+  __hip_atomic_store(&w->group[grp].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+  return true;
+}
+
+// ---------------------------------------------------------------------------
 // Grid barrier for a launch of `nblocks` co-resident workgroups.
 //
-// Sense-reversing barrier with an optional second level.  Thread 0 of each
-// workgroup:
-//   1. reads the generation g (relaxed);
-//   2. release fence at agent (device) scope -- one L2 write-back that makes
-//      the workgroup's earlier global stores visible across the XCDs'
-//      separate L2 caches -- then a relaxed increment of an arrival counter:
-//        groups <= 1 : the single counter (flat, centralized barrier);
-//        groups  > 1 : the counter of group (blockIdx.x % groups); the last
-//                      arrival of a group acquires its members' releases,
-//                      releases them onward and increments the top counter
-//                      (so at most nblocks / groups arrivals serialize on
-//                      one counter; with groups a multiple of 8 every group
-//                      lies on one XCD under round-robin dispatch);
-//   3. the last top-level arrival resets the counter, acquires, releases and
-//      bumps the generation; the others poll the generation with relaxed
-//      device-scope loads (s_sleep between polls, so polling neither
-//      invalidates the L2 nor floods the atomic unit);
-//   4. one acquire fence after the wait.
-// Each hop is a release fence / relaxed RMW / acquire fence chain, so every
-// workgroup's stores happen before every workgroup's loads after the
-// barrier.  The poll is bounded by `spin_limit`: on expiry the workgroup sets
-// the error word and leaves, so the kernel always ends (a grid in which not
-// every block arrives deadlocks, Section VIII-B of the paper).  Counters are
-// back at zero after every completed barrier.  Returns false on timeout.
+// Sense-reversing barrier in three shapes (`groups`):
+//   1        flat: every workgroup releases (one L2 write-back) and
+//            increments the single counter;
+//   2..32    two-level: the first level counts the workgroups with equal
+//            blockIdx.x % groups (each still releasing on its own), the
+//            last of a group acquires and increments the top counter;
+//   kBarrierXcd | nxcc
+//            XCD-aggregated: the first level is the XCD, with one L2
+//            write-back per XCD (xcd_arrive above).
+// Thread 0 of each workgroup reads the generation first; the last top-level
+// arrival resets the counter, acquires, releases and bumps the generation;
+// the others poll it with relaxed device-scope loads (s_sleep between
+// polls, so polling neither invalidates the L2 nor floods the atomic unit)
+// and acquire once after the wait.  Each hop is a release / relaxed RMW /
+// acquire chain, so every workgroup's stores happen before every
+// workgroup's loads after the barrier.  The poll is bounded by `spin_limit`:
+// on expiry the workgroup sets the error word and leaves, so the kernel
+// always ends (a grid in which not every block arrives deadlocks, Section
+// VIII-B of the paper).  Counters are back at zero after every completed
+// barrier.  Returns false on timeout.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool grid_barrier(BarrierWords* w, unsigned nblocks, unsigned groups,
                                              unsigned spin_limit) {
   __shared__ int timed_out;
+  const bool xcd = (groups & kBarrierXcd) != 0;
+  if (xcd) __builtin_amdgcn_s_waitcnt(0);  // every wave drains its stores
   __syncthreads();
   if (threadIdx.x == 0) {
     int to = 0;
     const unsigned g = __hip_atomic_load(&w->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    bool last;
-    if (groups <= 1) {
-      last = relaxed_add(&w->count.v, 1u) == nblocks - 1;
+    bool last = false;
+    if (xcd) {
+      const unsigned nxcc = groups & 0xFFu;
+      const unsigned active = nblocks < nxcc ? nblocks : nxcc;
+      if (xcd_arrive(w, nblocks, nxcc)) last = relaxed_add(&w->count.v, 1u) == active - 1;
     } else {
-      const unsigned grp = blockIdx.x % groups;
-      const unsigned members = (nblocks - grp + groups - 1) / groups;
-      const unsigned active = nblocks < groups ? nblocks : groups;
-      last = false;
-      if (relaxed_add(&w->group[grp].v, 1u) == members - 1) {
-        __hip_atomic_store(&w->group[grp].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-        last = relaxed_add(&w->count.v, 1u) == active - 1;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      if (groups <= 1) {
+        last = relaxed_add(&w->count.v, 1u) == nblocks - 1;
+      } else {
+        const unsigned grp = blockIdx.x % groups;
+        const unsigned members = (nblocks - grp + groups - 1) / groups;
+        const unsigned active = nblocks < groups ? nblocks : groups;
+        if (relaxed_add(&w->group[grp].v, 1u) == members - 1) {
+          __hip_atomic_store(&w->group[grp].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+          last = relaxed_add(&w->count.v, 1u) == active - 1;
+        }
       }
     }
     if (last) {
@@ -451,7 +499,7 @@ __device__ __forceinline__ bool grid_barrier(BarrierWords* w, unsigned nblocks, 
       unsigned spins = 0;
       while (__hip_atomic_load(&w->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
         if (++spins > spin_limit) {
-          __hip_atomic_store(&w->err.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&w->err.v, kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           to = 1;
           break;
         }

@@ -24,6 +24,7 @@ struct DeviceInfo {
   int64_t clock_khz = 0;
   int64_t l2_bytes = 0;
   int64_t hbm_bytes = 0;
+  int nxcc = 1;  // XCDs (accelerator complex dies) of the device
   bool coop = false;
 };
 
@@ -86,7 +87,7 @@ int validate_plan(const red_plan& p);
 red_plan default_plan(int dtype, int64_t n, const DeviceInfo& dev);
 int reduce_launch(const ReduceLaunch& rl, const void* x, int64_t n, void* out, Workspace* ws,
                   hipStream_t s, const DeviceInfo& dev);
-int reduce_max_coresident(int dtype, int acc, int ipt, bool nt, int wg, const DeviceInfo& dev,
+int reduce_max_coresident(int dtype, int acc, int ipt, bool nt, bool pipe, int wg, const DeviceInfo& dev,
                           int* n_wg);
 
 // Segmented ------------------------------------------------------------------

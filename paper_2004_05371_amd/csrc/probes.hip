@@ -95,6 +95,11 @@ __global__ __launch_bounds__(1024) void k_watchdog(BarrierWords* w, int skip, un
   grid_barrier(w, gridDim.x, groups, spin_limit);
 }
 
+// XCD of every workgroup (thread 0 records it).
+__global__ __launch_bounds__(1024) void k_xcc_map(int* out) {
+  if (threadIdx.x == 0) out[blockIdx.x] = (int)xcc_id();
+}
+
 __global__ void k_reset_words(BarrierWords* w) {
   if (threadIdx.x == 0) {
     w->count.v = 0;
@@ -118,6 +123,7 @@ __global__ __launch_bounds__(1024) void k_bw_proxy(const v4u* x, int64_t nvec, u
     v4u v[IPT];
 #pragma unroll
     for (int u = 0; u < IPT; ++u) v[u] = x[t * tile + u * bs + threadIdx.x];
+    __builtin_amdgcn_sched_barrier(0);  // all IPT loads in flight before use
 #pragma unroll
     for (int u = 0; u < IPT; ++u) acc += v[u].x + v[u].y;
   }
@@ -330,7 +336,7 @@ int sync_bench_grid_ex(int n_wg, int wg_size, int groups, int reps, double* ns, 
                        double* cycles, void* stream) {
   if (wg_size < 64 || wg_size > 1024 || wg_size % 64) return set_error(RED_EINVAL, "bad wg_size %d", wg_size);
   if (n_wg < 1 || n_wg > RED_MAX_GRID) return set_error(RED_EINVAL, "bad n_wg %d", n_wg);
-  if (groups < 0 || groups > kMaxBarrierGroups) return set_error(RED_EINVAL, "bad groups %d", groups);
+  if (groups < -1 || groups > kMaxBarrierGroups) return set_error(RED_EINVAL, "bad groups %d", groups);
   if (reps < 2 || !ns || !sigma_ns) return set_error(RED_EINVAL, "reps >= 2 and non-null outputs required");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const DeviceInfo* dev;
@@ -346,7 +352,9 @@ int sync_bench_grid_ex(int n_wg, int wg_size, int groups, int reps, double* ns, 
   if ((rc = reset_words(ws, s))) return rc;
   int r = 0;
   BarrierWords* w = ws->words;
-  unsigned grp = groups > 0 ? (unsigned)groups : barrier_groups(n_wg);
+  unsigned grp = groups > 0 ? (unsigned)groups
+                 : groups < 0 ? (dev->nxcc > 1 ? (kBarrierXcd | (unsigned)dev->nxcc) : 1u)
+                              : barrier_groups(n_wg);
   unsigned spin = watchdog_spins();
   long long* st = ws->stamps;
   void* args[] = {&r, &w, &grp, &spin, &st};
@@ -364,7 +372,8 @@ int sync_bench_grid_ex(int n_wg, int wg_size, int groups, int reps, double* ns, 
   RED_HIP(hipMemcpy(&err, &ws->words->err.v, 4, hipMemcpyDeviceToHost));
   if (err) {
     reset_words(ws, s);
-    return set_error(RED_ETIMEOUT, "grid probe: barrier watchdog fired");
+    return err == kErrDispatch ? set_error(RED_ENOTSUP, "grid probe: workgroup not on its round-robin XCD")
+                               : set_error(RED_ETIMEOUT, "grid probe: barrier watchdog fired");
   }
   return RED_OK;
 }
@@ -493,6 +502,23 @@ int sync_check_watchdog(int n_wg, int wg_size, int skip_wg, int spin_limit, void
   void* args[] = {&w, &skip_wg, &grp, &spin};
   if ((rc = launch(fn, n_wg, wg_size, args, s, true))) return rc;
   return red_check_error(stream);
+}
+
+int sync_xcc_map(int n_wg, int wg_size, int32_t* host_xcc, void* stream) {
+  if (wg_size < 64 || wg_size > 1024 || wg_size % 64) return set_error(RED_EINVAL, "bad wg_size %d", wg_size);
+  if (n_wg < 1 || n_wg > RED_MAX_GRID) return set_error(RED_EINVAL, "bad n_wg %d", n_wg);
+  if (!host_xcc) return set_error(RED_EINVAL, "null output");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DeviceInfo* dev;
+  Workspace* ws;
+  int rc = probe_prologue(s, &dev, &ws);
+  if (rc) return rc;
+  int* out = reinterpret_cast<int*>(ws->stamps);  // 2 * RED_MAX_GRID int64 slots
+  void* args[] = {&out};
+  if ((rc = launch(reinterpret_cast<const void*>(&k_xcc_map), n_wg, wg_size, args, s, false))) return rc;
+  RED_HIP(hipStreamSynchronize(s));
+  RED_HIP(hipMemcpy(host_xcc, out, (size_t)n_wg * sizeof(int32_t), hipMemcpyDeviceToHost));
+  return RED_OK;
 }
 
 int red_bw_proxy(const void* x, int64_t nbytes, int n_wg, int wg_size, void* stream) {

@@ -33,7 +33,8 @@ struct ReduceArgs {
   BarrierWords* words;
   void* out;      // one Part
   unsigned spin_limit;
-  unsigned bar_groups;  // grid-barrier groups (persistent variant)
+  unsigned bar_groups;  // grid-barrier shape (persistent variant)
+  unsigned xcd_nxcc;    // atomic variant: XCD-aggregated publication over this many XCDs (0 = off)
 };
 
 // Per-thread accumulation of this thread's grid-stride share.  The vector
@@ -41,7 +42,17 @@ struct ReduceArgs {
 // tiles g, g + G, ...; inside a tile, load u of thread t reads vector
 // u * blockDim.x + t, so each wavefront load instruction reads 1 KiB of
 // contiguous memory.  IPT independent accumulators keep IPT loads in flight.
-template <class M, int IPT, bool NT>
+// With PIPE the loads of the workgroup's next tile are issued before the
+// arithmetic of the current one (two register buffers), so a wave keeps
+// loads in flight while it computes.
+template <int IPT, bool NT, class Vec>
+__device__ __forceinline__ void load_tile(Vec (&v)[IPT], const Vec* xv, int64_t t, int64_t tile, int64_t bs) {
+  const Vec* p = xv + t * tile + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) v[u] = load_vec<NT>(p + u * bs);
+}
+
+template <class M, int IPT, bool NT, bool PIPE>
 __device__ __forceinline__ typename M::Acc thread_accumulate(const ReduceArgs& a) {
   using In = typename M::In;
   using Vec = typename M::Vec;
@@ -51,18 +62,54 @@ __device__ __forceinline__ typename M::Acc thread_accumulate(const ReduceArgs& a
   const int64_t bs = blockDim.x;
   const int64_t tile = bs * IPT;
   const int64_t ntiles = a.nvec / tile;
+  const int64_t G = gridDim.x;
 
   Acc acc[IPT];
 #pragma unroll
   for (int u = 0; u < IPT; ++u) acc[u] = M::zero();
 
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const Vec* p = xv + t * tile + threadIdx.x;
-    Vec v[IPT];
+  if constexpr (!PIPE) {
+    for (int64_t t = blockIdx.x; t < ntiles; t += G) {
+      Vec v[IPT];
+      load_tile<IPT, NT>(v, xv, t, tile, bs);
+      // Keep the IPT loads issued back to back before any of them is used,
+      // so that they are all in flight together.
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int u = 0; u < IPT; ++u) v[u] = load_vec<NT>(p + u * bs);
+      for (int u = 0; u < IPT; ++u) M::add_vec(acc[u], v[u]);
+    }
+  } else {
+    // The loop leaves before a prefetch rather than guarding it, so the
+    // loads stay in straight-line code and the compiler's wait counts only
+    // wait for the older buffer.
+    Vec va[IPT], vb[IPT];
+    int64_t t = blockIdx.x;
+    if (t < ntiles) {
+      load_tile<IPT, NT>(va, xv, t, tile, bs);
+      for (;;) {
+        const int64_t t2 = t + G;
+        if (t2 >= ntiles) {
 #pragma unroll
-    for (int u = 0; u < IPT; ++u) M::add_vec(acc[u], v[u]);
+          for (int u = 0; u < IPT; ++u) M::add_vec(acc[u], va[u]);
+          break;
+        }
+        load_tile<IPT, NT>(vb, xv, t2, tile, bs);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < IPT; ++u) M::add_vec(acc[u], va[u]);
+        const int64_t t3 = t2 + G;
+        if (t3 >= ntiles) {
+#pragma unroll
+          for (int u = 0; u < IPT; ++u) M::add_vec(acc[u], vb[u]);
+          break;
+        }
+        load_tile<IPT, NT>(va, xv, t3, tile, bs);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < IPT; ++u) M::add_vec(acc[u], vb[u]);
+        t = t3;
+      }
+    }
   }
   // Vectors after the last full tile.
   for (int64_t i = ntiles * tile + (int64_t)blockIdx.x * bs + threadIdx.x; i < a.nvec;
@@ -83,10 +130,10 @@ __device__ __forceinline__ typename M::Acc thread_accumulate(const ReduceArgs& a
 
 // Workgroup total of the thread accumulators, as the stored partial type
 // (valid in thread 0).
-template <class M, int IPT, bool NT>
+template <class M, int IPT, bool NT, bool PIPE>
 __device__ __forceinline__ typename M::Part workgroup_partial(const ReduceArgs& a) {
   __shared__ typename M::Op::T lds[kMaxWavesPerWG];
-  typename M::Acc acc = thread_accumulate<M, IPT, NT>(a);
+  typename M::Acc acc = thread_accumulate<M, IPT, NT, PIPE>(a);
   return M::to_part(block_reduce<typename M::Op>(acc, lds));
 }
 
@@ -106,9 +153,9 @@ __device__ __forceinline__ Part combine_partials(const Part* partials, int count
 // Variant 1, implicit barrier: kernel 1 writes one partial per workgroup,
 // kernel 2 (one workgroup) combines them.
 // ---------------------------------------------------------------------------
-template <class M, int IPT, bool NT>
+template <class M, int IPT, bool NT, bool PIPE>
 __global__ __launch_bounds__(1024) void k_partials(ReduceArgs a) {
-  typename M::Part p = workgroup_partial<M, IPT, NT>(a);
+  typename M::Part p = workgroup_partial<M, IPT, NT, PIPE>(a);
   if (threadIdx.x == 0) static_cast<typename M::Part*>(a.partials)[blockIdx.x] = p;
 }
 
@@ -136,26 +183,37 @@ __global__ __launch_bounds__(64) void k_final_wave(const Part* partials, int cou
 // then, after a device-scope release fence, takes a ticket with a relaxed
 // atomic; the workgroup that draws the last ticket acquires, does the final
 // combine and resets the ticket (and the int accumulator) for the next
-// launch.
+// launch.  With XCD-aggregated publication the release and the ticket are
+// taken once per XCD by its last workgroup.
 // ---------------------------------------------------------------------------
-template <class M, int IPT, bool NT>
+template <class M, int IPT, bool NT, bool PIPE>
 __global__ __launch_bounds__(1024) void k_atomic(ReduceArgs a) {
   using Part = typename M::Part;
-  __shared__ unsigned ticket;
-  Part p = workgroup_partial<M, IPT, NT>(a);
+  __shared__ int is_last;
+  Part p = workgroup_partial<M, IPT, NT, PIPE>(a);
   BarrierWords* w = a.words;
   if (threadIdx.x == 0) {
     if constexpr (__is_same(Part, long long))
       __hip_atomic_fetch_add(acc_i64(w), p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else
       static_cast<Part*>(a.partials)[blockIdx.x] = p;
-    // Release (one L2 write-back) publishes the partial; the ticket itself
-    // is relaxed, and only the last workgroup pays an acquire.
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    ticket = __hip_atomic_fetch_add(&w->ticket.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool last;
+    if (a.xcd_nxcc > 1) {
+      // One L2 write-back per XCD: the last member of each XCD releases and
+      // takes the ticket for the whole XCD.
+      const unsigned active = gridDim.x < a.xcd_nxcc ? gridDim.x : a.xcd_nxcc;
+      last = xcd_arrive(w, gridDim.x, a.xcd_nxcc) &&
+             relaxed_add(&w->ticket.v, 1u) == active - 1;
+    } else {
+      // Release (one L2 write-back) publishes the partial; the ticket itself
+      // is relaxed, and only the last workgroup pays an acquire.
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      last = relaxed_add(&w->ticket.v, 1u) == gridDim.x - 1;
+    }
+    is_last = last;
   }
   __syncthreads();
-  if (ticket != gridDim.x - 1) return;
+  if (!is_last) return;
   // Last workgroup: every thread acquires before reading the others' data.
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   if constexpr (__is_same(Part, long long)) {
@@ -179,10 +237,10 @@ __global__ __launch_bounds__(1024) void k_atomic(ReduceArgs a) {
 // workgroup stores its partial, all meet at the grid barrier, workgroup 0
 // combines.
 // ---------------------------------------------------------------------------
-template <class M, int IPT, bool NT>
+template <class M, int IPT, bool NT, bool PIPE>
 __global__ __launch_bounds__(1024) void k_persistent(ReduceArgs a) {
   using Part = typename M::Part;
-  Part p = workgroup_partial<M, IPT, NT>(a);
+  Part p = workgroup_partial<M, IPT, NT, PIPE>(a);
   if (threadIdx.x == 0) static_cast<Part*>(a.partials)[blockIdx.x] = p;
   grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit);
   if (blockIdx.x != 0) return;
@@ -225,38 +283,39 @@ struct KernelSet {
   const void* persistent;
 };
 
-template <class M, int IPT, bool NT>
+template <class M, int IPT, bool NT, bool PIPE>
 KernelSet make_set() {
-  return KernelSet{reinterpret_cast<const void*>(&k_partials<M, IPT, NT>),
-                   reinterpret_cast<const void*>(&k_atomic<M, IPT, NT>),
-                   reinterpret_cast<const void*>(&k_persistent<M, IPT, NT>)};
+  return KernelSet{reinterpret_cast<const void*>(&k_partials<M, IPT, NT, PIPE>),
+                   reinterpret_cast<const void*>(&k_atomic<M, IPT, NT, PIPE>),
+                   reinterpret_cast<const void*>(&k_persistent<M, IPT, NT, PIPE>)};
 }
 
-template <class M, bool NT>
+template <class M, bool NT, bool PIPE>
 void fill_ipts(KernelSet* row) {
-  row[0] = make_set<M, 1, NT>();
-  row[1] = make_set<M, 2, NT>();
-  row[2] = make_set<M, 4, NT>();
-  row[3] = make_set<M, 8, NT>();
+  row[0] = make_set<M, 1, NT, PIPE>();
+  row[1] = make_set<M, 2, NT, PIPE>();
+  row[2] = make_set<M, 4, NT, PIPE>();
+  row[3] = make_set<M, 8, NT, PIPE>();
+}
+
+template <class M>
+void fill_mode(KernelSet (*m)[2][4]) {
+  fill_ipts<M, false, false>(m[0][0]);
+  fill_ipts<M, false, true>(m[0][1]);
+  fill_ipts<M, true, false>(m[1][0]);
+  fill_ipts<M, true, true>(m[1][1]);
 }
 
 struct Table {
-  KernelSet k[kNumModes][2][4];  // mode, nontemporal, ipt index
+  KernelSet k[kNumModes][2][2][4];  // mode, nontemporal, pipelined, ipt index
   Table() {
-    fill_ipts<ModeI32, false>(k[kI32][0]);
-    fill_ipts<ModeI32, true>(k[kI32][1]);
-    fill_ipts<ModeF32Comp, false>(k[kF32C][0]);
-    fill_ipts<ModeF32Comp, true>(k[kF32C][1]);
-    fill_ipts<ModeF32Plain, false>(k[kF32P][0]);
-    fill_ipts<ModeF32Plain, true>(k[kF32P][1]);
-    fill_ipts<ModeHalfComp<F16>, false>(k[kF16C][0]);
-    fill_ipts<ModeHalfComp<F16>, true>(k[kF16C][1]);
-    fill_ipts<ModeHalfPlain<F16>, false>(k[kF16P][0]);
-    fill_ipts<ModeHalfPlain<F16>, true>(k[kF16P][1]);
-    fill_ipts<ModeHalfComp<Bf16>, false>(k[kBF16C][0]);
-    fill_ipts<ModeHalfComp<Bf16>, true>(k[kBF16C][1]);
-    fill_ipts<ModeHalfPlain<Bf16>, false>(k[kBF16P][0]);
-    fill_ipts<ModeHalfPlain<Bf16>, true>(k[kBF16P][1]);
+    fill_mode<ModeI32>(k[kI32]);
+    fill_mode<ModeF32Comp>(k[kF32C]);
+    fill_mode<ModeF32Plain>(k[kF32P]);
+    fill_mode<ModeHalfComp<F16>>(k[kF16C]);
+    fill_mode<ModeHalfPlain<F16>>(k[kF16P]);
+    fill_mode<ModeHalfComp<Bf16>>(k[kBF16C]);
+    fill_mode<ModeHalfPlain<Bf16>>(k[kBF16P]);
   }
 };
 
@@ -277,7 +336,7 @@ int validate_plan(const red_plan& p) {
   if (ipt_index(p.ipt) < 0) return set_error(RED_EINVAL, "plan: ipt %d must be 1, 2, 4 or 8", p.ipt);
   if (p.grid < 0 || p.grid > RED_MAX_GRID)
     return set_error(RED_EINVAL, "plan: grid %d out of range [0, %d]", p.grid, RED_MAX_GRID);
-  if (p.flags & ~(RED_FLAG_NONTEMPORAL | RED_FLAG_PLAIN_LAUNCH))
+  if (p.flags & ~(RED_FLAG_NONTEMPORAL | RED_FLAG_PLAIN_LAUNCH | RED_FLAG_PIPELINE | RED_FLAG_XCD))
     return set_error(RED_EINVAL, "plan: unknown flags 0x%x", p.flags);
   return RED_OK;
 }
@@ -296,13 +355,13 @@ red_plan default_plan(int dtype, int64_t n, const DeviceInfo& dev) {
   return p;
 }
 
-int reduce_max_coresident(int dtype, int acc, int ipt, bool nt, int wg, const DeviceInfo& dev,
+int reduce_max_coresident(int dtype, int acc, int ipt, bool nt, bool pipe, int wg, const DeviceInfo& dev,
                           int* n_wg) {
   int m = mode_of(dtype, acc);
   int ii = ipt_index(ipt);
   if (m < 0 || ii < 0) return set_error(RED_EINVAL, "bad dtype/ipt");
   int per_cu = 0;
-  RED_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, table().k[m][nt ? 1 : 0][ii].persistent,
+  RED_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, table().k[m][nt ? 1 : 0][pipe ? 1 : 0][ii].persistent,
                                                        wg, 0));
   *n_wg = per_cu * dev.cus;
   return RED_OK;
@@ -332,11 +391,14 @@ int reduce_launch(const ReduceLaunch& rl, const void* x, int64_t n, void* out, W
   a.out = out;
   a.spin_limit = watchdog_spins();
   a.bar_groups = 1;
+  const bool xcd = (rl.plan.flags & RED_FLAG_XCD) != 0 && dev.nxcc > 1;
+  a.xcd_nxcc = xcd ? (unsigned)dev.nxcc : 0u;
 
   const red_plan& p = rl.plan;
   const int ii = ipt_index(p.ipt);
   const bool nt = (p.flags & RED_FLAG_NONTEMPORAL) != 0;
-  const KernelSet& ks = table().k[m][nt ? 1 : 0][ii];
+  const bool pipe = (p.flags & RED_FLAG_PIPELINE) != 0;
+  const KernelSet& ks = table().k[m][nt ? 1 : 0][pipe ? 1 : 0][ii];
   // Grid: the requested size, else enough workgroups for the work, capped
   // at 4 per compute unit (and at the co-resident limit for the persistent
   // variant).
@@ -370,14 +432,14 @@ int reduce_launch(const ReduceLaunch& rl, const void* x, int64_t n, void* out, W
     }
     case RED_VARIANT_PERSISTENT: {
       int maxg = 0;
-      int rc = reduce_max_coresident(rl.dtype, rl.acc, p.ipt, nt, p.wg, dev, &maxg);
+      int rc = reduce_max_coresident(rl.dtype, rl.acc, p.ipt, nt, pipe, p.wg, dev, &maxg);
       if (rc) return rc;
       if (p.grid > 0 && p.grid > maxg)
         return set_error(RED_EINVAL, "persistent plan: grid %d exceeds the %d co-resident workgroups",
                          p.grid, maxg);
       grid = std::min(grid, maxg);
       if (grid < 1) return set_error(RED_EINVAL, "persistent kernel cannot be resident");
-      a.bar_groups = barrier_groups(grid);
+      a.bar_groups = xcd ? (kBarrierXcd | (unsigned)dev.nxcc) : barrier_groups(grid);
       const int slot = timer_begin(s);
       rc = launch(ks.persistent, grid, p.wg, args, s, (p.flags & RED_FLAG_PLAIN_LAUNCH) == 0);
       timer_end(s, slot);

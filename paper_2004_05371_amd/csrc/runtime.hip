@@ -133,6 +133,12 @@ int ensure_device(const DeviceInfo** info) {
   d.l2_bytes = prop.l2CacheSize;
   d.hbm_bytes = (int64_t)prop.totalGlobalMem;
   d.coop = prop.cooperativeLaunch != 0;
+  int nx = 1;
+  if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || nx < 1) {
+    (void)hipGetLastError();
+    nx = 1;
+  }
+  d.nxcc = nx;
   auto r = g_dev.emplace(dev, d);
   *info = &r.first->second;
   return RED_OK;
@@ -270,7 +276,7 @@ int validate_sum_args(int dtype, const void* x, int64_t n, void* out, const red_
   if (opts) {
     if (opts->acc != RED_ACC_COMPENSATED && opts->acc != RED_ACC_PLAIN)
       return set_error(RED_EINVAL, "unknown accumulation %d", opts->acc);
-    if (opts->flags & ~(RED_FLAG_NONTEMPORAL | RED_FLAG_PLAIN_LAUNCH))
+    if (opts->flags & ~(RED_FLAG_NONTEMPORAL | RED_FLAG_PLAIN_LAUNCH | RED_FLAG_PIPELINE | RED_FLAG_XCD))
       return set_error(RED_EINVAL, "unknown flags 0x%x", opts->flags);
     if (opts->plan.variant != RED_VARIANT_AUTO) {
       red_plan p = opts->plan;
@@ -308,7 +314,7 @@ int validate_seg_args(const float* x, const int64_t* offsets, int64_t nseg, doub
   if (reinterpret_cast<uintptr_t>(offsets) % 8) return set_error(RED_EINVAL, "offsets is not 8-byte aligned");
   if (reinterpret_cast<uintptr_t>(out) % 8) return set_error(RED_EINVAL, "out is not 8-byte aligned");
   if (opts) {
-    if (opts->flags & ~(RED_FLAG_NONTEMPORAL | RED_FLAG_NO_GRAPH | RED_FLAG_PLAIN_LAUNCH))
+    if (opts->flags & ~(RED_FLAG_NONTEMPORAL | RED_FLAG_NO_GRAPH | RED_FLAG_PLAIN_LAUNCH | RED_FLAG_XCD))
       return set_error(RED_EINVAL, "unknown flags 0x%x", opts->flags);
     if (opts->plan.variant != RED_VARIANT_AUTO) {
       red_plan p = opts->plan;
@@ -384,6 +390,9 @@ int red_check_error(void* stream) {
   // Clear the error and every barrier word (the barrier was abandoned).
   RED_HIP(hipMemset(ws->words, 0, kWordsBytes));
   RED_HIP(hipMemset(ws->seg_tickets, 0, kTicketBytes));
+  if (err == kErrDispatch)
+    return set_error(RED_ENOTSUP, "a workgroup ran on another XCD than round-robin dispatch implies "
+                                  "(XCD-aggregated publication is not valid on this device)");
   return set_error(RED_ETIMEOUT, "a grid-barrier watchdog fired on this stream");
 }
 
@@ -401,7 +410,7 @@ int red_sum_ex(int dtype, const void* x, int64_t n, void* out, void* stream, con
   rl.plan = (opts && opts->plan.variant != RED_VARIANT_AUTO)
                 ? complete_plan(opts->plan, default_plan(dtype, n, *dev))
                 : lookup_plan(dtype, rl.acc, n, *dev);
-  if (opts) rl.plan.flags |= opts->flags & (RED_FLAG_NONTEMPORAL | RED_FLAG_PLAIN_LAUNCH);
+  if (opts) rl.plan.flags |= opts->flags & (RED_FLAG_NONTEMPORAL | RED_FLAG_PLAIN_LAUNCH | RED_FLAG_PIPELINE | RED_FLAG_XCD);
   return reduce_launch(rl, x, n, out, ws, s, *dev);
 }
 
@@ -451,16 +460,17 @@ int red_max_coresident(int wg_size, int32_t* n_wg) {
   int rc = ensure_device(&dev);
   if (rc) return rc;
   int n = 0;
-  if ((rc = reduce_max_coresident(RED_F32, RED_ACC_COMPENSATED, 4, false, wg_size, *dev, &n))) return rc;
+  if ((rc = reduce_max_coresident(RED_F32, RED_ACC_COMPENSATED, 4, false, false, wg_size, *dev, &n))) return rc;
   *n_wg = n;
   return RED_OK;
 }
 
 int red_device_info(int32_t* cus, int64_t* wallclock_khz, int64_t* clock_khz, int64_t* l2_bytes,
-                    int64_t* hbm_bytes) {
+                    int64_t* hbm_bytes, int32_t* nxcc) {
   const DeviceInfo* dev;
   int rc = ensure_device(&dev);
   if (rc) return rc;
+  if (nxcc) *nxcc = dev->nxcc;
   if (cus) *cus = dev->cus;
   if (wallclock_khz) *wallclock_khz = dev->wallclock_khz;
   if (clock_khz) *clock_khz = dev->clock_khz;
@@ -510,8 +520,8 @@ int red_autotune(int dtype, int acc, const void* x, int64_t n, void* out, void* 
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (stream_capturing(s)) return set_error(RED_EINVAL, "autotuning cannot run inside stream capture");
   // Search: (1) nontemporal hint on the default shape; (2) every
-  // (wg, ipt, grid) of the relaunch variant with that hint; (3) the other
-  // synchronization variants on the best shape.  `budget` caps the number
+  // (pipelined?, wg, ipt, grid) of the relaunch variant with that hint;
+  // (3) the other synchronization variants on the best shape.  `budget` caps the number
   // of timed candidates (0 = no cap).  The grid candidates start at one
   // workgroup per CU; the in-flight bytes per CU (wg * ipt * 16 * grid /
   // CUs) is what the shapes trade off.
@@ -522,7 +532,8 @@ int red_autotune(int dtype, int acc, const void* x, int64_t n, void* out, void* 
     if (budget > 0 && timed >= budget) return RED_OK;
     if (p.variant == RED_VARIANT_PERSISTENT) {
       int maxg = 0;
-      int r = reduce_max_coresident(dtype, acc, p.ipt, (p.flags & RED_FLAG_NONTEMPORAL) != 0, p.wg, *dev, &maxg);
+      int r = reduce_max_coresident(dtype, acc, p.ipt, (p.flags & RED_FLAG_NONTEMPORAL) != 0,
+                                    (p.flags & RED_FLAG_PIPELINE) != 0, p.wg, *dev, &maxg);
       if (r) return r;
       if (p.grid == 0 || p.grid > maxg) p.grid = maxg;
     }
@@ -546,26 +557,30 @@ int red_autotune(int dtype, int acc, const void* x, int64_t n, void* out, void* 
   const int nt_flag = cur.flags & RED_FLAG_NONTEMPORAL;
   const int64_t nvec = n / (16 / esize(dtype));
   const int mults[] = {1, 2, 3, 4, 6, 8, 12, 16};
-  for (int wg : {128, 256, 512, 1024})
-    for (int ipt : {1, 2, 4, 8}) {
-      const int64_t tile = (int64_t)wg * ipt;
-      const int64_t want = std::max<int64_t>(1, (nvec + tile - 1) / tile);
-      for (int m : mults) {
-        const int64_t g = std::min<int64_t>({(int64_t)m * dev->cus, want, (int64_t)RED_MAX_GRID});
-        if ((rc = consider(red_plan{RED_VARIANT_RELAUNCH, wg, ipt, (int)g, nt_flag}))) return rc;
-        if (g == want) break;
+  for (int pipe : {0, RED_FLAG_PIPELINE})
+    for (int wg : {128, 256, 512, 1024})
+      for (int ipt : {1, 2, 4, 8}) {
+        const int64_t tile = (int64_t)wg * ipt;
+        const int64_t want = std::max<int64_t>(1, (nvec + tile - 1) / tile);
+        for (int m : mults) {
+          const int64_t g = std::min<int64_t>({(int64_t)m * dev->cus, want, (int64_t)RED_MAX_GRID});
+          if ((rc = consider(red_plan{RED_VARIANT_RELAUNCH, wg, ipt, (int)g, nt_flag | pipe}))) return rc;
+          if (g == want) break;
+        }
       }
-    }
   const red_plan shape = cur;
-  for (int v : {RED_VARIANT_ATOMIC, RED_VARIANT_PERSISTENT}) {
-    red_plan p = shape;
-    p.variant = v;
-    if ((rc = consider(p))) return rc;
-    if (v == RED_VARIANT_PERSISTENT) {
-      p.flags |= RED_FLAG_PLAIN_LAUNCH;
+  for (int v : {RED_VARIANT_ATOMIC, RED_VARIANT_PERSISTENT})
+    for (int xcd : {0, dev->nxcc > 1 ? RED_FLAG_XCD : 0}) {
+      red_plan p = shape;
+      p.variant = v;
+      p.flags |= xcd;
       if ((rc = consider(p))) return rc;
+      if (v == RED_VARIANT_PERSISTENT) {
+        p.flags |= RED_FLAG_PLAIN_LAUNCH;
+        if ((rc = consider(p))) return rc;
+      }
+      if (!xcd && dev->nxcc <= 1) break;
     }
-  }
   if ((rc = red_set_plan(dtype, acc, n, &cur))) return rc;
   if (best) *best = cur;
   if (best_us) *best_us = cur_us;
@@ -602,7 +617,7 @@ int red_sum_segmented_ex(const float* x, const int64_t* offsets, int64_t nseg, d
     auto it = g_plans.find(std::make_tuple(1, bucket(nseg), 0, 0));
     if (it != g_plans.end()) sl.plan = it->second;
   }
-  if (opts) sl.plan.flags |= opts->flags & (RED_FLAG_NONTEMPORAL | RED_FLAG_PLAIN_LAUNCH);
+  if (opts) sl.plan.flags |= opts->flags & (RED_FLAG_NONTEMPORAL | RED_FLAG_PLAIN_LAUNCH | RED_FLAG_XCD);
   // Persistent (co-resident) launches, the null stream and a caller's own
   // capture launch directly; otherwise the launch is replayed from a cached
   // graph.

@@ -65,6 +65,7 @@ __device__ __forceinline__ CompF32 thread_sum_range(const float* x, int64_t a, i
     v4f v[IPT];
 #pragma unroll
     for (int u = 0; u < IPT; ++u) v[u] = load_vec<NT>(p + u * bs);
+    __builtin_amdgcn_sched_barrier(0);  // all IPT loads in flight before use
 #pragma unroll
     for (int u = 0; u < IPT; ++u) M::add_vec(acc[u], v[u]);
   }
@@ -240,7 +241,8 @@ int seg_launch(const SegLaunch& sl, const float* x, const int64_t* offsets, int6
   a.tickets = ws->seg_tickets;
   a.words = ws->words;
   a.spin_limit = watchdog_spins();
-  a.bar_groups = barrier_groups(grid);
+  a.bar_groups = ((p.flags & RED_FLAG_XCD) && dev.nxcc > 1) ? (kBarrierXcd | (unsigned)dev.nxcc)
+                                                            : barrier_groups(grid);
   void* args[] = {&a};
   const bool nt = (p.flags & RED_FLAG_NONTEMPORAL) != 0;
   const bool coop = barrier && (p.flags & RED_FLAG_PLAIN_LAUNCH) == 0;

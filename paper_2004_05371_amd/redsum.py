@@ -29,6 +29,8 @@ RED_MAX_GRID = 8192
 FLAG_NONTEMPORAL = 1
 FLAG_NO_GRAPH = 2
 FLAG_PLAIN_LAUNCH = 4
+FLAG_PIPELINE = 8
+FLAG_XCD = 16
 
 STATUS_NAMES = {0: "RED_OK", -1: "RED_EINVAL", -2: "RED_ENOTSUP", -3: "RED_EHIP",
                 -4: "RED_ETIMEOUT", -5: "RED_ENOMEM", -6: "RED_ENODEV"}
@@ -42,7 +44,7 @@ EXPORTS = [
     "red_autotune_segmented", "red_set_segmented_plan", "red_get_segmented_plan",
     "red_kernel_timer", "red_kernel_timer_read", "sync_bench_wave", "sync_bench_block",
     "sync_bench_grid", "sync_bench_grid_ex", "sync_bench_relaunch", "sync_check_grid_order",
-    "sync_check_watchdog", "red_max_coresident", "red_device_info",
+    "sync_check_watchdog", "sync_xcc_map", "red_max_coresident", "red_device_info",
     "red_bw_proxy", "red_eq6_overhead", "red_eq7_latency", "red_eq8_sigma",
 ]
 
@@ -99,7 +101,8 @@ _SIGS = {
     "sync_check_grid_order": ([_i32, _i32, _i64p, _i64p, _vp], _i32),
     "sync_check_watchdog": ([_i32, _i32, _i32, _i32, _vp], _i32),
     "red_max_coresident": ([_i32, _i32p], _i32),
-    "red_device_info": ([_i32p, _i64p, _i64p, _i64p, _i64p], _i32),
+    "red_device_info": ([_i32p, _i64p, _i64p, _i64p, _i64p, _i32p], _i32),
+    "sync_xcc_map": ([_i32, _i32, _i32p, _vp], _i32),
     "red_bw_proxy": ([_vp, _i64, _i32, _i32, _vp], _i32),
     "red_eq6_overhead": ([_d, _d, _i32, _i32], _d),
     "red_eq7_latency": ([_d, _d, _i64, _i64], _d),
@@ -282,12 +285,19 @@ def red_max_coresident(wg_size: int) -> int:
 
 
 def red_device_info() -> dict:
-    cus = ctypes.c_int32()
+    cus, nx = ctypes.c_int32(), ctypes.c_int32()
     wc, ck, l2, hbm = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     _check(load().red_device_info(ctypes.byref(cus), ctypes.byref(wc), ctypes.byref(ck), ctypes.byref(l2),
-                                  ctypes.byref(hbm)), "red_device_info")
+                                  ctypes.byref(hbm), ctypes.byref(nx)), "red_device_info")
     return {"cus": cus.value, "wallclock_khz": wc.value, "clock_khz": ck.value,
-            "l2_bytes": l2.value, "hbm_bytes": hbm.value}
+            "l2_bytes": l2.value, "hbm_bytes": hbm.value, "nxcc": nx.value}
+
+
+def sync_xcc_map(n_wg: int, wg_size: int = 64, stream: int = 0):
+    """XCD of each workgroup of an ordinary launch (list of ints)."""
+    buf = (ctypes.c_int32 * n_wg)()
+    _check(load().sync_xcc_map(n_wg, wg_size, buf, stream), "sync_xcc_map")
+    return list(buf)
 
 
 def red_bw_proxy(x: int, nbytes: int, n_wg: int, wg_size: int, stream: int = 0) -> int:

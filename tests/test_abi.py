@@ -57,7 +57,7 @@ def test_validation_before_hip(lib):
     assert lib.red_sum_ex(R.RED_F32, ctypes.c_void_p(64), 4, ctypes.c_void_p(64), None, ctypes.byref(bad)) == R.RED_EINVAL
     bad = R.make_opts(acc=7)
     assert lib.red_sum_ex(R.RED_F32, ctypes.c_void_p(64), 4, ctypes.c_void_p(64), None, ctypes.byref(bad)) == R.RED_EINVAL
-    bad = R.make_opts(flags=16)
+    bad = R.make_opts(flags=32)
     assert lib.red_sum_ex(R.RED_F32, ctypes.c_void_p(64), 4, ctypes.c_void_p(64), None, ctypes.byref(bad)) == R.RED_EINVAL
     assert lib.red_sum_segmented(None, None, 3, None, None) == R.RED_EINVAL
     assert lib.red_sum_segmented(ctypes.c_void_p(64), ctypes.c_void_p(64), -1, ctypes.c_void_p(64), None) == R.RED_EINVAL

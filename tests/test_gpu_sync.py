@@ -139,3 +139,48 @@ def test_kernel_timer(lib):
     assert count == 3 and 0 < min_us <= mean_us < 1e5
     lib.sum(x)
     assert lib.red_kernel_timer_read(s)[2] == 0  # off: nothing recorded
+
+
+def test_dispatch_is_round_robin_over_xcds(lib):
+    """XCD-aggregated publication relies on workgroup g running on XCD
+    g mod nxcc; check it with the XCC_ID register."""
+    nx = lib.red_device_info()["nxcc"]
+    assert nx >= 1
+    for n in (1, 7, 64, 1000, 4096):
+        m = lib.sync_xcc_map(n, 256)
+        assert all(m[g] == g % nx for g in range(n)), n
+
+
+@pytest.mark.parametrize("variant", [2, 3])
+def test_xcd_publication_sums(lib, variant):
+    """Atomic-ticket and persistent variants with one L2 write-back per XCD:
+    int bit-exact, float within bound, grids smaller and larger than the
+    XCD count, repeated."""
+    xi = inputs.uniform_i32(3_000_017, lo=-2**31, hi=2**31 - 1, sub=17)
+    xf = inputs.mixed_f32(3_000_017, sub=18)
+    ti = torch.from_numpy(xi).to("cuda")
+    tf = torch.from_numpy(xf).to("cuda")
+    ref_i = oracle.sum_i32(xi)
+    ex_f = oracle.exact_sum(xf, "f32")
+    maxg = lib.red_max_coresident(256)
+    r = np.random.default_rng(6)
+    grids = [1, 3, 8, 9, 64, 100, 512] + [int(g) for g in r.integers(1, 2048, 20)]
+    for g in grids:
+        if variant == 3:
+            g = min(g, maxg)
+        o = lib.make_opts(variant=variant, wg=256, ipt=4, grid=g, flags=lib.FLAG_XCD | lib.FLAG_NONTEMPORAL)
+        oi = lib.sum(ti, opts=o)
+        of = lib.sum(tf, opts=o)
+        torch.cuda.synchronize()
+        assert oi.item() == ref_i, g
+        assert oracle.rel_err(of.item(), ex_f) <= 1e-6, g
+    assert lib.red_check_error(lib.current_stream()) == lib.RED_OK
+
+
+@pytest.mark.parametrize("n_wg", [1, 8, 9, 256, 1024])
+def test_xcd_barrier_probe(lib, n_wg):
+    n_wg = min(n_wg, lib.red_max_coresident(256))
+    ns, sigma, wall = lib.sync_bench_grid_ex(n_wg, 256, -1, reps=5)
+    say("grid %d WGs, XCD-aggregated: %.1f ns" % (n_wg, ns))
+    assert 0 < ns < 1e6
+    assert lib.red_check_error(lib.current_stream()) == lib.RED_OK
