@@ -125,11 +125,16 @@ def variant_table(R, plan, dtype, xt, n, out, sh, stream, dev, reps=50, flush=No
     cands = {
         "relaunch": R.make_opts(variant=1, wg=plan.wg, ipt=plan.ipt, grid=plan.grid, flags=nt),
         "atomic": R.make_opts(variant=2, wg=plan.wg, ipt=plan.ipt, grid=plan.grid, flags=nt),
+        "atomic_xcd": R.make_opts(variant=2, wg=plan.wg, ipt=plan.ipt, grid=plan.grid, flags=nt | R.FLAG_XCD),
         "persistent_cooperative": R.make_opts(variant=3, wg=plan.wg, ipt=plan.ipt, grid=min(g, coresident),
                                               flags=nt),
         "persistent_plain_launch": R.make_opts(variant=3, wg=plan.wg, ipt=plan.ipt, grid=min(g, coresident),
                                                flags=nt | R.FLAG_PLAIN_LAUNCH),
+        "persistent_xcd_plain_launch": R.make_opts(variant=3, wg=plan.wg, ipt=plan.ipt, grid=min(g, coresident),
+                                                   flags=nt | R.FLAG_PLAIN_LAUNCH | R.FLAG_XCD),
     }
+    if nbytes <= (64 << 20):
+        cands["single_workgroup"] = R.make_opts(variant=4, wg=1024, ipt=2, grid=1)
     res = {}
     for name, o in cands.items():
         fn = (lambda o=o: R.red_sum_ex(dtype, xt.data_ptr(), n, out.data_ptr(), sh, o))
@@ -140,6 +145,8 @@ def variant_table(R, plan, dtype, xt, n, out, sh, stream, dev, reps=50, flush=No
         else:
             tt = time_flushed(fn, reps, stream, flush)
         res[name] = gbps(nbytes, statistics.median(tt))
+    if R.red_check_error(sh) != R.RED_OK:
+        res["error"] = R.last_error()
     return res
 
 

@@ -70,8 +70,12 @@ typedef enum {
                                    one-workgroup final kernel on the same stream */
     RED_VARIANT_ATOMIC = 2,     /* one kernel; the last workgroup to take an
                                    atomic ticket does the final combine        */
-    RED_VARIANT_PERSISTENT = 3  /* one cooperative kernel; grid barrier, then
+    RED_VARIANT_PERSISTENT = 3, /* one cooperative kernel; grid barrier, then
                                    workgroup 0 does the final combine          */
+    RED_VARIANT_SINGLE = 4      /* one workgroup, no device-wide
+                                   synchronization at all: the "use fewer
+                                   workers" side of the performance model
+                                   (Section VII-A, Eq. 2-5), for small n      */
 } red_variant;
 
 /* In-register accumulation of floating-point inputs. */

@@ -31,7 +31,7 @@ FORMAT = 1
 DTYPES = {"i32": R.RED_I32, "f32": R.RED_F32, "f16": R.RED_F16, "bf16": R.RED_BF16}
 ACCS = {"compensated": R.RED_ACC_COMPENSATED, "plain": R.RED_ACC_PLAIN}
 VARIANTS = {"relaunch": R.RED_VARIANT_RELAUNCH, "atomic": R.RED_VARIANT_ATOMIC,
-            "persistent": R.RED_VARIANT_PERSISTENT}
+            "persistent": R.RED_VARIANT_PERSISTENT, "single": R.RED_VARIANT_SINGLE}
 
 
 def cache_path(path: Optional[str] = None) -> str:

@@ -388,7 +388,8 @@ struct BarrierWords {
   Line ticket;  // atomic-final variant: workgroups that have stored a partial
   Line err;     // watchdog flag (nonzero after a timeout)
   Line acc_lo;  // atomic-final int accumulator (int64 in acc_lo.v/acc_lo.pad[0])
-  Line group[kMaxBarrierGroups];  // arrivals per group (two-level barrier)
+  Line xcd_mask;  // XCD-aggregated publication: dispatch offsets seen (bit mask)
+  Line group[kMaxBarrierGroups];  // arrivals per group (two-level / per-XCD barrier)
 };
 
 __device__ __forceinline__ long long* acc_i64(BarrierWords* w) {
@@ -402,40 +403,54 @@ __device__ __forceinline__ unsigned relaxed_add(unsigned* p, unsigned v) {
 // ---------------------------------------------------------------------------
 // XCD-aggregated publication.
 //
-// Workgroups are dispatched to the XCDs round-robin (workgroup g runs on XCD
-// g mod nxcc; the library checks this with the XCC_ID register).  All
-// workgroups of one XCD share that XCD's L2, and a store is in that L2 once
-// the issuing wave's vector-memory counter has drained.  So instead of one
-// L2 write-back per workgroup (an agent-scope release fence), each
-// workgroup drains its stores and counts itself on its XCD's counter; the
-// last arrival of the XCD performs ONE agent-scope release (write-back of
-// that L2, which holds every member's stores) before it signals onward.  A
-// workgroup that finds itself on an unexpected XCD publishes with its own
-// release fence and sets err = kErrDispatch, so a violated assumption is
-// reported instead of silently trusted.
+// The dispatcher hands workgroups to the XCDs round-robin: within one
+// launch workgroup g runs on XCD (g + off) mod nxcc for a launch-wide offset
+// off (measured on MI355X).  All workgroups of one XCD share that XCD's L2,
+// and a store is in that L2 once the issuing wave's vector-memory counter
+// has drained.  So instead of one L2 write-back per workgroup (an
+// agent-scope release fence), each workgroup drains its stores and counts
+// itself on the counter of the XCD it runs on (its XCC_ID register); the
+// number of workgroups on that XCD is the number of g' with
+// g' = g (mod nxcc), whatever the offset.  The last arrival of the XCD
+// performs ONE agent-scope release (write-back of that L2, which holds every
+// member's stores) before it signals onward.  Every workgroup also records
+// the offset it implies in a bit mask; the final arrival reports more than
+// one offset (dispatch not round-robin) as err = kErrDispatch.
 // ---------------------------------------------------------------------------
 constexpr unsigned kErrTimeout = 1u;
 constexpr unsigned kErrDispatch = 2u;
 constexpr unsigned kBarrierXcd = 0x100u;  // groups value: XCD-aggregated barrier (| nxcc)
 
-// Makes this workgroup's earlier global stores visible to the members of
-// its XCD group and counts it there; returns true for the last member of
-// the group (which must then release agent-wide before signalling).
+// Makes this workgroup's earlier global stores visible to the other
+// workgroups of its XCD and counts it there; returns true for the last
+// arrival of the XCD, which has then released agent-wide for all of them.
 // Thread 0 only; every wave of the workgroup must have drained its stores
 // (s_waitcnt) before the workgroup barrier that precedes this call.
 __device__ __forceinline__ bool xcd_arrive(BarrierWords* w, unsigned nblocks, unsigned nxcc) {
-  const unsigned grp = blockIdx.x % nxcc;
-  const unsigned members = (nblocks - grp + nxcc - 1) / nxcc;
+  const unsigned r = blockIdx.x % nxcc;
+  const unsigned members = (nblocks - r + nxcc - 1) / nxcc;
+  unsigned phys = xcc_id();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_s_waitcnt(0);
-  if (xcc_id() != grp) {
+  if (phys >= nxcc) {  // not a valid XCD index for this grid: publish alone, report
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __hip_atomic_store(&w->err.v, kErrDispatch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    phys = r;
   }
-  if (relaxed_add(&w->group[grp].v, 1u) != members - 1) return false;
-  __hip_atomic_store(&w->group[grp].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const unsigned off = (phys + nxcc - r) % nxcc;
+  __hip_atomic_fetch_or(&w->xcd_mask.v, 1u << off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_s_waitcnt(0);
+  if (relaxed_add(&w->group[phys].v, 1u) != members - 1) return false;
+  __hip_atomic_store(&w->group[phys].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
   return true;
+}
+
+// Final arrival of an XCD-aggregated publication (after its acquire): check
+// that every workgroup implied the same dispatch offset, reset the mask.
+__device__ __forceinline__ void xcd_finish(BarrierWords* w) {
+  const unsigned m = __hip_atomic_exchange(&w->xcd_mask.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (m & (m - 1)) __hip_atomic_store(&w->err.v, kErrDispatch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------
@@ -494,6 +509,7 @@ __device__ __forceinline__ bool grid_barrier(BarrierWords* w, unsigned nblocks, 
     if (last) {
       __hip_atomic_store(&w->count.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+      if (xcd) xcd_finish(w);
       relaxed_add(&w->gen.v, 1u);
     } else {
       unsigned spins = 0;

@@ -85,6 +85,7 @@ struct ReduceLaunch {
 };
 int validate_plan(const red_plan& p);
 red_plan default_plan(int dtype, int64_t n, const DeviceInfo& dev);
+int64_t single_wg_switch_bytes();  // Eq. 5 switch point (bytes) of the default plan
 int reduce_launch(const ReduceLaunch& rl, const void* x, int64_t n, void* out, Workspace* ws,
                   hipStream_t s, const DeviceInfo& dev);
 int reduce_max_coresident(int dtype, int acc, int ipt, bool nt, bool pipe, int wg, const DeviceInfo& dev,

@@ -107,6 +107,7 @@ __global__ void k_reset_words(BarrierWords* w) {
     w->ticket.v = 0;
     w->err.v = 0;
     *acc_i64(w) = 0;
+    w->xcd_mask.v = 0;
     for (int i = 0; i < kMaxBarrierGroups; ++i) w->group[i].v = 0;
   }
 }

@@ -216,6 +216,7 @@ __global__ __launch_bounds__(1024) void k_atomic(ReduceArgs a) {
   if (!is_last) return;
   // Last workgroup: every thread acquires before reading the others' data.
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (a.xcd_nxcc > 1 && threadIdx.x == 0) xcd_finish(w);
   if constexpr (__is_same(Part, long long)) {
     if (threadIdx.x == 0) {
       long long s = __hip_atomic_load(acc_i64(w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -247,6 +248,16 @@ __global__ __launch_bounds__(1024) void k_persistent(ReduceArgs a) {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   Part s = combine_partials<Part>(static_cast<const Part*>(a.partials), gridDim.x);
   if (threadIdx.x == 0) *static_cast<Part*>(a.out) = s;
+}
+
+// ---------------------------------------------------------------------------
+// Variant 4, one workgroup: the whole sum in one workgroup, written directly
+// (no partials, no device-wide synchronization).
+// ---------------------------------------------------------------------------
+template <class M, int IPT, bool NT, bool PIPE>
+__global__ __launch_bounds__(1024) void k_single(ReduceArgs a) {
+  typename M::Part p = workgroup_partial<M, IPT, NT, PIPE>(a);
+  if (threadIdx.x == 0) *static_cast<typename M::Part*>(a.out) = p;
 }
 
 template <class Part>
@@ -281,13 +292,15 @@ struct KernelSet {
   const void* partials;
   const void* atomic;
   const void* persistent;
+  const void* single;
 };
 
 template <class M, int IPT, bool NT, bool PIPE>
 KernelSet make_set() {
   return KernelSet{reinterpret_cast<const void*>(&k_partials<M, IPT, NT, PIPE>),
                    reinterpret_cast<const void*>(&k_atomic<M, IPT, NT, PIPE>),
-                   reinterpret_cast<const void*>(&k_persistent<M, IPT, NT, PIPE>)};
+                   reinterpret_cast<const void*>(&k_persistent<M, IPT, NT, PIPE>),
+                   reinterpret_cast<const void*>(&k_single<M, IPT, NT, PIPE>)};
 }
 
 template <class M, bool NT, bool PIPE>
@@ -329,7 +342,7 @@ constexpr int kFinalWG = 256;
 }  // namespace
 
 int validate_plan(const red_plan& p) {
-  if (p.variant < RED_VARIANT_RELAUNCH || p.variant > RED_VARIANT_PERSISTENT)
+  if (p.variant < RED_VARIANT_RELAUNCH || p.variant > RED_VARIANT_SINGLE)
     return set_error(RED_EINVAL, "plan: variant %d out of range", p.variant);
   if (p.wg < 64 || p.wg > 1024 || p.wg % 64 != 0)
     return set_error(RED_EINVAL, "plan: workgroup size %d must be a multiple of 64 in [64, 1024]", p.wg);
@@ -341,17 +354,55 @@ int validate_plan(const red_plan& p) {
   return RED_OK;
 }
 
-// Default shape (measured on MI355X): 256 threads x 4 loads of 16 bytes,
-// two workgroups per CU (32 KiB in flight per CU), nontemporal loads.
+// Performance model of Section VII-A (Eq. 1-5) between one workgroup
+// ("basic": latency T, throughput Thr_basic) and the whole device ("more":
+// T + T_sync, Thr_more).  With C = T * Thr (Eq. 1), n bytes go to the basic
+// configuration when n <= C_basic; between the two concurrencies when
+// n < N_m = (T + T_sync) * Thr_basic (Eq. 4); beyond both when
+// n < N_l = T_sync * Thr_more * Thr_basic / (Thr_more - Thr_basic) (Eq. 5).
+// Constants measured on MI355X (one 1024-thread workgroup with two 16-byte
+// loads per thread; the device-wide atomic-ticket variant on a grid sized
+// by the work); the small-size sweep puts the measured crossover at about
+// 2^17 fp32 elements, the model at (T + T_sync) * Thr_basic = 500 KB.
+constexpr double kModelTBasicUs = 4.2;        // one-workgroup kernel, fixed cost
+constexpr double kModelTsyncUs = 0.8;         // extra fixed cost of the device-wide kernel
+constexpr double kModelThrBasicGBps = 100.0;  // one workgroup
+constexpr double kModelThrMoreGBps = 7000.0;  // whole device
+// Above this many bytes the two-kernel relaunch variant overtakes the
+// atomic ticket (its publication cost grows with the grid): measured.
+constexpr int64_t kAtomicMaxBytes = 2LL << 20;
+
+int64_t single_wg_switch_bytes() {
+  const double tb = kModelThrBasicGBps * 1e3, tm = kModelThrMoreGBps * 1e3;  // bytes / us
+  const double c_basic = kModelTBasicUs * tb;                                // Eq. 1
+  const double c_more = kModelTBasicUs * tm;
+  const double n_m = (kModelTBasicUs + kModelTsyncUs) * tb;                  // Eq. 4
+  const double n_l = kModelTsyncUs * tm * tb / (tm - tb);                    // Eq. 5
+  // Scenario 2 applies when N_m lies between the concurrencies.
+  double n = (n_m > c_basic && n_m <= c_more) ? n_m : std::max(c_basic, n_l);
+  return (int64_t)n;
+}
+
+// Default plan (measured on MI355X): below the model's switch point one
+// 1024-thread workgroup; up to kAtomicMaxBytes the atomic-ticket variant;
+// beyond, the relaunch variant with 256 threads x 4 loads of 16 bytes, two
+// workgroups per CU (32 KiB in flight per CU) and nontemporal loads.
 red_plan default_plan(int dtype, int64_t n, const DeviceInfo& dev) {
-  (void)dtype;
-  (void)n;
   red_plan p;
-  p.variant = RED_VARIANT_RELAUNCH;
+  const int64_t bytes = n * (dtype == RED_I32 || dtype == RED_F32 ? 4 : 2);
+  p.flags = RED_FLAG_NONTEMPORAL;
+  if (bytes < single_wg_switch_bytes()) {
+    p.variant = RED_VARIANT_SINGLE;
+    p.wg = 1024;
+    p.ipt = 2;
+    p.grid = 1;
+    p.flags = 0;
+    return p;
+  }
+  p.variant = bytes <= kAtomicMaxBytes ? RED_VARIANT_ATOMIC : RED_VARIANT_RELAUNCH;
   p.wg = 256;
   p.ipt = 4;
   p.grid = 2 * dev.cus;  // capped by the work at launch
-  p.flags = RED_FLAG_NONTEMPORAL;
   return p;
 }
 
@@ -423,6 +474,12 @@ int reduce_launch(const ReduceLaunch& rl, const void* x, int64_t n, void* out, W
                               : (wave ? reinterpret_cast<const void*>(&k_final_wave<double>)
                                       : reinterpret_cast<const void*>(&k_final<double>));
       return launch(fn, 1, wave ? kWave : kFinalWG, fargs, s, false);
+    }
+    case RED_VARIANT_SINGLE: {
+      const int slot = timer_begin(s);
+      int rc = launch(ks.single, 1, p.wg, args, s, false);
+      timer_end(s, slot);
+      return rc;
     }
     case RED_VARIANT_ATOMIC: {
       const int slot = timer_begin(s);

@@ -568,9 +568,20 @@ int red_autotune(int dtype, int acc, const void* x, int64_t n, void* out, void* 
           if (g == want) break;
         }
       }
+  // One workgroup (no device-wide synchronization) for small inputs.
+  if (n * esize(dtype) <= 64 * single_wg_switch_bytes())
+    for (int wg : {256, 512, 1024})
+      for (int ipt : {1, 2, 4})
+        for (int pipe : {0, RED_FLAG_PIPELINE})
+          if ((rc = consider(red_plan{RED_VARIANT_SINGLE, wg, ipt, 1, nt_flag | pipe}))) return rc;
   const red_plan shape = cur;
+  // XCD-aggregated publication relies on the dispatch order (checked in the
+  // kernels); it is a candidate only when REDSUM_ALLOW_XCD=1.
+  const char* allow = getenv("REDSUM_ALLOW_XCD");
+  const bool try_xcd = dev->nxcc > 1 && allow && atoi(allow) == 1;
   for (int v : {RED_VARIANT_ATOMIC, RED_VARIANT_PERSISTENT})
-    for (int xcd : {0, dev->nxcc > 1 ? RED_FLAG_XCD : 0}) {
+    for (int xcd : {0, try_xcd ? RED_FLAG_XCD : 0}) {
+      if (shape.variant == RED_VARIANT_SINGLE) break;
       red_plan p = shape;
       p.variant = v;
       p.flags |= xcd;
@@ -579,7 +590,7 @@ int red_autotune(int dtype, int acc, const void* x, int64_t n, void* out, void* 
         p.flags |= RED_FLAG_PLAIN_LAUNCH;
         if ((rc = consider(p))) return rc;
       }
-      if (!xcd && dev->nxcc <= 1) break;
+      if (!xcd && !try_xcd) break;
     }
   if ((rc = red_set_plan(dtype, acc, n, &cur))) return rc;
   if (best) *best = cur;

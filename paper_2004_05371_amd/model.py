@@ -13,9 +13,10 @@ which gives two switch points: N_m (Eq. 4) when N lies between the two
 concurrencies, and N_l (Eq. 5) when N exceeds both.  All quantities share
 one time unit (cycles in the paper) and bytes.
 
-The autotuner uses the same reasoning as its prior (never launch more
-workgroups than the work keeps busy); ``mi355x_switch_points`` evaluates
-the model with latencies measured by the library's probes.
+The library's default plan applies the same rule on MI355X: one workgroup
+(no device-wide synchronization) below the switch point computed from
+measured latencies and throughputs (``mi355x_single_workgroup_switch``),
+the whole device above it.
 """
 from __future__ import annotations
 
@@ -89,18 +90,30 @@ class Scenario:
         return n_bytes < self.n_l()
 
 
-def mi355x_switch_points(wave_reduce_ns: float, block_barrier_ns: float, lds_bytes_per_ns: float,
-                         clock_ghz: float = 2.4):
-    """Switch points for MI355X from probe measurements, in bytes.
+def switch_point(t_basic: float, t_sync: float, thr_basic: float, thr_more: float) -> float:
+    """Bytes below which the basic configuration wins, by the scenario rule
+    of Section VII-A: within the basic concurrency always basic; between
+    the concurrencies N_m (Eq. 4); beyond both N_l (Eq. 5).  Times and
+    throughputs in any consistent units (e.g. us and bytes/us)."""
+    c_basic = concurrency(t_basic, thr_basic)
+    c_more = concurrency(t_basic, thr_more)
+    n_m = switch_point_m(t_basic, t_sync, thr_basic)
+    if c_basic < n_m <= c_more:
+        return n_m
+    return max(c_basic, switch_point_l(t_sync, thr_more, thr_basic))
 
-    Scenario 1: one lane vs one wavefront (64 lanes) reading LDS; the
-    wavefront pays one full wavefront combine.  Scenario 2: one wavefront vs
-    a 1024-thread workgroup; the workgroup pays a barrier plus a combine.
-    ``lds_bytes_per_ns`` is the single-lane LDS streaming rate."""
-    cyc = clock_ghz
-    thr1 = lds_bytes_per_ns / cyc                  # bytes / cycle, one lane
-    s1 = Scenario("1 lane vs 1 wave", latency=64.0, thr_basic=thr1, thr_more=64 * thr1,
-                  t_sync=wave_reduce_ns * cyc)
-    s2 = Scenario("1 wave vs 1024 threads", latency=64.0, thr_basic=64 * thr1, thr_more=1024 * thr1,
-                  t_sync=(block_barrier_ns + wave_reduce_ns) * cyc)
-    return {s.name: {"n_l_bytes": s.n_l(), "n_m_bytes": s.n_m()} for s in (s1, s2)}
+
+# MI355X measurements (one GPU): one 1024-thread workgroup streaming fp32
+# (fixed cost 4.2 us, 100 GB/s) against the device-wide atomic-ticket
+# kernel (fixed cost 5.0 us, about 7000 GB/s) and the two-kernel relaunch
+# path (6.9 us).  The library's default plan uses the same constants.
+MI355X = {"t_single_us": 4.2, "thr_single_GBps": 100.0, "t_atomic_us": 5.0, "t_relaunch_us": 6.9,
+          "thr_device_GBps": 7000.0}
+
+
+def mi355x_single_workgroup_switch(versus: str = "atomic", m: dict = MI355X) -> float:
+    """Bytes below which one workgroup beats the device-wide kernel on
+    MI355X (scenario rule with the measured constants)."""
+    t_more = m["t_atomic_us"] if versus == "atomic" else m["t_relaunch_us"]
+    return switch_point(m["t_single_us"], t_more - m["t_single_us"], m["thr_single_GBps"] * 1e3,
+                        m["thr_device_GBps"] * 1e3)

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_PKG, "libredsum.so")
 RED_I32, RED_F32, RED_F16, RED_BF16 = 0, 1, 2, 3
 RED_OK, RED_EINVAL, RED_ENOTSUP, RED_EHIP, RED_ETIMEOUT, RED_ENOMEM, RED_ENODEV = 0, -1, -2, -3, -4, -5, -6
 RED_VARIANT_AUTO, RED_VARIANT_RELAUNCH, RED_VARIANT_ATOMIC, RED_VARIANT_PERSISTENT = 0, 1, 2, 3
+RED_VARIANT_SINGLE = 4
 RED_ACC_COMPENSATED, RED_ACC_PLAIN = 0, 1
 RED_WAVE_DPP, RED_WAVE_SWIZZLE, RED_WAVE_BPERMUTE, RED_WAVE_DPP_STEP = 0, 1, 2, 3
 RED_MAX_GRID = 8192
@@ -34,7 +35,7 @@ FLAG_XCD = 16
 
 STATUS_NAMES = {0: "RED_OK", -1: "RED_EINVAL", -2: "RED_ENOTSUP", -3: "RED_EHIP",
                 -4: "RED_ETIMEOUT", -5: "RED_ENOMEM", -6: "RED_ENODEV"}
-VARIANT_NAMES = {1: "relaunch", 2: "atomic", 3: "persistent"}
+VARIANT_NAMES = {1: "relaunch", 2: "atomic", 3: "persistent", 4: "single"}
 
 # every symbol declared in include/redsum.h
 EXPORTS = [

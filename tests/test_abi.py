@@ -97,3 +97,16 @@ def test_host_probe_formulas_match_oracle(lib):
     a = [10.0, 12.0, 11.0, 13.0, 9.0, 10.5]
     b = [5.0, 5.5, 4.5, 5.0, 6.0, 5.25]
     assert R.red_eq8_sigma(a, b, 64, 8) == pytest.approx(oracle.sigma_eq8(a, b, 64, 8), rel=1e-12)
+
+
+def test_default_plan_follows_model_switch_point(lib):
+    """Small inputs default to one workgroup (no device-wide sync), large
+    ones to the relaunch variant (Eq. 5 switch point)."""
+    small = R.red_get_plan(R.RED_F32, R.RED_ACC_COMPENSATED, 1000)
+    assert small.variant == R.RED_VARIANT_SINGLE
+    mid = R.red_get_plan(R.RED_F32, R.RED_ACC_COMPENSATED, 1 << 18)
+    assert mid.variant == R.RED_VARIANT_ATOMIC
+    large = R.red_get_plan(R.RED_F32, R.RED_ACC_COMPENSATED, 1 << 28)
+    assert large.variant == R.RED_VARIANT_RELAUNCH
+    # the same switch point in bytes for 16-bit inputs
+    assert R.red_get_plan(R.RED_BF16, R.RED_ACC_COMPENSATED, 2000).variant == R.RED_VARIANT_SINGLE

@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-VARIANTS = [1, 2, 3]  # relaunch, atomic, persistent
+VARIANTS = [1, 2, 3, 4]  # relaunch, atomic, persistent, single workgroup
 BOUND = {"f32": 1e-6, "f16": 1e-3, "bf16": 1e-3}
 
 
@@ -94,6 +94,8 @@ def test_int32_plans(lib, wg, ipt, grid):
         g = grid
         if variant == 3:
             g = min(grid, lib.red_max_coresident(wg))
+        if variant == 4:
+            g = 1
         assert gpu_sum(lib, t, variant=variant, wg=wg, ipt=ipt, grid=g) == ref
 
 

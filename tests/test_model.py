@@ -49,7 +49,21 @@ def test_eq2_matches_switch_point():
     assert not model.prefer_basic(nl * 1.02, t, ts, tb, tm)
 
 
-def test_mi355x_points_are_positive():
-    pts = model.mi355x_switch_points(wave_reduce_ns=40.0, block_barrier_ns=100.0, lds_bytes_per_ns=4.0)
-    for v in pts.values():
-        assert v["n_l_bytes"] > 0 and v["n_m_bytes"] > 0
+def test_scenario_rule_matches_eq2():
+    """The closed-form switch point agrees with Eq. 2 evaluated directly, in
+    the scenario it selects."""
+    for t, ts, tb, tm in [(4.2, 0.8, 100e3, 7000e3), (13.0, 110.0, 0.62, 19.6), (13.0, 420.0, 19.6, 215.0)]:
+        n = model.switch_point(t, ts, tb, tm)
+        assert model.prefer_basic(n * 0.97, t, ts, tb, tm)
+        assert not model.prefer_basic(n * 1.03, t, ts, tb, tm)
+
+
+def test_mi355x_switch_points():
+    """With the measured MI355X constants the model puts the one-workgroup /
+    whole-device switch between the measured crossovers (2^16 and 2^17
+    fp32 elements against the atomic ticket, about 2^17 against relaunch)."""
+    n_atomic = model.mi355x_single_workgroup_switch("atomic")
+    n_relaunch = model.mi355x_single_workgroup_switch("relaunch")
+    assert 2**16 * 4 <= n_atomic <= 2**17 * 4 * 1.1
+    assert 2**17 * 4 * 0.9 <= n_relaunch <= 2**18 * 4
+    assert n_relaunch > n_atomic
