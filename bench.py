@@ -37,6 +37,10 @@ N = 1 << 28
 METRIC = "reduction GB/s & % of HBM peak (fp32, 2^28 elems); grid-barrier latency ns"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_f32_2p28.json")
 CSRC = os.path.join(ROOT, "paper_2004_05371_amd", "csrc")
+# Sources of the dominant streaming kernel (the traffic summary is tied to them).
+KERNEL_SOURCES = ("device_prims.h", "reduce.hip")
+# The timed loop records kernel events on every TIMER_PERIOD-th step.
+TIMER_PERIOD = 8
 
 
 def log(*a):
@@ -45,7 +49,7 @@ def log(*a):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in sorted(os.listdir(CSRC)):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
@@ -331,11 +335,11 @@ def run_configs(R, dev, stream, path, plans):
         cores = R.red_max_coresident(wg)
         n = 1
         while n <= min(2048, cores):
-            for groups in ((1, 8, 0) if n >= 64 else (1,)):
+            for groups in ((1, 8, 0, -1) if n >= 64 else (1, -1)):
                 ns, sg, wall = R.sync_bench_grid_ex(n, wg, groups, reps=20)
                 emit({"probe": "grid", "wg": wg, "n_wg": n, "wg_per_cu": round(n / dev["cus"], 3),
-                      "groups": groups or "default", "ns": round(ns, 1), "sigma_ns": round(sg, 1),
-                      "in_kernel_ns": round(wall, 1)})
+                      "groups": {0: "default", -1: "xcd"}.get(groups, groups), "ns": round(ns, 1),
+                      "sigma_ns": round(sg, 1), "in_kernel_ns": round(wall, 1)})
             n *= 2
     for coop in (False, True):
         ns, sg, null_ns = R.sync_bench_relaunch(dev["cus"], 256, cooperative=coop, reps=30)
@@ -406,10 +410,10 @@ def headline(args, R, dev, stream, sh, plans, inputs):
     for _ in range(args.warmup):
         step()
     # Timed region: K steps between two synchronizations, with the library
-    # recording HIP events around the dominant kernel of every step (on the
-    # stream it runs on) for the roofline.
+    # recording HIP events around the dominant kernel of every
+    # TIMER_PERIOD-th step (on the stream it runs on) for the roofline.
     torch.cuda.synchronize()
-    R.red_kernel_timer(sh, True)
+    R.red_kernel_timer(sh, TIMER_PERIOD)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
@@ -435,6 +439,7 @@ def headline(args, R, dev, stream, sh, plans, inputs):
         (ms_per_step, wall_plain * 1e3 / args.steps, statistics.fmean(times), k_mean_us, k_min_us, k_count))
 
     extra = {"GBps_without_kernel_events": round(nbytes / (wall_plain / args.steps) / 1e9, 1),
+             "kernel_events_every_n_steps": TIMER_PERIOD, "kernel_launches_timed": k_count,
              "step_event_mean_us": round(statistics.fmean(times) * 1e3, 2),
              "dominant_kernel_mean_us": round(k_mean_us, 2), "dominant_kernel_min_us": round(k_min_us, 2)}
     extra["variants_GBps"] = variant_table(R, plan, R.RED_F32, xt, N, out, sh, stream, dev)
@@ -450,7 +455,7 @@ def headline(args, R, dev, stream, sh, plans, inputs):
         gb = {}
         for n_wg in (cus, 4 * cus):
             n = min(n_wg, R.red_max_coresident(256))
-            for groups, name in ((1, "flat"), (0, "two_level")):
+            for groups, name in ((1, "flat"), (0, "two_level"), (-1, "xcd")):
                 ns, sg, wall_ns = R.sync_bench_grid_ex(n, 256, groups, reps=20)
                 gb["%d_wg_%s" % (n, name)] = {"ns": round(ns, 1), "sigma_ns": round(sg, 1),
                                               "in_kernel_ns": round(wall_ns, 1)}

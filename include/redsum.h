@@ -315,9 +315,11 @@ int sync_xcc_map(int n_wg, int wg_size, int32_t *host_xcc, void *stream);
  * Measurement helpers (not part of a reduction)
  * ------------------------------------------------------------------- */
 
-/* While enabled on `stream`, every reduction / segmented launch on it
- * records a pair of HIP events around its dominant streaming kernel (the
- * partials kernel of the relaunch variant, the single kernel otherwise).
+/* While enabled on `stream`, reduction / segmented launches on it record a
+ * pair of HIP events (without system-scope fences) around their dominant
+ * streaming kernel (the partials kernel of the relaunch variant, the single
+ * kernel otherwise).  enable = 0 turns the timer off; enable = k > 0 times
+ * every k-th launch (k > 1 keeps the events' own cost off most launches).
  * Enabling clears earlier records.  Not recorded inside stream capture. */
 int red_kernel_timer(void *stream, int enable);
 

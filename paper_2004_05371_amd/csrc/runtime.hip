@@ -194,7 +194,8 @@ int get_workspace(hipStream_t s, Workspace** out) {
 // ---------------------------------------------------------------------------
 namespace {
 struct KernelTimer {
-  bool on = false;
+  int period = 0;        // 0 = off; k = time every k-th launch
+  uint64_t launches = 0; // launches seen while on
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
   size_t used = 0;
 };
@@ -206,9 +207,10 @@ int timer_begin(hipStream_t s) {
   if (hipGetDevice(&dev) != hipSuccess) return -1;
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_timers.find(std::make_pair(dev, s));
-  if (it == g_timers.end() || !it->second.on) return -1;
+  if (it == g_timers.end() || it->second.period <= 0) return -1;
   if (stream_capturing(s)) return -1;
   KernelTimer& t = it->second;
+  if (t.launches++ % (uint64_t)t.period != 0) return -1;
   if (t.used == t.ev.size()) {
     hipEvent_t a, b;
     if (hipEventCreateWithFlags(&a, hipEventDisableSystemFence) != hipSuccess) return -1;
@@ -681,8 +683,10 @@ int red_kernel_timer(void* stream, int enable) {
   if (rc) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::lock_guard<std::mutex> lk(g_mu);
+  if (enable < 0) return set_error(RED_EINVAL, "enable must be >= 0");
   KernelTimer& t = g_timers[std::make_pair(dev->id, s)];
-  t.on = enable != 0;
+  t.period = enable;
+  t.launches = 0;
   t.used = 0;
   return RED_OK;
 }

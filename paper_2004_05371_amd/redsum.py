@@ -222,8 +222,9 @@ def red_get_segmented_plan(nseg: int) -> Plan:
     return p
 
 
-def red_kernel_timer(stream: int = 0, enable: bool = True) -> int:
-    return _check(load().red_kernel_timer(stream, int(bool(enable))), "red_kernel_timer")
+def red_kernel_timer(stream: int = 0, enable=True) -> int:
+    """enable: False/0 off, True/1 every launch, k > 1 every k-th launch."""
+    return _check(load().red_kernel_timer(stream, int(enable)), "red_kernel_timer")
 
 
 def red_kernel_timer_read(stream: int = 0):

@@ -139,6 +139,12 @@ def test_kernel_timer(lib):
     assert count == 3 and 0 < min_us <= mean_us < 1e5
     lib.sum(x)
     assert lib.red_kernel_timer_read(s)[2] == 0  # off: nothing recorded
+    lib.red_kernel_timer(s, 3)  # every third launch: launches 0, 3 and 6 of 7
+    for _ in range(7):
+        lib.sum(x, opts=lib.make_opts(variant=1))
+    mean_us, min_us, count = lib.red_kernel_timer_read(s)
+    lib.red_kernel_timer(s, False)
+    assert count == 3 and 0 < min_us <= mean_us < 1e5
 
 
 def test_dispatch_is_round_robin_over_xcds(lib):
