@@ -69,6 +69,135 @@ def traffic_per_launch(plan_dict):
     return d.get("bytes_per_launch")
 
 
+VARIANT_KERNELS = {"relaunch": "k_partials", "atomic": "k_atomic", "persistent": "k_persistent",
+                   "single": "k_single"}
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+GIB_KIB = float(1 << 20)  # 1 GiB in KiB
+
+
+def dominant_kernel_name(plan_dict) -> str:
+    """Full name, as the profiler prints it, of the kernel that streams the
+    fp32 compensated input under `plan_dict`."""
+    f = int(plan_dict.get("flags", 0))
+    return "void redsum::%s<redsum::ModeF32Comp, %d, %s, %s>(redsum::ReduceArgs)" % (
+        VARIANT_KERNELS[plan_dict["variant"]], int(plan_dict["ipt"]), "true" if f & 1 else "false",
+        "true" if f & 8 else "false")
+
+
+def last_json_line(path):
+    with open(path) as fh:
+        return json.loads([l for l in fh.read().splitlines() if l.startswith("{")][-1])
+
+
+def counter_values(path, counter):
+    """{kernel name: [per-dispatch values]} from a rocprofv3 counter CSV."""
+    import csv
+    vals = {}
+    with open(path) as fh:
+        for row in csv.DictReader(fh):
+            if row["Counter_Name"] == counter:
+                vals.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+    return vals
+
+
+def summarize_pmc(fetch_dir, write_dir, bench_json, out_dir):
+    """HBM traffic per launch of the dominant kernel from two rocprofv3
+    --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by
+    the same counter on the 1 GiB device-to-device copies of the same run
+    (2^30 bytes read and written).  Writes hbm_traffic_f32_2p28.{json,md}."""
+    line = last_json_line(bench_json)
+    plan = line["config"]["plan"]
+    name = dominant_kernel_name(plan)
+    fetch = counter_values(os.path.join(fetch_dir, "run_counter_collection.csv"), "FETCH_SIZE")
+    write = counter_values(os.path.join(write_dir, "run_counter_collection.csv"), "WRITE_SIZE")
+    kf, kw = fetch[name], write[name]
+    # the calibration copies are the 1 GiB ones (other copies move a few bytes)
+    cf = [v for v in fetch[COPY_KERNEL] if v > GIB_KIB / 4]
+    cw = [v for v in write[COPY_KERNEL] if v > GIB_KIB / 4]
+    if not (kf and kw and cf and cw):
+        raise SystemExit("counter runs hold no dominant-kernel or 1 GiB copy dispatches")
+    f_kib, w_kib = statistics.mean(kf), statistics.mean(kw)
+    f_scale, w_scale = GIB_KIB / statistics.median(cf), GIB_KIB / statistics.median(cw)
+    traffic = int(round((f_kib * f_scale + w_kib * w_scale) * 1024))
+    algo = N * 4 + 8 * int(plan["grid"]) + 8
+    cmd = ("rocprofv3 --pmc %s --output-format csv -d <dir> -o run -- python3 bench.py --steps 5 --warmup 2 "
+           "--no-cpu-baseline --no-probes --calibrate-copy")
+    doc = {"kernel": name, "workload": "fp32 sum of 2^28 N(0,1) values (1 GiB)", "plan": plan,
+           "kernel_source_hash": kernel_source_hash(),
+           "fetch_kib_per_launch": round(f_kib, 1), "write_kib_per_launch": round(w_kib, 1),
+           "launches": [len(kf), len(kw)],
+           "calibration": {"kernel": COPY_KERNEL + ", 1 GiB device-to-device copy (torch copy_)",
+                           "fetch_kib": round(statistics.median(cf), 1), "write_kib": round(statistics.median(cw), 1),
+                           "fetch_scale": round(f_scale, 5), "write_scale": round(w_scale, 5)},
+           "bytes_per_launch": traffic, "algorithmic_bytes_per_launch": algo,
+           "traffic_over_algorithmic": round(traffic / algo, 5),
+           "commands": [cmd % "FETCH_SIZE", cmd % "WRITE_SIZE",
+                        "python3 bench.py --summarize-pmc <fetch dir> <write dir> <bench line of the fetch run>"]}
+    with open(os.path.join(out_dir, "hbm_traffic_f32_2p28.json"), "w") as fh:
+        json.dump(doc, fh, indent=1)
+    md = ["# HBM traffic: fp32 2^28 compensated sum, dominant kernel", "",
+          "Commands (two counter passes, then the summary; repository root):", "", "```"] + doc["commands"] + [
+          "```", "",
+          "Kernel `%s`, plan `%s`, %d launches per pass." % (name, json.dumps(plan), len(kf)), "",
+          "| Counter | Kernel (KiB/launch) | 1 GiB copy (KiB/dispatch) | Scale | Kernel, scaled (KiB) |",
+          "|---|---|---|---|---|",
+          "| FETCH_SIZE | %.1f | %.1f | %.5f | %.1f |" % (f_kib, statistics.median(cf), f_scale, f_kib * f_scale),
+          "| WRITE_SIZE | %.1f | %.1f | %.5f | %.1f |" % (w_kib, statistics.median(cw), w_scale, w_kib * w_scale),
+          "",
+          "- The calibration copy is torch's 1 GiB device-to-device `copy_` (`%s`), which reads and" % COPY_KERNEL,
+          "  writes exactly 1,048,576 KiB. Each counter is scaled by what it reads for that copy.",
+          "- Traffic per launch: %d bytes against %d algorithmic bytes (2^30 input, %d partials of 8 B, 8 B"
+          % (traffic, algo, int(plan["grid"])),
+          "  output): **%.5fx**." % (traffic / algo),
+          "- `hbm_traffic_f32_2p28.json` holds these figures with the hash of the kernel's sources; `bench.py`",
+          "  reports `roofline.traffic` only while the sources and the plan still match."]
+    with open(os.path.join(out_dir, "hbm_traffic_f32_2p28.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    log("traffic %d B per launch (%.5fx algorithmic)" % (traffic, traffic / algo))
+
+
+def summarize_trace(trace_dir, bench_json, out_dir):
+    """Kernel-trace summary of a profiled bench run: the per-kernel
+    statistics of rocprofv3 --kernel-trace --stats beside the bench line's
+    own event timing of the dominant kernel."""
+    import csv
+    line = last_json_line(bench_json)
+    plan = line["config"]["plan"]
+    name = dominant_kernel_name(plan)
+    with open(os.path.join(trace_dir, "run_kernel_stats.csv")) as fh:
+        rows = list(csv.DictReader(fh))
+    dom = [r for r in rows if r["Name"] == name]
+    if not dom:
+        raise SystemExit("kernel stats hold no dispatch of " + name)
+    avg_ns = float(dom[0]["AverageNs"])
+    algo = N * 4 + 8 * int(plan["grid"]) + 8
+    md = ["# Kernel trace: fp32 2^28 compensated sum (headline workload)", "",
+          "Command (repository root, plans from `paper_2004_05371_amd/tuned_plans.json`), then the summary:", "",
+          "```", "rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- python3 bench.py",
+          "python3 bench.py --summarize-trace <dir> <bench line of that run>", "```", "",
+          "Device: %s. Plan `%s`." % ("MI355X (gfx950, 256 CUs, 8 XCDs)", json.dumps(plan)), "",
+          "| Kernel | Calls | Average (us) | Min (us) | Max (us) |", "|---|---|---|---|---|"]
+    for r in rows[:12]:
+        k = r["Name"].replace("|", "/")
+        if len(k) > 95:
+            k = k[:92] + "..."
+        md.append("| `%s` | %s | %.2f | %.2f | %.2f |" % (k, r["Calls"], float(r["AverageNs"]) / 1e3,
+                                                          float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3))
+    md += ["",
+           "- Dominant kernel `%s`: %s launches (timed loop, warm-up, variant table), average **%.2f us** ="
+           % (name.split("(")[0].replace("void redsum::", ""), dom[0]["Calls"], avg_ns / 1e3),
+           "  %.1f GB/s for %d algorithmic bytes (%.1f %% of 8 TB/s)."
+           % (algo / avg_ns, algo, 100 * algo / avg_ns / 8000),
+           "- The bench line of the same run: HIP events around that kernel on its stream, mean %.2f us"
+           % line["extra"]["dominant_kernel_mean_us"],
+           "  (roofline.achieved %.1f GB/s); wall rate %.1f GB/s. Events include the dispatch latency."
+           % (line["roofline"]["achieved"], line["value"]),
+           "- Other rows come from the variant table and the probes of the same bench run."]
+    with open(os.path.join(out_dir, "k_partials_f32_2p28_kernel_trace.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    log("dominant kernel %.2f us average over %s launches" % (avg_ns / 1e3, dom[0]["Calls"]))
+
+
 def gbps(nbytes, ms):
     return round(nbytes / (ms * 1e-3) / 1e9, 1)
 
@@ -360,7 +489,19 @@ def main():
     ap.add_argument("--save-plans", metavar="JSON", help="write the plans tuned in this run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the headline, copy the 1 GiB input 3 times (byte-counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "BENCH_JSON"),
+                    help="no GPU: write the HBM traffic summary from two rocprofv3 --pmc runs")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "BENCH_JSON"),
+                    help="no GPU: write the kernel-trace summary of a profiled bench run")
+    ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles"), metavar="DIR")
     args = ap.parse_args()
+    if args.summarize_pmc or args.summarize_trace:
+        os.makedirs(args.summary_out, exist_ok=True)
+        if args.summarize_pmc:
+            summarize_pmc(*args.summarize_pmc, args.summary_out)
+        if args.summarize_trace:
+            summarize_trace(*args.summarize_trace, args.summary_out)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)

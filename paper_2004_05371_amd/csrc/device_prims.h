@@ -388,7 +388,6 @@ struct BarrierWords {
   Line ticket;  // atomic-final variant: workgroups that have stored a partial
   Line err;     // watchdog flag (nonzero after a timeout)
   Line acc_lo;  // atomic-final int accumulator (int64 in acc_lo.v/acc_lo.pad[0])
-  Line xcd_mask;  // XCD-aggregated publication: dispatch offsets seen (bit mask)
   Line group[kMaxBarrierGroups];  // arrivals per group (two-level / per-XCD barrier)
 };
 
@@ -413,20 +412,53 @@ __device__ __forceinline__ unsigned relaxed_add(unsigned* p, unsigned v) {
 // number of workgroups on that XCD is the number of g' with
 // g' = g (mod nxcc), whatever the offset.  The last arrival of the XCD
 // performs ONE agent-scope release (write-back of that L2, which holds every
-// member's stores) before it signals onward.  Every workgroup also records
-// the offset it implies in a bit mask; the final arrival reports more than
-// one offset (dispatch not round-robin) as err = kErrDispatch.
+// member's stores) before it signals onward.
+//
+// The dispatch rule is checked on the way, at no extra atomic: every counter
+// is a 64-bit tally that adds (1, k, k^2) for a key k in three fields
+// (count: bits 0-15, sum of k: bits 16-31, sum of k^2: bits 32-63).  At the
+// XCD level k = g mod nxcc, at the top level k = the offset the XCD implies.
+// By the Cauchy-Schwarz inequality, count * sum(k^2) = sum(k)^2 exactly when
+// all keys are equal, so the last arrival at each level sees whether one
+// rule held for all of its members and otherwise reports err = kErrDispatch.
+// Fields stay in range for up to 9362 workgroups per XCD.
 // ---------------------------------------------------------------------------
 constexpr unsigned kErrTimeout = 1u;
 constexpr unsigned kErrDispatch = 2u;
 constexpr unsigned kBarrierXcd = 0x100u;  // groups value: XCD-aggregated barrier (| nxcc)
 
+__device__ __forceinline__ unsigned long long* tally_word(Line& l) {
+  return reinterpret_cast<unsigned long long*>(&l.v);  // v and pad[0]
+}
+
+__device__ __forceinline__ unsigned long long tally_term(unsigned k) {
+  return 1ull | ((unsigned long long)k << 16) | ((unsigned long long)(k * k) << 32);
+}
+
+__device__ __forceinline__ bool tally_uniform(unsigned long long t) {
+  const unsigned long long c = t & 0xFFFFull, s1 = (t >> 16) & 0xFFFFull, s2 = t >> 32;
+  return c * s2 == s1 * s1;
+}
+
+// Adds key k to the tally in `l`; true for the arrival that completes
+// `expected` arrivals, which also resets the tally and checks the keys.
+__device__ __forceinline__ bool tally_arrive(BarrierWords* w, Line& l, unsigned k, unsigned expected) {
+  const unsigned long long t =
+      __hip_atomic_fetch_add(tally_word(l), tally_term(k), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if ((unsigned)(t & 0xFFFFull) != expected - 1) return false;
+  __hip_atomic_store(tally_word(l), 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!tally_uniform(t + tally_term(k)))
+    __hip_atomic_store(&w->err.v, kErrDispatch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return true;
+}
+
 // Makes this workgroup's earlier global stores visible to the other
 // workgroups of its XCD and counts it there; returns true for the last
-// arrival of the XCD, which has then released agent-wide for all of them.
-// Thread 0 only; every wave of the workgroup must have drained its stores
-// (s_waitcnt) before the workgroup barrier that precedes this call.
-__device__ __forceinline__ bool xcd_arrive(BarrierWords* w, unsigned nblocks, unsigned nxcc) {
+// arrival of the XCD, which has then released agent-wide for all of them
+// and must call xcd_top with *off.  Thread 0 only; every wave of the
+// workgroup must have drained its stores (s_waitcnt) before the workgroup
+// barrier that precedes this call.
+__device__ __forceinline__ bool xcd_arrive(BarrierWords* w, unsigned nblocks, unsigned nxcc, unsigned* off) {
   const unsigned r = blockIdx.x % nxcc;
   const unsigned members = (nblocks - r + nxcc - 1) / nxcc;
   unsigned phys = xcc_id();
@@ -437,20 +469,19 @@ __device__ __forceinline__ bool xcd_arrive(BarrierWords* w, unsigned nblocks, un
     __hip_atomic_store(&w->err.v, kErrDispatch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     phys = r;
   }
-  const unsigned off = (phys + nxcc - r) % nxcc;
-  __hip_atomic_fetch_or(&w->xcd_mask.v, 1u << off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __builtin_amdgcn_s_waitcnt(0);
-  if (relaxed_add(&w->group[phys].v, 1u) != members - 1) return false;
-  __hip_atomic_store(&w->group[phys].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  *off = (phys + nxcc - r) % nxcc;
+  if (!tally_arrive(w, w->group[phys], r, members)) return false;
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
   return true;
 }
 
-// Final arrival of an XCD-aggregated publication (after its acquire): check
-// that every workgroup implied the same dispatch offset, reset the mask.
-__device__ __forceinline__ void xcd_finish(BarrierWords* w) {
-  const unsigned m = __hip_atomic_exchange(&w->xcd_mask.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (m & (m - 1)) __hip_atomic_store(&w->err.v, kErrDispatch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Top-level arrival of an XCD's last workgroup on `top` (a counter of
+// min(nblocks, nxcc) XCDs); true for the last XCD, after the check that
+// every XCD implied the same dispatch offset.  Leaves `top` at zero.
+__device__ __forceinline__ bool xcd_top(BarrierWords* w, Line& top, unsigned nblocks, unsigned nxcc,
+                                        unsigned off) {
+  const unsigned active = nblocks < nxcc ? nblocks : nxcc;
+  return tally_arrive(w, top, off, active);
 }
 
 // ---------------------------------------------------------------------------
@@ -489,8 +520,8 @@ __device__ __forceinline__ bool grid_barrier(BarrierWords* w, unsigned nblocks, 
     bool last = false;
     if (xcd) {
       const unsigned nxcc = groups & 0xFFu;
-      const unsigned active = nblocks < nxcc ? nblocks : nxcc;
-      if (xcd_arrive(w, nblocks, nxcc)) last = relaxed_add(&w->count.v, 1u) == active - 1;
+      unsigned off;
+      last = xcd_arrive(w, nblocks, nxcc, &off) && xcd_top(w, w->count, nblocks, nxcc, off);
     } else {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       if (groups <= 1) {
@@ -509,7 +540,6 @@ __device__ __forceinline__ bool grid_barrier(BarrierWords* w, unsigned nblocks, 
     if (last) {
       __hip_atomic_store(&w->count.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-      if (xcd) xcd_finish(w);
       relaxed_add(&w->gen.v, 1u);
     } else {
       unsigned spins = 0;

@@ -102,13 +102,12 @@ __global__ __launch_bounds__(1024) void k_xcc_map(int* out) {
 
 __global__ void k_reset_words(BarrierWords* w) {
   if (threadIdx.x == 0) {
-    w->count.v = 0;
+    *tally_word(w->count) = 0;
     w->gen.v = 0;
-    w->ticket.v = 0;
+    *tally_word(w->ticket) = 0;
     w->err.v = 0;
     *acc_i64(w) = 0;
-    w->xcd_mask.v = 0;
-    for (int i = 0; i < kMaxBarrierGroups; ++i) w->group[i].v = 0;
+    for (int i = 0; i < kMaxBarrierGroups; ++i) *tally_word(w->group[i]) = 0;
   }
 }
 

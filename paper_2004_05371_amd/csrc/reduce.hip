@@ -201,9 +201,8 @@ __global__ __launch_bounds__(1024) void k_atomic(ReduceArgs a) {
     if (a.xcd_nxcc > 1) {
       // One L2 write-back per XCD: the last member of each XCD releases and
       // takes the ticket for the whole XCD.
-      const unsigned active = gridDim.x < a.xcd_nxcc ? gridDim.x : a.xcd_nxcc;
-      last = xcd_arrive(w, gridDim.x, a.xcd_nxcc) &&
-             relaxed_add(&w->ticket.v, 1u) == active - 1;
+      unsigned off;
+      last = xcd_arrive(w, gridDim.x, a.xcd_nxcc, &off) && xcd_top(w, w->ticket, gridDim.x, a.xcd_nxcc, off);
     } else {
       // Release (one L2 write-back) publishes the partial; the ticket itself
       // is relaxed, and only the last workgroup pays an acquire.
@@ -216,7 +215,6 @@ __global__ __launch_bounds__(1024) void k_atomic(ReduceArgs a) {
   if (!is_last) return;
   // Last workgroup: every thread acquires before reading the others' data.
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  if (a.xcd_nxcc > 1 && threadIdx.x == 0) xcd_finish(w);
   if constexpr (__is_same(Part, long long)) {
     if (threadIdx.x == 0) {
       long long s = __hip_atomic_load(acc_i64(w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
