@@ -158,8 +158,9 @@ const char *red_last_error(void);
 /* Synchronize `stream`, then report a grid-barrier watchdog timeout raised
  * by an earlier persistent kernel on that stream (RED_ETIMEOUT), or a
  * workgroup that ran on another XCD than round-robin dispatch implies under
- * RED_FLAG_XCD (RED_ENOTSUP), clearing the flag and the barrier words.
- * RED_OK if none. */
+ * RED_FLAG_XCD (RED_ENOTSUP: flagged by a tally, or arrival counters left
+ * incomplete, in which case that call's output was not written), clearing
+ * the flag and the barrier words.  RED_OK if none. */
 int red_check_error(void *stream);
 
 /* ---------------------------------------------------------------------

@@ -386,12 +386,22 @@ int red_check_error(void* stream) {
   Workspace* ws;
   if ((rc = get_workspace(s, &ws))) return rc;
   RED_HIP(hipStreamSynchronize(s));
-  unsigned err = 0;
-  RED_HIP(hipMemcpy(&err, &ws->words->err.v, 4, hipMemcpyDeviceToHost));
-  if (!err) return RED_OK;
+  BarrierWords hw;
+  RED_HIP(hipMemcpy(&hw, ws->words, sizeof(hw), hipMemcpyDeviceToHost));
+  const unsigned err = hw.err.v;
+  // Every completed launch leaves its arrival counters at zero; a counter
+  // left over means some workgroups never completed an arrival (on the
+  // XCD-aggregated path: a dispatch order other than round-robin).
+  bool stale = hw.count.v || hw.count.pad[0] || hw.ticket.v || hw.ticket.pad[0] || hw.acc_lo.v ||
+               hw.acc_lo.pad[0];
+  for (const Line& g : hw.group) stale = stale || g.v || g.pad[0];
+  if (!err && !stale) return RED_OK;
   // Clear the error and every barrier word (the barrier was abandoned).
   RED_HIP(hipMemset(ws->words, 0, kWordsBytes));
   RED_HIP(hipMemset(ws->seg_tickets, 0, kTicketBytes));
+  if (!err)
+    return set_error(RED_ENOTSUP, "arrival counters were left incomplete (a workgroup ran on another XCD "
+                                  "than round-robin dispatch implies)");
   if (err == kErrDispatch)
     return set_error(RED_ENOTSUP, "a workgroup ran on another XCD than round-robin dispatch implies "
                                   "(XCD-aggregated publication is not valid on this device)");
