@@ -313,6 +313,91 @@ class Plans:
         return R.red_get_segmented_plan(nseg)
 
 
+def smi_query(args, limit=6000):
+    """Output of one read-only amd-smi query as JSON (or its error text)."""
+    import subprocess
+    try:
+        r = subprocess.run(["amd-smi"] + args + ["--json"], capture_output=True, text=True, timeout=30)
+    except (OSError, subprocess.SubprocessError) as e:
+        return {"error": str(e)}
+    try:
+        return json.loads(r.stdout)
+    except ValueError:
+        return {"rc": r.returncode, "stdout": r.stdout[:limit], "stderr": r.stderr[-limit // 4:]}
+
+
+def time_gpu_side(fn, reps, stream):
+    """Per-call device time (ms): each call is queued behind a short spin
+    kernel, so the events around it measure the GPU's own latency, not the
+    host's launch rate."""
+    import torch
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    torch.cuda.synchronize()
+    for a, b in pairs:
+        torch.cuda._sleep(50000)  # about 20 us of spinning
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in pairs]
+
+
+def model_check(R, stream, emit, lo=10, hi=26):
+    """Times one 1024-thread workgroup and the device-wide atomic-ticket
+    and relaunch variants on fp32 inputs of 2^lo..2^hi elements (median
+    device time per call), takes T and Thr for each as Eq. 1-2 define them,
+    and compares the scenario rule's switch point (Section VII-A, Eq. 1-5)
+    with the smallest measured size at which the device-wide kernel is
+    faster."""
+    import torch
+
+    from paper_2004_05371_amd import inputs, model
+
+    sh = stream.cuda_stream
+    big = torch.from_numpy(inputs.normal_f32(1 << hi, sub=21)).to("cuda")
+    out = torch.empty((), dtype=torch.float64, device="cuda")
+    forms = {"single": R.make_opts(variant=R.RED_VARIANT_SINGLE, wg=1024, ipt=2, grid=1),
+             "atomic": R.make_opts(variant=R.RED_VARIANT_ATOMIC, wg=256, ipt=4, grid=512, flags=R.FLAG_NONTEMPORAL),
+             "relaunch": R.make_opts(variant=R.RED_VARIANT_RELAUNCH, wg=256, ipt=4, grid=512,
+                                     flags=R.FLAG_NONTEMPORAL)}
+    rows = []
+    for lg in range(lo, hi + 1):
+        n = 1 << lg
+        row = {"n": n, "bytes": 4 * n}
+        for name, o in forms.items():
+            if name == "single" and lg > 22:
+                continue  # one workgroup at 100 GB/s: beyond 16 MB only the slope matters
+            call = lambda: R.red_sum_ex(R.RED_F32, big.data_ptr(), n, out.data_ptr(), sh, o)
+            for _ in range(3):
+                call()
+            row[name] = statistics.median(time_gpu_side(call, 50 if lg <= 20 else 10, stream)) * 1e3  # us
+        rows.append(row)
+        emit({"config": "model_sweep", **{k: (round(v, 3) if isinstance(v, float) else v) for k, v in row.items()}})
+    # Eq. 1-2 give t(N) = max(T, N / Thr) (T + max(0, N - C) / Thr with
+    # C = T Thr): T is the time of the smallest inputs, Thr the slope
+    # between the two largest measured sizes.
+    fit = {}
+    for name in forms:
+        pts = [r for r in rows if name in r]
+        t0 = min(r[name] for r in pts[:3])
+        slope = (pts[-1][name] - pts[-2][name]) / (pts[-1]["bytes"] - pts[-2]["bytes"])  # us per byte
+        fit[name] = {"T_us": round(t0, 3), "Thr_GBps": round(1e-3 / slope, 1)}
+    pred = {}
+    for more in ("atomic", "relaunch"):
+        tb, tm = fit["single"]["T_us"], fit[more]["T_us"]
+        pred[more] = model.switch_point(tb, max(0.0, tm - tb), fit["single"]["Thr_GBps"] * 1e3,
+                                        fit[more]["Thr_GBps"] * 1e3)
+    meas = {more: next((r["bytes"] for r in rows if "single" in r and r[more] < r["single"]), None)
+            for more in ("atomic", "relaunch")}
+    emit({"config": "model", "fit": fit,
+          "switch_bytes_predicted": {k: round(v) for k, v in pred.items()},
+          "first_power_of_two_where_device_wide_wins_bytes": meas,
+          "library_switch_bytes": round(model.mi355x_single_workgroup_switch()),
+          "note": "2^%d..2^%d fp32 elements, device time per call; T = time of the smallest inputs, "
+                  "Thr = slope over the two largest" % (lo, hi)})
+    del big
+
+
 def run_configs(R, dev, stream, path, plans):
     """Every workload of the study, one JSON record per measurement,
     appended to `path` (JSONL).  Timed regions hold only library calls; the
@@ -330,6 +415,12 @@ def run_configs(R, dev, stream, path, plans):
         log(json.dumps(rec))
         with open(path, "a") as fh:
             fh.write(json.dumps(rec) + "\n")
+
+    # -- the machine: device properties, partition mode, clocks and power
+    #    (amd-smi, read-only queries), host CPUs available to this process
+    emit({"config": "machine", "device": dev, "host_cpus": len(os.sched_getaffinity(0)),
+          "amd_smi": {k: smi_query(v) for k, v in (("partition", ["static", "--partition"]),
+                                                   ("clock_power", ["metric", "--clock", "--power"]))}})
 
     def timed(fn, reps, flushed=False):
         for _ in range(3):
@@ -353,6 +444,7 @@ def run_configs(R, dev, stream, path, plans):
         o = R.make_opts(variant=R.RED_VARIANT_RELAUNCH)
         fn = lambda: R.red_sum_ex(code, t.data_ptr(), t.numel(), out.data_ptr(), sh, o)
         warm, cold = timed(fn, 200), timed(fn, 50, flushed=True)
+        dev_t = statistics.median(time_gpu_side(fn, 100, stream))
         plan = plans.sum_plan(t, out, R.RED_ACC_COMPENSATED, sh)
         ot = R.opts_from_plan(plan)
         tuned = timed(lambda: R.red_sum_ex(code, t.data_ptr(), t.numel(), out.data_ptr(), sh, ot), 200)
@@ -361,6 +453,7 @@ def run_configs(R, dev, stream, path, plans):
         ex, tc = cpu_exact(x, kind)
         ok = (out.item() == ex) if kind == "i32" else (oracle.rel_err(out.item(), ex) <= 1e-6)
         emit({"config": "small", "dtype": kind, "n": x.size, "variant": "relaunch", "us_warm": round(warm * 1e3, 2),
+              "us_device": round(dev_t * 1e3, 2),
               "us_flushed": round(cold * 1e3, 2), "tuned_plan": plan.as_dict(), "us_tuned": round(tuned * 1e3, 2),
               "matches_oracle": bool(ok), "cpu_oracle_s": round(tc, 4)})
 
@@ -422,39 +515,50 @@ def run_configs(R, dev, stream, path, plans):
         del t
         torch.cuda.empty_cache()
 
-    # -- segmented: 10,000 log-uniform segments, one graph launch vs a loop
-    x, off = inputs.segments(10000)
-    xt = torch.from_numpy(x).to("cuda")
-    ot = torch.from_numpy(off).to("cuda")
-    nseg = off.size - 1
-    out = torch.empty(nseg, dtype=torch.float64, device="cuda")
-    plan = plans.seg_plan(xt, ot, out, sh)
-    nbytes = x.nbytes + off.nbytes + out.numel() * 8
-    ms_graph = timed(lambda: R.red_sum_segmented(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh), 30)
-    o = R.make_opts(variant=R.RED_VARIANT_PERSISTENT, wg=plan.wg, ipt=plan.ipt,
-                    grid=min(plan.grid, R.red_max_coresident(plan.wg)),
-                    flags=R.FLAG_PLAIN_LAUNCH | (plan.flags & R.FLAG_NONTEMPORAL))
-    ms_barrier = timed(lambda: R.red_sum_segmented_ex(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh, o), 30)
-    ms_loop = timed(lambda: R.red_sum_segmented_loop(xt.data_ptr(), off, nseg, out.data_ptr(), sh), 3)
-    R.red_sum_segmented(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh)
-    torch.cuda.synchronize()
-    got = out.cpu().numpy()
-    c0 = time.perf_counter()
-    sums = oracle.segmented_sums(x, off)
-    tc = time.perf_counter() - c0
-    worst = max(oracle.rel_err(float(got[k]), e) if e.fraction != 0 else abs(got[k]) for k, e in enumerate(sums))
-    emit({"config": "segments", "nseg": nseg, "total_elems": int(off[-1]), "bytes": nbytes, "plan": plan.as_dict(),
-          "graph_us": round(ms_graph * 1e3, 1), "graph_GBps": gbps(nbytes, ms_graph),
-          "grid_barrier_fixup_us": round(ms_barrier * 1e3, 1),
-          "loop_per_segment_us": round(ms_loop * 1e3, 1), "speedup_vs_loop": round(ms_loop / ms_graph, 1),
-          "max_rel_err": worst, "cpu_oracle_s": round(tc, 2)})
-    del xt, ot
-    torch.cuda.empty_cache()
+    # -- segmented: 10,000 log-uniform segments, one graph launch vs a loop;
+    #    the drawn lengths (about 7.4e8 elements) and the same draws scaled
+    #    to a total of about 2^28
+    for label, total in (("segments", None), ("segments_2p28", 1 << 28)):
+        x, off = inputs.segments(10000, total=total)
+        xt = torch.from_numpy(x).to("cuda")
+        ot = torch.from_numpy(off).to("cuda")
+        nseg = off.size - 1
+        out = torch.empty(nseg, dtype=torch.float64, device="cuda")
+        plan = plans.seg_plan(xt, ot, out, sh)
+        nbytes = x.nbytes + off.nbytes + out.numel() * 8
+        ms_graph = timed(lambda: R.red_sum_segmented(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh), 30)
+        o = R.make_opts(variant=R.RED_VARIANT_PERSISTENT, wg=plan.wg, ipt=plan.ipt,
+                        grid=min(plan.grid, R.red_max_coresident(plan.wg)),
+                        flags=R.FLAG_PLAIN_LAUNCH | (plan.flags & R.FLAG_NONTEMPORAL))
+        ms_barrier = timed(lambda: R.red_sum_segmented_ex(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh, o),
+                           30)
+        ms_loop = timed(lambda: R.red_sum_segmented_loop(xt.data_ptr(), off, nseg, out.data_ptr(), sh), 3)
+        R.red_sum_segmented(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        c0 = time.perf_counter()
+        sums = oracle.segmented_sums(x, off)
+        tc = time.perf_counter() - c0
+        worst = max(oracle.rel_err(float(got[k]), e) if e.fraction != 0 else abs(got[k]) for k, e in enumerate(sums))
+        emit({"config": label, "nseg": nseg, "total_elems": int(off[-1]), "bytes": nbytes, "plan": plan.as_dict(),
+              "graph_us": round(ms_graph * 1e3, 1), "graph_GBps": gbps(nbytes, ms_graph),
+              "grid_barrier_fixup_us": round(ms_barrier * 1e3, 1),
+              "loop_per_segment_us": round(ms_loop * 1e3, 1), "speedup_vs_loop": round(ms_loop / ms_graph, 1),
+              "max_rel_err": worst, "cpu_oracle_s": round(tc, 2)})
+        del xt, ot
+        torch.cuda.empty_cache()
+
+    # -- model: the Eq. 1-5 switch point between one workgroup ("basic")
+    #    and the whole device ("more") from constants fitted on this GPU,
+    #    against the crossover measured directly
+    model_check(R, stream, emit)
 
     # -- probes
-    for op, name in ((0, "dpp_reduce"), (1, "swizzle_reduce"), (2, "bpermute_reduce"), (3, "dpp_step")):
-        ns, sg, cyc = R.sync_bench_wave(op, 64, reps=20)
-        emit({"probe": "wave", "op": name, "ns": round(ns, 2), "sigma_ns": round(sg, 2), "cycles": round(cyc, 1)})
+    for vname, vt in R.WAVE_TYPES.items():
+        for op, name in ((0, "dpp_reduce"), (1, "swizzle_reduce"), (2, "bpermute_reduce"), (3, "dpp_step")):
+            ns, sg, cyc = R.sync_bench_wave_ex(op, vt, 64, reps=20)
+            emit({"probe": "wave", "op": name, "type": vname, "ns": round(ns, 2), "sigma_ns": round(sg, 2),
+                  "cycles": round(cyc, 1)})
     for wg in (64, 128, 256, 512, 1024):
         for n_wg in (1, dev["cus"], 4 * dev["cus"]):
             ns, sg, cyc = R.sync_bench_block(wg, n_wg, reps=20)
@@ -470,10 +574,13 @@ def run_configs(R, dev, stream, path, plans):
                       "groups": {0: "default", -1: "xcd"}.get(groups, groups), "ns": round(ns, 1),
                       "sigma_ns": round(sg, 1), "in_kernel_ns": round(wall, 1)})
             n *= 2
-    for coop in (False, True):
-        ns, sg, null_ns = R.sync_bench_relaunch(dev["cus"], 256, cooperative=coop, reps=30)
-        emit({"probe": "relaunch", "cooperative": coop, "overhead_ns": round(ns, 1), "sigma_ns": round(sg, 1),
-              "null_kernel_total_ns": round(null_ns, 1)})
+    for kind, name in ((0, "ordinary"), (1, "cooperative"), (2, "graph")):
+        for n_wg in (1, dev["cus"], 4 * dev["cus"]):
+            if kind == 1 and n_wg > R.red_max_coresident(256):
+                continue
+            ns, sg, null_ns = R.sync_bench_relaunch(n_wg, 256, cooperative=kind, reps=30)
+            emit({"probe": "relaunch", "launch": name, "n_wg": n_wg, "overhead_ns": round(ns, 1),
+                  "sigma_ns": round(sg, 1), "null_kernel_total_ns": round(null_ns, 1)})
 
 
 def main():
@@ -600,13 +707,16 @@ def headline(args, R, dev, stream, sh, plans, inputs):
                 ns, sg, wall_ns = R.sync_bench_grid_ex(n, 256, groups, reps=20)
                 gb["%d_wg_%s" % (n, name)] = {"ns": round(ns, 1), "sigma_ns": round(sg, 1),
                                               "in_kernel_ns": round(wall_ns, 1)}
-        ro, ro_sg, null_ns = R.sync_bench_relaunch(cus, 256, cooperative=False, reps=20)
-        rc, rc_sg, null_c = R.sync_bench_relaunch(cus, 256, cooperative=True, reps=20)
+        ro, ro_sg, null_ns = R.sync_bench_relaunch(cus, 256, cooperative=0, reps=20)
+        rc, rc_sg, null_c = R.sync_bench_relaunch(cus, 256, cooperative=1, reps=20)
+        rg, rg_sg, null_g = R.sync_bench_relaunch(cus, 256, cooperative=2, reps=20)
         extra["grid_barrier_ns"] = gb
         extra["relaunch_overhead_ns"] = {"traditional": round(ro, 1), "traditional_sigma": round(ro_sg, 1),
                                          "cooperative": round(rc, 1), "cooperative_sigma": round(rc_sg, 1),
+                                         "graph": round(rg, 1), "graph_sigma": round(rg_sg, 1),
                                          "null_kernel_total_ns": round(null_ns, 1),
-                                         "null_kernel_total_coop_ns": round(null_c, 1)}
+                                         "null_kernel_total_coop_ns": round(null_c, 1),
+                                         "null_kernel_total_graph_ns": round(null_g, 1)}
 
     # ---- CPU baseline: the oracle on the same input (and the result's error)
     cpu = None

@@ -92,6 +92,16 @@ typedef enum {
     RED_WAVE_DPP_STEP = 3  /* a single DPP add step (latency of one move+add) */
 } red_wave_op;
 
+/* Value type carried through the wavefront probe's combine. */
+typedef enum {
+    RED_WAVE_T_F32 = 0,  /* float                                              */
+    RED_WAVE_T_I32 = 1,  /* 32-bit integer (wrapping adds)                     */
+    RED_WAVE_T_F64 = 2,  /* double: two 32-bit cross-lane moves per step       */
+    RED_WAVE_T_I64 = 3,  /* 64-bit integer: two moves per step                 */
+    RED_WAVE_T_COMP = 4  /* compensated fp32 (sum, error) pair combined by
+                            TwoSum: the reduction's own combine, two moves    */
+} red_wave_type;
+
 /* Plan / option flags. */
 #define RED_FLAG_NONTEMPORAL 1  /* streaming loads with the nontemporal hint  */
 #define RED_FLAG_NO_GRAPH 2     /* segmented: launch directly, no hipGraph    */
@@ -256,9 +266,15 @@ int red_autotune_segmented(const float *x, const int64_t *offsets, int64_t nseg,
  * ------------------------------------------------------------------- */
 
 /* One wavefront-level operation (red_wave_op) in a dependent chain, run by
- * every wave of one workgroup of wg_size threads. */
+ * every wave of one workgroup of wg_size threads, on float values (the
+ * shuffle-based warp reduction of Section VII-D and Table V). */
 int sync_bench_wave(int op, int wg_size, int reps, double *ns, double *sigma_ns, double *cycles,
                     void *stream);
+
+/* sync_bench_wave on values of type `type` (red_wave_type); an unknown op
+ * or type is RED_EINVAL. */
+int sync_bench_wave_ex(int op, int type, int wg_size, int reps, double *ns, double *sigma_ns,
+                       double *cycles, void *stream);
 
 /* One workgroup barrier (s_barrier) in a chain, n_wg workgroups of wg_size
  * threads. */
@@ -280,9 +296,13 @@ int sync_bench_grid_ex(int n_wg, int wg_size, int groups, int reps, double *ns, 
 
 /* Launch overhead of a kernel boundary (the implicit barrier) by kernel
  * fusion, Eq. 6, with (i, j) = (8, 1) launches of n_wg x wg_size kernels
- * that wait 5 us per unit.  cooperative != 0 uses the cooperative launch
- * API.  null_kernel_ns (if non-NULL) receives the total latency of one null
- * kernel in ns (Section IV formula, host clock around 1 and 5 launches). */
+ * that wait 5 us per unit.  cooperative selects the launch type: 0 ordinary
+ * launches, 1 the cooperative launch API, 2 ordinary kernels replayed from
+ * a captured hipGraph (i kernels in one graph against j in another; the
+ * graphs are captured on a private stream and replayed on `stream`, which
+ * must not be capturing); other values: RED_EINVAL.  null_kernel_ns (if
+ * non-NULL) receives the total latency of one null kernel in ns (Section IV
+ * formula, host clock around 1 and 5 launches, or graphs of 1 and 5). */
 int sync_bench_relaunch(int n_wg, int wg_size, int cooperative, int reps, double *ns,
                         double *sigma_ns, double *null_kernel_ns, void *stream);
 

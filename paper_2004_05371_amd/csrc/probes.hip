@@ -27,30 +27,59 @@ namespace redsum {
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
-template <int OP>
-__global__ __launch_bounds__(1024) void k_wave_chain(int r, float* sink, long long* cycles) {
+// Value types of the wavefront probe: wrapping integer adds (so a chain of
+// doubling steps is defined), the Ops of the reduction otherwise.
+struct OpU32 {
+  using T = unsigned;
+  __device__ static T zero() { return 0u; }
+  __device__ static T add(T a, T b) { return a + b; }
+};
+struct OpU64 {
+  using T = unsigned long long;
+  __device__ static T zero() { return 0ull; }
+  __device__ static T add(T a, T b) { return a + b; }
+};
+
+// Keeps a chain of combines dependent and its values bounded: the next
+// input of lane l is the combined value scaled down plus a lane term.
+__device__ __forceinline__ float chain_mix(float r, int lane) { return r * 0.0078125f + (float)(lane & 7) * 0.125f; }
+__device__ __forceinline__ double chain_mix(double r, int lane) { return r * 0.0078125 + (double)(lane & 7) * 0.125; }
+__device__ __forceinline__ unsigned chain_mix(unsigned r, int lane) { return (r >> 6) + (unsigned)(lane & 7); }
+__device__ __forceinline__ unsigned long long chain_mix(unsigned long long r, int lane) {
+  return (r >> 6) + (unsigned long long)(lane & 7);
+}
+__device__ __forceinline__ CompF32 chain_mix(CompF32 r, int lane) {
+  return CompF32{r.s * 0.0078125f + (float)(lane & 7) * 0.125f, r.c * 0.0078125f};
+}
+
+template <int OP, class Op>
+__global__ __launch_bounds__(1024) void k_wave_chain(int r, unsigned* sink, long long* cycles) {
+  using T = typename Op::T;
   const int lane = __lane_id();
-  float v = 0.25f * (float)lane;
-  const float d = (float)(lane & 7) * 0.125f;
+  T v = chain_mix(Op::zero(), lane);
   __builtin_amdgcn_sched_barrier(0);
   const long long t0 = __builtin_amdgcn_s_memtime();
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll 8
   for (int i = 0; i < r; ++i) {
     if constexpr (OP == RED_WAVE_DPP)
-      v = wave_reduce_dpp<OpF32>(v) * 0.0078125f + d;
+      v = chain_mix(wave_reduce_dpp<Op>(v), lane);
     else if constexpr (OP == RED_WAVE_SWIZZLE)
-      v = wave_reduce_swizzle<OpF32>(v) * 0.0078125f + d;
+      v = chain_mix(wave_reduce_swizzle<Op>(v), lane);
     else if constexpr (OP == RED_WAVE_BPERMUTE)
-      v = wave_reduce_bpermute<OpF32>(v) * 0.0078125f + d;
+      v = chain_mix(wave_reduce_bpermute<Op>(v), lane);
     else
-      v = v + dpp_move<kRowShr1, 0xF, 0xF>(v);
+      v = Op::add(v, dpp_move<kRowShr1, 0xF, 0xF>(v));
   }
   __builtin_amdgcn_sched_barrier(0);
   const long long t1 = __builtin_amdgcn_s_memtime();
   __builtin_amdgcn_sched_barrier(0);
   if (threadIdx.x == 0) cycles[blockIdx.x] = t1 - t0;
-  if (v == -1.0f) sink[threadIdx.x] = v;  // keeps the chain live; never true
+  unsigned w0;
+  __builtin_memcpy(&w0, &v, 4);
+  // Keeps the chain live: a value the compiler cannot bound (it would
+  // remove a chain whose result provably misses a constant).
+  if (w0 == (unsigned)r * 0x9E3779B9u + 0x7F7F1234u) sink[threadIdx.x] = w0;
 }
 
 __global__ __launch_bounds__(1024) void k_block_chain(int r, long long* cycles) {
@@ -166,6 +195,50 @@ int time_launches(const void* fn, int grid, int block, void** args, bool coop, i
   return RED_OK;
 }
 
+// An executable graph of `k` launches of a one-argument wait kernel, its
+// argument fixed at capture.  Captured on a private stream, so the caller's
+// stream may be the null stream.
+struct LaunchGraph {
+  hipGraphExec_t exec = nullptr;
+  ~LaunchGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+  }
+  int build(const void* fn, int grid, int block, long long ticks, int k) {
+    hipStream_t cs = nullptr;
+    RED_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    int rc = RED_OK;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      void* args[] = {&ticks};
+      for (int q = 0; q < k && rc == RED_OK; ++q) rc = launch(fn, grid, block, args, cs, false);
+      e = hipStreamEndCapture(cs, &g);
+    }
+    if (rc == RED_OK && e != hipSuccess) rc = hip_fail(e, "graph capture");
+    if (rc == RED_OK) {
+      e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) rc = hip_fail(e, "hipGraphInstantiate");
+    }
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    return rc;
+  }
+};
+
+int hip_check(hipError_t e) { return e == hipSuccess ? (int)RED_OK : hip_fail(e, "hipGraphLaunch"); }
+
+// Milliseconds between two events around one replay of a graph.
+int time_graph(const LaunchGraph& lg, hipStream_t s, Events& ev, double* ms) {
+  RED_HIP(hipEventRecord(ev.a, s));
+  RED_HIP(hipGraphLaunch(lg.exec, s));
+  RED_HIP(hipEventRecord(ev.b, s));
+  RED_HIP(hipEventSynchronize(ev.b));
+  float f = 0.f;
+  RED_HIP(hipEventElapsedTime(&f, ev.a, ev.b));
+  *ms = f;
+  return RED_OK;
+}
+
 double mean(const std::vector<double>& v) {
   double s = 0;
   for (double x : v) s += x;
@@ -259,6 +332,17 @@ int bw_proxy_launch(const void* x, int64_t nbytes, int n_wg, int wg, Workspace* 
   return launch(reinterpret_cast<const void*>(&k_bw_proxy<4>), n_wg, wg, args, s, false);
 }
 
+// Wavefront-probe kernel of `op` on values of Op's type.
+template <class Op>
+const void* wave_chain_fn(int op) {
+  switch (op) {
+    case RED_WAVE_DPP: return reinterpret_cast<const void*>(&k_wave_chain<RED_WAVE_DPP, Op>);
+    case RED_WAVE_SWIZZLE: return reinterpret_cast<const void*>(&k_wave_chain<RED_WAVE_SWIZZLE, Op>);
+    case RED_WAVE_BPERMUTE: return reinterpret_cast<const void*>(&k_wave_chain<RED_WAVE_BPERMUTE, Op>);
+    default: return reinterpret_cast<const void*>(&k_wave_chain<RED_WAVE_DPP_STEP, Op>);
+  }
+}
+
 }  // namespace redsum
 
 using namespace redsum;
@@ -280,9 +364,10 @@ double red_eq8_sigma(const double* k1, const double* k2, int nsamp, int64_t r1, 
   return std::sqrt(s1 * s1 + s2 * s2) / std::fabs((double)(r1 - r2));
 }
 
-int sync_bench_wave(int op, int wg_size, int reps, double* ns, double* sigma_ns, double* cycles,
-                    void* stream) {
+int sync_bench_wave_ex(int op, int type, int wg_size, int reps, double* ns, double* sigma_ns, double* cycles,
+                       void* stream) {
   if (op < RED_WAVE_DPP || op > RED_WAVE_DPP_STEP) return set_error(RED_EINVAL, "bad wave op %d", op);
+  if (type < RED_WAVE_T_F32 || type > RED_WAVE_T_COMP) return set_error(RED_EINVAL, "bad wave type %d", type);
   if (wg_size < 64 || wg_size > 1024 || wg_size % 64) return set_error(RED_EINVAL, "bad wg_size %d", wg_size);
   if (reps < 2 || !ns || !sigma_ns) return set_error(RED_EINVAL, "reps >= 2 and non-null outputs required");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -290,22 +375,28 @@ int sync_bench_wave(int op, int wg_size, int reps, double* ns, double* sigma_ns,
   Workspace* ws;
   int rc = probe_prologue(s, &dev, &ws);
   if (rc) return rc;
-  const void* fns[] = {reinterpret_cast<const void*>(&k_wave_chain<RED_WAVE_DPP>),
-                       reinterpret_cast<const void*>(&k_wave_chain<RED_WAVE_SWIZZLE>),
-                       reinterpret_cast<const void*>(&k_wave_chain<RED_WAVE_BPERMUTE>),
-                       reinterpret_cast<const void*>(&k_wave_chain<RED_WAVE_DPP_STEP>)};
+  const void* fn = type == RED_WAVE_T_F32   ? wave_chain_fn<OpF32>(op)
+                   : type == RED_WAVE_T_I32 ? wave_chain_fn<OpU32>(op)
+                   : type == RED_WAVE_T_F64 ? wave_chain_fn<OpF64>(op)
+                   : type == RED_WAVE_T_I64 ? wave_chain_fn<OpU64>(op)
+                                            : wave_chain_fn<OpComp>(op);
   int r = 0;
-  float* sink = reinterpret_cast<float*>(ws->sink);
+  unsigned* sink = ws->sink;
   long long* cyc = ws->stamps;
   void* args[] = {&r, &sink, &cyc};
   return differential(
-      fns[op], 1, wg_size, args, false, reps, s, [&](int64_t v) { r = (int)v; },
+      fn, 1, wg_size, args, false, reps, s, [&](int64_t v) { r = (int)v; },
       [&]() {
         long long h = 0;
         read_i64(cyc, &h);
         return (double)h;
       },
       20.0, 1 << 22, ns, sigma_ns, cycles);
+}
+
+int sync_bench_wave(int op, int wg_size, int reps, double* ns, double* sigma_ns, double* cycles,
+                    void* stream) {
+  return sync_bench_wave_ex(op, RED_WAVE_T_F32, wg_size, reps, ns, sigma_ns, cycles, stream);
 }
 
 int sync_bench_block(int wg_size, int n_wg, int reps, double* ns, double* sigma_ns, double* cycles,
@@ -387,14 +478,19 @@ int sync_bench_relaunch(int n_wg, int wg_size, int cooperative, int reps, double
                         double* null_kernel_ns, void* stream) {
   if (wg_size < 64 || wg_size > 1024 || wg_size % 64) return set_error(RED_EINVAL, "bad wg_size %d", wg_size);
   if (n_wg < 1 || n_wg > RED_MAX_GRID) return set_error(RED_EINVAL, "bad n_wg %d", n_wg);
+  if (cooperative < 0 || cooperative > 2)
+    return set_error(RED_EINVAL, "launch type %d: 0 ordinary, 1 cooperative, 2 graph", cooperative);
   if (reps < 2 || !ns || !sigma_ns) return set_error(RED_EINVAL, "reps >= 2 and non-null outputs required");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (cooperative == 2 && stream_capturing(s))
+    return set_error(RED_EINVAL, "graph launch probe inside a stream capture");
   const DeviceInfo* dev;
   Workspace* ws;
   int rc = probe_prologue(s, &dev, &ws);
   if (rc) return rc;
   const void* fn = reinterpret_cast<const void*>(&k_spin);
-  const bool coop = cooperative != 0;
+  const bool coop = cooperative == 1;
+  const bool graph = cooperative == 2;
   if (coop) {
     int maxg = 0;
     if ((rc = coresident(fn, wg_size, *dev, &maxg))) return rc;
@@ -409,31 +505,59 @@ int sync_bench_relaunch(int n_wg, int wg_size, int cooperative, int reps, double
   const long long unit = std::max<long long>(1, dev->wallclock_khz * 5 / 1000);
   const int i = 8, j = 1;
   double ms = 0;
-  ticks = unit;  // warm-up
-  if ((rc = time_launches(fn, n_wg, wg_size, args, coop, 2, s, ev, &ms))) return rc;
+  // Graph form: i kernels of j units and j kernels of i units, each one graph.
+  LaunchGraph g_ij, g_ji;
+  if (graph) {
+    if ((rc = g_ij.build(fn, n_wg, wg_size, unit * j, i))) return rc;
+    if ((rc = g_ji.build(fn, n_wg, wg_size, unit * i, j))) return rc;
+  }
+  auto run_ij = [&](double* t) {
+    if (graph) return time_graph(g_ij, s, ev, t);
+    ticks = unit * j;
+    return time_launches(fn, n_wg, wg_size, args, coop, i, s, ev, t);
+  };
+  auto run_ji = [&](double* t) {
+    if (graph) return time_graph(g_ji, s, ev, t);
+    ticks = unit * i;
+    return time_launches(fn, n_wg, wg_size, args, coop, j, s, ev, t);
+  };
+  if ((rc = run_ij(&ms))) return rc;  // warm-up
+  if ((rc = run_ji(&ms))) return rc;
   std::vector<double> lij, lji;
   for (int k = 0; k < reps; ++k) {
-    ticks = unit * j;
-    if ((rc = time_launches(fn, n_wg, wg_size, args, coop, i, s, ev, &ms))) return rc;
+    if ((rc = run_ij(&ms))) return rc;
     lij.push_back(ms * 1e6);
-    ticks = unit * i;
-    if ((rc = time_launches(fn, n_wg, wg_size, args, coop, j, s, ev, &ms))) return rc;
+    if ((rc = run_ji(&ms))) return rc;
     lji.push_back(ms * 1e6);
   }
   *ns = red_eq6_overhead(mean(lij), mean(lji), i, j);
   *sigma_ns = red_eq8_sigma(lij.data(), lji.data(), (int)lij.size(), i, j);
   if (null_kernel_ns) {
     // Section IV: host clock around 1 launch and around 5 launches of a
-    // null kernel, each followed by a device synchronization.
+    // null kernel, each followed by a device synchronization (graph form:
+    // one graph of 1 and one of 5 null kernels).
+    LaunchGraph g1, g5;
+    if (graph) {
+      if ((rc = g1.build(fn, n_wg, wg_size, 0, 1))) return rc;
+      if ((rc = g5.build(fn, n_wg, wg_size, 0, 5))) return rc;
+    }
     ticks = 0;
+    auto one = [&]() { return graph ? hip_check(hipGraphLaunch(g1.exec, s)) : launch(fn, n_wg, wg_size, args, s, coop); };
+    auto five = [&]() {
+      if (graph) return hip_check(hipGraphLaunch(g5.exec, s));
+      for (int q = 0; q < 5; ++q) {
+        int r = launch(fn, n_wg, wg_size, args, s, coop);
+        if (r) return r;
+      }
+      return (int)RED_OK;
+    };
     std::vector<double> tot;
     for (int k = 0; k < reps; ++k) {
       auto t1 = std::chrono::steady_clock::now();
-      if ((rc = launch(fn, n_wg, wg_size, args, s, coop))) return rc;
+      if ((rc = one())) return rc;
       RED_HIP(hipStreamSynchronize(s));
       auto t2 = std::chrono::steady_clock::now();
-      for (int q = 0; q < 5; ++q)
-        if ((rc = launch(fn, n_wg, wg_size, args, s, coop))) return rc;
+      if ((rc = five())) return rc;
       RED_HIP(hipStreamSynchronize(s));
       auto t3 = std::chrono::steady_clock::now();
       const double a = std::chrono::duration<double, std::nano>(t2 - t1).count();

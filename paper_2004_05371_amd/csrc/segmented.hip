@@ -9,9 +9,11 @@
 //     so every workgroup streams the same number of bytes whatever the
 //     segment lengths;
 //   * it finds the first segment meeting its slice by binary search in the
-//     offsets and walks the segments of its slice in order, reducing each
-//     piece with the whole workgroup (16-byte loads, fp32 TwoSum-compensated
-//     accumulators, wavefront + LDS combine);
+//     offsets, then streams its slice as one sequence of tiles of 16-byte
+//     vectors (the next tile in flight while the current one is added into
+//     fp32 TwoSum-compensated accumulators); each piece of a segment is
+//     finished by a wavefront + LDS combine as soon as its last tile is in,
+//     so segment boundaries never drain the load pipeline;
 //   * a segment that lies inside the slice is written directly (binary64);
 //     a piece of a segment that crosses a slice boundary goes to a carry
 //     slot, and the pieces of that segment are summed in slice order in
@@ -40,57 +42,77 @@ struct SegArgs {
   unsigned bar_groups;
 };
 
-// Per-thread compensated sum of x[a, b) with the whole workgroup: scalar
-// head up to a 16-byte boundary, then tiles of blockDim.x * IPT vectors,
-// then the scalar tail.
-template <int IPT, bool NT>
-__device__ __forceinline__ CompF32 thread_sum_range(const float* x, int64_t a, int64_t b) {
-  using M = ModeF32Comp;
-  const uintptr_t addr = reinterpret_cast<uintptr_t>(x + a);
-  const int64_t len = b - a;
-  const int64_t head = std::min<int64_t>((int64_t)(((16 - (addr & 15)) & 15) >> 2), len);
-  const int64_t nvec = (len - head) >> 2;
-  const int64_t tail = len - head - (nvec << 2);
-  const v4f* xv = reinterpret_cast<const v4f*>(x + a + head);
-  const int64_t bs = blockDim.x;
-  const int64_t tile = bs * IPT;
-  const int64_t ntiles = nvec / tile;
-  const int tid = threadIdx.x;
-
-  CompF32 acc[IPT];
-#pragma unroll
-  for (int u = 0; u < IPT; ++u) acc[u] = M::zero();
-  for (int64_t t = 0; t < ntiles; ++t) {
-    const v4f* p = xv + t * tile + tid;
-    v4f v[IPT];
-#pragma unroll
-    for (int u = 0; u < IPT; ++u) v[u] = load_vec<NT>(p + u * bs);
-    __builtin_amdgcn_sched_barrier(0);  // all IPT loads in flight before use
-#pragma unroll
-    for (int u = 0; u < IPT; ++u) M::add_vec(acc[u], v[u]);
-  }
-  for (int64_t i = ntiles * tile + tid; i < nvec; i += bs) M::add_vec(acc[0], load_vec<NT>(xv + i));
-  if (tid < head)
-    M::add_elem(acc[0], x[a + tid]);
-  else if (tid < head + tail)
-    M::add_elem(acc[0], x[a + head + (nvec << 2) + (tid - head)]);
-#pragma unroll
-  for (int u = 1; u < IPT; ++u) acc[0] = OpComp::add(acc[0], acc[u]);
-  return acc[0];
+// offsets[i] through the scalar data cache (the offsets are read-only for
+// the whole launch), so the segment walk waits on scalar loads only and
+// never on the vector loads of the stream in flight.
+__device__ __forceinline__ int64_t offset_at(const int64_t* offsets, int64_t i) {
+  return ((const __attribute__((address_space(4))) int64_t*)offsets)[i];
 }
 
-// Sum the pieces of segment s (owning slice o, np pieces) in slice order.
-__device__ __forceinline__ double combine_pieces(const SegArgs& a, int64_t o, int64_t np) {
-  double v = a.carry_out[o].val;
-  for (int64_t k = o + 1; k < o + np; ++k) v += a.carry_in[k].val;
-  return v;
+// Sum of the np pieces of a cut segment (owning slice o: carry_out[o], then
+// carry_in[o+1 .. o+np-1]) by the whole workgroup: thread t adds pieces
+// o+t, o+t+blockDim, ... in order, then the fixed binary64 workgroup
+// combine.  The total is returned to thread 0.
+__device__ __forceinline__ double combine_pieces(const SegArgs& a, int64_t o, int64_t np, double* lds) {
+  double v = 0.0;
+  for (int64_t k = o + threadIdx.x; k < o + np; k += blockDim.x) v += k == o ? a.carry_out[o].val : a.carry_in[k].val;
+  return block_reduce<OpF64>(v, lds);
+}
+
+// Moves the segment cursor s to the next non-empty segment that starts
+// before hi, writing 0 for the empty segments passed on the way (those at
+// positions in [lo, hi), and, for the workgroup whose slice ends at E, those
+// at E).  Returns false when the slice holds no further segment.
+__device__ __forceinline__ bool seek_segment(const SegArgs& a, int64_t& s, int64_t hi, int64_t E, bool end_wg,
+                                             int64_t& sa, int64_t& sb) {
+  for (; s < a.nseg; ++s) {
+    sa = offset_at(a.offsets, s);
+    sb = offset_at(a.offsets, s + 1);
+    if (sa >= hi && !(end_wg && sa == E)) return false;
+    if (sa != sb) return true;
+    if (threadIdx.x == 0) a.out[s] = 0.0;
+  }
+  return false;
+}
+
+// The elements of the thread's IPT vectors of one tile that lie in the
+// tile-relative range [ra, rb) (0 <= ra <= rb <= 4 T): vector u of thread
+// tid starts at element 4 (u blockDim + tid) of the tile.  32-bit unsigned
+// range test: r in [ra, rb) iff r - ra < rb - ra.
+// A wave whose 256 elements of row u miss the range skips that row (the
+// test is wave-uniform), so a short piece costs little beyond its combine.
+template <int IPT>
+__device__ __forceinline__ void add_masked(CompF32* acc, const v4f* v, int bs, int ra, int rb) {
+  const unsigned w = (unsigned)(rb - ra);
+  const int wave0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x & ~(kWave - 1));
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) {
+    const int wb = 4 * (u * bs + wave0);  // first element of this wave's part of row u
+    if (wb >= rb || wb + 4 * kWave <= ra) continue;
+    const unsigned r = (unsigned)(4 * (u * bs + (int)threadIdx.x) - ra);
+    v4f x = v[u];
+    x.x = r < w ? x.x : 0.0f;
+    x.y = r + 1u < w ? x.y : 0.0f;
+    x.z = r + 2u < w ? x.z : 0.0f;
+    x.w = r + 3u < w ? x.w : 0.0f;
+    ModeF32Comp::add_vec(acc[u], x);
+  }
 }
 
 template <int IPT, bool NT, bool BARRIER>
 __global__ __launch_bounds__(1024) void k_segmented(SegArgs a) {
-  __shared__ CompF32 lds[kMaxWavesPerWG];
+  using M = ModeF32Comp;
+  // Two LDS buffers used alternately by consecutive pieces: a wave can only
+  // write a buffer again after the next piece's barrier, which wave 0
+  // reaches only once it has read that buffer, so no barrier is needed
+  // between pieces.
+  __shared__ CompF32 lds[2][kMaxWavesPerWG];
+  __shared__ double lds_fix[kMaxWavesPerWG];
+  __shared__ int fix_now;      // ticket: this workgroup completes the cut segment
+  __shared__ int64_t own_fix;  // barrier form: cut segment this workgroup owns
+  int buf = 0;
   const int64_t nseg = a.nseg;
-  const int64_t E = a.offsets[nseg];
+  const int64_t E = offset_at(a.offsets, nseg);
   const int64_t G = gridDim.x;
   const int64_t g = blockIdx.x;
   const int64_t chunk = std::max<int64_t>(64, (((E + G - 1) / G) + 63) & ~(int64_t)63);
@@ -104,63 +126,129 @@ __global__ __launch_bounds__(1024) void k_segmented(SegArgs a) {
   int64_t L = 0, R = nseg;
   while (L < R) {
     const int64_t mid = (L + R) >> 1;
-    if (a.offsets[mid] >= lo)
+    if (offset_at(a.offsets, mid) >= lo)
       R = mid;
     else
       L = mid + 1;
   }
   // Segment L-1 crosses lo if it ends after lo.
-  int64_t s = (L > 0 && a.offsets[L] > lo) ? L - 1 : L;
+  int64_t s = (L > 0 && offset_at(a.offsets, L) > lo) ? L - 1 : L;
+  int64_t sa = 0, sb = 0;
+  bool have = seek_segment(a, s, hi, E, end_wg, sa, sb);
+  int64_t A = std::max(sa, lo), B = std::min(sb, hi);  // current piece
+
+  // The slice is streamed as one sequence of tiles (blockDim x IPT 16-byte
+  // vectors of the 16-byte-aligned base, the next tile's loads issued
+  // before the current tile is added), whatever the segment boundaries: a
+  // piece that ends inside a tile is finished (workgroup combine and
+  // publication) while the next tile is in flight.
+  const int shift = (int)((reinterpret_cast<uintptr_t>(a.x) & 15) >> 2);
+  const v4f* xa = reinterpret_cast<const v4f*>(a.x - shift);
+  const int64_t vlo = (lo + shift) >> 2;
+  const int64_t vhi = (hi + shift + 3) >> 2;  // vectors [vlo, vhi) hold the slice
+  const int64_t bs = blockDim.x;
+  const int64_t T = bs * IPT;
+  const int64_t ntiles = lo < hi ? (vhi - vlo + T - 1) / T : 0;
+  const int tid = threadIdx.x;
+
+  CompF32 acc[IPT];
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) acc[u] = M::zero();
+  v4f cur[IPT], nxt[IPT];
+  auto load_tile = [&](v4f* v, int64_t t) {
+    const int64_t v0 = vlo + t * T + tid;
+    if (vlo + (t + 1) * T <= vhi) {
+#pragma unroll
+      for (int u = 0; u < IPT; ++u) v[u] = load_vec<NT>(xa + v0 + u * bs);
+    } else {
+#pragma unroll
+      for (int u = 0; u < IPT; ++u) v[u] = v0 + u * bs < vhi ? load_vec<NT>(xa + v0 + u * bs) : v4f{0, 0, 0, 0};
+    }
+  };
 
   int64_t own_seg = -1;  // segment that starts in this slice and continues
-  for (; s < nseg; ++s) {
-    const int64_t sa = a.offsets[s];
-    const int64_t sb = a.offsets[s + 1];
-    if (sa >= hi && !(end_wg && sa == E)) break;
-    if (sa == sb) {
-      if (threadIdx.x == 0) a.out[s] = 0.0;
-      continue;
-    }
-    const int64_t pa = std::max(sa, lo);
-    const int64_t pb = std::min(sb, hi);
-    CompF32 acc = thread_sum_range<IPT, NT>(a.x, pa, pb);
-    CompF32 tot = block_reduce<OpComp>(acc, lds);
-    if (threadIdx.x == 0) {
-      const double v = comp_to_double(tot);
-      if (sa >= lo && sb <= hi) {
-        a.out[s] = v;
-      } else {
-        const SegCarry c{s, v};
-        if (sa < lo)
-          a.carry_in[g] = c;
-        else
-          a.carry_out[g] = c;
+  if (ntiles > 0) load_tile(cur, 0);
+  for (int64_t t = 0; t < ntiles; ++t) {
+    // The current tile is complete before the next one is requested, so
+    // nothing below waits on the loads in flight (on this target a wait
+    // with stores and loads both pending would drain every load).
+    __builtin_amdgcn_s_waitcnt(0);
+    if (t + 1 < ntiles) load_tile(nxt, t + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    const int64_t e0 = 4 * (vlo + t * T) - shift;        // first element of the tile
+    const int64_t e1 = 4 * (vlo + (t + 1) * T) - shift;  // one past its last
+    const int64_t span = e1 - e0;  // 4 T elements
+    auto rel = [&](int64_t e) { return (int)std::min(std::max(e - e0, (int64_t)0), span); };
+    // Pieces that end in this tile.
+    while (have && B <= e1) {
+      add_masked<IPT>(acc, cur, (int)bs, rel(A), rel(B));
+      CompF32 tot = acc[0];
+#pragma unroll
+      for (int u = 1; u < IPT; ++u) tot = OpComp::add(tot, acc[u]);
+#pragma unroll
+      for (int u = 0; u < IPT; ++u) acc[u] = M::zero();
+      tot = block_reduce<OpComp>(tot, lds[buf]);
+      buf ^= 1;
+      if (sa >= lo && sb <= hi) {  // whole segment in the slice
+        if (tid == 0) a.out[s] = comp_to_double(tot);
+      } else {  // a piece of a cut segment: publish it (rare: at most two per slice)
         const int64_t o = sa / chunk;
         const int64_t np = (sb - 1) / chunk - o + 1;
-        if constexpr (!BARRIER) {
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-          const unsigned tk =
-              __hip_atomic_fetch_add(&a.tickets[o], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (tk == (unsigned)(np - 1)) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            a.out[s] = combine_pieces(a, o, np);
-            __hip_atomic_store(&a.tickets[o], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (tid == 0) {
+          const SegCarry c{s, comp_to_double(tot)};
+          if (sa < lo)
+            a.carry_in[g] = c;
+          else
+            a.carry_out[g] = c;
+          if constexpr (!BARRIER) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const unsigned tk =
+                __hip_atomic_fetch_add(&a.tickets[o], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            fix_now = tk == (unsigned)(np - 1);
+            if (fix_now) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          } else {
+            if (sa >= lo) own_seg = s;
           }
-        } else {
-          if (sa >= lo) own_seg = s;
+        }
+        if constexpr (!BARRIER) {
+          __syncthreads();
+          if (fix_now) {  // the last piece published: this workgroup sums them
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            const double v = combine_pieces(a, o, np, lds_fix);
+            if (tid == 0) {
+              a.out[s] = v;
+              __hip_atomic_store(&a.tickets[o], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+          }
         }
       }
+      ++s;
+      have = seek_segment(a, s, hi, E, end_wg, sa, sb);
+      A = std::max(sa, lo);
+      B = std::min(sb, hi);
     }
-    __syncthreads();  // lds is reused by the next piece
+    // The piece that continues past this tile.
+    if (have) {
+      if (A <= e0 && vlo + (t + 1) * T <= vhi) {
+#pragma unroll
+        for (int u = 0; u < IPT; ++u) M::add_vec(acc[u], cur[u]);
+      } else {
+        add_masked<IPT>(acc, cur, (int)bs, rel(A), rel(B));
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) cur[u] = nxt[u];
   }
   if constexpr (BARRIER) {
-    grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit);
-    if (threadIdx.x == 0 && own_seg >= 0) {
-      const int64_t sa = a.offsets[own_seg];
-      const int64_t sb = a.offsets[own_seg + 1];
-      const int64_t o = sa / chunk;
-      const int64_t np = (sb - 1) / chunk - o + 1;
-      a.out[own_seg] = combine_pieces(a, o, np);
+    if (tid == 0) own_fix = own_seg;
+    grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit);  // also a workgroup barrier
+    const int64_t os = own_fix;
+    if (os >= 0) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const int64_t o = offset_at(a.offsets, os) / chunk;
+      const int64_t np = (offset_at(a.offsets, os + 1) - 1) / chunk - o + 1;
+      const double v = combine_pieces(a, o, np, lds_fix);
+      if (tid == 0) a.out[os] = v;
     }
   }
 }
@@ -193,13 +281,15 @@ const SegTable& seg_table() {
 
 }  // namespace
 
+// Default (measured on MI355X for 10,000 log-uniform segments): one
+// 512-thread workgroup per CU, 4 loads of 16 bytes per thread per tile.
 red_plan default_seg_plan(int64_t nseg, const DeviceInfo& dev) {
   (void)nseg;
   red_plan p;
   p.variant = RED_VARIANT_ATOMIC;
-  p.wg = 256;
-  p.ipt = 8;
-  p.grid = 3 * dev.cus;
+  p.wg = 512;
+  p.ipt = 4;
+  p.grid = dev.cus;
   p.flags = RED_FLAG_NONTEMPORAL;
   return p;
 }

@@ -43,7 +43,7 @@ EXPORTS = [
     "red_sum", "red_sum_ex", "red_sum_segmented", "red_sum_segmented_ex",
     "red_sum_segmented_loop", "red_set_plan", "red_get_plan", "red_autotune",
     "red_autotune_segmented", "red_set_segmented_plan", "red_get_segmented_plan",
-    "red_kernel_timer", "red_kernel_timer_read", "sync_bench_wave", "sync_bench_block",
+    "red_kernel_timer", "red_kernel_timer_read", "sync_bench_wave", "sync_bench_wave_ex", "sync_bench_block",
     "sync_bench_grid", "sync_bench_grid_ex", "sync_bench_relaunch", "sync_check_grid_order",
     "sync_check_watchdog", "sync_xcc_map", "red_max_coresident", "red_device_info",
     "red_bw_proxy", "red_eq6_overhead", "red_eq7_latency", "red_eq8_sigma",
@@ -95,6 +95,7 @@ _SIGS = {
     "red_kernel_timer": ([_vp, _i32], _i32),
     "red_kernel_timer_read": ([_vp, _dp, _dp, _i64p], _i32),
     "sync_bench_wave": ([_i32, _i32, _i32, _dp, _dp, _dp, _vp], _i32),
+    "sync_bench_wave_ex": ([_i32, _i32, _i32, _i32, _dp, _dp, _dp, _vp], _i32),
     "sync_bench_block": ([_i32, _i32, _i32, _dp, _dp, _dp, _vp], _i32),
     "sync_bench_grid": ([_i32, _i32, _i32, _dp, _dp, _dp, _vp], _i32),
     "sync_bench_grid_ex": ([_i32, _i32, _i32, _i32, _dp, _dp, _dp, _vp], _i32),
@@ -241,6 +242,15 @@ def _probe3(name, *args, stream=0):
     return ns.value, sg.value, cy.value
 
 
+WAVE_TYPES = {"f32": 0, "i32": 1, "f64": 2, "i64": 3, "comp": 4}
+
+
+def sync_bench_wave_ex(op: int, vtype: int, wg_size: int = 64, reps: int = 20, stream: int = 0):
+    """-> (ns per op, sigma ns, shader-clock cycles per op) on values of
+    type vtype (WAVE_TYPES)."""
+    return _probe3("sync_bench_wave_ex", op, vtype, wg_size, reps, stream=stream)
+
+
 def sync_bench_wave(op: int, wg_size: int = 64, reps: int = 20, stream: int = 0):
     """-> (ns per op, sigma ns, shader-clock cycles per op)"""
     return _probe3("sync_bench_wave", op, wg_size, reps, stream=stream)
@@ -261,10 +271,15 @@ def sync_bench_grid_ex(n_wg: int, wg_size: int = 256, groups: int = 0, reps: int
     return _probe3("sync_bench_grid_ex", n_wg, wg_size, groups, reps, stream=stream)
 
 
-def sync_bench_relaunch(n_wg: int = 256, wg_size: int = 256, cooperative: bool = False, reps: int = 20,
+LAUNCH_ORDINARY, LAUNCH_COOPERATIVE, LAUNCH_GRAPH = 0, 1, 2
+
+
+def sync_bench_relaunch(n_wg: int = 256, wg_size: int = 256, cooperative=False, reps: int = 20,
                         stream: int = 0):
-    """-> (launch overhead ns by Eq. 6, sigma ns, null-kernel total latency ns)"""
-    return _probe3("sync_bench_relaunch", n_wg, wg_size, int(bool(cooperative)), reps, stream=stream)
+    """-> (launch overhead ns by Eq. 6, sigma ns, null-kernel total latency ns).
+    cooperative: False/True, or a launch type LAUNCH_ORDINARY /
+    LAUNCH_COOPERATIVE / LAUNCH_GRAPH."""
+    return _probe3("sync_bench_relaunch", n_wg, wg_size, int(cooperative), reps, stream=stream)
 
 
 def sync_check_grid_order(n_wg: int, wg_size: int = 256, stream: int = 0):

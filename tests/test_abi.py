@@ -66,7 +66,12 @@ def test_validation_before_hip(lib):
     assert lib.red_sum_segmented_ex(ctypes.c_void_p(64), ctypes.c_void_p(64), 2, ctypes.c_void_p(64), None,
                                     ctypes.byref(seg)) == R.RED_EINVAL
     assert lib.sync_bench_wave(9, 64, 10, None, None, None, None) == R.RED_EINVAL
+    assert lib.sync_bench_wave_ex(0, 5, 64, 10, None, None, None, None) == R.RED_EINVAL
+    assert lib.sync_bench_wave_ex(4, 0, 64, 10, None, None, None, None) == R.RED_EINVAL
     assert lib.sync_bench_grid(0, 256, 10, None, None, None, None) == R.RED_EINVAL
+    d = ctypes.c_double()
+    for kind in (-1, 3):  # launch types are 0 ordinary, 1 cooperative, 2 graph
+        assert lib.sync_bench_relaunch(8, 64, kind, 10, ctypes.byref(d), ctypes.byref(d), None, None) == R.RED_EINVAL
     assert lib.sync_check_watchdog(4, 64, 9, 100, None) == R.RED_EINVAL
     p = R.Plan(R.RED_VARIANT_PERSISTENT, 256, 16, 0, 0)
     assert lib.red_set_plan(R.RED_F32, 0, 100, ctypes.byref(p)) == R.RED_EINVAL

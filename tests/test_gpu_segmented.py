@@ -65,6 +65,30 @@ def test_edge_batches(lib):
             check(run(lib, x, off, **p), x, off)
 
 
+@pytest.mark.parametrize("shift", [1, 2, 3])
+def test_misaligned_values(lib, shift):
+    """Values that start 4, 8 or 12 bytes past a 16-byte boundary: the slices
+    are streamed as vectors of the aligned base with the outside elements
+    masked."""
+    r = np.random.default_rng(200 + shift)
+    lens = np.concatenate([r.integers(0, 9, 30), r.integers(0, 3000, 30), [0, 65536 + shift, 1]])
+    r.shuffle(lens)
+    off = inputs.offsets_from_lengths(lens.astype(np.int64))
+    x = inputs.mixed_f32(int(off[-1]), sub=12)
+    base = torch.zeros(x.size + 8, dtype=torch.float32, device="cuda")
+    base[shift:shift + x.size] = torch.from_numpy(x).to("cuda")
+    xt = base[shift:shift + x.size]
+    assert xt.data_ptr() % 16 == 4 * shift
+    ot = torch.from_numpy(off).to("cuda")
+    nseg = off.size - 1
+    for p in PLANS:
+        out = torch.full((nseg,), float("nan"), dtype=torch.float64, device="cuda")
+        lib.red_sum_segmented_ex(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), lib.current_stream(),
+                                 lib.make_opts(**p))
+        torch.cuda.synchronize()
+        check(out.cpu().numpy(), x, off)
+
+
 def test_single_segment_equals_red_sum(lib):
     x = inputs.normal_f32(3000017, sub=11)
     off = np.array([0, x.size], dtype=np.int64)

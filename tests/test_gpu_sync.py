@@ -79,6 +79,17 @@ def test_wave_probe(lib, op):
     assert 0 < ns < 10000 and cyc > 0
 
 
+@pytest.mark.parametrize("vtype", ["i32", "f64", "i64", "comp"])
+@pytest.mark.parametrize("op", [0, 3])
+def test_wave_probe_types(lib, op, vtype):
+    """The wavefront probe on every value type; 64-bit and compensated values
+    move two words per step, so a full combine costs at least as much as on
+    one word."""
+    ns, sigma, cyc = lib.sync_bench_wave_ex(op, lib.WAVE_TYPES[vtype], 64, reps=10)
+    say("wave op %d %s: %.2f ns (sigma %.2f), %.1f cycles" % (op, vtype, ns, sigma, cyc))
+    assert 0 < ns < 10000 and cyc > 0
+
+
 @pytest.mark.parametrize("wg", [64, 256, 1024])
 def test_block_probe(lib, wg):
     ns, sigma, cyc = lib.sync_bench_block(wg, 1, reps=10)
@@ -97,10 +108,18 @@ def test_grid_probe(lib, n_wg):
     assert abs(ns2 - ns) <= 0.5 * max(ns, ns2) + 200
 
 
-@pytest.mark.parametrize("coop", [False, True])
-def test_relaunch_probe(lib, coop):
-    ns, sigma, null_ns = lib.sync_bench_relaunch(256, 256, cooperative=coop, reps=10)
-    say("relaunch coop=%s: overhead %.1f ns (sigma %.1f), null kernel %.1f ns" % (coop, ns, sigma, null_ns))
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_relaunch_probe(lib, kind):
+    """Ordinary, cooperative and graph-replayed launches (Eq. 6)."""
+    ns, sigma, null_ns = lib.sync_bench_relaunch(256, 256, cooperative=kind, reps=10)
+    say("relaunch kind=%d: overhead %.1f ns (sigma %.1f), null kernel %.1f ns" % (kind, ns, sigma, null_ns))
+    assert -2000 < ns < 1e5 and null_ns > 0
+
+
+def test_relaunch_probe_graph_on_side_stream(lib):
+    """The graph form replays on a caller's non-default stream as well."""
+    st = torch.cuda.Stream()
+    ns, sigma, null_ns = lib.sync_bench_relaunch(64, 256, cooperative=2, reps=5, stream=st.cuda_stream)
     assert -2000 < ns < 1e5 and null_ns > 0
 
 
