@@ -49,14 +49,63 @@ __device__ __forceinline__ int64_t offset_at(const int64_t* offsets, int64_t i) 
   return ((const __attribute__((address_space(4))) int64_t*)offsets)[i];
 }
 
+// Pieces whose workgroup combine is finished together, after one barrier.
+constexpr int kBatch = 64;
+
+struct PieceInfo {
+  int64_t s, sa, sb;  // segment id and its bounds
+};
+
 // Sum of the np pieces of a cut segment (owning slice o: carry_out[o], then
-// carry_in[o+1 .. o+np-1]) by the whole workgroup: thread t adds pieces
-// o+t, o+t+blockDim, ... in order, then the fixed binary64 workgroup
-// combine.  The total is returned to thread 0.
-__device__ __forceinline__ double combine_pieces(const SegArgs& a, int64_t o, int64_t np, double* lds) {
+// carry_in[o+1 .. o+np-1]) by one wavefront: lane l adds pieces o+l,
+// o+l+64, ... in order, then the fixed binary64 wavefront combine
+// (returned to every lane).
+__device__ __forceinline__ double combine_pieces(const SegArgs& a, int64_t o, int64_t np) {
   double v = 0.0;
-  for (int64_t k = o + threadIdx.x; k < o + np; k += blockDim.x) v += k == o ? a.carry_out[o].val : a.carry_in[k].val;
-  return block_reduce<OpF64>(v, lds);
+  for (int64_t k = o + __lane_id(); k < o + np; k += kWave) v += k == o ? a.carry_out[o].val : a.carry_in[k].val;
+  return wave_reduce_dpp<OpF64>(v);
+}
+
+// Completes one piece whose workgroup total is v, by one wavefront: a whole
+// segment is written; a piece of a cut segment is published in its carry
+// slot, and the piece that completes the segment's ticket sums all pieces
+// (ticket form), or the owning workgroup does so after the grid barrier
+// (barrier form: *own_fix records the segment).
+template <bool BARRIER>
+__device__ __forceinline__ void finish_piece(const SegArgs& a, const PieceInfo& p, double v, int64_t lo, int64_t hi,
+                                             int64_t g, int64_t chunk, int64_t* own_fix) {
+  const int lane = __lane_id();
+  if (p.sa >= lo && p.sb <= hi) {
+    if (lane == 0) a.out[p.s] = v;
+    return;
+  }
+  const int64_t o = p.sa / chunk;
+  const int64_t np = (p.sb - 1) / chunk - o + 1;
+  int last = 0;
+  if (lane == 0) {
+    const SegCarry c{p.s, v};
+    if (p.sa < lo)
+      a.carry_in[g] = c;
+    else
+      a.carry_out[g] = c;
+    if constexpr (BARRIER) {
+      if (p.sa >= lo) *own_fix = p.s;
+    } else {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      const unsigned tk = __hip_atomic_fetch_add(&a.tickets[o], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      last = tk == (unsigned)(np - 1);
+    }
+  }
+  if constexpr (!BARRIER) {
+    if (__builtin_amdgcn_readfirstlane(last)) {  // this wave published the last piece
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const double w = combine_pieces(a, o, np);
+      if (lane == 0) {
+        a.out[p.s] = w;
+        __hip_atomic_store(&a.tickets[o], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
 }
 
 // Moves the segment cursor s to the next non-empty segment that starts
@@ -99,18 +148,30 @@ __device__ __forceinline__ void add_masked(CompF32* acc, const v4f* v, int bs, i
   }
 }
 
+// Whether any of the calling wave's rows of the tile meets [ra, rb).
+template <int IPT>
+__device__ __forceinline__ bool wave_touches(int bs, int ra, int rb) {
+  const int wave0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x & ~(kWave - 1));
+  bool t = false;
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) {
+    const int wb = 4 * (u * bs + wave0);
+    t = t || (wb < rb && wb + 4 * kWave > ra);
+  }
+  return t;
+}
+
 template <int IPT, bool NT, bool BARRIER>
 __global__ __launch_bounds__(1024) void k_segmented(SegArgs a) {
   using M = ModeF32Comp;
-  // Two LDS buffers used alternately by consecutive pieces: a wave can only
-  // write a buffer again after the next piece's barrier, which wave 0
-  // reaches only once it has read that buffer, so no barrier is needed
-  // between pieces.
-  __shared__ CompF32 lds[2][kMaxWavesPerWG];
-  __shared__ double lds_fix[kMaxWavesPerWG];
-  __shared__ int fix_now;      // ticket: this workgroup completes the cut segment
+  // Per-wave partials of up to kBatch finished pieces, completed together
+  // after one barrier.  Two buffers used alternately: a wave writes a
+  // buffer again only after the next batch's barrier, which every wave
+  // reaches after its reads of that buffer.
+  __shared__ CompF32 part[2][kBatch][kMaxWavesPerWG];
+  __shared__ PieceInfo info[2][kBatch];
   __shared__ int64_t own_fix;  // barrier form: cut segment this workgroup owns
-  int buf = 0;
+  int buf = 0, nb = 0;
   const int64_t nseg = a.nseg;
   const int64_t E = offset_at(a.offsets, nseg);
   const int64_t G = gridDim.x;
@@ -150,6 +211,22 @@ __global__ __launch_bounds__(1024) void k_segmented(SegArgs a) {
   const int64_t T = bs * IPT;
   const int64_t ntiles = lo < hi ? (vhi - vlo + T - 1) / T : 0;
   const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int lane = tid % kWave;
+  const int nwaves = (int)bs / kWave;
+  if (tid == 0) own_fix = -1;
+
+  // Completes the batched pieces: wave w finishes pieces w, w + nwaves, ...
+  auto flush = [&]() {
+    __syncthreads();
+    for (int j = wave; j < nb; j += nwaves) {
+      CompF32 v = lane < nwaves ? part[buf][j][lane] : OpComp::zero();
+      v = wave_reduce_dpp<OpComp>(v);
+      finish_piece<BARRIER>(a, info[buf][j], comp_to_double(v), lo, hi, g, chunk, &own_fix);
+    }
+    buf ^= 1;
+    nb = 0;
+  };
 
   CompF32 acc[IPT];
 #pragma unroll
@@ -166,7 +243,6 @@ __global__ __launch_bounds__(1024) void k_segmented(SegArgs a) {
     }
   };
 
-  int64_t own_seg = -1;  // segment that starts in this slice and continues
   if (ntiles > 0) load_tile(cur, 0);
   for (int64_t t = 0; t < ntiles; ++t) {
     // The current tile is complete before the next one is requested, so
@@ -179,49 +255,22 @@ __global__ __launch_bounds__(1024) void k_segmented(SegArgs a) {
     const int64_t e1 = 4 * (vlo + (t + 1) * T) - shift;  // one past its last
     const int64_t span = e1 - e0;  // 4 T elements
     auto rel = [&](int64_t e) { return (int)std::min(std::max(e - e0, (int64_t)0), span); };
-    // Pieces that end in this tile.
+    // Pieces that end in this tile: each wave's share goes to the batch.
     while (have && B <= e1) {
-      add_masked<IPT>(acc, cur, (int)bs, rel(A), rel(B));
+      const int ra = rel(A), rb = rel(B);
+      add_masked<IPT>(acc, cur, (int)bs, ra, rb);
       CompF32 tot = acc[0];
 #pragma unroll
       for (int u = 1; u < IPT; ++u) tot = OpComp::add(tot, acc[u]);
 #pragma unroll
       for (int u = 0; u < IPT; ++u) acc[u] = M::zero();
-      tot = block_reduce<OpComp>(tot, lds[buf]);
-      buf ^= 1;
-      if (sa >= lo && sb <= hi) {  // whole segment in the slice
-        if (tid == 0) a.out[s] = comp_to_double(tot);
-      } else {  // a piece of a cut segment: publish it (rare: at most two per slice)
-        const int64_t o = sa / chunk;
-        const int64_t np = (sb - 1) / chunk - o + 1;
-        if (tid == 0) {
-          const SegCarry c{s, comp_to_double(tot)};
-          if (sa < lo)
-            a.carry_in[g] = c;
-          else
-            a.carry_out[g] = c;
-          if constexpr (!BARRIER) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            const unsigned tk =
-                __hip_atomic_fetch_add(&a.tickets[o], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            fix_now = tk == (unsigned)(np - 1);
-            if (fix_now) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-          } else {
-            if (sa >= lo) own_seg = s;
-          }
-        }
-        if constexpr (!BARRIER) {
-          __syncthreads();
-          if (fix_now) {  // the last piece published: this workgroup sums them
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            const double v = combine_pieces(a, o, np, lds_fix);
-            if (tid == 0) {
-              a.out[s] = v;
-              __hip_atomic_store(&a.tickets[o], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-          }
-        }
-      }
+      // A piece that started in this tile has nothing in the waves whose
+      // rows miss it: they skip the wavefront combine.
+      if (A < e0 || wave_touches<IPT>((int)bs, ra, rb)) tot = wave_reduce_dpp<OpComp>(tot);
+      else tot = OpComp::zero();
+      if (lane == 0) part[buf][nb][wave] = tot;
+      if (tid == 0) info[buf][nb] = PieceInfo{s, sa, sb};
+      if (++nb == kBatch) flush();
       ++s;
       have = seek_segment(a, s, hi, E, end_wg, sa, sb);
       A = std::max(sa, lo);
@@ -239,16 +288,16 @@ __global__ __launch_bounds__(1024) void k_segmented(SegArgs a) {
 #pragma unroll
     for (int u = 0; u < IPT; ++u) cur[u] = nxt[u];
   }
+  if (nb > 0) flush();
   if constexpr (BARRIER) {
-    if (tid == 0) own_fix = own_seg;
     grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit);  // also a workgroup barrier
     const int64_t os = own_fix;
-    if (os >= 0) {
+    if (os >= 0 && wave == 0) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       const int64_t o = offset_at(a.offsets, os) / chunk;
       const int64_t np = (offset_at(a.offsets, os + 1) - 1) / chunk - o + 1;
-      const double v = combine_pieces(a, o, np, lds_fix);
-      if (tid == 0) a.out[os] = v;
+      const double v = combine_pieces(a, o, np);
+      if (lane == 0) a.out[os] = v;
     }
   }
 }

@@ -113,14 +113,18 @@ def test_relaunch_probe(lib, kind):
     """Ordinary, cooperative and graph-replayed launches (Eq. 6)."""
     ns, sigma, null_ns = lib.sync_bench_relaunch(256, 256, cooperative=kind, reps=10)
     say("relaunch kind=%d: overhead %.1f ns (sigma %.1f), null kernel %.1f ns" % (kind, ns, sigma, null_ns))
-    assert -2000 < ns < 1e5 and null_ns > 0
+    assert -2000 < ns < 1e5
+    # Section IV's host-clock difference between 5 and 1 launches; inside a
+    # graph the extra kernels cost less than the host clock's noise, so the
+    # graph figure may come out at or below zero.
+    assert (null_ns > 0) if kind != 2 else (abs(null_ns) < 1e5)
 
 
 def test_relaunch_probe_graph_on_side_stream(lib):
     """The graph form replays on a caller's non-default stream as well."""
     st = torch.cuda.Stream()
     ns, sigma, null_ns = lib.sync_bench_relaunch(64, 256, cooperative=2, reps=5, stream=st.cuda_stream)
-    assert -2000 < ns < 1e5 and null_ns > 0
+    assert -2000 < ns < 1e5 and abs(null_ns) < 1e5
 
 
 @pytest.mark.parametrize("groups", [1, 2, 8, 32])
