@@ -294,10 +294,12 @@ struct F16 {
   __device__ static float one(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
 };
 
-// 16-bit inputs, compensated: the two halves of each 32-bit word are added
-// in fp32 (exact unless their exponents differ by more than the fp32
-// significand can bridge; then the error is at most half an fp32 ulp of the
-// pair), and each pair sum enters the (s, c) pair through TwoSum.
+// 16-bit inputs, compensated: the eight values of a 16-byte vector are
+// widened exactly and summed pairwise in fp32 (a sum of 16-bit values is
+// exact unless their exponents lie further apart than the fp32 significand
+// can bridge; otherwise each of the three levels rounds once), and the
+// vector's sum enters the (s, c) pair through one TwoSum.  About 2.75 VALU
+// operations per element instead of 5 for a TwoSum per pair.
 template <class H>
 struct ModeHalfComp {
   using In = uint16_t;
@@ -314,10 +316,11 @@ struct ModeHalfComp {
   }
   __device__ static void add_elem(Acc& a, In x) { add_f(a, H::one(x)); }
   __device__ static void add_vec(Acc& a, Vec v) {
-    add_f(a, H::lo(v.x) + H::hi(v.x));
-    add_f(a, H::lo(v.y) + H::hi(v.y));
-    add_f(a, H::lo(v.z) + H::hi(v.z));
-    add_f(a, H::lo(v.w) + H::hi(v.w));
+    const float p0 = H::lo(v.x) + H::hi(v.x);
+    const float p1 = H::lo(v.y) + H::hi(v.y);
+    const float p2 = H::lo(v.z) + H::hi(v.z);
+    const float p3 = H::lo(v.w) + H::hi(v.w);
+    add_f(a, (p0 + p1) + (p2 + p3));
   }
   __device__ static Part to_part(Acc a) { return comp_to_double(a); }
 };
