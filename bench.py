@@ -313,6 +313,33 @@ class Plans:
         return R.red_get_segmented_plan(nseg)
 
 
+def cpu_oracle_parallel(oracle, x, ex, nbytes):
+    """The same oracle call on one contiguous chunk per host CPU, in threads
+    (its C binning releases the GIL); the chunks' exact sums are added as
+    integers and must equal the single-thread exact sum."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    ncpu = len(os.sched_getaffinity(0))
+    chunks = [c for c in np_split(x, ncpu) if c.size]
+    with ThreadPoolExecutor(max_workers=ncpu) as pool:
+        ts = []
+        for _ in range(3):
+            c0 = time.perf_counter()
+            parts = list(pool.map(lambda c: oracle.exact_sum(c, "f32"), chunks))
+            ts.append(time.perf_counter() - c0)
+    same = (sum(p.num for p in parts) == ex.num and all(p.shift == ex.shift for p in parts)
+            and sum(p.n_nan for p in parts) == ex.n_nan)
+    t = statistics.median(ts)
+    return {"value": round(nbytes / t / 1e9, 3), "unit": "GB/s", "threads": ncpu, "matches_single_thread": same,
+            "sample": "the same 1 GiB input in %d contiguous chunks, one thread each, median of 3 runs of %.3f s"
+                      % (len(chunks), t)}
+
+
+def np_split(x, k):
+    import numpy as np
+    return np.array_split(x, k)
+
+
 def smi_query(args, limit=6000):
     """Output of one read-only amd-smi query as JSON (or its error text)."""
     import subprocess
@@ -733,6 +760,7 @@ def headline(args, R, dev, stream, sh, plans, inputs):
         cpu = {"value": round(nbytes / t_cpu / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
                "sample": "the full 2^28-element fp32 input (1 GiB), exact exponent-binned sum, "
                          "single thread, median of 3 runs of %.2f s" % t_cpu}
+        extra["cpu_oracle_all_cores"] = cpu_oracle_parallel(oracle, x, ex, nbytes)
 
     roof = {"bound": "hbm", "achieved": round(kernel_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(kernel_gbps / HBM_PEAK_GBPS, 4), "traffic": traffic_per_launch(plan.as_dict())}
