@@ -23,6 +23,12 @@ Contents
 * ``neumaier``           -- FP64 compensated sum, a secondary cross-check.
 * ``kernel_total_latency``, ``launch_overhead_eq6``, ``per_op_latency_eq7``,
   ``sigma_eq8``          -- the probe formulas of Sections IV and IX.
+* ``jacobi_1d_f32``      -- the iterative stencil whose time loop the paper
+                            proposes to move inside one persistent kernel
+                            (Section VII-B): explicit 1D Jacobi / heat steps
+                            in binary32 with one fixed operation order.
+* ``jacobi_1d_f64``      -- the same steps in binary64 (for the closed-form
+                            pins).
 
 Every function cites the passage it follows.  Pins (tests that fix this code
 to something other than itself) live in ``tests/test_oracle.py``.
@@ -267,3 +273,44 @@ def sigma_eq8(samples_k1: Sequence[float], samples_k2: Sequence[float], r1: int,
         m = sum(v) / len(v)
         return math.sqrt(sum((a - m) ** 2 for a in v) / (len(v) - 1))
     return math.sqrt(sd(samples_k1) ** 2 + sd(samples_k2) ** 2) / abs(r1 - r2)
+
+
+# ---------------------------------------------------------------------------
+# Iterative stencil.  Section VII-B names iterative stencil methods as the
+# case where a persistent kernel holding the time loop can keep data in
+# on-chip memory across grid barriers, instead of one kernel launch per
+# step.  The method is the explicit step of the 1D heat equation with fixed
+# end values:
+#     u'[i] = u[i] + r * ((u[i-1] + u[i+1]) - 2 u[i])   for 1 <= i <= n-2,
+#     u'[0] = u[0],  u'[n-1] = u[n-1],
+# evaluated in exactly this order.  In ``jacobi_1d_f32`` every operation is
+# one binary32 operation rounded to nearest even (numpy float32 arithmetic,
+# no fused multiply-add), so a GPU that performs the same operations in the
+# same order must reproduce it bit for bit.  Arrays of fewer than 3 values
+# have no interior and do not change.
+# ---------------------------------------------------------------------------
+def jacobi_1d_f32(u0: np.ndarray, steps: int, r: float) -> np.ndarray:
+    u = np.array(u0, dtype=np.float32, copy=True)
+    r32 = np.float32(r)
+    two = np.float32(2.0)
+    if u.size < 3:
+        return u
+    for _ in range(steps):
+        nxt = u.copy()
+        neighbours = u[:-2] + u[2:]        # u[i-1] + u[i+1]
+        centre = two * u[1:-1]             # 2 u[i], exact
+        nxt[1:-1] = u[1:-1] + r32 * (neighbours - centre)
+        u = nxt
+    return u
+
+
+def jacobi_1d_f64(u0: np.ndarray, steps: int, r: float) -> np.ndarray:
+    """The same steps in binary64."""
+    u = np.array(u0, dtype=np.float64, copy=True)
+    if u.size < 3:
+        return u
+    for _ in range(steps):
+        nxt = u.copy()
+        nxt[1:-1] = u[1:-1] + r * ((u[:-2] + u[2:]) - 2.0 * u[1:-1])
+        u = nxt
+    return u

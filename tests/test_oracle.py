@@ -253,3 +253,84 @@ def test_eq8_sigma():
     want = math.sqrt(statistics.stdev(a) ** 2 + statistics.stdev(b) ** 2) / 7
     assert oracle.sigma_eq8(a, b, 8, 1) == pytest.approx(want, rel=1e-12)
     assert oracle.sigma_eq8([3.0] * 4, [1.0] * 4, 2, 1) == 0.0
+
+
+# ------------------------------------------------------------- stencil
+# The iterative stencil of Section VII-B (the time loop a persistent kernel
+# can hold): u'[i] = u[i] + r ((u[i-1] + u[i+1]) - 2 u[i]), ends fixed.
+
+def test_jacobi_binomial_closed_form():
+    """r = 1/4 turns a step into u' = (u[i-1] + 2 u[i] + u[i+1]) / 4, so T
+    steps from a unit impulse give C(2T, T+k) / 4^T at distance k.  Every
+    value is a multiple of 4^-T below 1, exact in binary32 for T <= 12."""
+    for T in (0, 1, 2, 5, 12):
+        n = 2 * T + 9
+        c = n // 2
+        u = np.zeros(n, np.float32)
+        u[c] = 1.0
+        got = oracle.jacobi_1d_f32(u, T, 0.25)
+        want = np.zeros(n)
+        for k in range(-T, T + 1):
+            want[c + k] = math.comb(2 * T, T + k) / 4.0 ** T
+        assert np.array_equal(got.astype(np.float64), want), T
+
+
+def test_jacobi_constant_and_linear_fields_are_fixed_points():
+    """A constant or an integer-valued linear field has zero second
+    difference: every step leaves it unchanged, bit for bit."""
+    for r in (0.1, 0.25, 0.4999):
+        c = np.full(101, 3.75, np.float32)
+        assert np.array_equal(oracle.jacobi_1d_f32(c, 50, r), c)
+        lin = (7 - 3 * np.arange(101)).astype(np.float32)
+        assert np.array_equal(oracle.jacobi_1d_f32(lin, 50, r), lin)
+
+
+def test_jacobi_mirror_symmetry_and_fixed_ends():
+    x = inputs.normal_f32(1001, sub=50)
+    a = oracle.jacobi_1d_f32(x, 37, 0.3)
+    b = oracle.jacobi_1d_f32(x[::-1], 37, 0.3)
+    assert np.array_equal(a, b[::-1])  # (u[i-1] + u[i+1]) is symmetric
+    assert a[0] == x[0] and a[-1] == x[-1]
+    assert not np.array_equal(a[1:-1], x[1:-1])
+
+
+def test_jacobi_eigenmode_decay():
+    """sin(pi k i / (n-1)) vanishes at both ends and is an eigenvector:
+    one step multiplies it by 1 - 4 r sin^2(pi k / (2 (n-1)))."""
+    n, k, r, T = 257, 3, 0.3, 200
+    i = np.arange(n)
+    u0 = np.sin(np.pi * k * i / (n - 1))
+    lam = 1 - 4 * r * math.sin(math.pi * k / (2 * (n - 1))) ** 2
+    got = oracle.jacobi_1d_f64(u0, T, r)
+    assert np.max(np.abs(got - lam ** T * u0)) <= 1e-12
+    got32 = oracle.jacobi_1d_f32(u0.astype(np.float32), T, r).astype(np.float64)
+    assert np.max(np.abs(got32 - lam ** T * u0)) <= 2e-5
+
+
+def test_jacobi_brute_force_rationals():
+    """Exact rational evaluation of the recurrence on tiny random inputs:
+    the binary64 version agrees to rounding, the binary32 version within
+    its rounding bound (a few ulps of the largest value per step)."""
+    rng = random.Random(7)
+    for _ in range(20):
+        n = rng.randint(3, 9)
+        T = rng.randint(0, 6)
+        r = rng.choice([0.125, 0.3, 0.45])
+        x = np.array([rng.uniform(-2, 2) for _ in range(n)], np.float32)
+        u = [Fraction(float(v)) for v in x]
+        fr = Fraction(float(np.float32(r)))
+        for _ in range(T):
+            u = [u[0]] + [u[j] + fr * ((u[j - 1] + u[j + 1]) - 2 * u[j]) for j in range(1, n - 1)] + [u[-1]]
+        exact = np.array([float(v) for v in u])
+        g64 = oracle.jacobi_1d_f64(x.astype(np.float64), T, float(np.float32(r)))
+        assert np.max(np.abs(g64 - exact)) <= 1e-14
+        g32 = oracle.jacobi_1d_f32(x, T, r).astype(np.float64)
+        assert np.max(np.abs(g32 - exact)) <= 4 * (T + 1) * 2.0 ** -22
+
+
+def test_jacobi_short_arrays_and_zero_steps():
+    for n in (0, 1, 2):
+        x = np.arange(n, dtype=np.float32)
+        assert np.array_equal(oracle.jacobi_1d_f32(x, 5, 0.25), x)
+    x = inputs.normal_f32(50, sub=51)
+    assert np.array_equal(oracle.jacobi_1d_f32(x, 0, 0.25), x)
