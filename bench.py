@@ -340,6 +340,47 @@ def np_split(x, k):
     return np.array_split(x, k)
 
 
+def stencil_configs(R, dev, stream, emit, timed):
+    """Microseconds per step of the 1D Jacobi stencil: relaunch (one kernel
+    per step, u and scratch through the caches / HBM every step) and the
+    persistent form with a grid barrier every k steps; the forms' results
+    are compared bit for bit on the GPU."""
+    import torch
+
+    from paper_2004_05371_amd import inputs
+
+    sh = stream.cuda_stream
+    forms = [("relaunch", R.RED_VARIANT_RELAUNCH, 0, 0), ("persistent_k1", R.RED_VARIANT_PERSISTENT, 1, 0),
+             ("persistent_k8", R.RED_VARIANT_PERSISTENT, 8, 0), ("persistent_k32", R.RED_VARIANT_PERSISTENT, 32, 0),
+             ("persistent_xcd_k8", R.RED_VARIANT_PERSISTENT, 8, R.FLAG_XCD)]
+    for n in (1 << 16, 1 << 20, 1 << 22, 8_000_000):
+        steps = 1000 if n <= (1 << 20) else 200
+        x = torch.from_numpy(inputs.normal_f32(n, sub=66)).to("cuda")
+        u = torch.empty_like(x)
+        sc = torch.empty_like(x)
+        rec = {"config": "stencil", "n": n, "steps": steps, "r": 0.25, "bytes_per_step_relaunch": 8 * n}
+        results = {}
+        for name, variant, k, flags in forms:
+            o = R.make_opts(variant=variant, flags=flags)
+            call = lambda: R.stencil_jacobi_1d(u.data_ptr(), sc.data_ptr(), n, steps, 0.25, k, sh, o)
+            try:
+                u.copy_(x)
+                call()
+                torch.cuda.synchronize()
+                results[name] = u.clone()
+                ms = timed(call, 5)
+            except R.RedError as e:
+                rec[name] = "refused: %s" % e
+                continue
+            rec[name + "_us_per_step"] = round(ms * 1e3 / steps, 3)
+            rec[name + "_GBps_equiv"] = round(8 * n / (ms * 1e-3 / steps) / 1e9, 1)
+        ref = results.get("relaunch")
+        rec["forms_bit_identical"] = bool(ref is not None and all(torch.equal(ref, v) for v in results.values()))
+        emit(rec)
+        del x, u, sc, results
+        torch.cuda.empty_cache()
+
+
 def smi_query(args, limit=6000):
     """Output of one read-only amd-smi query as JSON (or its error text)."""
     import subprocess
@@ -574,6 +615,10 @@ def run_configs(R, dev, stream, path, plans):
               "max_rel_err": worst, "cpu_oracle_s": round(tc, 2)})
         del xt, ot
         torch.cuda.empty_cache()
+
+    # -- iterative stencil: one launch per step against the time loop inside
+    #    one persistent kernel (values kept in LDS across grid barriers)
+    stencil_configs(R, dev, stream, emit, timed)
 
     # -- model: the Eq. 1-5 switch point between one workgroup ("basic")
     #    and the whole device ("more") from constants fitted on this GPU,

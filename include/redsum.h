@@ -226,6 +226,50 @@ int red_sum_segmented_loop(const float *x, const int64_t *host_offsets, int64_t 
                            void *stream);
 
 /* ---------------------------------------------------------------------
+ * Iterative stencil (Section VII-B: a persistent kernel that holds the time
+ * loop of an iterative stencil method can keep its data on chip across
+ * grid barriers, where one launch per step cannot)
+ * ------------------------------------------------------------------- */
+
+/* `steps` explicit steps of the 1D heat equation (Jacobi smoothing) on
+ * u[0..n), in place:
+ *     u'[i] = u[i] + r * ((u[i-1] + u[i+1]) - 2 u[i])   1 <= i <= n-2,
+ *     u[0] and u[n-1] unchanged,
+ * every operation one binary32 operation in exactly this order (no fused
+ * multiply-add), so the result is the same bit for bit whatever the form.
+ *   u        device pointer to n floats, updated in place.
+ *   scratch  device pointer to n floats owned by the caller, not
+ *            overlapping u; its contents are overwritten.
+ *   n        number of values, 0 <= n < 2^40; n < 3 or steps == 0 leaves u
+ *            as it is.
+ *   steps    number of steps, >= 0.
+ *   r        the step's coefficient (stable for 0 <= r <= 1/2).
+ *   steps_per_sync  persistent form: steps between grid barriers, which
+ *            is also the halo width each workgroup keeps (1 = a barrier
+ *            every step); 0 = 8.  Any value gives the same result.
+ *   opts     NULL or plan.variant:
+ *            RED_VARIANT_RELAUNCH    one kernel launch per step (the
+ *                                    implicit barrier), u and scratch
+ *                                    alternating;
+ *            RED_VARIANT_PERSISTENT  one launch holding the time loop: each
+ *                                    workgroup keeps its block and halos in
+ *                                    LDS and exchanges boundary values with
+ *                                    its neighbours through u / scratch at a
+ *                                    grid barrier every steps_per_sync steps;
+ *            RED_VARIANT_AUTO        persistent when the array fits the
+ *                                    co-resident workgroups' LDS, else
+ *                                    relaunch.
+ *            plan.wg (default 512), plan.grid (default one workgroup per
+ *            CU, or as many 64 KB LDS windows as the array needs, capped at
+ *            the co-resident limit) and flags
+ *            RED_FLAG_PLAIN_LAUNCH / RED_FLAG_XCD as for red_sum.
+ * Asynchronous on `stream`.  RED_EINVAL for bad arguments, overlapping
+ * arrays, or a persistent request whose block does not fit one LDS window;
+ * a grid-barrier watchdog timeout is reported by red_check_error. */
+int stencil_jacobi_1d(float *u, float *scratch, int64_t n, int32_t steps, float r, int32_t steps_per_sync,
+                      void *stream, const red_opts *opts);
+
+/* ---------------------------------------------------------------------
  * Plans and autotuning (performance model of Section VII-A/B as prior)
  * ------------------------------------------------------------------- */
 

@@ -19,7 +19,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libredsum.so")
 BUILD_DIR = os.path.join(PKG, "_build")
-SOURCES = ["reduce.hip", "segmented.hip", "probes.hip", "runtime.hip"]
+SOURCES = ["reduce.hip", "segmented.hip", "probes.hip", "stencil.hip", "runtime.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

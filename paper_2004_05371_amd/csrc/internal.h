@@ -25,6 +25,7 @@ struct DeviceInfo {
   int64_t l2_bytes = 0;
   int64_t hbm_bytes = 0;
   int nxcc = 1;  // XCDs (accelerator complex dies) of the device
+  int64_t lds_per_wg = 65536;  // largest LDS allocation of one workgroup
   bool coop = false;
 };
 
@@ -76,7 +77,7 @@ int timer_begin(hipStream_t s);
 void timer_end(hipStream_t s, int slot);
 
 // Kernel launch (uniform signature: one argument struct by value).
-int launch(const void* fn, int grid, int block, void** args, hipStream_t s, bool cooperative);
+int launch(const void* fn, int grid, int block, void** args, hipStream_t s, bool cooperative, size_t lds_bytes = 0);
 
 // Reductions ---------------------------------------------------------------
 struct ReduceLaunch {
@@ -102,5 +103,9 @@ int seg_max_coresident(int ipt, int wg, const DeviceInfo& dev, int* n_wg);
 
 // Probes -------------------------------------------------------------------
 int bw_proxy_launch(const void* x, int64_t nbytes, int n_wg, int wg, Workspace* ws, hipStream_t s);
+
+// Iterative stencil ---------------------------------------------------------
+int stencil_launch(float* u, float* scratch, int64_t n, int steps, float r, int steps_per_sync, const red_plan& p,
+                   Workspace* ws, hipStream_t s, const DeviceInfo& dev);
 
 }  // namespace redsum

@@ -133,6 +133,7 @@ int ensure_device(const DeviceInfo** info) {
   d.l2_bytes = prop.l2CacheSize;
   d.hbm_bytes = (int64_t)prop.totalGlobalMem;
   d.coop = prop.cooperativeLaunch != 0;
+  d.lds_per_wg = (int64_t)prop.sharedMemPerBlock;
   int nx = 1;
   if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || nx < 1) {
     (void)hipGetLastError();
@@ -238,12 +239,12 @@ void timer_end(hipStream_t s, int slot) {
   (void)hipEventRecord(it->second.ev[slot].second, s);
 }
 
-int launch(const void* fn, int grid, int block, void** args, hipStream_t s, bool cooperative) {
+int launch(const void* fn, int grid, int block, void** args, hipStream_t s, bool cooperative, size_t lds_bytes) {
   hipError_t e;
   if (cooperative)
-    e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, 0, s);
+    e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, (unsigned)lds_bytes, s);
   else
-    e = hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, s);
+    e = hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds_bytes, s);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     if (e == hipErrorCooperativeLaunchTooLarge)
@@ -616,6 +617,44 @@ int red_autotune(int dtype, int acc, const void* x, int64_t n, void* out, void* 
 static int seg_direct(const SegLaunch& sl, const float* x, const int64_t* offsets, int64_t nseg, double* out,
                       Workspace* ws, hipStream_t s, const DeviceInfo& dev) {
   return seg_launch(sl, x, offsets, nseg, out, ws, s, dev);
+}
+
+int stencil_jacobi_1d(float* u, float* scratch, int64_t n, int32_t steps, float r, int32_t steps_per_sync,
+                      void* stream, const red_opts* opts) {
+  if (n < 0 || n >= ((int64_t)1 << 40)) return set_error(RED_EINVAL, "n out of range");
+  if (steps < 0) return set_error(RED_EINVAL, "steps must be >= 0");
+  if (steps_per_sync < 0) return set_error(RED_EINVAL, "steps_per_sync must be >= 0");
+  if (n > 0 && (!u || !scratch)) return set_error(RED_EINVAL, "u or scratch is NULL");
+  if (reinterpret_cast<uintptr_t>(u) % 4 || reinterpret_cast<uintptr_t>(scratch) % 4)
+    return set_error(RED_EINVAL, "u and scratch must be 4-byte aligned");
+  if (n > 0) {
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(u), b0 = reinterpret_cast<uintptr_t>(scratch);
+    const uintptr_t bytes = (uintptr_t)n * 4;
+    if (a0 < b0 + bytes && b0 < a0 + bytes) return set_error(RED_EINVAL, "u and scratch overlap");
+  }
+  red_plan p{RED_VARIANT_AUTO, 512, 1, 0, 0};
+  if (opts) {
+    if (opts->flags & ~(RED_FLAG_PLAIN_LAUNCH | RED_FLAG_XCD))
+      return set_error(RED_EINVAL, "unknown flags 0x%x", opts->flags);
+    const red_plan& q = opts->plan;
+    if (q.variant != RED_VARIANT_AUTO && q.variant != RED_VARIANT_RELAUNCH && q.variant != RED_VARIANT_PERSISTENT)
+      return set_error(RED_EINVAL, "stencil: variant must be AUTO, RELAUNCH or PERSISTENT");
+    if (q.wg != 0 && (q.wg < 64 || q.wg > 1024 || q.wg % 64)) return set_error(RED_EINVAL, "bad wg %d", q.wg);
+    if (q.grid < 0 || q.grid > RED_MAX_GRID) return set_error(RED_EINVAL, "bad grid %d", q.grid);
+    if (q.flags & ~(RED_FLAG_PLAIN_LAUNCH | RED_FLAG_XCD)) return set_error(RED_EINVAL, "bad plan flags");
+    p.variant = q.variant;
+    if (q.wg) p.wg = q.wg;
+    p.grid = q.grid;
+    p.flags = q.flags | opts->flags;
+  }
+  const DeviceInfo* dev;
+  int rc = ensure_device(&dev);
+  if (rc) return rc;
+  if (n < 3 || steps == 0) return RED_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace* ws;
+  if ((rc = get_workspace(s, &ws))) return rc;
+  return stencil_launch(u, scratch, n, steps, r, steps_per_sync, p, ws, s, *dev);
 }
 
 int red_sum_segmented_ex(const float* x, const int64_t* offsets, int64_t nseg, double* out, void* stream,

@@ -1,0 +1,256 @@
+// Iterative 1D Jacobi stencil: the time loop inside one persistent kernel
+// versus one kernel launch per step (gfx950).
+//
+// Section VII-B of Zhang et al. points out a benefit of grid barriers that
+// the reduction does not show: a persistent kernel that holds the time loop
+// of an iterative stencil keeps its data in on-chip memory across the
+// barriers, where one launch per step (the implicit barrier) must stream
+// the whole array through HBM or the caches every step.
+//
+// The step is u'[i] = u[i] + r ((u[i-1] + u[i+1]) - 2 u[i]) for
+// 1 <= i <= n-2, with u[0] and u[n-1] fixed, each operation one binary32
+// operation in that order (no contraction), so both forms reproduce the
+// step-by-step definition bit for bit.
+//
+//   * relaunch:   k_jacobi_step per step, ping-pong between u and the
+//                 caller's scratch array;
+//   * persistent: workgroup g owns the block [g m, (g+1) m) and holds it in
+//                 LDS with a halo of K values on each side.  It runs K steps
+//                 on the shrinking valid range (redundantly recomputing the
+//                 halo, so neighbours need no exchange inside the K steps),
+//                 then publishes its first and last K values, meets the
+//                 other workgroups at a grid barrier and reads its
+//                 neighbours' values into its halo.  One barrier per K steps;
+//                 HBM is touched only at the start, at the end and for the
+//                 2 K boundary values per workgroup and barrier.
+#include <algorithm>
+
+#include "device_prims.h"
+#include "internal.h"
+
+namespace redsum {
+
+// One step at an interior point, in the method's operation order.
+__device__ __forceinline__ float jacobi_point(float left, float centre, float right, float r) {
+#pragma clang fp contract(off)
+  const float neighbours = left + right;
+  const float twice = 2.0f * centre;
+  return centre + r * (neighbours - twice);
+}
+
+__global__ __launch_bounds__(1024) void k_jacobi_step(const float* __restrict__ u, float* __restrict__ v, int64_t n,
+                                                      float r) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float c = u[i];
+    v[i] = (i == 0 || i == n - 1) ? c : jacobi_point(u[i - 1], c, u[i + 1], r);
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_copy_f32(const float* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+struct StencilArgs {
+  float* u;        // values, in and out
+  float* scratch;  // n values: boundary publication, alternating with u
+  int64_t n;
+  int64_t m;       // block length per workgroup
+  int steps;
+  int k;           // steps per grid barrier = halo width, 1 <= k <= m
+  float r;
+  BarrierWords* words;
+  unsigned spin_limit;
+  unsigned bar_groups;
+};
+
+// Values per thread held in registers during one step: the LDS window of a
+// workgroup is at most kStencilPT x blockDim values.  The kernel is built
+// for PT = 1, 2, 4, ..., kStencilPT rows per window and launched with the
+// smallest that holds the window, so a small window costs few instructions.
+constexpr int kStencilPT = 32;
+
+template <int PT>
+__global__ __launch_bounds__(1024) void k_jacobi_persistent(StencilArgs a) {
+  extern __shared__ float win[];  // elements [lo - k, hi + k), win[j] = element lo - k + j
+  const int64_t n = a.n;
+  const int k = a.k;
+  const int64_t lo = (int64_t)blockIdx.x * a.m;
+  const int64_t hi = std::min(lo + a.m, n);
+  const int blen = (int)(hi - lo);
+  const int len = blen + 2 * k;
+  const int64_t base = lo - k;
+  const int tid = threadIdx.x;
+  const int bs = blockDim.x;
+  const int qn = (len + bs - 1) / bs;  // window rows of bs values
+
+  for (int j = tid; j < len; j += bs) {
+    const int64_t e = base + j;
+    win[j] = (e >= 0 && e < n) ? a.u[e] : 0.0f;
+  }
+  __syncthreads();
+
+  int sync = 0;
+  for (int step = 0; step < a.steps;) {
+    const int kk = std::min(k, a.steps - step);
+    for (int s = 1; s <= kk; ++s) {
+      // Window indices still valid after this step: elements
+      // [lo - k + s, hi + k - s); the end points of the array never change.
+      const int jlo = (int)(std::max<int64_t>(base + s, 1) - base);
+      const int jhi = (int)(std::min<int64_t>(hi + k - s, n - 1) - base);
+      float nv[PT];
+#pragma unroll
+      for (int q = 0; q < PT; ++q) {
+        if (q < qn) {  // workgroup-uniform: only the rows of the window
+          const int j = tid + q * bs;
+          nv[q] = (j >= jlo && j < jhi) ? jacobi_point(win[j - 1], win[j], win[j + 1], a.r) : 0.0f;
+        }
+      }
+      __syncthreads();  // every read of the old values precedes the writes
+#pragma unroll
+      for (int q = 0; q < PT; ++q) {
+        if (q < qn) {
+          const int j = tid + q * bs;
+          if (j >= jlo && j < jhi) win[j] = nv[q];
+        }
+      }
+      __syncthreads();
+    }
+    step += kk;
+    if (step < a.steps) {
+      // Publish the first and last k values of the block (time `step`) to
+      // the buffer of this barrier's parity, meet, read the neighbours'.
+      // The first publication goes to scratch: u is still being read for
+      // the initial halos.
+      float* pub = (sync & 1) ? a.u : a.scratch;
+      const int w = std::min(k, blen);
+      for (int j = tid; j < w; j += bs) {
+        pub[lo + j] = win[k + j];
+        pub[hi - 1 - j] = win[k + blen - 1 - j];
+      }
+      grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit);
+      for (int j = tid; j < k; j += bs) {
+        const int64_t el = lo - k + j;  // left halo: the left neighbour's last k values
+        if (el >= 0) win[j] = pub[el];
+        const int64_t er = hi + j;      // right halo: the right neighbour's first k values
+        if (er < n) win[k + blen + j] = pub[er];
+      }
+      __syncthreads();
+      ++sync;
+    }
+  }
+  // Neighbours read u for their initial halos and, at odd exchanges, as the
+  // publication buffer: the block is written back only once every
+  // workgroup is past its last read of u.
+  grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit);
+  for (int j = tid; j < blen; j += bs) a.u[lo + j] = win[k + j];
+}
+
+namespace {
+
+const void* persistent_kernel(int pt) {
+  switch (pt) {
+    case 1: return reinterpret_cast<const void*>(&k_jacobi_persistent<1>);
+    case 2: return reinterpret_cast<const void*>(&k_jacobi_persistent<2>);
+    case 4: return reinterpret_cast<const void*>(&k_jacobi_persistent<4>);
+    case 8: return reinterpret_cast<const void*>(&k_jacobi_persistent<8>);
+    case 16: return reinterpret_cast<const void*>(&k_jacobi_persistent<16>);
+    default: return reinterpret_cast<const void*>(&k_jacobi_persistent<kStencilPT>);
+  }
+}
+
+int stencil_coresident(int wg, size_t lds_bytes, const DeviceInfo& dev, int* n_wg) {
+  int per_cu = 0;
+  RED_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel(kStencilPT), wg, lds_bytes));
+  *n_wg = per_cu * dev.cus;
+  if (*n_wg < 1) return set_error(RED_EINVAL, "persistent stencil: a %d-thread workgroup with %zu bytes of LDS "
+                                              "cannot be resident", wg, lds_bytes);
+  return RED_OK;
+}
+
+}  // namespace
+
+int stencil_launch(float* u, float* scratch, int64_t n, int steps, float r, int steps_per_sync, const red_plan& p,
+                   Workspace* ws, hipStream_t s, const DeviceInfo& dev) {
+  if (n < 3 || steps == 0) return RED_OK;
+  const int wg = p.wg;
+  int variant = p.variant;
+  const int k_req = steps_per_sync > 0 ? steps_per_sync : 8;
+  // LDS window: the 64 KB a workgroup gets without opting in to more, less
+  // a margin for the barrier's static LDS.
+  const int64_t lds_floats =
+      std::min<int64_t>((std::min<int64_t>(dev.lds_per_wg, 65536) - 256) / 4, (int64_t)kStencilPT * wg);
+
+  // Persistent geometry: one workgroup per CU unless the array needs more
+  // LDS windows, never more than are co-resident with the largest window,
+  // at least 64 values per workgroup.
+  int grid = 0;
+  int64_t m = 0;
+  int k = 0;
+  size_t lds_bytes = 0;
+  if (variant != RED_VARIANT_RELAUNCH) {
+    int g_max = 0;
+    int rc = stencil_coresident(wg, (size_t)lds_floats * 4, dev, &g_max);
+    if (rc) return rc;
+    const int64_t cap = std::max<int64_t>(1, lds_floats - 2 * (int64_t)k_req);  // block values per window
+    int64_t g = p.grid > 0 ? p.grid : std::max<int64_t>(dev.cus, (n + cap - 1) / cap);
+    g = std::max<int64_t>(1, std::min<int64_t>({g, (int64_t)g_max, (n + 63) / 64}));
+    m = (n + g - 1) / g;
+    grid = (int)((n + m - 1) / m);
+    k = (int)std::min<int64_t>(k_req, m);
+    const int64_t len = m + 2 * (int64_t)k;
+    if (len > lds_floats) {
+      if (variant == RED_VARIANT_PERSISTENT)
+        return set_error(RED_EINVAL,
+                         "persistent stencil: %lld values per workgroup with halos exceed the %lld values of an "
+                         "LDS window at this workgroup size (%d co-resident workgroups hold about %lld values)",
+                         (long long)len, (long long)lds_floats, g_max, (long long)cap * g_max);
+      variant = RED_VARIANT_RELAUNCH;  // AUTO: the array does not fit on chip
+    } else {
+      variant = RED_VARIANT_PERSISTENT;
+      lds_bytes = (size_t)len * 4;
+    }
+  }
+
+  if (variant == RED_VARIANT_RELAUNCH) {
+    int gridr = p.grid > 0 ? p.grid : 4 * dev.cus;
+    gridr = (int)std::max<int64_t>(1, std::min<int64_t>(gridr, (n + wg - 1) / wg));
+    float* src = u;
+    float* dst = scratch;
+    for (int t = 0; t < steps; ++t) {
+      void* args[] = {&src, &dst, &n, &r};
+      int rc = launch(reinterpret_cast<const void*>(&k_jacobi_step), gridr, wg, args, s, false);
+      if (rc) return rc;
+      std::swap(src, dst);
+    }
+    if (src != u) {
+      void* args[] = {&src, &u, &n};
+      return launch(reinterpret_cast<const void*>(&k_copy_f32), gridr, wg, args, s, false);
+    }
+    return RED_OK;
+  }
+
+  StencilArgs a;
+  a.u = u;
+  a.scratch = scratch;
+  a.n = n;
+  a.m = m;
+  a.steps = steps;
+  a.k = k;
+  a.r = r;
+  a.words = ws->words;
+  a.spin_limit = watchdog_spins();
+  a.bar_groups = ((p.flags & RED_FLAG_XCD) && dev.nxcc > 1) ? (kBarrierXcd | (unsigned)dev.nxcc)
+                                                            : barrier_groups(grid);
+  void* args[] = {&a};
+  const bool coop = (p.flags & RED_FLAG_PLAIN_LAUNCH) == 0;
+  const int slot = timer_begin(s);
+  int pt = 1;
+  while (pt < kStencilPT && (int64_t)pt * wg < m + 2 * (int64_t)k) pt *= 2;
+  int rc = launch(persistent_kernel(pt), grid, wg, args, s, coop, lds_bytes);
+  timer_end(s, slot);
+  return rc;
+}
+
+}  // namespace redsum

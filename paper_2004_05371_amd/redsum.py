@@ -46,7 +46,7 @@ EXPORTS = [
     "red_kernel_timer", "red_kernel_timer_read", "sync_bench_wave", "sync_bench_wave_ex", "sync_bench_block",
     "sync_bench_grid", "sync_bench_grid_ex", "sync_bench_relaunch", "sync_check_grid_order",
     "sync_check_watchdog", "sync_xcc_map", "red_max_coresident", "red_device_info",
-    "red_bw_proxy", "red_eq6_overhead", "red_eq7_latency", "red_eq8_sigma",
+    "red_bw_proxy", "red_eq6_overhead", "red_eq7_latency", "red_eq8_sigma", "stencil_jacobi_1d",
 ]
 
 
@@ -109,6 +109,7 @@ _SIGS = {
     "red_eq6_overhead": ([_d, _d, _i32, _i32], _d),
     "red_eq7_latency": ([_d, _d, _i64, _i64], _d),
     "red_eq8_sigma": ([_dp, _dp, _i32, _i64, _i64], _d),
+    "stencil_jacobi_1d": ([_vp, _vp, _i64, _i32, ctypes.c_float, _i32, _vp, _vp], _i32),
 }
 
 
@@ -315,6 +316,24 @@ def sync_xcc_map(n_wg: int, wg_size: int = 64, stream: int = 0):
     buf = (ctypes.c_int32 * n_wg)()
     _check(load().sync_xcc_map(n_wg, wg_size, buf, stream), "sync_xcc_map")
     return list(buf)
+
+
+def stencil_jacobi_1d(u: int, scratch: int, n: int, steps: int, r: float, steps_per_sync: int = 0,
+                      stream: int = 0, opts: Optional[Opts] = None) -> int:
+    return _check(load().stencil_jacobi_1d(u, scratch, n, steps, r, steps_per_sync, stream,
+                                           ctypes.byref(opts) if opts is not None else None), "stencil_jacobi_1d")
+
+
+def jacobi(t, steps: int, r: float, scratch=None, steps_per_sync: int = 0, opts: Optional[Opts] = None):
+    """In-place steps of the 1D Jacobi stencil on a contiguous float32 CUDA
+    tensor (asynchronous); returns t."""
+    import torch
+    if not t.is_cuda or not t.is_contiguous() or t.dtype != torch.float32:
+        raise ValueError("expected a contiguous float32 CUDA tensor")
+    if scratch is None:
+        scratch = torch.empty_like(t)
+    stencil_jacobi_1d(t.data_ptr(), scratch.data_ptr(), t.numel(), steps, r, steps_per_sync, current_stream(), opts)
+    return t
 
 
 def red_bw_proxy(x: int, nbytes: int, n_wg: int, wg_size: int, stream: int = 0) -> int:

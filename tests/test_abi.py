@@ -69,6 +69,14 @@ def test_validation_before_hip(lib):
     assert lib.sync_bench_wave_ex(0, 5, 64, 10, None, None, None, None) == R.RED_EINVAL
     assert lib.sync_bench_wave_ex(4, 0, 64, 10, None, None, None, None) == R.RED_EINVAL
     assert lib.sync_bench_grid(0, 256, 10, None, None, None, None) == R.RED_EINVAL
+    # stencil: negative steps, overlapping arrays, bad variant
+    assert lib.stencil_jacobi_1d(ctypes.c_void_p(64), ctypes.c_void_p(1 << 20), 10, -1, ctypes.c_float(0.25), 0,
+                                 None, None) == R.RED_EINVAL
+    assert lib.stencil_jacobi_1d(ctypes.c_void_p(64), ctypes.c_void_p(64 + 16), 10, 1, ctypes.c_float(0.25), 0,
+                                 None, None) == R.RED_EINVAL
+    bad = R.make_opts(variant=R.RED_VARIANT_ATOMIC)
+    assert lib.stencil_jacobi_1d(ctypes.c_void_p(64), ctypes.c_void_p(1 << 20), 10, 1, ctypes.c_float(0.25), 0,
+                                 None, ctypes.byref(bad)) == R.RED_EINVAL
     d = ctypes.c_double()
     for kind in (-1, 3):  # launch types are 0 ordinary, 1 cooperative, 2 graph
         assert lib.sync_bench_relaunch(8, 64, kind, 10, ctypes.byref(d), ctypes.byref(d), None, None) == R.RED_EINVAL
