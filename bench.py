@@ -490,12 +490,18 @@ def run_configs(R, dev, stream, path, plans):
           "amd_smi": {k: smi_query(v) for k, v in (("partition", ["static", "--partition"]),
                                                    ("clock_power", ["metric", "--clock", "--power"]))}})
 
+    last = {}  # statistics of the latest timed() call, in microseconds
+
     def timed(fn, reps, flushed=False):
         for _ in range(3):
             fn()
         if flushed:
-            return statistics.median(time_flushed(fn, reps, stream, flush))
-        tt, _ = time_steps(fn, reps, stream)
+            tt = time_flushed(fn, reps, stream, flush)
+        else:
+            tt, _ = time_steps(fn, reps, stream)
+        last.clear()
+        last.update(median=round(statistics.median(tt) * 1e3, 2), min=round(min(tt) * 1e3, 2),
+                    sigma=round(statistics.stdev(tt) * 1e3, 3) if len(tt) > 1 else 0.0, reps=len(tt))
         return statistics.median(tt)
 
     def cpu_exact(x, kind):
@@ -555,10 +561,11 @@ def run_configs(R, dev, stream, path, plans):
             plan = plans.sum_plan(t, out, acc, sh)
             o = R.opts_from_plan(plan, acc=acc)
             ms = timed(lambda: R.red_sum_ex(R.RED_F32, t.data_ptr(), t.numel(), out.data_ptr(), sh, o), 50)
+            stats = dict(last)
             torch.cuda.synchronize()
             r = out.item()
             emit({"config": "f32", "dist": gen, "acc": name, "n": x.size, "plan": plan.as_dict(),
-                  "GBps": gbps(x.nbytes, ms), "rel_err": oracle.rel_err(r, ex),
+                  "GBps": gbps(x.nbytes, ms), "timing_us": stats, "rel_err": oracle.rel_err(r, ex),
                   "err_over_sum_abs": abs(float(ex.fraction) - r) / absx, "cpu_oracle_s": round(tc, 3)})
         del t
 
@@ -576,7 +583,7 @@ def run_configs(R, dev, stream, path, plans):
             o = R.opts_from_plan(plan, acc=acc)
             ms = timed(lambda: R.red_sum_ex(code, t.data_ptr(), t.numel(), out.data_ptr(), sh, o), 50)
             torch.cuda.synchronize()
-            res[name] = {"plan": plan.as_dict(), "GBps": gbps(bits.nbytes, ms),
+            res[name] = {"plan": plan.as_dict(), "GBps": gbps(bits.nbytes, ms), "timing_us": dict(last),
                          "Gelem_per_s": round(bits.size / (ms * 1e-3) / 1e9, 1),
                          "rel_err": oracle.rel_err(out.item(), ex)}
         emit({"config": "half", "dtype": kind, "n": bits.size, **res, "cpu_oracle_s": round(tc, 3)})
@@ -595,6 +602,7 @@ def run_configs(R, dev, stream, path, plans):
         plan = plans.seg_plan(xt, ot, out, sh)
         nbytes = x.nbytes + off.nbytes + out.numel() * 8
         ms_graph = timed(lambda: R.red_sum_segmented(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh), 30)
+        graph_stats = dict(last)
         o = R.make_opts(variant=R.RED_VARIANT_PERSISTENT, wg=plan.wg, ipt=plan.ipt,
                         grid=min(plan.grid, R.red_max_coresident(plan.wg)),
                         flags=R.FLAG_PLAIN_LAUNCH | (plan.flags & R.FLAG_NONTEMPORAL))
@@ -609,7 +617,7 @@ def run_configs(R, dev, stream, path, plans):
         tc = time.perf_counter() - c0
         worst = max(oracle.rel_err(float(got[k]), e) if e.fraction != 0 else abs(got[k]) for k, e in enumerate(sums))
         emit({"config": label, "nseg": nseg, "total_elems": int(off[-1]), "bytes": nbytes, "plan": plan.as_dict(),
-              "graph_us": round(ms_graph * 1e3, 1), "graph_GBps": gbps(nbytes, ms_graph),
+              "graph_us": round(ms_graph * 1e3, 1), "graph_GBps": gbps(nbytes, ms_graph), "graph_timing_us": graph_stats,
               "grid_barrier_fixup_us": round(ms_barrier * 1e3, 1),
               "loop_per_segment_us": round(ms_loop * 1e3, 1), "speedup_vs_loop": round(ms_loop / ms_graph, 1),
               "max_rel_err": worst, "cpu_oracle_s": round(tc, 2)})
