@@ -203,7 +203,7 @@ int red_sum_ex(int dtype, const void *x, int64_t n, void *out, void *stream, con
  *           offsets[0] == 0 (not checked on the device).
  *   nseg    number of segments, 0 <= nseg < 2^31.
  *   out     device pointer to nseg doubles.  Empty segments give 0.
- * One persistent launch: every workgroup owns an equal slice of the
+ * One persistent launch: every wavefront owns an equal slice of the
  * elements, sums the pieces of the segments that meet its slice, and the
  * pieces of segments that cross slice boundaries are combined in slice order
  * in binary64 by the last contributor.  The launch is captured in a hipGraph
@@ -216,7 +216,9 @@ int red_sum_segmented(const float *x, const int64_t *offsets, int64_t nseg, doub
 /* red_sum_segmented with explicit options.  opts->plan.variant selects the
  * cross-slice fix-up: RED_VARIANT_ATOMIC (ticket, default) or
  * RED_VARIANT_PERSISTENT (co-resident grid + grid barrier, launched
- * directly, not from a graph).  RED_FLAG_NO_GRAPH disables graph capture. */
+ * directly, not from a graph).  plan.wg is at most 512 here (RED_EINVAL
+ * otherwise); grid x wg / 64 wavefront slices are capped at 65536.
+ * RED_FLAG_NO_GRAPH disables graph capture. */
 int red_sum_segmented_ex(const float *x, const int64_t *offsets, int64_t nseg, double *out,
                          void *stream, const red_opts *opts);
 
@@ -290,7 +292,8 @@ int red_autotune(int dtype, int acc, const void *x, int64_t n, void *out, void *
                  red_plan *best, double *best_us);
 
 /* Install / read the plan of segmented batches whose nseg has the same
- * bit length as `nseg` (variant RED_VARIANT_ATOMIC or _PERSISTENT). */
+ * bit length as `nseg` (variant RED_VARIANT_ATOMIC or _PERSISTENT, wg at
+ * most 512). */
 int red_set_segmented_plan(int64_t nseg, const red_plan *plan);
 int red_get_segmented_plan(int64_t nseg, red_plan *plan);
 

@@ -515,7 +515,10 @@ __device__ __forceinline__ bool grid_barrier(BarrierWords* w, unsigned nblocks, 
                                              unsigned spin_limit) {
   __shared__ int timed_out;
   const bool xcd = (groups & kBarrierXcd) != 0;
-  if (xcd) __builtin_amdgcn_s_waitcnt(0);  // every wave drains its stores
+  // Every wave drains its own stores first, so they are in its XCD's L2
+  // when thread 0's release writes that L2 back (the stores of a workgroup
+  // may come from any of its waves).
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
     int to = 0;

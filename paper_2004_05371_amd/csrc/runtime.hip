@@ -327,6 +327,7 @@ int validate_seg_args(const float* x, const int64_t* offsets, int64_t nseg, doub
       if (rc) return rc;
       if (opts->plan.variant != RED_VARIANT_ATOMIC && opts->plan.variant != RED_VARIANT_PERSISTENT)
         return set_error(RED_EINVAL, "segmented: variant must be ATOMIC or PERSISTENT");
+      if (p.wg > 512) return set_error(RED_EINVAL, "segmented: at most 512 threads per workgroup");
     }
   }
   return RED_OK;
@@ -776,6 +777,7 @@ int red_set_segmented_plan(int64_t nseg, const red_plan* plan) {
   if (rc) return rc;
   if (plan->variant != RED_VARIANT_ATOMIC && plan->variant != RED_VARIANT_PERSISTENT)
     return set_error(RED_EINVAL, "segmented: variant must be ATOMIC or PERSISTENT");
+  if (plan->wg > 512) return set_error(RED_EINVAL, "segmented: at most 512 threads per workgroup");
   std::lock_guard<std::mutex> lk(g_mu);
   g_plans[std::make_tuple(1, bucket(nseg), 0, 0)] = *plan;
   return RED_OK;
@@ -867,7 +869,7 @@ int red_autotune_segmented(const float* x, const int64_t* offsets, int64_t nseg,
     if (!rc) rc = consider(p);
   }
   const int nt_flag = cur.flags & RED_FLAG_NONTEMPORAL;
-  for (int wg : {128, 256, 512, 1024})
+  for (int wg : {128, 256, 512})
     for (int ipt : {2, 4, 8})
       for (int m : {1, 2, 3, 4, 6, 8})
         if (!rc) rc = consider(red_plan{RED_VARIANT_ATOMIC, wg, ipt, std::min(m * dev->cus, RED_MAX_GRID), nt_flag});

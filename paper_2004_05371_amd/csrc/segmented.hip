@@ -2,26 +2,32 @@
 //
 // The paper's persistent-kernel reduction (Section VII-C, explicit
 // synchronization) keeps one grid of blocks alive for the whole job.  Here a
-// fixed grid of G workgroups handles a whole CSR batch of uneven segments:
+// fixed grid handles a whole CSR batch of uneven segments:
 //
-//   * workgroup g owns the element slice [g*chunk, (g+1)*chunk) of the
-//     concatenated values (chunk = ceil(E / G) rounded up to 64 elements),
-//     so every workgroup streams the same number of bytes whatever the
-//     segment lengths;
-//   * it finds the first segment meeting its slice by binary search in the
-//     offsets, then streams its slice as one sequence of tiles of 16-byte
-//     vectors (the next tile in flight while the current one is added into
-//     fp32 TwoSum-compensated accumulators); each piece of a segment is
-//     finished by a wavefront + LDS combine as soon as its last tile is in,
-//     so segment boundaries never drain the load pipeline;
+//   * the concatenated values are cut into equal slices (chunk = ceil(E / S)
+//     rounded up to 64 values), one per workgroup or, when the batch's mean
+//     segment is short, one per wavefront, so every slice streams the same
+//     number of bytes whatever the segment lengths;
+//   * a slice finds its first segment by binary search in the offsets
+//     (read through the scalar cache), then streams its values as one
+//     sequence of tiles of 16-byte vectors (the next tile in flight while
+//     the current one is added into fp32 TwoSum-compensated accumulators);
+//   * a piece of a segment that ends in a tile is finished while the next
+//     tile is in flight: by a DPP wavefront combine (wavefront slices), or
+//     by a wavefront combine per wave whose results are completed in
+//     batches of 64 pieces after one workgroup barrier (workgroup slices);
 //   * a segment that lies inside the slice is written directly (binary64);
 //     a piece of a segment that crosses a slice boundary goes to a carry
 //     slot, and the pieces of that segment are summed in slice order in
-//     binary64, either by the last contributing workgroup (atomic ticket per
-//     owning slice; no co-residency needed, graph-capturable) or, in the
-//     cooperative form, by the owning workgroup after a grid barrier.
+//     binary64, either by the wavefront that publishes the last piece
+//     (atomic ticket per owning slice; no co-residency needed,
+//     graph-capturable) or, in the cooperative form, by the owning slice
+//     after a grid barrier.
 //
-// Empty segments write 0.  The result is deterministic for a given grid.
+// Workgroup slices keep few concurrent streams (better DRAM locality) and
+// suit long segments; wavefront slices let every wave walk its own pieces
+// without barriers and suit short ones.  Empty segments write 0.  The
+// result is deterministic for a given grid and workgroup size.
 #include <algorithm>
 
 #include "device_prims.h"
@@ -49,13 +55,6 @@ __device__ __forceinline__ int64_t offset_at(const int64_t* offsets, int64_t i) 
   return ((const __attribute__((address_space(4))) int64_t*)offsets)[i];
 }
 
-// Pieces whose workgroup combine is finished together, after one barrier.
-constexpr int kBatch = 64;
-
-struct PieceInfo {
-  int64_t s, sa, sb;  // segment id and its bounds
-};
-
 // Sum of the np pieces of a cut segment (owning slice o: carry_out[o], then
 // carry_in[o+1 .. o+np-1]) by one wavefront: lane l adds pieces o+l,
 // o+l+64, ... in order, then the fixed binary64 wavefront combine
@@ -66,42 +65,46 @@ __device__ __forceinline__ double combine_pieces(const SegArgs& a, int64_t o, in
   return wave_reduce_dpp<OpF64>(v);
 }
 
-// Completes one piece whose workgroup total is v, by one wavefront: a whole
-// segment is written; a piece of a cut segment is published in its carry
-// slot, and the piece that completes the segment's ticket sums all pieces
-// (ticket form), or the owning workgroup does so after the grid barrier
-// (barrier form: *own_fix records the segment).
+// Completes, by one wavefront, the piece [max(sa, lo), min(sb, hi)) of
+// segment s whose total is v: a whole segment is written; a piece of a cut
+// segment is published in its carry slot (slice w), and the wavefront that
+// completes the segment's ticket sums all of its pieces (ticket form), or
+// the owning wavefront does so after the grid barrier (barrier form:
+// *own_fix records the segment).
 template <bool BARRIER>
-__device__ __forceinline__ void finish_piece(const SegArgs& a, const PieceInfo& p, double v, int64_t lo, int64_t hi,
-                                             int64_t g, int64_t chunk, int64_t* own_fix) {
+__device__ __forceinline__ void finish_piece(const SegArgs& a, int64_t s, int64_t sa, int64_t sb, double v,
+                                             int64_t lo, int64_t hi, int64_t w, int64_t chunk, int64_t* own_fix) {
   const int lane = __lane_id();
-  if (p.sa >= lo && p.sb <= hi) {
-    if (lane == 0) a.out[p.s] = v;
+  if (sa >= lo && sb <= hi) {
+    if (lane == 0) a.out[s] = v;
     return;
   }
-  const int64_t o = p.sa / chunk;
-  const int64_t np = (p.sb - 1) / chunk - o + 1;
-  int last = 0;
-  if (lane == 0) {
-    const SegCarry c{p.s, v};
-    if (p.sa < lo)
-      a.carry_in[g] = c;
-    else
-      a.carry_out[g] = c;
-    if constexpr (BARRIER) {
-      if (p.sa >= lo) *own_fix = p.s;
-    } else {
+  const int64_t o = sa / chunk;
+  const int64_t np = (sb - 1) / chunk - o + 1;
+  if constexpr (BARRIER) {
+    if (lane == 0) {
+      if (sa < lo)
+        a.carry_in[w] = SegCarry{s, v};
+      else
+        a.carry_out[w] = SegCarry{s, v};
+    }
+    if (sa >= lo) *own_fix = s;
+  } else {
+    int last = 0;
+    if (lane == 0) {
+      if (sa < lo)
+        a.carry_in[w] = SegCarry{s, v};
+      else
+        a.carry_out[w] = SegCarry{s, v};
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       const unsigned tk = __hip_atomic_fetch_add(&a.tickets[o], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       last = tk == (unsigned)(np - 1);
     }
-  }
-  if constexpr (!BARRIER) {
     if (__builtin_amdgcn_readfirstlane(last)) {  // this wave published the last piece
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      const double w = combine_pieces(a, o, np);
+      const double t = combine_pieces(a, o, np);
       if (lane == 0) {
-        a.out[p.s] = w;
+        a.out[s] = t;
         __hip_atomic_store(&a.tickets[o], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
@@ -109,36 +112,36 @@ __device__ __forceinline__ void finish_piece(const SegArgs& a, const PieceInfo& 
 }
 
 // Moves the segment cursor s to the next non-empty segment that starts
-// before hi, writing 0 for the empty segments passed on the way (those at
-// positions in [lo, hi), and, for the workgroup whose slice ends at E, those
-// at E).  Returns false when the slice holds no further segment.
-__device__ __forceinline__ bool seek_segment(const SegArgs& a, int64_t& s, int64_t hi, int64_t E, bool end_wg,
-                                             int64_t& sa, int64_t& sb) {
+// before hi, writing 0 (if `writer`) for the empty segments passed on the
+// way (those at positions in [lo, hi), and, for the slice that ends at E,
+// those at E).  Returns false when the slice holds no further segment.
+__device__ __forceinline__ bool seek_segment(const SegArgs& a, int64_t& s, int64_t hi, int64_t E, bool end_slice,
+                                             int64_t& sa, int64_t& sb, bool writer) {
   for (; s < a.nseg; ++s) {
     sa = offset_at(a.offsets, s);
     sb = offset_at(a.offsets, s + 1);
-    if (sa >= hi && !(end_wg && sa == E)) return false;
+    if (sa >= hi && !(end_slice && sa == E)) return false;
     if (sa != sb) return true;
-    if (threadIdx.x == 0) a.out[s] = 0.0;
+    if (writer) a.out[s] = 0.0;
   }
   return false;
 }
 
-// The elements of the thread's IPT vectors of one tile that lie in the
-// tile-relative range [ra, rb) (0 <= ra <= rb <= 4 T): vector u of thread
-// tid starts at element 4 (u blockDim + tid) of the tile.  32-bit unsigned
-// range test: r in [ra, rb) iff r - ra < rb - ra.
+// Adds to acc the elements of the thread's IPT vectors of one tile that lie
+// in the tile-relative range [ra, rb) (0 <= ra <= rb <= 4 T): vector u of
+// thread idx (0 <= idx < bs) starts at element 4 (u bs + idx) of the tile.
 // A wave whose 256 elements of row u miss the range skips that row (the
-// test is wave-uniform), so a short piece costs little beyond its combine.
+// test is wave-uniform).  32-bit unsigned range test: r in [ra, rb) iff
+// r - ra < rb - ra.
 template <int IPT>
-__device__ __forceinline__ void add_masked(CompF32* acc, const v4f* v, int bs, int ra, int rb) {
+__device__ __forceinline__ void add_masked(CompF32* acc, const v4f* v, int bs, int idx, int ra, int rb) {
   const unsigned w = (unsigned)(rb - ra);
-  const int wave0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x & ~(kWave - 1));
+  const int wave0 = __builtin_amdgcn_readfirstlane(idx & ~(kWave - 1));
 #pragma unroll
   for (int u = 0; u < IPT; ++u) {
     const int wb = 4 * (u * bs + wave0);  // first element of this wave's part of row u
     if (wb >= rb || wb + 4 * kWave <= ra) continue;
-    const unsigned r = (unsigned)(4 * (u * bs + (int)threadIdx.x) - ra);
+    const unsigned r = (unsigned)(4 * (u * bs + idx) - ra);
     v4f x = v[u];
     x.x = r < w ? x.x : 0.0f;
     x.y = r + 1u < w ? x.y : 0.0f;
@@ -148,7 +151,7 @@ __device__ __forceinline__ void add_masked(CompF32* acc, const v4f* v, int bs, i
   }
 }
 
-// Whether any of the calling wave's rows of the tile meets [ra, rb).
+// Whether any of the calling wave's rows of a workgroup tile meets [ra, rb).
 template <int IPT>
 __device__ __forceinline__ bool wave_touches(int bs, int ra, int rb) {
   const int wave0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x & ~(kWave - 1));
@@ -161,8 +164,142 @@ __device__ __forceinline__ bool wave_touches(int bs, int ra, int rb) {
   return t;
 }
 
+// Pieces whose workgroup combine is finished together, after one barrier.
+constexpr int kBatch = 64;
+
+struct PieceInfo {
+  int64_t s, sa, sb;  // segment id and its bounds
+};
+
+// At most 512 threads per workgroup: a thread keeps two tiles of IPT
+// 16-byte vectors and IPT compensated accumulators in registers, which for
+// IPT = 8 needs more than the 128 VGPRs a 1024-thread workgroup allows.
+constexpr int kSegMaxWG = 512;
+
+// Batches whose mean segment holds fewer values than this take wavefront
+// slices, the others workgroup slices (measured on MI355X: 64- to
+// 4096-value segments run 2 to 8 times faster on wavefront slices, long
+// ones about 10 to 30 % faster on workgroup slices).
+constexpr int64_t kWaveSliceMeanLen = 16384;
+
+// Wavefront-granular slices (short segments: every wave walks its own
+// pieces, with no workgroup barrier): wavefront w of the grid owns slice
+// w and streams it as tiles of 64 x IPT vectors.
 template <int IPT, bool NT, bool BARRIER>
-__global__ __launch_bounds__(1024) void k_segmented(SegArgs a) {
+__device__ __forceinline__ void seg_wave_slices(const SegArgs& a) {
+  using M = ModeF32Comp;
+  const int nwaves = blockDim.x / kWave;
+  const int lane = __lane_id();
+  const int64_t w = (int64_t)blockIdx.x * nwaves + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int64_t W = (int64_t)gridDim.x * nwaves;
+  const int64_t nseg = a.nseg;
+  const int64_t E = offset_at(a.offsets, nseg);
+  const int64_t chunk = std::max<int64_t>(64, (((E + W - 1) / W) + 63) & ~(int64_t)63);
+  const int64_t lo = std::min(w * chunk, E);
+  const int64_t hi = std::min(lo + chunk, E);
+  // The slice that ends at E also writes the empty segments that sit at
+  // position E (for E == 0: slice 0).
+  const bool end_slice = E > 0 ? (lo < E && hi == E) : (w == 0);
+
+  // First s in [0, nseg] with offsets[s] >= lo (offsets[nseg] = E >= lo).
+  int64_t L = 0, R = nseg;
+  while (L < R) {
+    const int64_t mid = (L + R) >> 1;
+    if (offset_at(a.offsets, mid) >= lo)
+      R = mid;
+    else
+      L = mid + 1;
+  }
+  // Segment L-1 crosses lo if it ends after lo.
+  int64_t s = (L > 0 && offset_at(a.offsets, L) > lo) ? L - 1 : L;
+  int64_t sa = 0, sb = 0;
+  bool have = seek_segment(a, s, hi, E, end_slice, sa, sb, lane == 0);
+  int64_t A = std::max(sa, lo), B = std::min(sb, hi);  // current piece
+
+  // The slice is streamed as one sequence of tiles (64 x IPT 16-byte
+  // vectors of the 16-byte-aligned base, the next tile's loads issued
+  // before the current tile is added), whatever the segment boundaries.
+  const int shift = (int)((reinterpret_cast<uintptr_t>(a.x) & 15) >> 2);
+  const v4f* xa = reinterpret_cast<const v4f*>(a.x - shift);
+  const int64_t vlo = (lo + shift) >> 2;
+  const int64_t vhi = (hi + shift + 3) >> 2;  // vectors [vlo, vhi) hold the slice
+  constexpr int64_t T = kWave * IPT;
+  const int64_t ntiles = lo < hi ? (vhi - vlo + T - 1) / T : 0;
+
+  CompF32 acc[IPT];
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) acc[u] = M::zero();
+  v4f cur[IPT], nxt[IPT];
+  auto load_tile = [&](v4f* v, int64_t t) {
+    const int64_t v0 = vlo + t * T + lane;
+    if (vlo + (t + 1) * T <= vhi) {
+#pragma unroll
+      for (int u = 0; u < IPT; ++u) v[u] = load_vec<NT>(xa + v0 + u * kWave);
+    } else {
+#pragma unroll
+      for (int u = 0; u < IPT; ++u)
+        v[u] = v0 + u * kWave < vhi ? load_vec<NT>(xa + v0 + u * kWave) : v4f{0, 0, 0, 0};
+    }
+  };
+
+  int64_t own_fix = -1;  // barrier form: the cut segment this slice owns
+  if (ntiles > 0) load_tile(cur, 0);
+  for (int64_t t = 0; t < ntiles; ++t) {
+    // The current tile is complete before the next one is requested, so
+    // nothing below waits on the loads in flight (on this target a wait
+    // with stores and loads both pending would drain every load).
+    __builtin_amdgcn_s_waitcnt(0);
+    if (t + 1 < ntiles) load_tile(nxt, t + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    const int64_t e0 = 4 * (vlo + t * T) - shift;        // first element of the tile
+    const int64_t e1 = 4 * (vlo + (t + 1) * T) - shift;  // one past its last
+    auto rel = [&](int64_t e) { return (int)std::min(std::max(e - e0, (int64_t)0), 4 * T); };
+    // Pieces that end in this tile.
+    while (have && B <= e1) {
+      add_masked<IPT>(acc, cur, kWave, lane, rel(A), rel(B));
+      CompF32 tot = acc[0];
+#pragma unroll
+      for (int u = 1; u < IPT; ++u) tot = OpComp::add(tot, acc[u]);
+#pragma unroll
+      for (int u = 0; u < IPT; ++u) acc[u] = M::zero();
+      tot = wave_reduce_dpp<OpComp>(tot);
+      finish_piece<BARRIER>(a, s, sa, sb, comp_to_double(tot), lo, hi, w, chunk, &own_fix);
+      ++s;
+      have = seek_segment(a, s, hi, E, end_slice, sa, sb, lane == 0);
+      A = std::max(sa, lo);
+      B = std::min(sb, hi);
+    }
+    // The piece that continues past this tile.
+    if (have) {
+      if (A <= e0 && vlo + (t + 1) * T <= vhi) {
+#pragma unroll
+        for (int u = 0; u < IPT; ++u) M::add_vec(acc[u], cur[u]);
+      } else {
+        add_masked<IPT>(acc, cur, kWave, lane, rel(A), rel(B));
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) cur[u] = nxt[u];
+  }
+  if constexpr (BARRIER) {
+    grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit);
+    if (own_fix >= 0) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const int64_t o = offset_at(a.offsets, own_fix) / chunk;
+      const int64_t np = (offset_at(a.offsets, own_fix + 1) - 1) / chunk - o + 1;
+      const double v = combine_pieces(a, o, np);
+      if (lane == 0) a.out[own_fix] = v;
+    }
+  }
+}
+
+// Workgroup-granular slices (long segments: few streams, little per-piece
+// work): workgroup g owns slice g, streams it as tiles of blockDim x IPT
+// vectors, and finishes the pieces that end in a tile in batches of
+// kBatch after one workgroup barrier, wave w finishing pieces w,
+// w + nwaves, ...
+template <int IPT, bool NT, bool BARRIER>
+__device__ __forceinline__ void seg_workgroup_slices(const SegArgs& a) {
   using M = ModeF32Comp;
   // Per-wave partials of up to kBatch finished pieces, completed together
   // after one barrier.  Two buffers used alternately: a wave writes a
@@ -195,7 +332,7 @@ __global__ __launch_bounds__(1024) void k_segmented(SegArgs a) {
   // Segment L-1 crosses lo if it ends after lo.
   int64_t s = (L > 0 && offset_at(a.offsets, L) > lo) ? L - 1 : L;
   int64_t sa = 0, sb = 0;
-  bool have = seek_segment(a, s, hi, E, end_wg, sa, sb);
+  bool have = seek_segment(a, s, hi, E, end_wg, sa, sb, threadIdx.x == 0);
   int64_t A = std::max(sa, lo), B = std::min(sb, hi);  // current piece
 
   // The slice is streamed as one sequence of tiles (blockDim x IPT 16-byte
@@ -222,7 +359,8 @@ __global__ __launch_bounds__(1024) void k_segmented(SegArgs a) {
     for (int j = wave; j < nb; j += nwaves) {
       CompF32 v = lane < nwaves ? part[buf][j][lane] : OpComp::zero();
       v = wave_reduce_dpp<OpComp>(v);
-      finish_piece<BARRIER>(a, info[buf][j], comp_to_double(v), lo, hi, g, chunk, &own_fix);
+      const PieceInfo& pi = info[buf][j];
+      finish_piece<BARRIER>(a, pi.s, pi.sa, pi.sb, comp_to_double(v), lo, hi, g, chunk, &own_fix);
     }
     buf ^= 1;
     nb = 0;
@@ -258,7 +396,7 @@ __global__ __launch_bounds__(1024) void k_segmented(SegArgs a) {
     // Pieces that end in this tile: each wave's share goes to the batch.
     while (have && B <= e1) {
       const int ra = rel(A), rb = rel(B);
-      add_masked<IPT>(acc, cur, (int)bs, ra, rb);
+      add_masked<IPT>(acc, cur, (int)bs, tid, ra, rb);
       CompF32 tot = acc[0];
 #pragma unroll
       for (int u = 1; u < IPT; ++u) tot = OpComp::add(tot, acc[u]);
@@ -272,7 +410,7 @@ __global__ __launch_bounds__(1024) void k_segmented(SegArgs a) {
       if (tid == 0) info[buf][nb] = PieceInfo{s, sa, sb};
       if (++nb == kBatch) flush();
       ++s;
-      have = seek_segment(a, s, hi, E, end_wg, sa, sb);
+      have = seek_segment(a, s, hi, E, end_wg, sa, sb, threadIdx.x == 0);
       A = std::max(sa, lo);
       B = std::min(sb, hi);
     }
@@ -282,7 +420,7 @@ __global__ __launch_bounds__(1024) void k_segmented(SegArgs a) {
 #pragma unroll
         for (int u = 0; u < IPT; ++u) M::add_vec(acc[u], cur[u]);
       } else {
-        add_masked<IPT>(acc, cur, (int)bs, rel(A), rel(B));
+        add_masked<IPT>(acc, cur, (int)bs, tid, rel(A), rel(B));
       }
     }
 #pragma unroll
@@ -300,6 +438,15 @@ __global__ __launch_bounds__(1024) void k_segmented(SegArgs a) {
       if (lane == 0) a.out[os] = v;
     }
   }
+}
+
+template <int IPT, bool NT, bool BARRIER>
+__global__ __launch_bounds__(kSegMaxWG) void k_segmented(SegArgs a) {
+  const int64_t E = offset_at(a.offsets, a.nseg);
+  if (E < kWaveSliceMeanLen * a.nseg)  // the same decision in every workgroup
+    seg_wave_slices<IPT, NT, BARRIER>(a);
+  else
+    seg_workgroup_slices<IPT, NT, BARRIER>(a);
 }
 
 namespace {
@@ -357,11 +504,14 @@ int seg_launch(const SegLaunch& sl, const float* x, const int64_t* offsets, int6
   const red_plan& p = sl.plan;
   const int ii = ipt_index(p.ipt);
   if (ii < 0) return set_error(RED_EINVAL, "bad ipt %d", p.ipt);
+  if (p.wg > kSegMaxWG) return set_error(RED_EINVAL, "segmented: at most %d threads per workgroup", kSegMaxWG);
   const bool barrier = p.variant == RED_VARIANT_PERSISTENT;
   if (!barrier && p.variant != RED_VARIANT_ATOMIC)
     return set_error(RED_EINVAL, "segmented: variant must be ATOMIC (ticket) or PERSISTENT (barrier)");
   int grid = p.grid > 0 ? p.grid : 4 * dev.cus;
   grid = std::max(1, std::min(grid, RED_MAX_GRID));
+  // One carry slot and one ticket per wavefront slice.
+  grid = std::min<int>(grid, (int)(kMaxChunks / (p.wg / kWave)));
   if (barrier) {
     int maxg = 0;
     int rc = seg_max_coresident(p.ipt, p.wg, dev, &maxg);

@@ -60,6 +60,9 @@ def test_validation_before_hip(lib):
     bad = R.make_opts(flags=32)
     assert lib.red_sum_ex(R.RED_F32, ctypes.c_void_p(64), 4, ctypes.c_void_p(64), None, ctypes.byref(bad)) == R.RED_EINVAL
     assert lib.red_sum_segmented(None, None, 3, None, None) == R.RED_EINVAL
+    big_wg = R.make_opts(variant=R.RED_VARIANT_ATOMIC, wg=1024, ipt=4, grid=8)  # segmented: <= 512 threads
+    assert lib.red_sum_segmented_ex(ctypes.c_void_p(64), ctypes.c_void_p(64), 2, ctypes.c_void_p(64), None,
+                                    ctypes.byref(big_wg)) == R.RED_EINVAL
     assert lib.red_sum_segmented(ctypes.c_void_p(64), ctypes.c_void_p(64), -1, ctypes.c_void_p(64), None) == R.RED_EINVAL
     assert lib.red_sum_segmented(ctypes.c_void_p(64), ctypes.c_void_p(68), 2, ctypes.c_void_p(64), None) == R.RED_EINVAL
     seg = R.make_opts(variant=R.RED_VARIANT_RELAUNCH, wg=256, ipt=4)

@@ -13,14 +13,14 @@ def test_roundtrip_installs_plans(tmp_path):
         {"kind": "sum", "dtype": "bf16", "acc": "plain", "n": 1 << 30,
          "plan": {"variant": "atomic", "wg": 256, "ipt": 8, "grid": 1536, "flags": 1}, "us": 1.0},
         {"kind": "segmented", "nseg": 1 << 17,
-         "plan": {"variant": "atomic", "wg": 1024, "ipt": 2, "grid": 512, "flags": 1}, "us": 2.0},
+         "plan": {"variant": "atomic", "wg": 512, "ipt": 2, "grid": 512, "flags": 1}, "us": 2.0},
     ]
     p = autotune.save(entries, str(tmp_path / "c.json"))
     assert autotune.load(p) == 2
     q = R.red_get_plan(R.RED_BF16, R.RED_ACC_PLAIN, 1 << 30)
     assert (q.variant, q.wg, q.ipt, q.grid, q.flags) == (2, 256, 8, 1536, 1)
     s = R.red_get_segmented_plan(1 << 17)
-    assert (s.variant, s.wg, s.ipt, s.grid, s.flags) == (2, 1024, 2, 512, 1)
+    assert (s.variant, s.wg, s.ipt, s.grid, s.flags) == (2, 512, 2, 512, 1)
 
 
 def test_corrupt_cache_keeps_defaults(tmp_path):

@@ -40,7 +40,7 @@ def check(res, x, off):
             assert e <= BOUND, (k, res[k], ex.value, e)
 
 
-PLANS = [dict(), dict(variant=2, wg=256, ipt=1, grid=7), dict(variant=2, wg=1024, ipt=8, grid=1),
+PLANS = [dict(), dict(variant=2, wg=256, ipt=1, grid=7), dict(variant=2, wg=512, ipt=8, grid=1),
          dict(variant=2, wg=64, ipt=2, grid=300), dict(variant=3, wg=256, ipt=4, grid=64),
          dict(variant=2, wg=512, ipt=4, grid=0, flags=2)]
 
