@@ -56,6 +56,20 @@ def test_small_batches(lib, plan):
     check(run(lib, x, off, **p), x, off)
 
 
+@pytest.mark.parametrize("plan", range(len(PLANS)))
+def test_long_segment_batches(lib, plan):
+    """Mean segment length above 16384 values: workgroup slices (the
+    short-segment batches above take wavefront slices), with short and empty
+    segments between long ones."""
+    r = np.random.default_rng(300 + plan)
+    lens = np.concatenate([r.integers(20000, 300000, 12), [0, 1, 3, 0, 5, 2, 1000, 0, 64, 65]])
+    r.shuffle(lens)
+    off = inputs.offsets_from_lengths(lens.astype(np.int64))
+    assert off[-1] >= 16384 * (off.size - 1)
+    x = inputs.mixed_f32(int(off[-1]), sub=13)
+    check(run(lib, x, off, **PLANS[plan]), x, off)
+
+
 def test_edge_batches(lib):
     # empty total, leading / trailing empties, a single segment, all length-1
     for lens in ([0], [0, 0, 0], [0, 5, 0], [1], [12345], [3, 0, 0], [1] * 3000, [0] * 10 + [100] + [0] * 10):
