@@ -624,6 +624,25 @@ def run_configs(R, dev, stream, path, plans):
         del xt, ot
         torch.cuda.empty_cache()
 
+    # -- segmented batches of uniform lengths over 2^28 values: the cost of
+    #    short segments, the slice granularity switch
+    xs = torch.from_numpy(inputs.normal_f32(1 << 28, sub=3)).to("cuda")
+    o = R.make_opts(variant=R.RED_VARIANT_ATOMIC, wg=512, ipt=4, grid=dev["cus"], flags=R.FLAG_NONTEMPORAL)
+    for L in (64, 256, 1024, 4096, 16384, 65536, 262144, 1 << 28):
+        nseg = (1 << 28) // L
+        offs = torch.arange(0, (1 << 28) + 1, L, dtype=torch.int64, device="cuda")
+        outs = torch.empty(nseg, dtype=torch.float64, device="cuda")
+        ms = timed(lambda: R.red_sum_segmented_ex(xs.data_ptr(), offs.data_ptr(), nseg, outs.data_ptr(), sh, o), 20)
+        stats = dict(last)
+        ref = xs.view(nseg, L).double().sum(1)  # torch check on the GPU (the oracle covers parity in the tests)
+        emit({"config": "segments_uniform", "length": L, "nseg": nseg, "plan": {"wg": 512, "ipt": 4,
+              "grid": dev["cus"]}, "us": round(ms * 1e3, 1), "GBps": gbps((1 << 28) * 4, ms), "timing_us": stats,
+              "slices": "wavefront" if L < 16384 else "workgroup",
+              "max_abs_diff_vs_fp64_torch": float((outs - ref).abs().max())})
+        del offs, outs, ref
+    del xs
+    torch.cuda.empty_cache()
+
     # -- iterative stencil: one launch per step against the time loop inside
     #    one persistent kernel (values kept in LDS across grid barriers)
     stencil_configs(R, dev, stream, emit, timed)
