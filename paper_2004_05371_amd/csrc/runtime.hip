@@ -58,18 +58,35 @@ struct GraphKey {
   int64_t nseg;
   void* out;
   int variant, wg, ipt, grid, nt;
-  bool operator<(const GraphKey& o) const {
-    return std::tie(dev, s, x, off, nseg, out, variant, wg, ipt, grid, nt) <
-           std::tie(o.dev, o.s, o.x, o.off, o.nseg, o.out, o.variant, o.wg, o.ipt, o.grid, o.nt);
-  }
+  auto tie() const { return std::tie(dev, s, x, off, nseg, out, variant, wg, ipt, grid, nt); }
+  bool operator<(const GraphKey& o) const { return tie() < o.tie(); }
+  bool operator==(const GraphKey& o) const { return tie() == o.tie(); }
 };
 struct GraphEntry {
   hipGraph_t g = nullptr;
   hipGraphExec_t e = nullptr;
 };
 std::map<GraphKey, GraphEntry> g_graphs;
-std::list<GraphKey> g_graph_lru;
+std::list<GraphKey> g_graph_lru;  // least recently used first
 constexpr size_t kMaxGraphs = 64;
+std::map<int, hipStream_t> g_capture_streams;  // per device, for building graphs
+std::mutex g_capture_mu;                        // serializes captures
+
+// The library's capture stream of device `dev` (non-blocking, default
+// priority), created on first use.
+int capture_stream(int dev, hipStream_t* out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_capture_streams.find(dev);
+  if (it != g_capture_streams.end()) {
+    *out = it->second;
+    return RED_OK;
+  }
+  hipStream_t cs = nullptr;
+  RED_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  g_capture_streams[dev] = cs;
+  *out = cs;
+  return RED_OK;
+}
 
 int bucket(int64_t n) {
   int b = 0;
@@ -363,21 +380,30 @@ int red_init(int device) {
 
 void red_shutdown(void) {
   std::lock_guard<std::mutex> lk(g_mu);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  // Nothing of the library may still run: graphs and workspaces go below.
+  for (auto& kv : g_dev) {
+    (void)hipSetDevice(kv.first);
+    (void)hipDeviceSynchronize();
+  }
   for (auto& kv : g_graphs) {
     if (kv.second.e) (void)hipGraphExecDestroy(kv.second.e);
     if (kv.second.g) (void)hipGraphDestroy(kv.second.g);
   }
   g_graphs.clear();
   g_graph_lru.clear();
-  int cur = 0;
-  (void)hipGetDevice(&cur);
   for (auto& kv : g_ws) {
     (void)hipSetDevice(kv.first.first);
-    (void)hipDeviceSynchronize();
     (void)hipFree(kv.second.base);
   }
-  if (!g_ws.empty()) (void)hipSetDevice(cur);
   g_ws.clear();
+  for (auto& kv : g_capture_streams) {
+    (void)hipSetDevice(kv.first);
+    (void)hipStreamDestroy(kv.second);
+  }
+  g_capture_streams.clear();
+  (void)hipSetDevice(cur);
 }
 
 int red_check_error(void* stream) {
@@ -692,14 +718,24 @@ int red_sum_segmented_ex(const float* x, const int64_t* offsets, int64_t nseg, d
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_graphs.find(key);
-    if (it != g_graphs.end()) exec = it->second.e;
+    if (it != g_graphs.end()) {
+      exec = it->second.e;
+      // most recently used at the back
+      g_graph_lru.remove(key);
+      g_graph_lru.push_back(key);
+    }
   }
   if (!exec) {
-    // Capture the one launch on this stream into a graph.
-    RED_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    rc = seg_launch(sl, x, offsets, nseg, out, ws, s, *dev);
+    // Capture the one launch into a graph on the library's own capture
+    // stream (the caller's stream is never put into capture mode); the
+    // kernels use the workspace of the caller's stream.
+    hipStream_t cs = nullptr;
+    if ((rc = capture_stream(dev->id, &cs))) return rc;
+    std::lock_guard<std::mutex> capture_lock(g_capture_mu);  // one capture at a time on cs
+    RED_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    rc = seg_launch(sl, x, offsets, nseg, out, ws, cs, *dev);
     hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(s, &g);
+    hipError_t e = hipStreamEndCapture(cs, &g);
     if (rc) {
       if (g) (void)hipGraphDestroy(g);
       return rc;
@@ -714,6 +750,8 @@ int red_sum_segmented_ex(const float* x, const int64_t* offsets, int64_t nseg, d
     if (g_graphs.size() >= kMaxGraphs && !g_graph_lru.empty()) {
       auto old = g_graphs.find(g_graph_lru.front());
       if (old != g_graphs.end()) {
+        // A replay of the evicted graph may still run on its stream.
+        (void)hipStreamSynchronize(old->first.s);
         (void)hipGraphExecDestroy(old->second.e);
         (void)hipGraphDestroy(old->second.g);
         g_graphs.erase(old);

@@ -158,3 +158,26 @@ def test_full_batch_config(lib):
     for p in (dict(), dict(variant=3, wg=512, ipt=4, grid=256)):
         res = run(lib, x, off, **p)
         check(res, x, off)
+
+
+def test_graph_cache_eviction(lib):
+    """More distinct batches than the graph cache holds (64): the oldest
+    graphs are evicted (after their stream drains) and rebuilt on reuse;
+    every result stays exact and bit-identical."""
+    r = np.random.default_rng(400)
+    lens = r.integers(0, 3000, 50)
+    off = inputs.offsets_from_lengths(lens.astype(np.int64))
+    x = inputs.normal_f32(int(off[-1]), sub=14)
+    xt = torch.from_numpy(x).to("cuda")
+    ot = torch.from_numpy(off).to("cuda")
+    nseg = off.size - 1
+    st = torch.cuda.Stream()
+    outs = torch.full((80, nseg), float("nan"), dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(st):
+        for rep in range(2):  # the second pass finds the first graphs evicted
+            for i in range(80):
+                lib.red_sum_segmented(xt.data_ptr(), ot.data_ptr(), nseg, outs[i].data_ptr(), st.cuda_stream)
+    st.synchronize()
+    res = outs.cpu().numpy()
+    assert (res == res[0]).all()
+    check(res[0], x, off)
