@@ -661,8 +661,12 @@ def run_configs(R, dev, stream, path, plans):
     for wg in (64, 128, 256, 512, 1024):
         for n_wg in (1, dev["cus"], 4 * dev["cus"]):
             ns, sg, cyc = R.sync_bench_block(wg, n_wg, reps=20)
-            emit({"probe": "block", "wg": wg, "n_wg": n_wg, "waves_per_wg": wg // 64, "ns": round(ns, 2),
-                  "sigma_ns": round(sg, 2), "cycles": round(cyc, 1)})
+            # Table II's throughput view: barriers completed per CU per
+            # microsecond with n_wg / cus resident workgroups per CU
+            emit({"probe": "block", "wg": wg, "n_wg": n_wg, "waves_per_wg": wg // 64,
+                  "waves_per_cu": round(n_wg / dev["cus"] * wg / 64, 2), "ns": round(ns, 2),
+                  "sigma_ns": round(sg, 2), "cycles": round(cyc, 1),
+                  "barriers_per_us_per_cu": round(n_wg / dev["cus"] / (ns * 1e-3), 2) if ns > 0 else None})
     for wg in (64, 256, 1024):
         cores = R.red_max_coresident(wg)
         n = 1
