@@ -214,3 +214,26 @@ def test_xcd_barrier_probe(lib, n_wg):
     say("grid %d WGs, XCD-aggregated: %.1f ns" % (n_wg, ns))
     assert 0 < ns < 1e6
     assert lib.red_check_error(lib.current_stream()) == lib.RED_OK
+
+
+@pytest.mark.parametrize("op", [0, 3])
+def test_in_kernel_clock_agrees_with_host_differential(lib, op):
+    """Section IX-C's in-SM clock and the host differential of Eq. 7 time
+    the same dependent chain: cycles / shader clock ~ ns per operation."""
+    clock_ghz = lib.red_device_info()["clock_khz"] / 1e6
+    ns, sigma, cyc = lib.sync_bench_wave(op, 64, reps=10)
+    say("op %d: %.2f ns host, %.1f cycles = %.2f ns at %.2f GHz" % (op, ns, cyc, cyc / clock_ghz, clock_ghz))
+    assert abs(ns - cyc / clock_ghz) <= 0.2 * ns
+
+
+def test_grid_probe_rejects_grids_that_cannot_be_resident(lib):
+    """A grid barrier needs every workgroup resident: larger grids are
+    refused, not launched."""
+    too_many = 8 * lib.red_device_info()["cus"] + 1  # 8 workgroups of 1024 threads per CU cannot be resident
+    with pytest.raises(lib.RedError) as e:
+        lib.sync_bench_grid(too_many, 1024, reps=2)
+    assert e.value.code == lib.RED_EINVAL
+    x = torch.ones(1 << 20, dtype=torch.int32, device="cuda")
+    with pytest.raises(lib.RedError):
+        lib.sum(x, opts=lib.make_opts(variant=3, wg=1024, ipt=1, grid=too_many))
+    assert lib.red_check_error(lib.current_stream()) == lib.RED_OK
