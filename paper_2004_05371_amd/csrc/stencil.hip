@@ -65,15 +65,21 @@ struct StencilArgs {
   unsigned bar_groups;
 };
 
-// Values per thread held in registers during one step: the LDS window of a
-// workgroup is at most kStencilPT x blockDim values.  The kernel is built
-// for PT = 1, 2, 4, ..., kStencilPT rows per window and launched with the
+// Per step each thread updates 4 consecutive window values per row of
+// 4 x blockDim values (one 128-bit LDS read, two neighbour reads); the LDS
+// window of a workgroup is at most 4 x kStencilRows x blockDim values.  The
+// kernel is built for ROWS = 1, 2, 4, kStencilRows and launched with the
 // smallest that holds the window, so a small window costs few instructions.
-constexpr int kStencilPT = 32;
+constexpr int kStencilRows = 8;
 
-template <int PT>
+// The window is padded to whole 4-value groups plus one group, so the last
+// group's 128-bit read and its right neighbour stay inside the allocation.
+__host__ __device__ inline int stencil_window_alloc(int len) { return ((len + 3) & ~3) + 4; }
+
+template <int ROWS>
 __global__ __launch_bounds__(1024) void k_jacobi_persistent(StencilArgs a) {
-  extern __shared__ float win[];  // elements [lo - k, hi + k), win[j] = element lo - k + j
+  extern __shared__ v4f win4[];  // 16-byte aligned window
+  float* win = reinterpret_cast<float*>(win4);  // win[j] = element lo - k + j, j in [0, len)
   const int64_t n = a.n;
   const int k = a.k;
   const int64_t lo = (int64_t)blockIdx.x * a.m;
@@ -83,7 +89,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_persistent(StencilArgs a) {
   const int64_t base = lo - k;
   const int tid = threadIdx.x;
   const int bs = blockDim.x;
-  const int qn = (len + bs - 1) / bs;  // window rows of bs values
+  const int qn = (len + 4 * bs - 1) / (4 * bs);  // rows of 4 bs values in the window
 
   for (int j = tid; j < len; j += bs) {
     const int64_t e = base + j;
@@ -99,22 +105,34 @@ __global__ __launch_bounds__(1024) void k_jacobi_persistent(StencilArgs a) {
       // [lo - k + s, hi + k - s); the end points of the array never change.
       const int jlo = (int)(std::max<int64_t>(base + s, 1) - base);
       const int jhi = (int)(std::min<int64_t>(hi + k - s, n - 1) - base);
-      float nv[PT];
+      // Group q of this thread: window values j0 .. j0+3, j0 = 4 (q bs + tid).
+      // A value outside [jlo, jhi) keeps its old value, so whole groups are
+      // written back (each group belongs to one thread).
+      v4f nv[ROWS];
+      bool any[ROWS];
 #pragma unroll
-      for (int q = 0; q < PT; ++q) {
+      for (int q = 0; q < ROWS; ++q) {
+        any[q] = false;
         if (q < qn) {  // workgroup-uniform: only the rows of the window
-          const int j = tid + q * bs;
-          nv[q] = (j >= jlo && j < jhi) ? jacobi_point(win[j - 1], win[j], win[j + 1], a.r) : 0.0f;
+          const int j0 = 4 * (q * bs + tid);
+          any[q] = j0 < jhi && j0 + 4 > jlo;
+          if (any[q]) {
+            const v4f c = win4[j0 >> 2];
+            const float left = j0 > 0 ? win[j0 - 1] : 0.0f;  // value 0 is never updated (jlo >= 1)
+            const float right = win[j0 + 4];
+            v4f v;
+            v.x = (j0 >= jlo && j0 < jhi) ? jacobi_point(left, c.x, c.y, a.r) : c.x;
+            v.y = (j0 + 1 >= jlo && j0 + 1 < jhi) ? jacobi_point(c.x, c.y, c.z, a.r) : c.y;
+            v.z = (j0 + 2 >= jlo && j0 + 2 < jhi) ? jacobi_point(c.y, c.z, c.w, a.r) : c.z;
+            v.w = (j0 + 3 >= jlo && j0 + 3 < jhi) ? jacobi_point(c.z, c.w, right, a.r) : c.w;
+            nv[q] = v;
+          }
         }
       }
       __syncthreads();  // every read of the old values precedes the writes
 #pragma unroll
-      for (int q = 0; q < PT; ++q) {
-        if (q < qn) {
-          const int j = tid + q * bs;
-          if (j >= jlo && j < jhi) win[j] = nv[q];
-        }
-      }
+      for (int q = 0; q < ROWS; ++q)
+        if (q < qn && any[q]) win4[(4 * (q * bs + tid)) >> 2] = nv[q];
       __syncthreads();
     }
     step += kk;
@@ -149,20 +167,18 @@ __global__ __launch_bounds__(1024) void k_jacobi_persistent(StencilArgs a) {
 
 namespace {
 
-const void* persistent_kernel(int pt) {
-  switch (pt) {
+const void* persistent_kernel(int rows) {
+  switch (rows) {
     case 1: return reinterpret_cast<const void*>(&k_jacobi_persistent<1>);
     case 2: return reinterpret_cast<const void*>(&k_jacobi_persistent<2>);
     case 4: return reinterpret_cast<const void*>(&k_jacobi_persistent<4>);
-    case 8: return reinterpret_cast<const void*>(&k_jacobi_persistent<8>);
-    case 16: return reinterpret_cast<const void*>(&k_jacobi_persistent<16>);
-    default: return reinterpret_cast<const void*>(&k_jacobi_persistent<kStencilPT>);
+    default: return reinterpret_cast<const void*>(&k_jacobi_persistent<kStencilRows>);
   }
 }
 
 int stencil_coresident(int wg, size_t lds_bytes, const DeviceInfo& dev, int* n_wg) {
   int per_cu = 0;
-  RED_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel(kStencilPT), wg, lds_bytes));
+  RED_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel(kStencilRows), wg, lds_bytes));
   *n_wg = per_cu * dev.cus;
   if (*n_wg < 1) return set_error(RED_EINVAL, "persistent stencil: a %d-thread workgroup with %zu bytes of LDS "
                                               "cannot be resident", wg, lds_bytes);
@@ -180,7 +196,7 @@ int stencil_launch(float* u, float* scratch, int64_t n, int steps, float r, int 
   // LDS window: the 64 KB a workgroup gets without opting in to more, less
   // a margin for the barrier's static LDS.
   const int64_t lds_floats =
-      std::min<int64_t>((std::min<int64_t>(dev.lds_per_wg, 65536) - 256) / 4, (int64_t)kStencilPT * wg);
+      std::min<int64_t>((std::min<int64_t>(dev.lds_per_wg, 65536) - 256) / 4 - 8, (int64_t)4 * kStencilRows * wg);
 
   // Persistent geometry: one workgroup per CU unless the array needs more
   // LDS windows, never more than are co-resident with the largest window,
@@ -191,7 +207,7 @@ int stencil_launch(float* u, float* scratch, int64_t n, int steps, float r, int 
   size_t lds_bytes = 0;
   if (variant != RED_VARIANT_RELAUNCH) {
     int g_max = 0;
-    int rc = stencil_coresident(wg, (size_t)lds_floats * 4, dev, &g_max);
+    int rc = stencil_coresident(wg, (size_t)stencil_window_alloc((int)lds_floats) * 4, dev, &g_max);
     if (rc) return rc;
     const int64_t cap = std::max<int64_t>(1, lds_floats - 2 * (int64_t)k_req);  // block values per window
     int64_t g = p.grid > 0 ? p.grid : std::max<int64_t>(dev.cus, (n + cap - 1) / cap);
@@ -209,7 +225,7 @@ int stencil_launch(float* u, float* scratch, int64_t n, int steps, float r, int 
       variant = RED_VARIANT_RELAUNCH;  // AUTO: the array does not fit on chip
     } else {
       variant = RED_VARIANT_PERSISTENT;
-      lds_bytes = (size_t)len * 4;
+      lds_bytes = (size_t)stencil_window_alloc((int)len) * 4;
     }
   }
 
@@ -246,9 +262,9 @@ int stencil_launch(float* u, float* scratch, int64_t n, int steps, float r, int 
   void* args[] = {&a};
   const bool coop = (p.flags & RED_FLAG_PLAIN_LAUNCH) == 0;
   const int slot = timer_begin(s);
-  int pt = 1;
-  while (pt < kStencilPT && (int64_t)pt * wg < m + 2 * (int64_t)k) pt *= 2;
-  int rc = launch(persistent_kernel(pt), grid, wg, args, s, coop, lds_bytes);
+  int rows = 1;
+  while (rows < kStencilRows && (int64_t)4 * rows * wg < m + 2 * (int64_t)k) rows *= 2;
+  int rc = launch(persistent_kernel(rows), grid, wg, args, s, coop, lds_bytes);
   timer_end(s, slot);
   return rc;
 }
