@@ -250,6 +250,34 @@ def test_full_f32_config(lib, gen):
     torch.cuda.empty_cache()
 
 
+def test_headline_plan_from_the_cache(lib):
+    """The launch configuration the benchmark times: the committed plan for
+    fp32 compensated 2^28, repeated calls bit-identical and within bound."""
+    from paper_2004_05371_amd import autotune
+    assert autotune.load() > 0
+    n = 1 << 28
+    plan = lib.red_get_plan(lib.RED_F32, lib.RED_ACC_COMPENSATED, n)
+    say("headline plan", plan.as_dict())
+    import json
+    with open(autotune.cache_path()) as fh:
+        entries = json.load(fh)["entries"]
+    cached = [e["plan"] for e in entries
+              if e["kind"] == "sum" and e["dtype"] == "f32" and e["acc"] == "compensated"
+              and autotune.bucket(e["n"]) == autotune.bucket(n)]
+    assert len(cached) == 1 and plan.as_dict() == cached[0]
+    x = inputs.normal_f32(n)
+    t = dev_tensor(x)
+    ex = oracle.exact_sum(x, "f32")
+    o = lib.opts_from_plan(plan)
+    outs = [lib.sum(t, opts=o) for _ in range(5)]
+    torch.cuda.synchronize()
+    vals = [v.item() for v in outs]
+    assert len(set(vals)) == 1
+    assert oracle.rel_err(vals[0], ex) <= BOUND["f32"]
+    del t
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("kind", ["bf16", "f16"])
 def test_full_half_config(lib, kind):
     """bf16 / fp16 2^29 N(0,1), compensated."""
