@@ -123,6 +123,15 @@ typedef enum {
                                    which every workgroup checks against its
                                    XCC_ID register; a mismatch is reported
                                    by red_check_error as RED_ENOTSUP        */
+/* Segmented batches: force one way of cutting and walking the slices
+ * (at most one of the three; by default the device picks from the mean
+ * segment length).  For experiments and tests. */
+#define RED_FLAG_SEG_WORKGROUP 32 /* one slice per workgroup                 */
+#define RED_FLAG_SEG_PIECES 64    /* one slice per wavefront, one wavefront
+                                     combine per piece of a segment         */
+#define RED_FLAG_SEG_RUNS 128     /* one slice per wavefront, reduce-by-key
+                                     over runs of consecutive values (plan
+                                     ipt <= 4, RED_EINVAL otherwise)        */
 
 /* Launch plan of one reduction. */
 typedef struct {
@@ -203,10 +212,13 @@ int red_sum_ex(int dtype, const void *x, int64_t n, void *out, void *stream, con
  *           offsets[0] == 0 (not checked on the device).
  *   nseg    number of segments, 0 <= nseg < 2^31.
  *   out     device pointer to nseg doubles.  Empty segments give 0.
- * One persistent launch: every wavefront owns an equal slice of the
- * elements, sums the pieces of the segments that meet its slice, and the
- * pieces of segments that cross slice boundaries are combined in slice order
- * in binary64 by the last contributor.  The launch is captured in a hipGraph
+ * One persistent launch: every workgroup (long segments) or every
+ * wavefront (short ones) owns an equal slice of the elements and sums the
+ * pieces of the segments that meet its slice; for very short segments a
+ * wavefront reduces by key over runs of consecutive values with a
+ * segmented scan across its lanes.  The pieces of segments that cross slice
+ * boundaries are combined in slice order in binary64 by the last
+ * contributor.  The launch is captured in a hipGraph
  * on the first call for a given (x, offsets, nseg, out, stream, plan) and
  * replayed afterwards; when the stream is already being captured by the
  * caller the kernel is simply launched into that capture.
@@ -218,7 +230,9 @@ int red_sum_segmented(const float *x, const int64_t *offsets, int64_t nseg, doub
  * RED_VARIANT_PERSISTENT (co-resident grid + grid barrier, launched
  * directly, not from a graph).  plan.wg is at most 512 here (RED_EINVAL
  * otherwise); grid x wg / 64 wavefront slices are capped at 65536.
- * RED_FLAG_NO_GRAPH disables graph capture. */
+ * RED_FLAG_NO_GRAPH disables graph capture; RED_FLAG_SEG_WORKGROUP,
+ * RED_FLAG_SEG_PIECES or RED_FLAG_SEG_RUNS forces one form (RED_EINVAL for
+ * two of them, or for RED_FLAG_SEG_RUNS with plan.ipt > 4). */
 int red_sum_segmented_ex(const float *x, const int64_t *offsets, int64_t nseg, double *out,
                          void *stream, const red_opts *opts);
 

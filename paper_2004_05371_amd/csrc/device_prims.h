@@ -142,6 +142,9 @@ constexpr int kQuadPerm2301 = 0x4E;  // quad_perm:[2,3,0,1]  (lane ^ 2)
 constexpr int kRowRor4 = 0x124;      // rotate right by 4 within a 16-lane row
 constexpr int kRowRor8 = 0x128;      // rotate right by 8 within a row
 constexpr int kRowShr1 = 0x111;      // shift right by 1 within a row
+constexpr int kRowShr2 = 0x112;      // shift right by 2 within a row
+constexpr int kRowShr4 = 0x114;      // shift right by 4 within a row
+constexpr int kRowShr8 = 0x118;      // shift right by 8 within a row
 constexpr int kRowBcast15 = 0x142;   // lane 15 of each row -> next row
 constexpr int kRowBcast31 = 0x143;   // lane 31 -> rows 2 and 3
 
@@ -163,6 +166,31 @@ __device__ __forceinline__ typename Op::T wave_reduce_dpp(typename Op::T v) {
   v = Op::add(v, dpp_move<kRowBcast15, 0xA, 0xF>(v));
   v = Op::add(v, dpp_move<kRowBcast31, 0xC, 0xF>(v));
   return read_lane(v, 63);
+}
+
+// Segmented inclusive scan across the wavefront (reduce-by-key): lane l
+// ends with v summed in binary64 over lanes j..l, where j is the last lane
+// at or below l whose flag is set (lane 0 if none), and f with the OR of
+// the flags of lanes 0..l.  Hillis-Steele inside each 16-lane row (row
+// shifts 1, 2, 4, 8), then row 0 into row 1 and row 2 into row 3
+// (row_bcast:15), then rows 0-1 into rows 2-3 (row_bcast:31).  A lane whose
+// source is invalid receives (0, 0), the identity.  Fixed order, so the
+// result is deterministic.  All 64 lanes must be active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void segscan_step(double& v, int& f) {
+  const double pv = dpp_move<CTRL, ROW_MASK, 0xF>(v);
+  const int pf = dpp_move<CTRL, ROW_MASK, 0xF>(f);
+  v = f ? v : pv + v;
+  f = f | pf;
+}
+
+__device__ __forceinline__ void wave_segscan(double& v, int& f) {
+  segscan_step<kRowShr1, 0xF>(v, f);
+  segscan_step<kRowShr2, 0xF>(v, f);
+  segscan_step<kRowShr4, 0xF>(v, f);
+  segscan_step<kRowShr8, 0xF>(v, f);
+  segscan_step<kRowBcast15, 0xA>(v, f);
+  segscan_step<kRowBcast31, 0xC>(v, f);
 }
 
 // ds_swizzle: xor butterfly (masks 1, 2, 4, 8, 16) inside each 32-lane half

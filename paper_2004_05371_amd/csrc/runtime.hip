@@ -334,8 +334,11 @@ int validate_seg_args(const float* x, const int64_t* offsets, int64_t nseg, doub
   if (reinterpret_cast<uintptr_t>(offsets) % 8) return set_error(RED_EINVAL, "offsets is not 8-byte aligned");
   if (reinterpret_cast<uintptr_t>(out) % 8) return set_error(RED_EINVAL, "out is not 8-byte aligned");
   if (opts) {
-    if (opts->flags & ~(RED_FLAG_NONTEMPORAL | RED_FLAG_NO_GRAPH | RED_FLAG_PLAIN_LAUNCH | RED_FLAG_XCD))
+    const int forms = RED_FLAG_SEG_WORKGROUP | RED_FLAG_SEG_PIECES | RED_FLAG_SEG_RUNS;
+    if (opts->flags & ~(RED_FLAG_NONTEMPORAL | RED_FLAG_NO_GRAPH | RED_FLAG_PLAIN_LAUNCH | RED_FLAG_XCD | forms))
       return set_error(RED_EINVAL, "unknown flags 0x%x", opts->flags);
+    const int f = opts->flags & forms;
+    if (f & (f - 1)) return set_error(RED_EINVAL, "segmented: at most one of the form flags");
     if (opts->plan.variant != RED_VARIANT_AUTO) {
       red_plan p = opts->plan;
       if (p.wg == 0) p.wg = 512;
@@ -706,7 +709,11 @@ int red_sum_segmented_ex(const float* x, const int64_t* offsets, int64_t nseg, d
     auto it = g_plans.find(std::make_tuple(1, bucket(nseg), 0, 0));
     if (it != g_plans.end()) sl.plan = it->second;
   }
-  if (opts) sl.plan.flags |= opts->flags & (RED_FLAG_NONTEMPORAL | RED_FLAG_PLAIN_LAUNCH | RED_FLAG_XCD);
+  if (opts)
+    sl.plan.flags |= opts->flags & (RED_FLAG_NONTEMPORAL | RED_FLAG_PLAIN_LAUNCH | RED_FLAG_XCD |
+                                    RED_FLAG_SEG_WORKGROUP | RED_FLAG_SEG_PIECES | RED_FLAG_SEG_RUNS);
+  if ((sl.plan.flags & RED_FLAG_SEG_RUNS) && sl.plan.ipt > 4)
+    return set_error(RED_EINVAL, "segmented: the reduce-by-key form takes at most 4 loads per thread");
   // Persistent (co-resident) launches, the null stream and a caller's own
   // capture launch directly; otherwise the launch is replayed from a cached
   // graph.

@@ -46,6 +46,15 @@ struct SegArgs {
   BarrierWords* words;
   unsigned spin_limit;
   unsigned bar_groups;
+  int form;  // SegForm: automatic, or one form forced
+};
+
+// How the slices are cut and walked.
+enum SegForm : int {
+  kSegAuto = 0,        // chosen on the device from the mean segment length
+  kSegWorkgroup = 1,   // workgroup slices
+  kSegWavePieces = 2,  // wavefront slices, one combine per piece
+  kSegWaveRuns = 3,    // wavefront slices, reduce-by-key over lane runs
 };
 
 // offsets[i] through the scalar data cache (the offsets are read-only for
@@ -127,6 +136,22 @@ __device__ __forceinline__ bool seek_segment(const SegArgs& a, int64_t& s, int64
   return false;
 }
 
+// The segment that holds element lo of a non-empty slice, or for an empty
+// slice the first one that starts at or after lo: the first s in
+// [0, nseg] with offsets[s] >= lo by binary search (offsets[nseg] = E >= lo),
+// stepped back by one when segment s-1 crosses lo.
+__device__ __forceinline__ int64_t first_segment(const SegArgs& a, int64_t lo) {
+  int64_t L = 0, R = a.nseg;
+  while (L < R) {
+    const int64_t mid = (L + R) >> 1;
+    if (offset_at(a.offsets, mid) >= lo)
+      R = mid;
+    else
+      L = mid + 1;
+  }
+  return (L > 0 && offset_at(a.offsets, L) > lo) ? L - 1 : L;
+}
+
 // Adds to acc the elements of the thread's IPT vectors of one tile that lie
 // in the tile-relative range [ra, rb) (0 <= ra <= rb <= 4 T): vector u of
 // thread idx (0 <= idx < bs) starts at element 4 (u bs + idx) of the tile.
@@ -182,6 +207,13 @@ constexpr int kSegMaxWG = 512;
 // ones about 10 to 30 % faster on workgroup slices).
 constexpr int64_t kWaveSliceMeanLen = 16384;
 
+// Batches whose mean segment holds fewer values than this take the
+// reduce-by-key form of the wavefront slices (plans of at most 4 loads per
+// thread).  Measured on MI355X with 2^28 values, 512 x 4, two workgroups
+// per CU: 4.7 TB/s against 0.9 per piece at 64 values, 5.7 against 5.0 at
+// 512, even at 1024.
+constexpr int64_t kRunsMeanLen = 1024;
+
 // Wavefront-granular slices (short segments: every wave walks its own
 // pieces, with no workgroup barrier): wavefront w of the grid owns slice
 // w and streams it as tiles of 64 x IPT vectors.
@@ -201,17 +233,7 @@ __device__ __forceinline__ void seg_wave_slices(const SegArgs& a) {
   // position E (for E == 0: slice 0).
   const bool end_slice = E > 0 ? (lo < E && hi == E) : (w == 0);
 
-  // First s in [0, nseg] with offsets[s] >= lo (offsets[nseg] = E >= lo).
-  int64_t L = 0, R = nseg;
-  while (L < R) {
-    const int64_t mid = (L + R) >> 1;
-    if (offset_at(a.offsets, mid) >= lo)
-      R = mid;
-    else
-      L = mid + 1;
-  }
-  // Segment L-1 crosses lo if it ends after lo.
-  int64_t s = (L > 0 && offset_at(a.offsets, L) > lo) ? L - 1 : L;
+  int64_t s = first_segment(a, lo);
   int64_t sa = 0, sb = 0;
   bool have = seek_segment(a, s, hi, E, end_slice, sa, sb, lane == 0);
   int64_t A = std::max(sa, lo), B = std::min(sb, hi);  // current piece
@@ -293,21 +315,276 @@ __device__ __forceinline__ void seg_wave_slices(const SegArgs& a) {
   }
 }
 
+// Reduce-by-key form of the wavefront slices, for very short segments.
+//
+// Each tile of 64 x IPT 16-byte vectors (256 IPT contiguous values) is
+// transposed through LDS so that lane l holds the run of RL = 4 IPT
+// consecutive values that starts at value RL l of the tile.  The starts of
+// the segments that follow the open one come from a window of the offsets
+// held in registers (entries j0 .. j0 + 63 of two 64-entry windows, a third
+// one prefetched).  When fewer than 64 segments start in the tile and no
+// run holds two starts:
+//   * each lane sums its run with fp32 TwoSum, cut at the start it holds (if
+//     any) into a head, the end of the segment open on its left, and a
+//     tail;
+//   * a segmented inclusive scan of the tails in binary64 across the lanes,
+//     seeded with the slice's partial of the open segment, gives every lane
+//     the partial of the segment open at its right end;
+//   * a lane that holds a start completes the segment that ends there (its
+//     head plus the scan of the lane on its left): it writes the sum when
+//     the segment began in the tile, and the first start of the tile closes
+//     the segment that was open, which may have begun before the slice and
+//     goes through finish_piece.
+// Other tiles (an empty segment, two starts in one run, 64 starts or more)
+// are finished piece by piece as in seg_wave_slices, the open partial
+// carried in binary64 between the two.
+struct RunLds {
+  v4f tile[kWave * 4];  // one tile of up to 4 rows, swizzled
+  unsigned slot[kWave]; // per lane run: (k + 1) << 16 | tile position of start k, or 0
+};
+
+// Position of vector i of the transposition buffer: within each group of 16
+// vectors the low bits are XOR-ed so that both the row writes (lane l, vector
+// 64 u + l) and the run reads (lane l, vector IPT l + j) of 16 consecutive
+// lanes fall in distinct 16-byte bank groups.
+template <int IPT>
+__device__ __forceinline__ int run_swz(int i) {
+  return i ^ ((i >> 4) & (IPT - 1));
+}
+
+template <int IPT, bool NT, bool BARRIER>
+__device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all) {
+  static_assert(IPT <= 4, "runs of at most 16 values");
+  using M = ModeF32Comp;
+  constexpr int RL = 4 * IPT;  // values per lane run
+  const int nwaves = blockDim.x / kWave;
+  const int lane = __lane_id();
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  RunLds& L = lds_all[wv];
+  const int64_t w = (int64_t)blockIdx.x * nwaves + wv;
+  const int64_t W = (int64_t)gridDim.x * nwaves;
+  const int64_t nseg = a.nseg;
+  const int64_t E = offset_at(a.offsets, nseg);
+  const int64_t chunk = std::max<int64_t>(64, (((E + W - 1) / W) + 63) & ~(int64_t)63);
+  const int64_t lo = std::min(w * chunk, E);
+  const int64_t hi = std::min(lo + chunk, E);
+  const bool end_slice = E > 0 ? (lo < E && hi == E) : (w == 0);
+
+  int64_t s = first_segment(a, lo);
+  int64_t sa = 0, sb = 0;
+  bool have = seek_segment(a, s, hi, E, end_slice, sa, sb, lane == 0);
+  double C = 0.0;  // partial of segment s over [max(sa, lo), current position)
+
+  const int shift = (int)((reinterpret_cast<uintptr_t>(a.x) & 15) >> 2);
+  const v4f* xa = reinterpret_cast<const v4f*>(a.x - shift);
+  const int64_t vlo = (lo + shift) >> 2;
+  const int64_t vhi = (hi + shift + 3) >> 2;
+  constexpr int64_t T = kWave * IPT;
+  const int64_t ntiles = lo < hi ? (vhi - vlo + T - 1) / T : 0;
+
+  // Offsets window: entry j is offsets[wb + j] (INT64_MAX past nseg).
+  auto off_entry = [&](int64_t i) -> int64_t { return i <= nseg ? a.offsets[i] : INT64_MAX; };
+  int64_t wb = s + 1;
+  int64_t win0 = 0, win1 = 0, win2 = 0;
+  if (have) {
+    win0 = off_entry(wb + lane);
+    win1 = off_entry(wb + kWave + lane);
+    win2 = off_entry(wb + 2 * kWave + lane);
+  }
+
+  v4f cur[IPT], nxt[IPT];
+  auto load_tile = [&](v4f* v, int64_t t) {
+    const int64_t v0 = vlo + t * T + lane;
+    if (vlo + (t + 1) * T <= vhi) {
+#pragma unroll
+      for (int u = 0; u < IPT; ++u) v[u] = load_vec<NT>(xa + v0 + u * kWave);
+    } else {
+#pragma unroll
+      for (int u = 0; u < IPT; ++u)
+        v[u] = v0 + u * kWave < vhi ? load_vec<NT>(xa + v0 + u * kWave) : v4f{0, 0, 0, 0};
+    }
+  };
+
+  int64_t own_fix = -1;
+  if (ntiles > 0) load_tile(cur, 0);
+  for (int64_t t = 0; t < ntiles; ++t) {
+    // Every load has completed here (see seg_wave_slices), so the window
+    // registers move without a wait.
+    __builtin_amdgcn_s_waitcnt(0);
+    if (have) {
+      const int64_t j0 = s + 1 - wb;
+      if (j0 >= 2 * kWave) {  // after a long stretch finished piece by piece
+        wb = s + 1;
+        win0 = off_entry(wb + lane);
+        win1 = off_entry(wb + kWave + lane);
+        win2 = off_entry(wb + 2 * kWave + lane);
+      } else if (j0 >= kWave) {
+        win0 = win1;
+        win1 = win2;
+        wb += kWave;
+        win2 = off_entry(wb + 2 * kWave + lane);
+      }
+    }
+    if (t + 1 < ntiles) load_tile(nxt, t + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    const int64_t e0 = 4 * (vlo + t * T) - shift;
+    const int64_t e1 = 4 * (vlo + (t + 1) * T) - shift;
+
+    // Segment starts in the tile, from the window.
+    bool fast = false, valid = false;
+    int64_t O = 0;
+    int m = 0, rel = 0, r = 0;
+    if (have) {
+      const int64_t tend = std::min(e1, hi);
+      const int j0 = (int)(s + 1 - wb);  // 0 .. 63
+      const int src = (j0 + lane) & (kWave - 1);
+      const int64_t p0 = bpermute_move(win0, src), p1 = bpermute_move(win1, src);
+      O = j0 + lane < kWave ? p0 : p1;  // start of segment s + 1 + lane
+      valid = O < tend;
+      m = __popcll(__ballot(valid));  // the valid lanes are 0 .. m-1
+      rel = valid ? (int)(O - e0) : 0;
+      r = rel / RL;  // lane whose run holds start `lane`
+      const int rn = __builtin_amdgcn_ds_bpermute(((lane + 1) & (kWave - 1)) << 2, r);
+      const bool clash = valid && lane + 1 < m && rn == r;
+      fast = m < kWave && __ballot(clash) == 0;
+    }
+    if (fast) {
+      {
+        // Start k (lane k) tells lane r_k where it lies.
+        volatile unsigned* slot = L.slot;
+        slot[lane] = 0u;
+        if (valid) slot[r] = ((unsigned)(lane + 1) << 16) | (unsigned)rel;
+        const unsigned word = slot[lane];
+        // Transpose: row u of the tile in, run of RL values out.
+#pragma unroll
+        for (int u = 0; u < IPT; ++u) L.tile[run_swz<IPT>(u * kWave + lane)] = cur[u];
+        __builtin_amdgcn_wave_barrier();
+        float xr[RL];
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+          const v4f y = L.tile[run_swz<IPT>(lane * IPT + j)];
+          xr[4 * j] = y.x;
+          xr[4 * j + 1] = y.y;
+          xr[4 * j + 2] = y.z;
+          xr[4 * j + 3] = y.w;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (e0 < lo || e1 > hi) {  // first or last tile: values outside the slice are not its own
+          const int64_t p = e0 + (int64_t)RL * lane;
+#pragma unroll
+          for (int i = 0; i < RL; ++i) xr[i] = (p + i >= lo && p + i < hi) ? xr[i] : 0.0f;
+        }
+        const bool has = word != 0u;
+        const int b = has ? (int)(word & 0xFFFFu) - RL * lane : RL;  // the start's place in the run
+        CompF32 run = M::zero(), head = M::zero();
+#pragma unroll
+        for (int i = 0; i < RL; ++i) {
+          if (i > 0) {
+            const bool at = i == b;
+            head.s = at ? run.s : head.s;
+            head.c = at ? run.c : head.c;
+            run.s = at ? 0.0f : run.s;
+            run.c = at ? 0.0f : run.c;
+          }
+          M::add_elem(run, xr[i]);
+        }
+        double v = comp_to_double(run);
+        int f = has ? 1 : 0;
+        wave_segscan(v, f);
+        if (!f) v = C + v;  // lanes 0 .. l hold no start: the open segment continues
+        const double left = bpermute_move(v, (lane - 1) & (kWave - 1));
+        const double total = (lane == 0 ? C : left) + comp_to_double(head);
+        const int k = (int)(word >> 16) - 1;
+        if (has && k > 0 && k < m) a.out[s + k] = total;  // segment s + k lies in the tile
+        const double c_next = read_lane(v, kWave - 1);
+        if (m > 0) {
+          const int r0 = __builtin_amdgcn_readfirstlane(r);
+          const int64_t o0 = read_lane(O, 0);
+          finish_piece<BARRIER>(a, s, sa, o0, read_lane(total, r0), lo, hi, w, chunk, &own_fix);
+          sa = read_lane(O, m - 1);
+          sb = read_lane(O, m);
+          s += m;
+        }
+        C = c_next;
+      }
+    } else if (have) {
+      // Piece by piece, as in seg_wave_slices, with the open partial C.
+      CompF32 acc[IPT];
+#pragma unroll
+      for (int u = 0; u < IPT; ++u) acc[u] = M::zero();
+      auto relp = [&](int64_t e) { return (int)std::min(std::max(e - e0, (int64_t)0), 4 * T); };
+      int64_t A = std::max(sa, lo), B = std::min(sb, hi);
+      while (have && B <= e1) {
+        add_masked<IPT>(acc, cur, kWave, lane, relp(A), relp(B));
+        CompF32 tot = acc[0];
+#pragma unroll
+        for (int u = 1; u < IPT; ++u) tot = OpComp::add(tot, acc[u]);
+#pragma unroll
+        for (int u = 0; u < IPT; ++u) acc[u] = M::zero();
+        tot = wave_reduce_dpp<OpComp>(tot);
+        finish_piece<BARRIER>(a, s, sa, sb, C + comp_to_double(tot), lo, hi, w, chunk, &own_fix);
+        C = 0.0;
+        ++s;
+        have = seek_segment(a, s, hi, E, end_slice, sa, sb, lane == 0);
+        A = std::max(sa, lo);
+        B = std::min(sb, hi);
+      }
+      if (have) {
+        if (A <= e0 && vlo + (t + 1) * T <= vhi) {
+#pragma unroll
+          for (int u = 0; u < IPT; ++u) M::add_vec(acc[u], cur[u]);
+        } else {
+          add_masked<IPT>(acc, cur, kWave, lane, relp(A), relp(B));
+        }
+        CompF32 tot = acc[0];
+#pragma unroll
+        for (int u = 1; u < IPT; ++u) tot = OpComp::add(tot, acc[u]);
+#pragma unroll
+        for (int u = 0; u < IPT; ++u) acc[u] = M::zero();
+        C += comp_to_double(wave_reduce_dpp<OpComp>(tot));
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) cur[u] = nxt[u];
+  }
+  if (have) {  // the segment open at the slice's end ends at or after hi
+    finish_piece<BARRIER>(a, s, sa, sb, C, lo, hi, w, chunk, &own_fix);
+    ++s;
+    seek_segment(a, s, hi, E, end_slice, sa, sb, lane == 0);  // empty segments at E
+  }
+  if constexpr (BARRIER) {
+    grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit);
+    if (own_fix >= 0) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const int64_t o = offset_at(a.offsets, own_fix) / chunk;
+      const int64_t np = (offset_at(a.offsets, own_fix + 1) - 1) / chunk - o + 1;
+      const double v = combine_pieces(a, o, np);
+      if (lane == 0) a.out[own_fix] = v;
+    }
+  }
+}
+
 // Workgroup-granular slices (long segments: few streams, little per-piece
 // work): workgroup g owns slice g, streams it as tiles of blockDim x IPT
 // vectors, and finishes the pieces that end in a tile in batches of
 // kBatch after one workgroup barrier, wave w finishing pieces w,
 // w + nwaves, ...
+// Per-wave partials of up to kBatch finished pieces, completed together
+// after one barrier.  Two buffers used alternately: a wave writes a buffer
+// again only after the next batch's barrier, which every wave reaches after
+// its reads of that buffer.
+struct WorkgroupLds {
+  CompF32 part[2][kBatch][kMaxWavesPerWG];
+  PieceInfo info[2][kBatch];
+  int64_t own_fix;  // barrier form: cut segment this workgroup owns
+};
+
 template <int IPT, bool NT, bool BARRIER>
-__device__ __forceinline__ void seg_workgroup_slices(const SegArgs& a) {
+__device__ __forceinline__ void seg_workgroup_slices(const SegArgs& a, WorkgroupLds& lds) {
   using M = ModeF32Comp;
-  // Per-wave partials of up to kBatch finished pieces, completed together
-  // after one barrier.  Two buffers used alternately: a wave writes a
-  // buffer again only after the next batch's barrier, which every wave
-  // reaches after its reads of that buffer.
-  __shared__ CompF32 part[2][kBatch][kMaxWavesPerWG];
-  __shared__ PieceInfo info[2][kBatch];
-  __shared__ int64_t own_fix;  // barrier form: cut segment this workgroup owns
+  auto& part = lds.part;
+  auto& info = lds.info;
+  int64_t& own_fix = lds.own_fix;
   int buf = 0, nb = 0;
   const int64_t nseg = a.nseg;
   const int64_t E = offset_at(a.offsets, nseg);
@@ -320,17 +597,7 @@ __device__ __forceinline__ void seg_workgroup_slices(const SegArgs& a) {
   // sit at position E (for E == 0: workgroup 0).
   const bool end_wg = E > 0 ? (lo < E && hi == E) : (g == 0);
 
-  // First s in [0, nseg] with offsets[s] >= lo (offsets[nseg] = E >= lo).
-  int64_t L = 0, R = nseg;
-  while (L < R) {
-    const int64_t mid = (L + R) >> 1;
-    if (offset_at(a.offsets, mid) >= lo)
-      R = mid;
-    else
-      L = mid + 1;
-  }
-  // Segment L-1 crosses lo if it ends after lo.
-  int64_t s = (L > 0 && offset_at(a.offsets, L) > lo) ? L - 1 : L;
+  int64_t s = first_segment(a, lo);
   int64_t sa = 0, sb = 0;
   bool have = seek_segment(a, s, hi, E, end_wg, sa, sb, threadIdx.x == 0);
   int64_t A = std::max(sa, lo), B = std::min(sb, hi);  // current piece
@@ -440,13 +707,29 @@ __device__ __forceinline__ void seg_workgroup_slices(const SegArgs& a) {
   }
 }
 
+// One form runs per launch, so the forms share the workgroup's LDS.
+union SegLds {
+  WorkgroupLds wg;
+  RunLds runs[kSegMaxWG / kWave];
+};
+
 template <int IPT, bool NT, bool BARRIER>
 __global__ __launch_bounds__(kSegMaxWG) void k_segmented(SegArgs a) {
-  const int64_t E = offset_at(a.offsets, a.nseg);
-  if (E < kWaveSliceMeanLen * a.nseg)  // the same decision in every workgroup
+  __shared__ SegLds lds;
+  int form = a.form;
+  if (form == kSegAuto) {  // the same decision in every workgroup
+    const int64_t E = offset_at(a.offsets, a.nseg);
+    form = E >= kWaveSliceMeanLen * a.nseg ? kSegWorkgroup
+           : (IPT <= 4 && E < kRunsMeanLen * a.nseg) ? kSegWaveRuns
+                                                   : kSegWavePieces;
+  }
+  if (form == kSegWorkgroup) {
+    seg_workgroup_slices<IPT, NT, BARRIER>(a, lds.wg);
+  } else if (form == kSegWaveRuns) {
+    if constexpr (IPT <= 4) seg_wave_runs<IPT, NT, BARRIER>(a, lds.runs);
+  } else {
     seg_wave_slices<IPT, NT, BARRIER>(a);
-  else
-    seg_workgroup_slices<IPT, NT, BARRIER>(a);
+  }
 }
 
 namespace {
@@ -477,15 +760,17 @@ const SegTable& seg_table() {
 
 }  // namespace
 
-// Default (measured on MI355X for 10,000 log-uniform segments): one
-// 512-thread workgroup per CU, 4 loads of 16 bytes per thread per tile.
+// Default (measured on MI355X over uniform segment lengths from 16 to
+// 16384 values): two 512-thread workgroups per CU, the most the
+// reduce-by-key form keeps resident, 4 loads of 16 bytes per thread per
+// tile.
 red_plan default_seg_plan(int64_t nseg, const DeviceInfo& dev) {
   (void)nseg;
   red_plan p;
   p.variant = RED_VARIANT_ATOMIC;
   p.wg = 512;
   p.ipt = 4;
-  p.grid = dev.cus;
+  p.grid = 2 * dev.cus;
   p.flags = RED_FLAG_NONTEMPORAL;
   return p;
 }
@@ -532,6 +817,12 @@ int seg_launch(const SegLaunch& sl, const float* x, const int64_t* offsets, int6
   a.spin_limit = watchdog_spins();
   a.bar_groups = ((p.flags & RED_FLAG_XCD) && dev.nxcc > 1) ? (kBarrierXcd | (unsigned)dev.nxcc)
                                                             : barrier_groups(grid);
+  a.form = (p.flags & RED_FLAG_SEG_WORKGROUP) ? kSegWorkgroup
+           : (p.flags & RED_FLAG_SEG_PIECES)  ? kSegWavePieces
+           : (p.flags & RED_FLAG_SEG_RUNS)    ? kSegWaveRuns
+                                              : kSegAuto;
+  if (a.form == kSegWaveRuns && p.ipt > 4)
+    return set_error(RED_EINVAL, "segmented: the reduce-by-key form takes at most 4 loads per thread");
   void* args[] = {&a};
   const bool nt = (p.flags & RED_FLAG_NONTEMPORAL) != 0;
   const bool coop = barrier && (p.flags & RED_FLAG_PLAIN_LAUNCH) == 0;

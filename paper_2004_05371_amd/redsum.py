@@ -32,6 +32,9 @@ FLAG_NO_GRAPH = 2
 FLAG_PLAIN_LAUNCH = 4
 FLAG_PIPELINE = 8
 FLAG_XCD = 16
+FLAG_SEG_WORKGROUP = 32
+FLAG_SEG_PIECES = 64
+FLAG_SEG_RUNS = 128
 
 STATUS_NAMES = {0: "RED_OK", -1: "RED_EINVAL", -2: "RED_ENOTSUP", -3: "RED_EHIP",
                 -4: "RED_ETIMEOUT", -5: "RED_ENOMEM", -6: "RED_ENODEV"}

@@ -65,6 +65,10 @@ def test_validation_before_hip(lib):
                                     ctypes.byref(big_wg)) == R.RED_EINVAL
     assert lib.red_sum_segmented(ctypes.c_void_p(64), ctypes.c_void_p(64), -1, ctypes.c_void_p(64), None) == R.RED_EINVAL
     assert lib.red_sum_segmented(ctypes.c_void_p(64), ctypes.c_void_p(68), 2, ctypes.c_void_p(64), None) == R.RED_EINVAL
+    for f in (R.FLAG_SEG_WORKGROUP | R.FLAG_SEG_RUNS, R.FLAG_SEG_PIECES | R.FLAG_SEG_RUNS, 256):
+        two = R.make_opts(flags=f)  # at most one form flag; unknown bits rejected
+        assert lib.red_sum_segmented_ex(ctypes.c_void_p(64), ctypes.c_void_p(64), 2, ctypes.c_void_p(64), None,
+                                        ctypes.byref(two)) == R.RED_EINVAL
     seg = R.make_opts(variant=R.RED_VARIANT_RELAUNCH, wg=256, ipt=4)
     assert lib.red_sum_segmented_ex(ctypes.c_void_p(64), ctypes.c_void_p(64), 2, ctypes.c_void_p(64), None,
                                     ctypes.byref(seg)) == R.RED_EINVAL

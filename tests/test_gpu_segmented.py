@@ -70,6 +70,108 @@ def test_long_segment_batches(lib, plan):
     check(run(lib, x, off, **PLANS[plan]), x, off)
 
 
+FORM_PLANS = [dict(variant=2, wg=512, ipt=4, grid=0), dict(variant=2, wg=256, ipt=4, grid=7),
+              dict(variant=2, wg=64, ipt=1, grid=300), dict(variant=2, wg=128, ipt=2, grid=33),
+              dict(variant=3, wg=256, ipt=2, grid=64)]
+
+
+def form_layouts():
+    """Short-segment batches: uniform lengths around the lane run (4 to 16
+    values) and the tile (256 to 1024), runs of empty segments, leading and
+    trailing empties, and mixtures that make some tiles fall back to the
+    per-piece walk."""
+    r = np.random.default_rng(500)
+    out = []
+    for L in (1, 3, 4, 15, 16, 17, 63, 64, 65, 100, 1000, 1500):
+        out.append(("uniform%d" % L, np.full(max(1, 200000 // L), L, dtype=np.int64)))
+    out.append(("short0to40", r.integers(0, 41, 20000)))
+    out.append(("empties", r.choice([0, 0, 0, 50], 20000)))
+    out.append(("mixed", r.choice([0, 1, 5, 64, 300, 2000], 3000)))
+    lens = r.integers(10, 200, 5000)
+    lens[::97] = 0
+    out.append(("sprinkled_empties", np.concatenate([[0] * 300, lens, [0] * 7])))
+    out.append(("long_then_short", np.concatenate([[300000], r.integers(1, 30, 10000), [0, 70000]])))
+    return out
+
+
+FORMS = {"workgroup": 32, "pieces": 64, "runs": 128, "auto": 0}
+_EXPECTED = {}
+
+
+def expected(name, x, off):
+    """Per segment: the exact sum rounded to binary64 and the allowed error
+    (BOUND relative, or 1e-6 of the sum of magnitudes when the exact sum is
+    0), computed once per batch."""
+    if name not in _EXPECTED:
+        sums = oracle.segmented_sums(x, off)
+        val = np.array([e.value for e in sums], dtype=np.float64)
+        tol = np.abs(val) * BOUND
+        for k in np.nonzero([e.fraction == 0 for e in sums])[0]:
+            tol[k] = 1e-6 * float(oracle.exact_abs_sum(x[off[k]:off[k + 1]], "f32").fraction)
+        _EXPECTED[name] = (val, tol)
+    return _EXPECTED[name]
+
+
+def check_fast(res, val, tol, what):
+    bad = np.nonzero(~(np.abs(res - val) <= tol))[0]
+    assert bad.size == 0, (what, int(bad[0]), res[bad[0]], val[bad[0]], bad.size)
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+def test_forms_short_segments(lib, form):
+    """Every way of cutting and walking the slices, forced through the form
+    flags, on the same short-segment batches, against the oracle."""
+    for name, lens in form_layouts():
+        off = inputs.offsets_from_lengths(lens.astype(np.int64))
+        x = inputs.mixed_f32(int(off[-1]), sub=15)
+        val, tol = expected(name, x, off)
+        for i, p in enumerate(FORM_PLANS):
+            say("form", form, name, "plan", i, "nseg", off.size - 1, "values", int(off[-1]))
+            check_fast(run(lib, x, off, flags=FORMS[form], **p), val, tol, (form, name, i))
+
+
+@pytest.mark.parametrize("shift", [1, 3])
+def test_runs_form_misaligned(lib, shift):
+    """The reduce-by-key form on values 4 or 12 bytes past a 16-byte
+    boundary: the first and last tiles of every slice mask values that are
+    not the slice's own."""
+    r = np.random.default_rng(600 + shift)
+    lens = np.concatenate([r.integers(1, 70, 30000), [0, 5000, 0]])
+    off = inputs.offsets_from_lengths(lens.astype(np.int64))
+    x = inputs.mixed_f32(int(off[-1]), sub=16)
+    base = torch.zeros(x.size + 8, dtype=torch.float32, device="cuda")
+    base[shift:shift + x.size] = torch.from_numpy(x).to("cuda")
+    xt = base[shift:shift + x.size]
+    ot = torch.from_numpy(off).to("cuda")
+    nseg = off.size - 1
+    for p in FORM_PLANS:
+        out = torch.full((nseg,), float("nan"), dtype=torch.float64, device="cuda")
+        lib.red_sum_segmented_ex(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), lib.current_stream(),
+                                 lib.make_opts(flags=lib.FLAG_SEG_RUNS, **p))
+        torch.cuda.synchronize()
+        check(out.cpu().numpy(), x, off)
+
+
+def test_runs_form_repeat_bit_identical(lib):
+    lens = np.random.default_rng(700).integers(0, 100, 100000)
+    off = inputs.offsets_from_lengths(lens.astype(np.int64))
+    x = inputs.normal_f32(int(off[-1]), sub=17)
+    first = None
+    for i in range(3):
+        got = run(lib, x, off, flags=lib.FLAG_SEG_RUNS)
+        if first is None:
+            check(got, x, off)
+            first = got
+        assert np.array_equal(got, first), i
+
+
+def test_runs_form_rejects_eight_loads(lib):
+    off = np.array([0, 4], dtype=np.int64)
+    x = np.ones(4, dtype=np.float32)
+    with pytest.raises(lib.RedError):
+        run(lib, x, off, variant=2, wg=256, ipt=8, flags=lib.FLAG_SEG_RUNS)
+
+
 def test_edge_batches(lib):
     # empty total, leading / trailing empties, a single segment, all length-1
     for lens in ([0], [0, 0, 0], [0, 5, 0], [1], [12345], [3, 0, 0], [1] * 3000, [0] * 10 + [100] + [0] * 10):
