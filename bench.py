@@ -608,6 +608,11 @@ def run_configs(R, dev, stream, path, plans):
                         flags=R.FLAG_PLAIN_LAUNCH | (plan.flags & R.FLAG_NONTEMPORAL))
         ms_barrier = timed(lambda: R.red_sum_segmented_ex(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh, o),
                            30)
+        fixups = {}
+        for vname, v in (("relaunch", R.RED_VARIANT_RELAUNCH), ("ticket", R.RED_VARIANT_ATOMIC)):
+            ov = R.make_opts(variant=v, wg=plan.wg, ipt=plan.ipt, grid=plan.grid, flags=plan.flags)
+            fixups[vname] = round(timed(lambda: R.red_sum_segmented_ex(xt.data_ptr(), ot.data_ptr(), nseg,
+                                                                       out.data_ptr(), sh, ov), 30) * 1e3, 1)
         ms_loop = timed(lambda: R.red_sum_segmented_loop(xt.data_ptr(), off, nseg, out.data_ptr(), sh), 3)
         R.red_sum_segmented(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh)
         torch.cuda.synchronize()
@@ -618,7 +623,7 @@ def run_configs(R, dev, stream, path, plans):
         worst = max(oracle.rel_err(float(got[k]), e) if e.fraction != 0 else abs(got[k]) for k, e in enumerate(sums))
         emit({"config": label, "nseg": nseg, "total_elems": int(off[-1]), "bytes": nbytes, "plan": plan.as_dict(),
               "graph_us": round(ms_graph * 1e3, 1), "graph_GBps": gbps(nbytes, ms_graph), "graph_timing_us": graph_stats,
-              "grid_barrier_fixup_us": round(ms_barrier * 1e3, 1),
+              "grid_barrier_fixup_us": round(ms_barrier * 1e3, 1), "plan_with_fixup_us": fixups,
               "loop_per_segment_us": round(ms_loop * 1e3, 1), "speedup_vs_loop": round(ms_loop / ms_graph, 1),
               "max_rel_err": worst, "cpu_oracle_s": round(tc, 2)})
         del xt, ot
@@ -627,17 +632,30 @@ def run_configs(R, dev, stream, path, plans):
     # -- segmented batches of uniform lengths over 2^28 values: the cost of
     #    short segments, the slice granularity switch
     xs = torch.from_numpy(inputs.normal_f32(1 << 28, sub=3)).to("cuda")
-    o = R.make_opts(variant=R.RED_VARIANT_ATOMIC, wg=512, ipt=4, grid=dev["cus"], flags=R.FLAG_NONTEMPORAL)
-    for L in (64, 256, 1024, 4096, 16384, 65536, 262144, 1 << 28):
+    splan = dict(wg=512, ipt=4, grid=2 * dev["cus"])
+    forms = {"workgroup": R.FLAG_SEG_WORKGROUP, "pieces": R.FLAG_SEG_PIECES, "runs": R.FLAG_SEG_RUNS}
+    for L in (16, 32, 64, 256, 768, 1024, 4096, 16384, 65536, 262144, 1 << 28):
         nseg = (1 << 28) // L
-        offs = torch.arange(0, (1 << 28) + 1, L, dtype=torch.int64, device="cuda")
+        ntot = nseg * L
+        offs = torch.arange(0, ntot + 1, L, dtype=torch.int64, device="cuda")
         outs = torch.empty(nseg, dtype=torch.float64, device="cuda")
-        ms = timed(lambda: R.red_sum_segmented_ex(xs.data_ptr(), offs.data_ptr(), nseg, outs.data_ptr(), sh, o), 20)
-        stats = dict(last)
-        ref = xs.view(nseg, L).double().sum(1)  # torch check on the GPU (the oracle covers parity in the tests)
-        emit({"config": "segments_uniform", "length": L, "nseg": nseg, "plan": {"wg": 512, "ipt": 4,
-              "grid": dev["cus"]}, "us": round(ms * 1e3, 1), "GBps": gbps((1 << 28) * 4, ms), "timing_us": stats,
-              "slices": "wavefront" if L < 16384 else "workgroup",
+        nb = ntot * 4 + (nseg + 1) * 8 + nseg * 8
+        row = {}
+        for fname, ff in [("auto", 0)] + list(forms.items()):
+            if (fname == "workgroup" and L < 4096) or (fname == "pieces" and L < 64) or (fname == "runs" and L > 16384):
+                continue
+            for vname, v in (("relaunch", R.RED_VARIANT_RELAUNCH), ("ticket", R.RED_VARIANT_ATOMIC)):
+                if fname != "auto" and vname == "ticket":
+                    continue
+                o = R.make_opts(variant=v, flags=R.FLAG_NONTEMPORAL | ff, **splan)
+                ms = timed(lambda: R.red_sum_segmented_ex(xs.data_ptr(), offs.data_ptr(), nseg, outs.data_ptr(),
+                                                          sh, o), 20)
+                row["%s_%s_us" % (fname, vname)] = round(ms * 1e3, 1)
+        ms = row["auto_relaunch_us"] / 1e3
+        ref = xs[:ntot].view(nseg, L).double().sum(1)  # torch check on the GPU (the oracle covers parity in the tests)
+        emit({"config": "segments_uniform", "length": L, "nseg": nseg, "plan": splan, "us": row["auto_relaunch_us"],
+              "GBps": gbps(nb, ms), "by_form_and_fixup_us": row,
+              "form": "workgroup" if L >= 16384 else "runs" if L < 1024 else "pieces",
               "max_abs_diff_vs_fp64_torch": float((outs - ref).abs().max())})
         del offs, outs, ref
     del xs

@@ -345,8 +345,9 @@ int validate_seg_args(const float* x, const int64_t* offsets, int64_t nseg, doub
       if (p.ipt == 0) p.ipt = 4;
       int rc = validate_plan(p);
       if (rc) return rc;
-      if (opts->plan.variant != RED_VARIANT_ATOMIC && opts->plan.variant != RED_VARIANT_PERSISTENT)
-        return set_error(RED_EINVAL, "segmented: variant must be ATOMIC or PERSISTENT");
+      if (opts->plan.variant != RED_VARIANT_RELAUNCH && opts->plan.variant != RED_VARIANT_ATOMIC &&
+          opts->plan.variant != RED_VARIANT_PERSISTENT)
+        return set_error(RED_EINVAL, "segmented: variant must be RELAUNCH, ATOMIC or PERSISTENT");
       if (p.wg > 512) return set_error(RED_EINVAL, "segmented: at most 512 threads per workgroup");
     }
   }
@@ -820,8 +821,9 @@ int red_set_segmented_plan(int64_t nseg, const red_plan* plan) {
   if (!plan || nseg < 0) return set_error(RED_EINVAL, "bad plan or nseg");
   int rc = validate_plan(*plan);
   if (rc) return rc;
-  if (plan->variant != RED_VARIANT_ATOMIC && plan->variant != RED_VARIANT_PERSISTENT)
-    return set_error(RED_EINVAL, "segmented: variant must be ATOMIC or PERSISTENT");
+  if (plan->variant != RED_VARIANT_RELAUNCH && plan->variant != RED_VARIANT_ATOMIC &&
+      plan->variant != RED_VARIANT_PERSISTENT)
+    return set_error(RED_EINVAL, "segmented: variant must be RELAUNCH, ATOMIC or PERSISTENT");
   if (plan->wg > 512) return set_error(RED_EINVAL, "segmented: at most 512 threads per workgroup");
   std::lock_guard<std::mutex> lk(g_mu);
   g_plans[std::make_tuple(1, bucket(nseg), 0, 0)] = *plan;
@@ -914,10 +916,11 @@ int red_autotune_segmented(const float* x, const int64_t* offsets, int64_t nseg,
     if (!rc) rc = consider(p);
   }
   const int nt_flag = cur.flags & RED_FLAG_NONTEMPORAL;
-  for (int wg : {128, 256, 512})
-    for (int ipt : {2, 4, 8})
-      for (int m : {1, 2, 3, 4, 6, 8})
-        if (!rc) rc = consider(red_plan{RED_VARIANT_ATOMIC, wg, ipt, std::min(m * dev->cus, RED_MAX_GRID), nt_flag});
+  for (int v : {RED_VARIANT_RELAUNCH, RED_VARIANT_ATOMIC})
+    for (int wg : {128, 256, 512})
+      for (int ipt : {2, 4, 8})
+        for (int m : {1, 2, 3, 4, 6, 8})
+          if (!rc) rc = consider(red_plan{v, wg, ipt, std::min(m * dev->cus, RED_MAX_GRID), nt_flag});
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (rc) return rc;

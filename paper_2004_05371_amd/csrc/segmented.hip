@@ -47,6 +47,15 @@ struct SegArgs {
   unsigned spin_limit;
   unsigned bar_groups;
   int form;  // SegForm: automatic, or one form forced
+  int grid;  // workgroups of the slice kernel
+  int wg;    // threads per workgroup of the slice kernel
+};
+
+// How the pieces of a segment cut by slice boundaries are summed.
+enum SegFix : int {
+  kFixTicket = 0,    // the wavefront that publishes the last piece (atomic ticket)
+  kFixBarrier = 1,   // the owning slice, after a grid barrier (co-resident grid)
+  kFixRelaunch = 2,  // a second kernel, after the implicit barrier between launches
 };
 
 // How the slices are cut and walked.
@@ -77,10 +86,12 @@ __device__ __forceinline__ double combine_pieces(const SegArgs& a, int64_t o, in
 // Completes, by one wavefront, the piece [max(sa, lo), min(sb, hi)) of
 // segment s whose total is v: a whole segment is written; a piece of a cut
 // segment is published in its carry slot (slice w), and the wavefront that
-// completes the segment's ticket sums all of its pieces (ticket form), or
-// the owning wavefront does so after the grid barrier (barrier form:
-// *own_fix records the segment).
-template <bool BARRIER>
+// completes the segment's ticket sums all of its pieces (ticket fix-up), or
+// the owning wavefront does so after the grid barrier (barrier fix-up:
+// *own_fix records the segment), or the fix-up kernel that follows does
+// (relaunch fix-up: the slot is an ordinary store, made visible by the
+// kernel boundary).
+template <int FIX>
 __device__ __forceinline__ void finish_piece(const SegArgs& a, int64_t s, int64_t sa, int64_t sb, double v,
                                              int64_t lo, int64_t hi, int64_t w, int64_t chunk, int64_t* own_fix) {
   const int lane = __lane_id();
@@ -90,7 +101,14 @@ __device__ __forceinline__ void finish_piece(const SegArgs& a, int64_t s, int64_
   }
   const int64_t o = sa / chunk;
   const int64_t np = (sb - 1) / chunk - o + 1;
-  if constexpr (BARRIER) {
+  if constexpr (FIX == kFixRelaunch) {
+    if (lane == 0) {
+      if (sa < lo)
+        a.carry_in[w] = SegCarry{s, v};
+      else
+        a.carry_out[w] = SegCarry{s, v};
+    }
+  } else if constexpr (FIX == kFixBarrier) {
     if (lane == 0) {
       if (sa < lo)
         a.carry_in[w] = SegCarry{s, v};
@@ -217,7 +235,7 @@ constexpr int64_t kRunsMeanLen = 1024;
 // Wavefront-granular slices (short segments: every wave walks its own
 // pieces, with no workgroup barrier): wavefront w of the grid owns slice
 // w and streams it as tiles of 64 x IPT vectors.
-template <int IPT, bool NT, bool BARRIER>
+template <int IPT, bool NT, int FIX>
 __device__ __forceinline__ void seg_wave_slices(const SegArgs& a) {
   using M = ModeF32Comp;
   const int nwaves = blockDim.x / kWave;
@@ -232,6 +250,10 @@ __device__ __forceinline__ void seg_wave_slices(const SegArgs& a) {
   // The slice that ends at E also writes the empty segments that sit at
   // position E (for E == 0: slice 0).
   const bool end_slice = E > 0 ? (lo < E && hi == E) : (w == 0);
+  // Relaunch fix-up: the slot says "no cut segment starts here" unless a
+  // later store by the same lane replaces it.
+  if constexpr (FIX == kFixRelaunch)
+    if (lane == 0) a.carry_out[w] = SegCarry{-1, 0.0};
 
   int64_t s = first_segment(a, lo);
   int64_t sa = 0, sb = 0;
@@ -285,7 +307,7 @@ __device__ __forceinline__ void seg_wave_slices(const SegArgs& a) {
 #pragma unroll
       for (int u = 0; u < IPT; ++u) acc[u] = M::zero();
       tot = wave_reduce_dpp<OpComp>(tot);
-      finish_piece<BARRIER>(a, s, sa, sb, comp_to_double(tot), lo, hi, w, chunk, &own_fix);
+      finish_piece<FIX>(a, s, sa, sb, comp_to_double(tot), lo, hi, w, chunk, &own_fix);
       ++s;
       have = seek_segment(a, s, hi, E, end_slice, sa, sb, lane == 0);
       A = std::max(sa, lo);
@@ -303,7 +325,7 @@ __device__ __forceinline__ void seg_wave_slices(const SegArgs& a) {
 #pragma unroll
     for (int u = 0; u < IPT; ++u) cur[u] = nxt[u];
   }
-  if constexpr (BARRIER) {
+  if constexpr (FIX == kFixBarrier) {
     grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit);
     if (own_fix >= 0) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -352,7 +374,7 @@ __device__ __forceinline__ int run_swz(int i) {
   return i ^ ((i >> 4) & (IPT - 1));
 }
 
-template <int IPT, bool NT, bool BARRIER>
+template <int IPT, bool NT, int FIX>
 __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all) {
   static_assert(IPT <= 4, "runs of at most 16 values");
   using M = ModeF32Comp;
@@ -369,6 +391,10 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
   const int64_t lo = std::min(w * chunk, E);
   const int64_t hi = std::min(lo + chunk, E);
   const bool end_slice = E > 0 ? (lo < E && hi == E) : (w == 0);
+  // Relaunch fix-up: the slot says "no cut segment starts here" unless a
+  // later store by the same lane replaces it.
+  if constexpr (FIX == kFixRelaunch)
+    if (lane == 0) a.carry_out[w] = SegCarry{-1, 0.0};
 
   int64_t s = first_segment(a, lo);
   int64_t sa = 0, sb = 0;
@@ -500,7 +526,7 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
         if (m > 0) {
           const int r0 = __builtin_amdgcn_readfirstlane(r);
           const int64_t o0 = read_lane(O, 0);
-          finish_piece<BARRIER>(a, s, sa, o0, read_lane(total, r0), lo, hi, w, chunk, &own_fix);
+          finish_piece<FIX>(a, s, sa, o0, read_lane(total, r0), lo, hi, w, chunk, &own_fix);
           sa = read_lane(O, m - 1);
           sb = read_lane(O, m);
           s += m;
@@ -522,7 +548,7 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
 #pragma unroll
         for (int u = 0; u < IPT; ++u) acc[u] = M::zero();
         tot = wave_reduce_dpp<OpComp>(tot);
-        finish_piece<BARRIER>(a, s, sa, sb, C + comp_to_double(tot), lo, hi, w, chunk, &own_fix);
+        finish_piece<FIX>(a, s, sa, sb, C + comp_to_double(tot), lo, hi, w, chunk, &own_fix);
         C = 0.0;
         ++s;
         have = seek_segment(a, s, hi, E, end_slice, sa, sb, lane == 0);
@@ -548,11 +574,11 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
     for (int u = 0; u < IPT; ++u) cur[u] = nxt[u];
   }
   if (have) {  // the segment open at the slice's end ends at or after hi
-    finish_piece<BARRIER>(a, s, sa, sb, C, lo, hi, w, chunk, &own_fix);
+    finish_piece<FIX>(a, s, sa, sb, C, lo, hi, w, chunk, &own_fix);
     ++s;
     seek_segment(a, s, hi, E, end_slice, sa, sb, lane == 0);  // empty segments at E
   }
-  if constexpr (BARRIER) {
+  if constexpr (FIX == kFixBarrier) {
     grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit);
     if (own_fix >= 0) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -579,7 +605,7 @@ struct WorkgroupLds {
   int64_t own_fix;  // barrier form: cut segment this workgroup owns
 };
 
-template <int IPT, bool NT, bool BARRIER>
+template <int IPT, bool NT, int FIX>
 __device__ __forceinline__ void seg_workgroup_slices(const SegArgs& a, WorkgroupLds& lds) {
   using M = ModeF32Comp;
   auto& part = lds.part;
@@ -619,6 +645,10 @@ __device__ __forceinline__ void seg_workgroup_slices(const SegArgs& a, Workgroup
   const int lane = tid % kWave;
   const int nwaves = (int)bs / kWave;
   if (tid == 0) own_fix = -1;
+  // Relaunch fix-up: "no cut segment starts here" unless a store after the
+  // first batch barrier replaces it.
+  if constexpr (FIX == kFixRelaunch)
+    if (tid == 0) a.carry_out[g] = SegCarry{-1, 0.0};
 
   // Completes the batched pieces: wave w finishes pieces w, w + nwaves, ...
   auto flush = [&]() {
@@ -627,7 +657,7 @@ __device__ __forceinline__ void seg_workgroup_slices(const SegArgs& a, Workgroup
       CompF32 v = lane < nwaves ? part[buf][j][lane] : OpComp::zero();
       v = wave_reduce_dpp<OpComp>(v);
       const PieceInfo& pi = info[buf][j];
-      finish_piece<BARRIER>(a, pi.s, pi.sa, pi.sb, comp_to_double(v), lo, hi, g, chunk, &own_fix);
+      finish_piece<FIX>(a, pi.s, pi.sa, pi.sb, comp_to_double(v), lo, hi, g, chunk, &own_fix);
     }
     buf ^= 1;
     nb = 0;
@@ -694,7 +724,7 @@ __device__ __forceinline__ void seg_workgroup_slices(const SegArgs& a, Workgroup
     for (int u = 0; u < IPT; ++u) cur[u] = nxt[u];
   }
   if (nb > 0) flush();
-  if constexpr (BARRIER) {
+  if constexpr (FIX == kFixBarrier) {
     grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit);  // also a workgroup barrier
     const int64_t os = own_fix;
     if (os >= 0 && wave == 0) {
@@ -713,23 +743,48 @@ union SegLds {
   RunLds runs[kSegMaxWG / kWave];
 };
 
-template <int IPT, bool NT, bool BARRIER>
+// The form of a launch: forced, or from the batch's mean segment length
+// (the same decision in every workgroup, and in the fix-up kernel).
+template <int IPT>
+__device__ __forceinline__ int seg_form(const SegArgs& a) {
+  if (a.form != kSegAuto) return a.form;
+  const int64_t E = offset_at(a.offsets, a.nseg);
+  return E >= kWaveSliceMeanLen * a.nseg ? kSegWorkgroup
+         : (IPT <= 4 && E < kRunsMeanLen * a.nseg) ? kSegWaveRuns
+                                                 : kSegWavePieces;
+}
+
+template <int IPT, bool NT, int FIX>
 __global__ __launch_bounds__(kSegMaxWG) void k_segmented(SegArgs a) {
   __shared__ SegLds lds;
-  int form = a.form;
-  if (form == kSegAuto) {  // the same decision in every workgroup
-    const int64_t E = offset_at(a.offsets, a.nseg);
-    form = E >= kWaveSliceMeanLen * a.nseg ? kSegWorkgroup
-           : (IPT <= 4 && E < kRunsMeanLen * a.nseg) ? kSegWaveRuns
-                                                   : kSegWavePieces;
-  }
+  const int form = seg_form<IPT>(a);
   if (form == kSegWorkgroup) {
-    seg_workgroup_slices<IPT, NT, BARRIER>(a, lds.wg);
+    seg_workgroup_slices<IPT, NT, FIX>(a, lds.wg);
   } else if (form == kSegWaveRuns) {
-    if constexpr (IPT <= 4) seg_wave_runs<IPT, NT, BARRIER>(a, lds.runs);
+    if constexpr (IPT <= 4) seg_wave_runs<IPT, NT, FIX>(a, lds.runs);
   } else {
-    seg_wave_slices<IPT, NT, BARRIER>(a);
+    seg_wave_slices<IPT, NT, FIX>(a);
   }
+}
+
+// Relaunch fix-up: wavefront w of this grid looks at slice w of the slice
+// kernel; if a cut segment starts there it sums the segment's pieces in
+// slice order (the same combine as the ticket and barrier fix-ups) and
+// writes it.
+constexpr int kFixupWG = 256;
+
+template <int IPT>
+__global__ __launch_bounds__(kFixupWG) void k_seg_fixup(SegArgs a) {
+  const int64_t W = seg_form<IPT>(a) == kSegWorkgroup ? (int64_t)a.grid : (int64_t)a.grid * (a.wg / kWave);
+  const int64_t w = (int64_t)blockIdx.x * (kFixupWG / kWave) + threadIdx.x / kWave;
+  if (w >= W) return;
+  const int64_t seg = a.carry_out[w].seg;
+  if (seg < 0) return;
+  const int64_t E = offset_at(a.offsets, a.nseg);
+  const int64_t chunk = std::max<int64_t>(64, (((E + W - 1) / W) + 63) & ~(int64_t)63);
+  const int64_t np = (offset_at(a.offsets, seg + 1) - 1) / chunk - w + 1;
+  const double v = combine_pieces(a, w, np);
+  if (__lane_id() == 0) a.out[seg] = v;
 }
 
 namespace {
@@ -737,19 +792,26 @@ namespace {
 int ipt_index(int ipt) { return ipt == 1 ? 0 : ipt == 2 ? 1 : ipt == 4 ? 2 : ipt == 8 ? 3 : -1; }
 
 struct SegTable {
-  const void* k[2][2][4];  // barrier, nontemporal, ipt index
-  template <bool B, bool NT>
+  const void* k[3][2][4];  // SegFix, nontemporal, ipt index
+  const void* fixup[4];    // ipt index
+  template <int F, bool NT>
   void fill() {
-    k[B][NT][0] = reinterpret_cast<const void*>(&k_segmented<1, NT, B>);
-    k[B][NT][1] = reinterpret_cast<const void*>(&k_segmented<2, NT, B>);
-    k[B][NT][2] = reinterpret_cast<const void*>(&k_segmented<4, NT, B>);
-    k[B][NT][3] = reinterpret_cast<const void*>(&k_segmented<8, NT, B>);
+    k[F][NT][0] = reinterpret_cast<const void*>(&k_segmented<1, NT, F>);
+    k[F][NT][1] = reinterpret_cast<const void*>(&k_segmented<2, NT, F>);
+    k[F][NT][2] = reinterpret_cast<const void*>(&k_segmented<4, NT, F>);
+    k[F][NT][3] = reinterpret_cast<const void*>(&k_segmented<8, NT, F>);
   }
   SegTable() {
-    fill<false, false>();
-    fill<false, true>();
-    fill<true, false>();
-    fill<true, true>();
+    fill<kFixTicket, false>();
+    fill<kFixTicket, true>();
+    fill<kFixBarrier, false>();
+    fill<kFixBarrier, true>();
+    fill<kFixRelaunch, false>();
+    fill<kFixRelaunch, true>();
+    fixup[0] = reinterpret_cast<const void*>(&k_seg_fixup<1>);
+    fixup[1] = reinterpret_cast<const void*>(&k_seg_fixup<2>);
+    fixup[2] = reinterpret_cast<const void*>(&k_seg_fixup<4>);
+    fixup[3] = reinterpret_cast<const void*>(&k_seg_fixup<8>);
   }
 };
 
@@ -761,13 +823,17 @@ const SegTable& seg_table() {
 }  // namespace
 
 // Default (measured on MI355X over uniform segment lengths from 16 to
-// 16384 values): two 512-thread workgroups per CU, the most the
-// reduce-by-key form keeps resident, 4 loads of 16 bytes per thread per
+// 65536 values and 10,000 log-uniform ones): the relaunch fix-up, whose
+// slices publish their cut pieces with ordinary stores (a release fence
+// per cut piece writes back the XCD's L2: 768-value segments cut at every
+// one of 4096 slice boundaries took 405 us with tickets, 194 us with the
+// second launch); two 512-thread workgroups per CU, the most the
+// reduce-by-key form keeps resident; 4 loads of 16 bytes per thread per
 // tile.
 red_plan default_seg_plan(int64_t nseg, const DeviceInfo& dev) {
   (void)nseg;
   red_plan p;
-  p.variant = RED_VARIANT_ATOMIC;
+  p.variant = RED_VARIANT_RELAUNCH;
   p.wg = 512;
   p.ipt = 4;
   p.grid = 2 * dev.cus;
@@ -779,7 +845,7 @@ int seg_max_coresident(int ipt, int wg, const DeviceInfo& dev, int* n_wg) {
   const int ii = ipt_index(ipt);
   if (ii < 0) return set_error(RED_EINVAL, "bad ipt %d", ipt);
   int per_cu = 0;
-  RED_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, seg_table().k[1][0][ii], wg, 0));
+  RED_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, seg_table().k[kFixBarrier][0][ii], wg, 0));
   *n_wg = per_cu * dev.cus;
   return RED_OK;
 }
@@ -791,8 +857,9 @@ int seg_launch(const SegLaunch& sl, const float* x, const int64_t* offsets, int6
   if (ii < 0) return set_error(RED_EINVAL, "bad ipt %d", p.ipt);
   if (p.wg > kSegMaxWG) return set_error(RED_EINVAL, "segmented: at most %d threads per workgroup", kSegMaxWG);
   const bool barrier = p.variant == RED_VARIANT_PERSISTENT;
-  if (!barrier && p.variant != RED_VARIANT_ATOMIC)
-    return set_error(RED_EINVAL, "segmented: variant must be ATOMIC (ticket) or PERSISTENT (barrier)");
+  const int fix = barrier ? kFixBarrier : p.variant == RED_VARIANT_RELAUNCH ? kFixRelaunch : kFixTicket;
+  if (!barrier && p.variant != RED_VARIANT_ATOMIC && p.variant != RED_VARIANT_RELAUNCH)
+    return set_error(RED_EINVAL, "segmented: variant must be RELAUNCH, ATOMIC (ticket) or PERSISTENT (barrier)");
   int grid = p.grid > 0 ? p.grid : 4 * dev.cus;
   grid = std::max(1, std::min(grid, RED_MAX_GRID));
   // One carry slot and one ticket per wavefront slice.
@@ -823,11 +890,20 @@ int seg_launch(const SegLaunch& sl, const float* x, const int64_t* offsets, int6
                                               : kSegAuto;
   if (a.form == kSegWaveRuns && p.ipt > 4)
     return set_error(RED_EINVAL, "segmented: the reduce-by-key form takes at most 4 loads per thread");
+  a.grid = grid;
+  a.wg = p.wg;
   void* args[] = {&a};
   const bool nt = (p.flags & RED_FLAG_NONTEMPORAL) != 0;
   const bool coop = barrier && (p.flags & RED_FLAG_PLAIN_LAUNCH) == 0;
   const int slot = timer_begin(s);
-  int rc = launch(seg_table().k[barrier ? 1 : 0][nt ? 1 : 0][ii], grid, p.wg, args, s, coop);
+  int rc = launch(seg_table().k[fix][nt ? 1 : 0][ii], grid, p.wg, args, s, coop);
+  if (rc == RED_OK && fix == kFixRelaunch) {
+    // One wavefront per possible slice (the wavefront-slice count bounds the
+    // workgroup-slice count).
+    const int64_t waves = (int64_t)grid * (p.wg / kWave);
+    const int fix_grid = (int)((waves + kFixupWG / kWave - 1) / (kFixupWG / kWave));
+    rc = launch(seg_table().fixup[ii], fix_grid, kFixupWG, args, s, false);
+  }
   timer_end(s, slot);
   return rc;
 }

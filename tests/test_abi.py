@@ -69,7 +69,7 @@ def test_validation_before_hip(lib):
         two = R.make_opts(flags=f)  # at most one form flag; unknown bits rejected
         assert lib.red_sum_segmented_ex(ctypes.c_void_p(64), ctypes.c_void_p(64), 2, ctypes.c_void_p(64), None,
                                         ctypes.byref(two)) == R.RED_EINVAL
-    seg = R.make_opts(variant=R.RED_VARIANT_RELAUNCH, wg=256, ipt=4)
+    seg = R.make_opts(variant=R.RED_VARIANT_SINGLE, wg=256, ipt=4)
     assert lib.red_sum_segmented_ex(ctypes.c_void_p(64), ctypes.c_void_p(64), 2, ctypes.c_void_p(64), None,
                                     ctypes.byref(seg)) == R.RED_EINVAL
     assert lib.sync_bench_wave(9, 64, 10, None, None, None, None) == R.RED_EINVAL

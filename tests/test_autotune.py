@@ -45,7 +45,7 @@ def test_foreign_arch_and_bad_entries(tmp_path):
          "plan": {"variant": "relaunch", "wg": 100, "ipt": 4, "grid": 0}},  # wg not a multiple of 64
         {"kind": "sum", "dtype": "nope", "acc": "compensated", "n": 77,
          "plan": {"variant": "relaunch", "wg": 256, "ipt": 4, "grid": 0}},
-        {"kind": "segmented", "nseg": 5, "plan": {"variant": "relaunch", "wg": 256, "ipt": 4, "grid": 0}},
+        {"kind": "segmented", "nseg": 5, "plan": {"variant": "single", "wg": 256, "ipt": 4, "grid": 0}},
         {"kind": "sum", "dtype": "i32", "acc": "compensated", "n": 77,
          "plan": {"variant": "persistent", "wg": 512, "ipt": 2, "grid": 64}},
     ]}))

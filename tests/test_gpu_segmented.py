@@ -42,7 +42,8 @@ def check(res, x, off):
 
 PLANS = [dict(), dict(variant=2, wg=256, ipt=1, grid=7), dict(variant=2, wg=512, ipt=8, grid=1),
          dict(variant=2, wg=64, ipt=2, grid=300), dict(variant=3, wg=256, ipt=4, grid=64),
-         dict(variant=2, wg=512, ipt=4, grid=0, flags=2)]
+         dict(variant=2, wg=512, ipt=4, grid=0, flags=2), dict(variant=1, wg=256, ipt=2, grid=50),
+         dict(variant=1, wg=512, ipt=8, grid=3, flags=2)]
 
 
 @pytest.mark.parametrize("plan", range(len(PLANS)))
@@ -72,7 +73,8 @@ def test_long_segment_batches(lib, plan):
 
 FORM_PLANS = [dict(variant=2, wg=512, ipt=4, grid=0), dict(variant=2, wg=256, ipt=4, grid=7),
               dict(variant=2, wg=64, ipt=1, grid=300), dict(variant=2, wg=128, ipt=2, grid=33),
-              dict(variant=3, wg=256, ipt=2, grid=64)]
+              dict(variant=3, wg=256, ipt=2, grid=64), dict(variant=1, wg=512, ipt=4, grid=0),
+              dict(variant=1, wg=64, ipt=1, grid=1000)]
 
 
 def form_layouts():
@@ -163,6 +165,25 @@ def test_runs_form_repeat_bit_identical(lib):
             check(got, x, off)
             first = got
         assert np.array_equal(got, first), i
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3])
+def test_fixups_agree_bit_for_bit(lib, variant):
+    """Segments cut by many slice boundaries (768-value segments over 4096
+    wavefront slices, and one segment across every slice): the relaunch,
+    ticket and barrier fix-ups sum the pieces in the same order, so they
+    give the same bits; all match the oracle."""
+    for name, lens in (("uniform768", np.full(3000, 768, dtype=np.int64)),
+                       ("one_long", np.array([0, 2000003, 0], dtype=np.int64)),
+                       ("drawn", inputs.segment_lengths(300, max_len=1 << 15))):
+        off = inputs.offsets_from_lengths(lens.astype(np.int64))
+        x = inputs.mixed_f32(int(off[-1]), sub=18)
+        val, tol = expected(name, x, off)
+        grid = 64 if variant == 3 else 512
+        got = run(lib, x, off, variant=variant, wg=512, ipt=4, grid=grid)
+        check_fast(got, val, tol, (name, variant))
+        ref = run(lib, x, off, variant=1, wg=512, ipt=4, grid=grid)
+        assert np.array_equal(got, ref), name
 
 
 def test_runs_form_rejects_eight_loads(lib):
