@@ -283,6 +283,45 @@ def test_full_batch_config(lib):
         check(res, x, off)
 
 
+@pytest.mark.parametrize("L", [64, 768])
+def test_full_size_uniform_segments(lib, L):
+    """2^28 N(0,1) values in segments of 64 values (reduce-by-key form, 4M
+    segments) and of 768 values (a segment cut at every slice edge), default
+    plan through the graph path: 3000 sampled segments against the oracle's
+    exact sums, every segment within 1e-12 of its sum of magnitudes of a
+    binary64 row sum, and the ticket fix-up bit-identical."""
+    n = (1 << 28) // L * L
+    x = inputs.normal_f32(1 << 28, sub=19)[:n]
+    nseg = n // L
+    xt = torch.from_numpy(x).to("cuda")
+    ot = torch.arange(0, n + 1, L, dtype=torch.int64, device="cuda")
+    out = torch.full((nseg,), float("nan"), dtype=torch.float64, device="cuda")
+    say("full-size uniform segments", L, nseg)
+    lib.red_sum_segmented(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), lib.current_stream())
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    rows = x.reshape(nseg, L)
+    approx = rows.astype(np.float64).sum(axis=1)
+    mag = np.abs(rows).astype(np.float64).sum(axis=1)
+    bad = np.nonzero(~(np.abs(got - approx) <= 1e-12 * mag))[0]
+    assert bad.size == 0, (int(bad[0]), got[bad[0]], approx[bad[0]])
+    pick = np.random.default_rng(800 + L).choice(nseg, 3000, replace=False)
+    for k in pick:
+        ex = oracle.exact_sum(rows[k], "f32")
+        assert oracle.rel_err(float(got[k]), ex) <= BOUND, (k, got[k], ex.value)
+    ticket = torch.full((nseg,), float("nan"), dtype=torch.float64, device="cuda")
+    lib.red_sum_segmented_ex(xt.data_ptr(), ot.data_ptr(), nseg, ticket.data_ptr(), lib.current_stream(),
+                             lib.make_opts(variant=2, wg=512, ipt=4, grid=512, flags=lib.FLAG_NONTEMPORAL))
+    torch.cuda.synchronize()
+    p = lib.red_get_segmented_plan(nseg)
+    if (p.variant, p.wg, p.ipt, p.grid) == (1, 512, 4, 512):
+        assert np.array_equal(ticket.cpu().numpy(), got)
+    else:
+        check_fast(ticket.cpu().numpy(), approx, 1e-12 * mag, "ticket")
+    del xt, ot, out, ticket
+    torch.cuda.empty_cache()
+
+
 def test_graph_cache_eviction(lib):
     """More distinct batches than the graph cache holds (64): the oldest
     graphs are evicted (after their stream drains) and rebuilt on reuse;
