@@ -29,6 +29,7 @@
 // without barriers and suit short ones.  Empty segments write 0.  The
 // result is deterministic for a given grid and workgroup size.
 #include <algorithm>
+#include <type_traits>
 
 #include "device_prims.h"
 #include "internal.h"
@@ -378,7 +379,6 @@ template <int IPT, bool NT, int FIX>
 __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all) {
   static_assert(IPT <= 4, "runs of at most 16 values");
   using M = ModeF32Comp;
-  constexpr int RL = 4 * IPT;  // values per lane run
   const int nwaves = blockDim.x / kWave;
   const int lane = __lane_id();
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -408,15 +408,23 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
   constexpr int64_t T = kWave * IPT;
   const int64_t ntiles = lo < hi ? (vhi - vlo + T - 1) / T : 0;
 
-  // Offsets window: entry j is offsets[wb + j] (INT64_MAX past nseg).
+  // Offsets window: entry j of four 64-entry blocks is offsets[wb + j]
+  // (INT64_MAX past nseg).  A (sub-)tile views entries j0 .. j0 + 63 of
+  // the first three; the fourth is in flight.
   auto off_entry = [&](int64_t i) -> int64_t { return i <= nseg ? a.offsets[i] : INT64_MAX; };
-  int64_t wb = s + 1;
-  int64_t win0 = 0, win1 = 0, win2 = 0;
-  if (have) {
+  int64_t wb = 0;
+  int64_t win0 = 0, win1 = 0, win2 = 0, win3 = 0;
+  auto reload = [&]() {
+    wb = s + 1;
     win0 = off_entry(wb + lane);
     win1 = off_entry(wb + kWave + lane);
     win2 = off_entry(wb + 2 * kWave + lane);
-  }
+    win3 = off_entry(wb + 3 * kWave + lane);
+  };
+  if (have) reload();
+  // Batches whose mean segment is under 32 values walk each tile as two
+  // halves of IPT/2 rows, so that a half holds fewer than 64 starts.
+  const bool halves = IPT >= 2 && E < 32 * nseg;
 
   v4f cur[IPT], nxt[IPT];
   auto load_tile = [&](v4f* v, int64_t t) {
@@ -435,20 +443,21 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
   if (ntiles > 0) load_tile(cur, 0);
   for (int64_t t = 0; t < ntiles; ++t) {
     // Every load has completed here (see seg_wave_slices), so the window
-    // registers move without a wait.
+    // blocks move without a wait.
     __builtin_amdgcn_s_waitcnt(0);
     if (have) {
-      const int64_t j0 = s + 1 - wb;
-      if (j0 >= 2 * kWave) {  // after a long stretch finished piece by piece
-        wb = s + 1;
-        win0 = off_entry(wb + lane);
-        win1 = off_entry(wb + kWave + lane);
-        win2 = off_entry(wb + 2 * kWave + lane);
-      } else if (j0 >= kWave) {
-        win0 = win1;
-        win1 = win2;
-        wb += kWave;
-        win2 = off_entry(wb + 2 * kWave + lane);
+      int64_t j0 = s + 1 - wb;
+      if (j0 >= 3 * kWave) {  // after a long stretch finished piece by piece
+        reload();
+      } else {
+        while (j0 >= kWave) {
+          win0 = win1;
+          win1 = win2;
+          win2 = win3;
+          wb += kWave;
+          win3 = off_entry(wb + 3 * kWave + lane);
+          j0 -= kWave;
+        }
       }
     }
     if (t + 1 < ntiles) load_tile(nxt, t + 1);
@@ -456,90 +465,96 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
     const int64_t e0 = 4 * (vlo + t * T) - shift;
     const int64_t e1 = 4 * (vlo + (t + 1) * T) - shift;
 
-    // Segment starts in the tile, from the window.
-    bool fast = false, valid = false;
-    int64_t O = 0;
-    int m = 0, rel = 0, r = 0;
-    if (have) {
-      const int64_t tend = std::min(e1, hi);
-      const int j0 = (int)(s + 1 - wb);  // 0 .. 63
-      const int src = (j0 + lane) & (kWave - 1);
-      const int64_t p0 = bpermute_move(win0, src), p1 = bpermute_move(win1, src);
-      O = j0 + lane < kWave ? p0 : p1;  // start of segment s + 1 + lane
-      valid = O < tend;
-      m = __popcll(__ballot(valid));  // the valid lanes are 0 .. m-1
-      rel = valid ? (int)(O - e0) : 0;
-      r = rel / RL;  // lane whose run holds start `lane`
+    // Reduce-by-key walk over rows [Q RS, Q RS + RS) of the tile (values
+    // [f0, f1)); returns false, having changed nothing, when the rows need
+    // the per-piece walk.
+    auto try_runs = [&](auto rs_tag, auto q_tag) -> bool {
+      constexpr int RS = decltype(rs_tag)::value;
+      constexpr int Q = decltype(q_tag)::value;
+      constexpr int RL = 4 * RS;  // values per lane run
+      const int64_t f0 = e0 + (int64_t)kWave * RL * Q;
+      const int64_t f1 = f0 + (int64_t)kWave * RL;
+      const int64_t j0l = s + 1 - wb;
+      if (j0l > 2 * kWave) return false;  // the view would pass the third block
+      const int j0 = (int)j0l;
+      const int idx = j0 + lane;
+      const int src = idx & (kWave - 1);
+      const int64_t p0 = bpermute_move(win0, src), p1 = bpermute_move(win1, src), p2 = bpermute_move(win2, src);
+      const int64_t O = idx < kWave ? p0 : idx < 2 * kWave ? p1 : p2;  // start of segment s + 1 + lane
+      const bool valid = O < std::min(f1, hi);
+      const int m = __popcll(__ballot(valid));  // the valid lanes are 0 .. m-1
+      const int rel = valid ? (int)(O - f0) : 0;
+      const int r = rel / RL;  // lane whose run holds start `lane`
       const int rn = __builtin_amdgcn_ds_bpermute(((lane + 1) & (kWave - 1)) << 2, r);
       const bool clash = valid && lane + 1 < m && rn == r;
-      fast = m < kWave && __ballot(clash) == 0;
-    }
-    if (fast) {
-      {
-        // Start k (lane k) tells lane r_k where it lies.
-        volatile unsigned* slot = L.slot;
-        slot[lane] = 0u;
-        if (valid) slot[r] = ((unsigned)(lane + 1) << 16) | (unsigned)rel;
-        const unsigned word = slot[lane];
-        // Transpose: row u of the tile in, run of RL values out.
+      if (m >= kWave || __ballot(clash) != 0) return false;
+      // Start k (lane k) tells lane r_k where it lies.
+      volatile unsigned* slot = L.slot;
+      slot[lane] = 0u;
+      if (valid) slot[r] = ((unsigned)(lane + 1) << 16) | (unsigned)rel;
+      const unsigned word = slot[lane];
+      // Transpose: row u of the rows in, a run of RL values out.
 #pragma unroll
-        for (int u = 0; u < IPT; ++u) L.tile[run_swz<IPT>(u * kWave + lane)] = cur[u];
-        __builtin_amdgcn_wave_barrier();
-        float xr[RL];
+      for (int u = 0; u < RS; ++u) L.tile[run_swz<RS>(u * kWave + lane)] = cur[Q * RS + u];
+      __builtin_amdgcn_wave_barrier();
+      float xr[RL];
 #pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-          const v4f y = L.tile[run_swz<IPT>(lane * IPT + j)];
-          xr[4 * j] = y.x;
-          xr[4 * j + 1] = y.y;
-          xr[4 * j + 2] = y.z;
-          xr[4 * j + 3] = y.w;
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (e0 < lo || e1 > hi) {  // first or last tile: values outside the slice are not its own
-          const int64_t p = e0 + (int64_t)RL * lane;
-#pragma unroll
-          for (int i = 0; i < RL; ++i) xr[i] = (p + i >= lo && p + i < hi) ? xr[i] : 0.0f;
-        }
-        const bool has = word != 0u;
-        const int b = has ? (int)(word & 0xFFFFu) - RL * lane : RL;  // the start's place in the run
-        CompF32 run = M::zero(), head = M::zero();
-#pragma unroll
-        for (int i = 0; i < RL; ++i) {
-          if (i > 0) {
-            const bool at = i == b;
-            head.s = at ? run.s : head.s;
-            head.c = at ? run.c : head.c;
-            run.s = at ? 0.0f : run.s;
-            run.c = at ? 0.0f : run.c;
-          }
-          M::add_elem(run, xr[i]);
-        }
-        double v = comp_to_double(run);
-        int f = has ? 1 : 0;
-        wave_segscan(v, f);
-        if (!f) v = C + v;  // lanes 0 .. l hold no start: the open segment continues
-        const double left = bpermute_move(v, (lane - 1) & (kWave - 1));
-        const double total = (lane == 0 ? C : left) + comp_to_double(head);
-        const int k = (int)(word >> 16) - 1;
-        if (has && k > 0 && k < m) a.out[s + k] = total;  // segment s + k lies in the tile
-        const double c_next = read_lane(v, kWave - 1);
-        if (m > 0) {
-          const int r0 = __builtin_amdgcn_readfirstlane(r);
-          const int64_t o0 = read_lane(O, 0);
-          finish_piece<FIX>(a, s, sa, o0, read_lane(total, r0), lo, hi, w, chunk, &own_fix);
-          sa = read_lane(O, m - 1);
-          sb = read_lane(O, m);
-          s += m;
-        }
-        C = c_next;
+      for (int jj = 0; jj < RS; ++jj) {
+        const v4f y = L.tile[run_swz<RS>(lane * RS + jj)];
+        xr[4 * jj] = y.x;
+        xr[4 * jj + 1] = y.y;
+        xr[4 * jj + 2] = y.z;
+        xr[4 * jj + 3] = y.w;
       }
-    } else if (have) {
-      // Piece by piece, as in seg_wave_slices, with the open partial C.
+      __builtin_amdgcn_wave_barrier();
+      if (f0 < lo || f1 > hi) {  // values outside the slice are not its own
+        const int64_t p = f0 + (int64_t)RL * lane;
+#pragma unroll
+        for (int i = 0; i < RL; ++i) xr[i] = (p + i >= lo && p + i < hi) ? xr[i] : 0.0f;
+      }
+      const bool has = word != 0u;
+      const int b = has ? (int)(word & 0xFFFFu) - RL * lane : RL;  // the start's place in the run
+      CompF32 run = M::zero(), head = M::zero();
+#pragma unroll
+      for (int i = 0; i < RL; ++i) {
+        if (i > 0) {
+          const bool at = i == b;
+          head.s = at ? run.s : head.s;
+          head.c = at ? run.c : head.c;
+          run.s = at ? 0.0f : run.s;
+          run.c = at ? 0.0f : run.c;
+        }
+        M::add_elem(run, xr[i]);
+      }
+      double v = comp_to_double(run);
+      int f = has ? 1 : 0;
+      wave_segscan(v, f);
+      if (!f) v = C + v;  // lanes 0 .. l hold no start: the open segment continues
+      const double left = bpermute_move(v, (lane - 1) & (kWave - 1));
+      const double total = (lane == 0 ? C : left) + comp_to_double(head);
+      const int k = (int)(word >> 16) - 1;
+      if (has && k > 0 && k < m) a.out[s + k] = total;  // segment s + k lies in the rows
+      const double c_next = read_lane(v, kWave - 1);
+      if (m > 0) {
+        const int r0 = __builtin_amdgcn_readfirstlane(r);
+        const int64_t o0 = read_lane(O, 0);
+        finish_piece<FIX>(a, s, sa, o0, read_lane(total, r0), lo, hi, w, chunk, &own_fix);
+        sa = read_lane(O, m - 1);
+        sb = read_lane(O, m);
+        s += m;
+      }
+      C = c_next;
+      return true;
+    };
+
+    // Piece by piece, as in seg_wave_slices, over the tile's values from p0
+    // on, with the open partial C.
+    auto pieces_from = [&](int64_t p0) {
       CompF32 acc[IPT];
 #pragma unroll
       for (int u = 0; u < IPT; ++u) acc[u] = M::zero();
       auto relp = [&](int64_t e) { return (int)std::min(std::max(e - e0, (int64_t)0), 4 * T); };
-      int64_t A = std::max(sa, lo), B = std::min(sb, hi);
+      int64_t A = std::max(std::max(sa, lo), p0), B = std::min(sb, hi);
       while (have && B <= e1) {
         add_masked<IPT>(acc, cur, kWave, lane, relp(A), relp(B));
         CompF32 tot = acc[0];
@@ -568,6 +583,25 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
 #pragma unroll
         for (int u = 0; u < IPT; ++u) acc[u] = M::zero();
         C += comp_to_double(wave_reduce_dpp<OpComp>(tot));
+      }
+    };
+
+    if (have) {
+      using Full = std::integral_constant<int, IPT>;
+      using Half = std::integral_constant<int, (IPT >= 2 ? IPT / 2 : 1)>;
+      using Q0 = std::integral_constant<int, 0>;
+      using Q1 = std::integral_constant<int, 1>;
+      if constexpr (IPT >= 2) {
+        if (halves) {
+          if (!try_runs(Half{}, Q0{}))
+            pieces_from(e0);
+          else if (!try_runs(Half{}, Q1{}))
+            pieces_from(e0 + (int64_t)kWave * 4 * (IPT / 2));
+        } else if (!try_runs(Full{}, Q0{})) {
+          pieces_from(e0);
+        }
+      } else {
+        if (!try_runs(Full{}, Q0{})) pieces_from(e0);
       }
     }
 #pragma unroll
