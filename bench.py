@@ -604,7 +604,7 @@ def run_configs(R, dev, stream, path, plans):
         ms_graph = timed(lambda: R.red_sum_segmented(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh), 30)
         graph_stats = dict(last)
         o = R.make_opts(variant=R.RED_VARIANT_PERSISTENT, wg=plan.wg, ipt=plan.ipt,
-                        grid=min(plan.grid, R.red_max_coresident(plan.wg)),
+                        grid=min(plan.grid, R.red_max_coresident_segmented(plan.ipt, plan.wg)),
                         flags=R.FLAG_PLAIN_LAUNCH | (plan.flags & R.FLAG_NONTEMPORAL))
         ms_barrier = timed(lambda: R.red_sum_segmented_ex(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh, o),
                            30)

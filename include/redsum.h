@@ -387,6 +387,12 @@ int sync_check_watchdog(int n_wg, int wg_size, int skip_wg, int spin_limit, void
  * persistent reduction kernel (occupancy x compute units). */
 int red_max_coresident(int wg_size, int32_t *n_wg);
 
+/* Largest number of co-resident workgroups of wg_size threads (at most
+ * 512) for the segmented kernel with `ipt` loads per thread: the grid
+ * limit of the RED_VARIANT_PERSISTENT (grid barrier) fix-up of
+ * red_sum_segmented_ex.  Errors: RED_EINVAL, RED_ENODEV, RED_EHIP. */
+int red_max_coresident_segmented(int ipt, int wg_size, int32_t *n_wg);
+
 /* Device facts: compute units, wall-clock rate (kHz), shader clock (kHz),
  * L2 bytes (per XCD), HBM bytes, number of XCDs.  Any pointer may be NULL. */
 int red_device_info(int32_t *cus, int64_t *wallclock_khz, int64_t *clock_khz, int64_t *l2_bytes,

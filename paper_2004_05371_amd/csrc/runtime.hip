@@ -509,6 +509,17 @@ int red_max_coresident(int wg_size, int32_t* n_wg) {
   return RED_OK;
 }
 
+int red_max_coresident_segmented(int ipt, int wg_size, int32_t* n_wg) {
+  if (!n_wg || wg_size < 64 || wg_size > 512 || wg_size % 64) return set_error(RED_EINVAL, "bad arguments");
+  const DeviceInfo* dev;
+  int rc = ensure_device(&dev);
+  if (rc) return rc;
+  int n = 0;
+  if ((rc = seg_max_coresident(ipt, wg_size, *dev, &n))) return rc;
+  *n_wg = n;
+  return RED_OK;
+}
+
 int red_device_info(int32_t* cus, int64_t* wallclock_khz, int64_t* clock_khz, int64_t* l2_bytes,
                     int64_t* hbm_bytes, int32_t* nxcc) {
   const DeviceInfo* dev;

@@ -48,7 +48,8 @@ EXPORTS = [
     "red_autotune_segmented", "red_set_segmented_plan", "red_get_segmented_plan",
     "red_kernel_timer", "red_kernel_timer_read", "sync_bench_wave", "sync_bench_wave_ex", "sync_bench_block",
     "sync_bench_grid", "sync_bench_grid_ex", "sync_bench_relaunch", "sync_check_grid_order",
-    "sync_check_watchdog", "sync_xcc_map", "red_max_coresident", "red_device_info",
+    "sync_check_watchdog", "sync_xcc_map", "red_max_coresident", "red_max_coresident_segmented",
+    "red_device_info",
     "red_bw_proxy", "red_eq6_overhead", "red_eq7_latency", "red_eq8_sigma", "stencil_jacobi_1d",
 ]
 
@@ -106,6 +107,7 @@ _SIGS = {
     "sync_check_grid_order": ([_i32, _i32, _i64p, _i64p, _vp], _i32),
     "sync_check_watchdog": ([_i32, _i32, _i32, _i32, _vp], _i32),
     "red_max_coresident": ([_i32, _i32p], _i32),
+    "red_max_coresident_segmented": ([_i32, _i32, _i32p], _i32),
     "red_device_info": ([_i32p, _i64p, _i64p, _i64p, _i64p, _i32p], _i32),
     "sync_xcc_map": ([_i32, _i32, _i32p, _vp], _i32),
     "red_bw_proxy": ([_vp, _i64, _i32, _i32, _vp], _i32),
@@ -302,6 +304,12 @@ def sync_check_watchdog(n_wg: int, wg_size: int = 64, skip_wg: int = 1, spin_lim
 def red_max_coresident(wg_size: int) -> int:
     n = ctypes.c_int32()
     _check(load().red_max_coresident(wg_size, ctypes.byref(n)), "red_max_coresident")
+    return n.value
+
+
+def red_max_coresident_segmented(ipt: int, wg_size: int) -> int:
+    n = ctypes.c_int32()
+    _check(load().red_max_coresident_segmented(ipt, wg_size, ctypes.byref(n)), "red_max_coresident_segmented")
     return n.value
 
 

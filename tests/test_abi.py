@@ -72,6 +72,9 @@ def test_validation_before_hip(lib):
     seg = R.make_opts(variant=R.RED_VARIANT_SINGLE, wg=256, ipt=4)
     assert lib.red_sum_segmented_ex(ctypes.c_void_p(64), ctypes.c_void_p(64), 2, ctypes.c_void_p(64), None,
                                     ctypes.byref(seg)) == R.RED_EINVAL
+    n = ctypes.c_int32()
+    assert lib.red_max_coresident_segmented(4, 1024, ctypes.byref(n)) == R.RED_EINVAL  # segmented: <= 512
+    assert lib.red_max_coresident_segmented(4, 100, ctypes.byref(n)) == R.RED_EINVAL
     assert lib.sync_bench_wave(9, 64, 10, None, None, None, None) == R.RED_EINVAL
     assert lib.sync_bench_wave_ex(0, 5, 64, 10, None, None, None, None) == R.RED_EINVAL
     assert lib.sync_bench_wave_ex(4, 0, 64, 10, None, None, None, None) == R.RED_EINVAL

@@ -186,6 +186,21 @@ def test_fixups_agree_bit_for_bit(lib, variant):
         assert np.array_equal(got, ref), name
 
 
+@pytest.mark.parametrize("ipt,wg", [(2, 512), (4, 512), (8, 256)])
+def test_barrier_fixup_at_the_coresident_limit(lib, ipt, wg):
+    """The grid-barrier fix-up runs at exactly the co-resident grid the
+    library reports for the segmented kernel and refuses one workgroup
+    more."""
+    g = lib.red_max_coresident_segmented(ipt, wg)
+    assert g >= 256
+    lens = np.random.default_rng(900 + ipt).integers(0, 3000, 2000)
+    off = inputs.offsets_from_lengths(lens.astype(np.int64))
+    x = inputs.mixed_f32(int(off[-1]), sub=20)
+    check(run(lib, x, off, variant=3, wg=wg, ipt=ipt, grid=g), x, off)
+    with pytest.raises(lib.RedError):
+        run(lib, x, off, variant=3, wg=wg, ipt=ipt, grid=g + 1)
+
+
 def test_runs_form_rejects_eight_loads(lib):
     off = np.array([0, 4], dtype=np.int64)
     x = np.ones(4, dtype=np.float32)
