@@ -1,4 +1,4 @@
-// Batched segmented sum reduction in one persistent launch (gfx950).
+// Batched segmented sum reduction over a fixed grid (gfx950).
 //
 // The paper's persistent-kernel reduction (Section VII-C, explicit
 // synchronization) keeps one grid of blocks alive for the whole job.  Here a
@@ -12,22 +12,26 @@
 //     (read through the scalar cache), then streams its values as one
 //     sequence of tiles of 16-byte vectors (the next tile in flight while
 //     the current one is added into fp32 TwoSum-compensated accumulators);
-//   * a piece of a segment that ends in a tile is finished while the next
-//     tile is in flight: by a DPP wavefront combine (wavefront slices), or
-//     by a wavefront combine per wave whose results are completed in
-//     batches of 64 pieces after one workgroup barrier (workgroup slices);
+//   * the segments are finished in one of three forms, chosen on the device
+//     from the mean segment length: a piece that ends in a tile is finished
+//     by a wavefront combine per wave, completed in batches of 64 pieces
+//     after one workgroup barrier (workgroup slices); by one DPP wavefront
+//     combine (wavefront slices); or, for very short segments, the wavefront
+//     reduces by key over per-lane runs of consecutive values with a
+//     segmented scan across its lanes (seg_wave_runs);
 //   * a segment that lies inside the slice is written directly (binary64);
 //     a piece of a segment that crosses a slice boundary goes to a carry
 //     slot, and the pieces of that segment are summed in slice order in
-//     binary64, either by the wavefront that publishes the last piece
-//     (atomic ticket per owning slice; no co-residency needed,
-//     graph-capturable) or, in the cooperative form, by the owning slice
-//     after a grid barrier.
+//     binary64 by one wavefront: in a second kernel after the launch
+//     boundary (relaunch fix-up), by the wavefront that publishes the last
+//     piece (atomic ticket per owning slice), or by the owning slice after a
+//     grid barrier (co-resident grid).
 //
 // Workgroup slices keep few concurrent streams (better DRAM locality) and
 // suit long segments; wavefront slices let every wave walk its own pieces
 // without barriers and suit short ones.  Empty segments write 0.  The
-// result is deterministic for a given grid and workgroup size.
+// result is deterministic for a given grid and workgroup size, and the
+// three fix-ups give the same bits.
 #include <algorithm>
 #include <type_traits>
 
