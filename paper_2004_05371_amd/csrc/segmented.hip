@@ -365,9 +365,12 @@ __device__ __forceinline__ void seg_wave_slices(const SegArgs& a) {
 // Other tiles (an empty segment, two starts in one run, 64 starts or more)
 // are finished piece by piece as in seg_wave_slices, the open partial
 // carried in binary64 between the two.
+constexpr int kRing = 384;  // offsets entries held in LDS per wavefront
+
 struct RunLds {
-  v4f tile[kWave * 4];  // one tile of up to 4 rows, swizzled
-  unsigned slot[kWave]; // per lane run: (k + 1) << 16 | tile position of start k, or 0
+  v4f tile[kWave * 4];   // one tile of up to 4 rows, swizzled
+  unsigned slot[kWave];  // per lane run: (k + 1) << 16 | tile position of start k, or 0
+  int64_t ring[kRing];   // offsets[i] at i mod kRing, for i in [fill - kRing, fill)
 };
 
 // Position of vector i of the transposition buffer: within each group of 16
@@ -412,23 +415,44 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
   constexpr int64_t T = kWave * IPT;
   const int64_t ntiles = lo < hi ? (vhi - vlo + T - 1) / T : 0;
 
-  // Offsets window: entry j of four 64-entry blocks is offsets[wb + j]
-  // (INT64_MAX past nseg).  A (sub-)tile views entries j0 .. j0 + 63 of
-  // the first three; the fourth is in flight.
+  // Offsets ring in LDS: entry i mod kRing holds offsets[i] (INT64_MAX
+  // past nseg) for i in [fill - kRing, fill).  At the top of a tile, when
+  // every load has completed, the blocks of 64 entries loaded at the top of
+  // the previous tile are written, and up to three more are requested, as
+  // many as fit without overwriting entries from s + 1 on.  A (sub-)tile
+  // reads entries s + 1 .. s + 64, those that are in the ring.
   auto off_entry = [&](int64_t i) -> int64_t { return i <= nseg ? a.offsets[i] : INT64_MAX; };
-  int64_t wb = 0;
-  int64_t win0 = 0, win1 = 0, win2 = 0, win3 = 0;
-  auto reload = [&]() {
-    wb = s + 1;
-    win0 = off_entry(wb + lane);
-    win1 = off_entry(wb + kWave + lane);
-    win2 = off_entry(wb + 2 * kWave + lane);
-    win3 = off_entry(wb + 3 * kWave + lane);
+  volatile int64_t* ring = L.ring;
+  int64_t fill = 0;
+  int npend = 0;
+  int64_t pend0 = 0, pend1 = 0, pend2 = 0;
+  auto ring_pos = [&](int64_t i) {  // i mod kRing for entry i = base + lane
+    const int h = (int)(__builtin_amdgcn_readfirstlane((int)((i - lane) % kRing))) + lane;
+    return h >= kRing ? h - kRing : h;
   };
-  if (have) reload();
-  // Batches whose mean segment is under 32 values walk each tile as two
-  // halves of IPT/2 rows, so that a half holds fewer than 64 starts.
-  const bool halves = IPT >= 2 && E < 32 * nseg;
+  auto put = [&](int64_t v, int64_t base) { ring[ring_pos(base + lane)] = v; };
+  auto refill = [&]() {
+    if (npend > 0) put(pend0, fill);
+    if (npend > 1) put(pend1, fill + kWave);
+    if (npend > 2) put(pend2, fill + 2 * kWave);
+    fill += (int64_t)npend * kWave;
+    npend = 0;
+    if (fill - (s + 1) < kWave) {  // first tile, or after a long stretch walked piece by piece
+      fill = s + 1;
+      put(off_entry(fill + lane), fill);
+      put(off_entry(fill + kWave + lane), fill + kWave);
+      put(off_entry(fill + 2 * kWave + lane), fill + 2 * kWave);
+      fill += 3 * kWave;
+    }
+    npend = (int)std::min<int64_t>(3, (kRing - (fill - (s + 1))) / kWave);
+    if (npend > 0) pend0 = off_entry(fill + lane);
+    if (npend > 1) pend1 = off_entry(fill + kWave + lane);
+    if (npend > 2) pend2 = off_entry(fill + 2 * kWave + lane);
+  };
+  // Batches whose mean segment is short walk each tile in parts of fewer
+  // rows, so that a part holds fewer than 64 starts: halves under a mean of
+  // 32 values, quarters (4 loads per thread) under 12.
+  const int nparts = (IPT >= 4 && E < 12 * nseg) ? 4 : (IPT >= 2 && E < 32 * nseg) ? 2 : 1;
 
   v4f cur[IPT], nxt[IPT];
   auto load_tile = [&](v4f* v, int64_t t) {
@@ -449,21 +473,7 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
     // Every load has completed here (see seg_wave_slices), so the window
     // blocks move without a wait.
     __builtin_amdgcn_s_waitcnt(0);
-    if (have) {
-      int64_t j0 = s + 1 - wb;
-      if (j0 >= 3 * kWave) {  // after a long stretch finished piece by piece
-        reload();
-      } else {
-        while (j0 >= kWave) {
-          win0 = win1;
-          win1 = win2;
-          win2 = win3;
-          wb += kWave;
-          win3 = off_entry(wb + 3 * kWave + lane);
-          j0 -= kWave;
-        }
-      }
-    }
+    if (have) refill();
     if (t + 1 < ntiles) load_tile(nxt, t + 1);
     __builtin_amdgcn_sched_barrier(0);
     const int64_t e0 = 4 * (vlo + t * T) - shift;
@@ -478,20 +488,19 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
       constexpr int RL = 4 * RS;  // values per lane run
       const int64_t f0 = e0 + (int64_t)kWave * RL * Q;
       const int64_t f1 = f0 + (int64_t)kWave * RL;
-      const int64_t j0l = s + 1 - wb;
-      if (j0l > 2 * kWave) return false;  // the view would pass the third block
-      const int j0 = (int)j0l;
-      const int idx = j0 + lane;
-      const int src = idx & (kWave - 1);
-      const int64_t p0 = bpermute_move(win0, src), p1 = bpermute_move(win1, src), p2 = bpermute_move(win2, src);
-      const int64_t O = idx < kWave ? p0 : idx < 2 * kWave ? p1 : p2;  // start of segment s + 1 + lane
+      // Entries s + 1 .. s + vis are in the ring; a view of fewer than 64
+      // must end past the rows to show every start in them.
+      const int vis = (int)std::min<int64_t>(kWave, fill - (s + 1));
+      if (vis <= 0) return false;
+      const int64_t O = lane < vis ? ring[ring_pos(s + 1 + lane)] : INT64_MAX;  // start of segment s + 1 + lane
       const bool valid = O < std::min(f1, hi);
       const int m = __popcll(__ballot(valid));  // the valid lanes are 0 .. m-1
+      if (m >= vis) return false;
       const int rel = valid ? (int)(O - f0) : 0;
       const int r = rel / RL;  // lane whose run holds start `lane`
       const int rn = __builtin_amdgcn_ds_bpermute(((lane + 1) & (kWave - 1)) << 2, r);
       const bool clash = valid && lane + 1 < m && rn == r;
-      if (m >= kWave || __ballot(clash) != 0) return false;
+      if (__ballot(clash) != 0) return false;
       // Start k (lane k) tells lane r_k where it lies.
       volatile unsigned* slot = L.slot;
       slot[lane] = 0u;
@@ -591,21 +600,47 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
     };
 
     if (have) {
-      using Full = std::integral_constant<int, IPT>;
-      using Half = std::integral_constant<int, (IPT >= 2 ? IPT / 2 : 1)>;
       using Q0 = std::integral_constant<int, 0>;
       using Q1 = std::integral_constant<int, 1>;
-      if constexpr (IPT >= 2) {
-        if (halves) {
-          if (!try_runs(Half{}, Q0{}))
-            pieces_from(e0);
-          else if (!try_runs(Half{}, Q1{}))
-            pieces_from(e0 + (int64_t)kWave * 4 * (IPT / 2));
-        } else if (!try_runs(Full{}, Q0{})) {
+      using Q2 = std::integral_constant<int, 2>;
+      using Q3 = std::integral_constant<int, 3>;
+      // Parts of RS rows in order; the first part that cannot take the
+      // reduce-by-key walk, and the rest of the tile, go piece by piece.
+      auto one = [&](auto rs) {
+        if (!try_runs(rs, Q0{})) pieces_from(e0);
+      };
+      auto two = [&](auto rs) {
+        constexpr int64_t P = (int64_t)kWave * 4 * decltype(rs)::value;
+        if (!try_runs(rs, Q0{}))
           pieces_from(e0);
-        }
+        else if (!try_runs(rs, Q1{}))
+          pieces_from(e0 + P);
+      };
+      auto four = [&](auto rs) {
+        constexpr int64_t P = (int64_t)kWave * 4 * decltype(rs)::value;
+        if (!try_runs(rs, Q0{}))
+          pieces_from(e0);
+        else if (!try_runs(rs, Q1{}))
+          pieces_from(e0 + P);
+        else if (!try_runs(rs, Q2{}))
+          pieces_from(e0 + 2 * P);
+        else if (!try_runs(rs, Q3{}))
+          pieces_from(e0 + 3 * P);
+      };
+      if constexpr (IPT == 4) {
+        if (nparts == 4)
+          four(std::integral_constant<int, 1>{});
+        else if (nparts == 2)
+          two(std::integral_constant<int, 2>{});
+        else
+          one(std::integral_constant<int, 4>{});
+      } else if constexpr (IPT == 2) {
+        if (nparts == 2)
+          two(std::integral_constant<int, 1>{});
+        else
+          one(std::integral_constant<int, 2>{});
       } else {
-        if (!try_runs(Full{}, Q0{})) pieces_from(e0);
+        one(std::integral_constant<int, 1>{});
       }
     }
 #pragma unroll
@@ -775,11 +810,17 @@ __device__ __forceinline__ void seg_workgroup_slices(const SegArgs& a, Workgroup
   }
 }
 
-// One form runs per launch, so the forms share the workgroup's LDS.
+// One form runs per launch, so the forms share the workgroup's LDS, which
+// is dynamic: the reduce-by-key form needs one RunLds per wavefront, so a
+// small workgroup does not reserve the space of a 512-thread one.
 union SegLds {
   WorkgroupLds wg;
   RunLds runs[kSegMaxWG / kWave];
 };
+
+size_t seg_lds_bytes(int wg) {
+  return std::max(sizeof(WorkgroupLds), (size_t)(wg / kWave) * sizeof(RunLds));
+}
 
 // The form of a launch: forced, or from the batch's mean segment length
 // (the same decision in every workgroup, and in the fix-up kernel).
@@ -794,7 +835,8 @@ __device__ __forceinline__ int seg_form(const SegArgs& a) {
 
 template <int IPT, bool NT, int FIX>
 __global__ __launch_bounds__(kSegMaxWG) void k_segmented(SegArgs a) {
-  __shared__ SegLds lds;
+  extern __shared__ __align__(16) unsigned char seg_lds[];
+  SegLds& lds = *reinterpret_cast<SegLds*>(seg_lds);
   const int form = seg_form<IPT>(a);
   if (form == kSegWorkgroup) {
     seg_workgroup_slices<IPT, NT, FIX>(a, lds.wg);
@@ -883,7 +925,8 @@ int seg_max_coresident(int ipt, int wg, const DeviceInfo& dev, int* n_wg) {
   const int ii = ipt_index(ipt);
   if (ii < 0) return set_error(RED_EINVAL, "bad ipt %d", ipt);
   int per_cu = 0;
-  RED_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, seg_table().k[kFixBarrier][0][ii], wg, 0));
+  RED_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, seg_table().k[kFixBarrier][0][ii], wg,
+                                                         seg_lds_bytes(wg)));
   *n_wg = per_cu * dev.cus;
   return RED_OK;
 }
@@ -934,7 +977,7 @@ int seg_launch(const SegLaunch& sl, const float* x, const int64_t* offsets, int6
   const bool nt = (p.flags & RED_FLAG_NONTEMPORAL) != 0;
   const bool coop = barrier && (p.flags & RED_FLAG_PLAIN_LAUNCH) == 0;
   const int slot = timer_begin(s);
-  int rc = launch(seg_table().k[fix][nt ? 1 : 0][ii], grid, p.wg, args, s, coop);
+  int rc = launch(seg_table().k[fix][nt ? 1 : 0][ii], grid, p.wg, args, s, coop, seg_lds_bytes(p.wg));
   if (rc == RED_OK && fix == kFixRelaunch) {
     // One wavefront per possible slice (the wavefront-slice count bounds the
     // workgroup-slice count).

@@ -84,7 +84,7 @@ def form_layouts():
     per-piece walk."""
     r = np.random.default_rng(500)
     out = []
-    for L in (1, 3, 4, 8, 15, 16, 17, 24, 31, 63, 64, 65, 100, 1000, 1500):
+    for L in (1, 3, 4, 5, 6, 8, 10, 15, 16, 17, 24, 31, 63, 64, 65, 100, 1000, 1500):
         out.append(("uniform%d" % L, np.full(max(1, 200000 // L), L, dtype=np.int64)))
     out.append(("short0to40", r.integers(0, 41, 20000)))
     out.append(("empties", r.choice([0, 0, 0, 50], 20000)))
