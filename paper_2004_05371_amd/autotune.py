@@ -1,9 +1,10 @@
 """Plan cache of the autotuner.
 
 The search itself runs in the library (``red_autotune`` /
-``red_autotune_segmented``: coordinate search over the nontemporal hint,
-workgroup size x loads per thread, grid size and synchronization variant,
-timed with HIP events on the caller's data).  This module persists its
+``red_autotune_segmented``: the nontemporal hint, workgroup size x loads
+per thread, grid size and synchronization variant, timed with HIP events
+on the caller's data; the segmented search re-times its best candidates in
+interleaved rounds).  This module persists its
 results as JSON and installs them into the library's plan table:
 
     {"format": 1, "arch": "gfx950", "cus": 256,

@@ -891,50 +891,88 @@ int red_autotune_segmented(const float* x, const int64_t* offsets, int64_t nseg,
   if (stream_capturing(s)) return set_error(RED_EINVAL, "autotuning cannot run inside stream capture");
   Workspace* ws;
   if ((rc = get_workspace(s, &ws))) return rc;
-  hipEvent_t a, b;
-  RED_HIP(hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
-  RED_HIP(hipEventCreateWithFlags(&b, hipEventDisableSystemFence));
-  red_plan cur = default_seg_plan(nseg, *dev);
-  double cur_us = 1e300;
+  // Each candidate: one warm launch, then kReps back-to-back launches timed
+  // one by one with events (median).  The best few are then timed again in
+  // interleaved rounds, so that a slow or fast stretch of the device does
+  // not pick the plan.
+  constexpr int kReps = 8, kFinalists = 4, kRounds = 3;
+  struct Events {
+    hipEvent_t e[2 * kReps] = {};
+    ~Events() {
+      for (hipEvent_t x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } ev;
+  for (hipEvent_t& x : ev.e) RED_HIP(hipEventCreateWithFlags(&x, hipEventDisableSystemFence));
+  auto time_plan = [&](const red_plan& p, double* us) -> int {
+    SegLaunch sl{p};
+    int r = seg_launch(sl, x, offsets, nseg, out, ws, s, *dev);
+    if (r) return r;
+    for (int i = 0; i < kReps; ++i) {
+      RED_HIP(hipEventRecord(ev.e[2 * i], s));
+      if ((r = seg_launch(sl, x, offsets, nseg, out, ws, s, *dev))) return r;
+      RED_HIP(hipEventRecord(ev.e[2 * i + 1], s));
+    }
+    RED_HIP(hipEventSynchronize(ev.e[2 * kReps - 1]));
+    std::vector<double> t;
+    for (int i = 0; i < kReps; ++i) {
+      float ms = 0;
+      RED_HIP(hipEventElapsedTime(&ms, ev.e[2 * i], ev.e[2 * i + 1]));
+      t.push_back(ms * 1e3);
+    }
+    *us = median(t);
+    return RED_OK;
+  };
+  std::vector<std::pair<double, red_plan>> timed_plans;
   int timed = 0;
   auto consider = [&](red_plan p) -> int {
     if (budget > 0 && timed >= budget) return RED_OK;
-    SegLaunch sl{p};
-    std::vector<double> t;
-    for (int i = 0; i < 6; ++i) {
-      RED_HIP(hipEventRecord(a, s));
-      int r = seg_launch(sl, x, offsets, nseg, out, ws, s, *dev);
-      if (r) return r;
-      RED_HIP(hipEventRecord(b, s));
-      RED_HIP(hipEventSynchronize(b));
-      float ms = 0;
-      RED_HIP(hipEventElapsedTime(&ms, a, b));
-      if (i >= 1) t.push_back(ms * 1e3);
-    }
+    double us = 0;
+    int r = time_plan(p, &us);
+    if (r) return r;
     ++timed;
-    const double us = median(t);
-    if (us < cur_us) {
-      cur_us = us;
-      cur = p;
-    }
+    timed_plans.push_back({us, p});
     return RED_OK;
   };
+  red_plan base = default_seg_plan(nseg, *dev);
   {
-    red_plan p = cur;
+    red_plan p = base;
     p.flags &= ~RED_FLAG_NONTEMPORAL;
     rc = consider(p);
     p.flags |= RED_FLAG_NONTEMPORAL;
     if (!rc) rc = consider(p);
   }
-  const int nt_flag = cur.flags & RED_FLAG_NONTEMPORAL;
+  if (rc) return rc;
+  const int nt_flag = (timed_plans.size() == 2 && timed_plans[0].first < timed_plans[1].first)
+                          ? 0 : RED_FLAG_NONTEMPORAL;
   for (int v : {RED_VARIANT_RELAUNCH, RED_VARIANT_ATOMIC})
     for (int wg : {128, 256, 512})
       for (int ipt : {2, 4, 8})
         for (int m : {1, 2, 3, 4, 6, 8})
           if (!rc) rc = consider(red_plan{v, wg, ipt, std::min(m * dev->cus, RED_MAX_GRID), nt_flag});
-  (void)hipEventDestroy(a);
-  (void)hipEventDestroy(b);
   if (rc) return rc;
+  if (timed_plans.empty()) return set_error(RED_EINVAL, "no plan timed (budget 0?)");
+  std::stable_sort(timed_plans.begin(), timed_plans.end(),
+                   [](const std::pair<double, red_plan>& u, const std::pair<double, red_plan>& v) {
+                     return u.first < v.first;
+                   });
+  const size_t nf = std::min<size_t>(kFinalists, timed_plans.size());
+  std::vector<std::vector<double>> rounds(nf);
+  for (int r = 0; r < kRounds; ++r)
+    for (size_t k = 0; k < nf; ++k) {
+      double us = 0;
+      if ((rc = time_plan(timed_plans[k].second, &us))) return rc;
+      rounds[k].push_back(us);
+    }
+  red_plan cur = timed_plans[0].second;
+  double cur_us = 1e300;
+  for (size_t k = 0; k < nf; ++k) {
+    const double us = median(rounds[k]);
+    if (us < cur_us) {
+      cur_us = us;
+      cur = timed_plans[k].second;
+    }
+  }
   {
     std::lock_guard<std::mutex> lk(g_mu);
     g_plans[std::make_tuple(1, bucket(nseg), 0, 0)] = cur;

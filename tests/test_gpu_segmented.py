@@ -201,6 +201,29 @@ def test_barrier_fixup_at_the_coresident_limit(lib, ipt, wg):
         run(lib, x, off, variant=3, wg=wg, ipt=ipt, grid=g + 1)
 
 
+def test_segmented_autotune_installs_a_working_plan(lib):
+    """A budgeted search on a small batch installs a plan for its nseg
+    bucket; the graph path then uses it and stays exact.  The default plan
+    is put back afterwards."""
+    from paper_2004_05371_amd import autotune
+    lens = np.random.default_rng(950).integers(0, 600, 3000)
+    off = inputs.offsets_from_lengths(lens.astype(np.int64))
+    x = inputs.mixed_f32(int(off[-1]), sub=21)
+    xt = torch.from_numpy(x).to("cuda")
+    ot = torch.from_numpy(off).to("cuda")
+    out = torch.empty(3000, dtype=torch.float64, device="cuda")
+    before = lib.red_get_segmented_plan(3000)
+    try:
+        e = autotune.tune_segmented(xt, ot, out, budget=12)
+        p = lib.red_get_segmented_plan(3000)
+        assert p.as_dict() == e["plan"]
+        assert e["plan"]["variant"] in ("relaunch", "atomic") and e["us"] > 0
+        res = run(lib, x, off)
+        check(res, x, off)
+    finally:
+        lib.red_set_segmented_plan(3000, before)
+
+
 def test_runs_form_rejects_eight_loads(lib):
     off = np.array([0, 4], dtype=np.int64)
     x = np.ones(4, dtype=np.float32)
