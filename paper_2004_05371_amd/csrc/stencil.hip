@@ -121,10 +121,16 @@ __global__ __launch_bounds__(1024) void k_jacobi_persistent(StencilArgs a) {
             const float left = j0 > 0 ? win[j0 - 1] : 0.0f;  // value 0 is never updated (jlo >= 1)
             const float right = win[j0 + 4];
             v4f v;
-            v.x = (j0 >= jlo && j0 < jhi) ? jacobi_point(left, c.x, c.y, a.r) : c.x;
-            v.y = (j0 + 1 >= jlo && j0 + 1 < jhi) ? jacobi_point(c.x, c.y, c.z, a.r) : c.y;
-            v.z = (j0 + 2 >= jlo && j0 + 2 < jhi) ? jacobi_point(c.y, c.z, c.w, a.r) : c.z;
-            v.w = (j0 + 3 >= jlo && j0 + 3 < jhi) ? jacobi_point(c.z, c.w, right, a.r) : c.w;
+            v.x = jacobi_point(left, c.x, c.y, a.r);
+            v.y = jacobi_point(c.x, c.y, c.z, a.r);
+            v.z = jacobi_point(c.y, c.z, c.w, a.r);
+            v.w = jacobi_point(c.z, c.w, right, a.r);
+            if (j0 < jlo || j0 + 4 > jhi) {  // a group at an edge of the valid range
+              v.x = (j0 >= jlo && j0 < jhi) ? v.x : c.x;
+              v.y = (j0 + 1 >= jlo && j0 + 1 < jhi) ? v.y : c.y;
+              v.z = (j0 + 2 >= jlo && j0 + 2 < jhi) ? v.z : c.z;
+              v.w = (j0 + 3 >= jlo && j0 + 3 < jhi) ? v.w : c.w;
+            }
             nv[q] = v;
           }
         }
