@@ -426,11 +426,11 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
   int64_t fill = 0;
   int npend = 0;
   int64_t pend0 = 0, pend1 = 0, pend2 = 0;
-  auto ring_pos = [&](int64_t i) {  // i mod kRing for entry i = base + lane
-    const int h = (int)(__builtin_amdgcn_readfirstlane((int)((i - lane) % kRing))) + lane;
+  auto ring_pos = [&](int64_t base) {  // (base + lane) mod kRing; base is wave-uniform
+    const int h = __builtin_amdgcn_readfirstlane((int)(base % kRing)) + lane;
     return h >= kRing ? h - kRing : h;
   };
-  auto put = [&](int64_t v, int64_t base) { ring[ring_pos(base + lane)] = v; };
+  auto put = [&](int64_t v, int64_t base) { ring[ring_pos(base)] = v; };
   auto refill = [&]() {
     if (npend > 0) put(pend0, fill);
     if (npend > 1) put(pend1, fill + kWave);
@@ -492,7 +492,7 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
       // must end past the rows to show every start in them.
       const int vis = (int)std::min<int64_t>(kWave, fill - (s + 1));
       if (vis <= 0) return false;
-      const int64_t O = lane < vis ? ring[ring_pos(s + 1 + lane)] : INT64_MAX;  // start of segment s + 1 + lane
+      const int64_t O = lane < vis ? ring[ring_pos(s + 1)] : INT64_MAX;  // start of segment s + 1 + lane
       const bool valid = O < std::min(f1, hi);
       const int m = __popcll(__ballot(valid));  // the valid lanes are 0 .. m-1
       if (m >= vis) return false;
