@@ -31,10 +31,42 @@ def pattern(n: int, dtype):
     return base.repeat(n // PERIOD + 1)[:n]
 
 
+# 16-bit inputs: the integers -128 .. 128 (period 257), exact in bf16 and fp16.
+PERIOD16 = 257
+
+
+def prefix16(m: int) -> int:
+    r = m % PERIOD16
+    return r * (r - 1) // 2 - 128 * r
+
+
+def pattern16(n: int, dtype):
+    base = (torch.arange(PERIOD16, dtype=torch.float32, device="cuda") - 128).to(dtype)
+    return base.repeat(n // PERIOD16 + 1)[:n]
+
+
 def test_closed_form():
     x = np.arange(5 * PERIOD + 77) % PERIOD - 1000
     for m in (0, 1, 1000, PERIOD, 3 * PERIOD + 5, x.size):
         assert prefix(m) == int(x[:m].sum())
+    y = np.arange(5 * PERIOD16 + 77) % PERIOD16 - 128
+    for m in (0, 1, 128, PERIOD16, 3 * PERIOD16 + 5, y.size):
+        assert prefix16(m) == int(y[:m].sum())
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("kind", ["bf16", "f16"])
+def test_half_sum_beyond_2p31(lib, kind):
+    say(kind, "sum, n =", N)
+    dtype = torch.bfloat16 if kind == "bf16" else torch.float16
+    code = lib.RED_BF16 if kind == "bf16" else lib.RED_F16
+    x = pattern16(N, dtype)
+    out = torch.empty((), dtype=torch.float64, device="cuda")
+    lib.red_sum_ex(code, x.data_ptr(), N, out.data_ptr(), lib.current_stream(), lib.make_opts())
+    torch.cuda.synchronize()
+    assert out.item() == float(prefix16(N))
+    del x
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.gpu
