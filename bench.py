@@ -12,8 +12,9 @@ Prints ONE JSON line: GB/s (= 2^30 bytes / wall time per step) and the
 fraction of the 8 TB/s HBM peak; the roofline of the dominant (streaming)
 kernel from its own HIP-event durations; the grid-barrier and relaunch
 latencies, the other synchronization variants and the bandwidth-proxy
-ceiling; the error of the result against the exact CPU oracle and the
-oracle's own CPU time.
+ceiling; one figure each for the segmented batch (10,000 log-uniform
+segments) and the iterative stencil (4M values); the error of the result
+against the exact CPU oracle and the oracle's own CPU time.
 
     python bench.py [--gpus 1] [--steps 200] [--warmup 20]
     python bench.py --configs out.jsonl [--only-configs]   # every workload + probe sweeps
@@ -838,6 +839,46 @@ def headline(args, R, dev, stream, sh, plans, inputs):
                                          "null_kernel_total_ns": round(null_ns, 1),
                                          "null_kernel_total_coop_ns": round(null_c, 1),
                                          "null_kernel_total_graph_ns": round(null_g, 1)}
+
+    # ---- the extensions, one figure each: the segmented batch of 10,000
+    #      log-uniform segments (cached plan; graph replay and direct
+    #      launches) and the iterative stencil on 4M values (one launch per
+    #      step against the persistent form with a grid barrier every 32 steps)
+    if not args.no_probes:
+        xs, off = inputs.segments(10000)
+        xst = torch.from_numpy(xs).to("cuda")
+        del xs
+        ot = torch.from_numpy(off).to("cuda")
+        nseg = off.size - 1
+        so = torch.empty(nseg, dtype=torch.float64, device="cuda")
+        sp = plans.seg_plan(xst, ot, so, sh)
+        od = R.make_opts(variant=sp.variant, wg=sp.wg, ipt=sp.ipt, grid=sp.grid, flags=sp.flags | R.FLAG_NO_GRAPH)
+        seg_bytes = xst.numel() * 4 + ot.numel() * 8 + nseg * 8
+        seg = {"values": int(off[-1]), "segments": nseg, "plan": sp.as_dict()}
+        for name, fn in (("graph", lambda: R.red_sum_segmented(xst.data_ptr(), ot.data_ptr(), nseg, so.data_ptr(), sh)),
+                         ("direct", lambda: R.red_sum_segmented_ex(xst.data_ptr(), ot.data_ptr(), nseg, so.data_ptr(),
+                                                                   sh, od))):
+            for _ in range(3):
+                fn()
+            tt, _ = time_steps(fn, 20, stream)
+            seg[name + "_us"] = round(statistics.median(tt) * 1e3, 1)
+            seg[name + "_GBps"] = gbps(seg_bytes, statistics.median(tt))
+        extra["segmented_10000"] = seg
+        del xst, ot, so
+        torch.cuda.empty_cache()
+        n_st, steps_st = 1 << 22, 200
+        u = torch.from_numpy(inputs.normal_f32(n_st, sub=66)).to("cuda")
+        sc = torch.empty_like(u)
+        st = {"n": n_st, "steps": steps_st}
+        for name, variant, k in (("relaunch", R.RED_VARIANT_RELAUNCH, 0), ("persistent_k32", R.RED_VARIANT_PERSISTENT, 32)):
+            o = R.make_opts(variant=variant)
+            fn = lambda: R.stencil_jacobi_1d(u.data_ptr(), sc.data_ptr(), n_st, steps_st, 0.25, k, sh, o)
+            fn()
+            tt, _ = time_steps(fn, 5, stream)
+            st[name + "_us_per_step"] = round(statistics.median(tt) * 1e3 / steps_st, 3)
+        extra["stencil_4M"] = st
+        del u, sc
+        torch.cuda.empty_cache()
 
     # ---- CPU baseline: the oracle on the same input (and the result's error)
     cpu = None
