@@ -382,6 +382,16 @@ int sync_bench_relaunch(int n_wg, int wg_size, int cooperative, int reps, double
 int sync_check_grid_order(int n_wg, int wg_size, int64_t *max_before, int64_t *min_after,
                           void *stream);
 
+/* Grid-barrier visibility check: a cooperative kernel of `rounds` rounds in
+ * which every workgroup stores one value with an ordinary store, meets the
+ * others at a grid barrier, and reads every workgroup's value with ordinary
+ * loads (the same addresses each round), then meets them again.  *errors
+ * (host) receives the number of reads that did not see the round's value;
+ * a correct barrier gives 0.  groups as in sync_bench_grid_ex.  Errors:
+ * RED_EINVAL (bad arguments, grid not co-resident), RED_ETIMEOUT (watchdog),
+ * RED_ENOTSUP (XCD dispatch rule broken), RED_EHIP. */
+int sync_check_grid_visibility(int n_wg, int wg_size, int groups, int rounds, int64_t *errors, void *stream);
+
 /* Watchdog check: a cooperative kernel in which workgroup `skip_wg` never
  * arrives at the grid barrier while the others wait with a spin limit of
  * `spin_limit` polls; returns RED_ETIMEOUT when the watchdog fires (the

@@ -117,6 +117,26 @@ __global__ __launch_bounds__(1024) void k_grid_order(BarrierWords* w, unsigned g
   if (threadIdx.x == 0) after[blockIdx.x] = __builtin_amdgcn_s_memrealtime();
 }
 
+// Visibility across the grid barrier: in round r thread 0 of workgroup g
+// stores r * G + g to data[g] with an ordinary store; after the barrier
+// every thread reads its share of data[0 .. G) with ordinary loads (the
+// same addresses every round, so a stale line in either cache level would
+// show) and counts the slots that do not hold this round's value; a second
+// barrier keeps round r + 1's stores after every read of round r.
+__global__ __launch_bounds__(1024) void k_grid_visibility(BarrierWords* w, unsigned groups, unsigned spin_limit,
+                                                         long long* data, unsigned long long* errors,
+                                                         int rounds) {
+  const unsigned G = gridDim.x;
+  unsigned long long bad = 0;
+  for (int r = 0; r < rounds; ++r) {
+    if (threadIdx.x == 0) data[blockIdx.x] = (long long)r * G + blockIdx.x;
+    if (!grid_barrier(w, G, groups, spin_limit)) break;
+    for (unsigned i = threadIdx.x; i < G; i += blockDim.x) bad += data[i] != (long long)r * G + i;
+    if (!grid_barrier(w, G, groups, spin_limit)) break;
+  }
+  if (bad) atomicAdd(errors, bad);
+}
+
 // Workgroup `skip` never arrives; the others leave through the watchdog.
 __global__ __launch_bounds__(1024) void k_watchdog(BarrierWords* w, int skip, unsigned groups,
                                                   unsigned spin_limit) {
@@ -602,6 +622,45 @@ int sync_check_grid_order(int n_wg, int wg_size, int64_t* max_before, int64_t* m
   }
   *max_before = *std::max_element(hb.begin(), hb.end());
   *min_after = *std::min_element(ha.begin(), ha.end());
+  return RED_OK;
+}
+
+int sync_check_grid_visibility(int n_wg, int wg_size, int groups, int rounds, int64_t* errors, void* stream) {
+  if (wg_size < 64 || wg_size > 1024 || wg_size % 64) return set_error(RED_EINVAL, "bad wg_size %d", wg_size);
+  if (n_wg < 1 || n_wg > RED_MAX_GRID) return set_error(RED_EINVAL, "bad n_wg %d", n_wg);
+  if (groups < -1 || groups > kMaxBarrierGroups) return set_error(RED_EINVAL, "bad groups %d", groups);
+  if (rounds < 1 || rounds > 100000) return set_error(RED_EINVAL, "bad rounds %d", rounds);
+  if (!errors) return set_error(RED_EINVAL, "null output");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DeviceInfo* dev;
+  Workspace* ws;
+  int rc = probe_prologue(s, &dev, &ws);
+  if (rc) return rc;
+  const void* fn = reinterpret_cast<const void*>(&k_grid_visibility);
+  int maxg = 0;
+  if ((rc = coresident(fn, wg_size, *dev, &maxg))) return rc;
+  if (n_wg > maxg) return set_error(RED_EINVAL, "visibility check: grid too large (max %d)", maxg);
+  if ((rc = reset_words(ws, s))) return rc;
+  BarrierWords* w = ws->words;
+  unsigned grp = groups > 0 ? (unsigned)groups
+                 : groups < 0 ? (dev->nxcc > 1 ? (kBarrierXcd | (unsigned)dev->nxcc) : 1u)
+                              : barrier_groups(n_wg);
+  unsigned spin = watchdog_spins();
+  long long* data = ws->stamps;  // RED_MAX_GRID slots
+  unsigned long long* err_count = reinterpret_cast<unsigned long long*>(ws->stamps + RED_MAX_GRID);
+  RED_HIP(hipMemsetAsync(err_count, 0, sizeof(unsigned long long), s));
+  void* args[] = {&w, &grp, &spin, &data, &err_count, &rounds};
+  if ((rc = launch(fn, n_wg, wg_size, args, s, true))) return rc;
+  RED_HIP(hipStreamSynchronize(s));
+  unsigned long long h = 0;
+  RED_HIP(hipMemcpy(&h, err_count, sizeof h, hipMemcpyDeviceToHost));
+  unsigned err = 0;
+  RED_HIP(hipMemcpy(&err, &ws->words->err.v, 4, hipMemcpyDeviceToHost));
+  if (err) {
+    reset_words(ws, s);
+    return set_error(err == kErrTimeout ? RED_ETIMEOUT : RED_ENOTSUP, "visibility check: barrier error %u", err);
+  }
+  *errors = (int64_t)h;
   return RED_OK;
 }
 

@@ -48,6 +48,7 @@ EXPORTS = [
     "red_autotune_segmented", "red_set_segmented_plan", "red_get_segmented_plan",
     "red_kernel_timer", "red_kernel_timer_read", "sync_bench_wave", "sync_bench_wave_ex", "sync_bench_block",
     "sync_bench_grid", "sync_bench_grid_ex", "sync_bench_relaunch", "sync_check_grid_order",
+    "sync_check_grid_visibility",
     "sync_check_watchdog", "sync_xcc_map", "red_max_coresident", "red_max_coresident_segmented",
     "red_device_info",
     "red_bw_proxy", "red_eq6_overhead", "red_eq7_latency", "red_eq8_sigma", "stencil_jacobi_1d",
@@ -105,6 +106,7 @@ _SIGS = {
     "sync_bench_grid_ex": ([_i32, _i32, _i32, _i32, _dp, _dp, _dp, _vp], _i32),
     "sync_bench_relaunch": ([_i32, _i32, _i32, _i32, _dp, _dp, _dp, _vp], _i32),
     "sync_check_grid_order": ([_i32, _i32, _i64p, _i64p, _vp], _i32),
+    "sync_check_grid_visibility": ([_i32, _i32, _i32, _i32, _i64p, _vp], _i32),
     "sync_check_watchdog": ([_i32, _i32, _i32, _i32, _vp], _i32),
     "red_max_coresident": ([_i32, _i32p], _i32),
     "red_max_coresident_segmented": ([_i32, _i32, _i32p], _i32),
@@ -286,6 +288,15 @@ def sync_bench_relaunch(n_wg: int = 256, wg_size: int = 256, cooperative=False, 
     cooperative: False/True, or a launch type LAUNCH_ORDINARY /
     LAUNCH_COOPERATIVE / LAUNCH_GRAPH."""
     return _probe3("sync_bench_relaunch", n_wg, wg_size, int(cooperative), reps, stream=stream)
+
+
+def sync_check_grid_visibility(n_wg: int, wg_size: int = 256, groups: int = 0, rounds: int = 50,
+                               stream: int = 0) -> int:
+    """Reads that missed the round's value across the grid barrier (0 when correct)."""
+    e = ctypes.c_int64()
+    _check(load().sync_check_grid_visibility(n_wg, wg_size, groups, rounds, ctypes.byref(e), stream),
+           "sync_check_grid_visibility")
+    return e.value
 
 
 def sync_check_grid_order(n_wg: int, wg_size: int = 256, stream: int = 0):

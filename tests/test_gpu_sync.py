@@ -33,6 +33,17 @@ def test_grid_barrier_ordering(lib, n_wg, wg):
         assert before <= after, (n_wg, wg, before, after)
 
 
+@pytest.mark.parametrize("groups", [1, 0, 8, -1])
+@pytest.mark.parametrize("n_wg", [2, 64, 256, 512])
+def test_grid_barrier_visibility(lib, n_wg, groups):
+    """Ordinary stores before a grid barrier are seen by ordinary loads of
+    every workgroup after it, round after round on the same addresses, for
+    the flat, default, 8-group and XCD-aggregated barriers."""
+    n = min(n_wg, lib.red_max_coresident(256))
+    say("visibility", n, "workgroups, groups", groups)
+    assert lib.sync_check_grid_visibility(n, 256, groups, rounds=200) == 0
+
+
 def test_watchdog_fires_and_recovers(lib):
     rc = lib.sync_check_watchdog(8, 64, skip_wg=3, spin_limit=2000)
     assert rc == lib.RED_ETIMEOUT
