@@ -197,6 +197,50 @@ def summarize_trace(trace_dir, bench_json, out_dir):
     with open(os.path.join(out_dir, "k_partials_f32_2p28_kernel_trace.md"), "w") as fh:
         fh.write("\n".join(md) + "\n")
     log("dominant kernel %.2f us average over %s launches" % (avg_ns / 1e3, dom[0]["Calls"]))
+    summarize_extensions(rows, line, out_dir)
+
+
+def summarize_extensions(rows, line, out_dir):
+    """Kernel-trace rows of the extension figures of the same bench run:
+    the segmented batch (slice kernel and fix-up) and the stencil."""
+    seg = line.get("extra", {}).get("segmented_10000")
+    st = line.get("extra", {}).get("stencil_4M")
+    if not seg or not st:
+        return
+    pick = [r for r in rows if "k_segmented<" in r["Name"] or "k_seg_fixup" in r["Name"]
+            or "k_jacobi" in r["Name"] or "k_copy_f32" in r["Name"]]
+    if not pick:
+        return
+    seg_bytes = seg["values"] * 4 + (seg["segments"] + 1) * 8 + seg["segments"] * 8
+    md = ["# Kernel trace: segmented batch and iterative stencil (extension figures of the bench line)", "",
+          "Same command and run as `k_partials_f32_2p28_kernel_trace.md`:", "",
+          "```", "rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- python3 bench.py",
+          "python3 bench.py --summarize-trace <dir> <bench line of that run>", "```", "",
+          "Workloads: %d fp32 values in %d log-uniform segments, plan `%s` (graph replay and direct "
+          "launches); a 1D Jacobi stencil on %d values, %d steps per call, one launch per step and "
+          "the persistent form with a grid barrier every 32 steps."
+          % (seg["values"], seg["segments"], json.dumps(seg["plan"]), st["n"], st["steps"]), "",
+          "| Kernel | Calls | Average (us) | Min (us) | Max (us) |", "|---|---|---|---|---|"]
+    for r in pick:
+        k = r["Name"].replace("|", "/")
+        md.append("| `%s` | %s | %.2f | %.2f | %.2f |" % (k[:95], r["Calls"], float(r["AverageNs"]) / 1e3,
+                                                          float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3))
+    sk = [r for r in pick if "k_segmented<" in r["Name"]]
+    fx = [r for r in pick if "k_seg_fixup" in r["Name"]]
+    if sk:
+        a = float(sk[0]["AverageNs"])
+        md += ["", "- Slice kernel: average %.1f us = %.1f GB/s for %d algorithmic bytes (values, offsets, "
+               "outputs; %.1f %% of 8 TB/s)%s." % (a / 1e3, seg_bytes / a, seg_bytes, 100 * seg_bytes / a / 8000,
+                                                   "; fix-up kernel %.2f us" % (float(fx[0]["AverageNs"]) / 1e3)
+                                                   if fx else ""),
+               "- The bench line's own event timing of a whole call: %.1f us replayed from the graph, %.1f us "
+               "launched directly." % (seg["graph_us"], seg["direct_us"])]
+    md += ["- Stencil, from the bench line: %.3f us per step with one launch per step, %.3f us in the "
+           "persistent form." % (st["relaunch_us_per_step"], st["persistent_k32_us_per_step"]),
+           "- The bench-line figures of this run were taken under the profiler, which adds time to every "
+           "launch (most visible in the one-launch-per-step stencil)."]
+    with open(os.path.join(out_dir, "k_segmented_and_stencil_kernel_trace.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
 
 
 def gbps(nbytes, ms):
