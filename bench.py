@@ -862,6 +862,10 @@ def headline(args, R, dev, stream, sh, plans, inputs):
     extra["plain_fp32_GBps"] = gbps(nbytes, statistics.median(tt))
     tt, _ = time_steps(lambda: R.red_bw_proxy(xt.data_ptr(), nbytes, 1024, 512, sh), 50, stream)
     extra["bw_proxy_GBps"] = gbps(nbytes, statistics.median(tt))
+    # the same read-only loop with the nontemporal hint, in the headline plan's shape
+    tt, _ = time_steps(lambda: R.red_bw_proxy_ex(xt.data_ptr(), nbytes, plan.grid or 512, plan.wg,
+                                                 R.FLAG_NONTEMPORAL, sh), 50, stream)
+    extra["bw_proxy_nt_GBps"] = gbps(nbytes, statistics.median(tt))
 
     # ---- synchronization latencies (ns)
     if not args.no_probes:

@@ -439,6 +439,12 @@ int red_kernel_timer_read(void *stream, double *mean_us, double *min_us, int64_t
  * workspace.  Asynchronous. */
 int red_bw_proxy(const void *x, int64_t nbytes, int n_wg, int wg_size, void *stream);
 
+/* red_bw_proxy with flags: RED_FLAG_NONTEMPORAL issues the loads with the
+ * nontemporal hint (the hint the reductions stream with), other bits
+ * RED_EINVAL.  Without it the loads are ordinary, which also fills the
+ * memory-side cache (the benchmark's cache flush relies on that). */
+int red_bw_proxy_ex(const void *x, int64_t nbytes, int n_wg, int wg_size, int flags, void *stream);
+
 /* Host-side probe formulas, exported so host logic can be tested without a
  * GPU: Eq. 6, Eq. 7, Eq. 8 (from two sample arrays of length nsamp). */
 double red_eq6_overhead(double lat_ij, double lat_ji, int i, int j);

@@ -102,7 +102,7 @@ int seg_launch(const SegLaunch& sl, const float* x, const int64_t* offsets, int6
 int seg_max_coresident(int ipt, int wg, const DeviceInfo& dev, int* n_wg);
 
 // Probes -------------------------------------------------------------------
-int bw_proxy_launch(const void* x, int64_t nbytes, int n_wg, int wg, Workspace* ws, hipStream_t s);
+int bw_proxy_launch(const void* x, int64_t nbytes, int n_wg, int wg, bool nt, Workspace* ws, hipStream_t s);
 
 // Iterative stencil ---------------------------------------------------------
 int stencil_launch(float* u, float* scratch, int64_t n, int steps, float r, int steps_per_sync, const red_plan& p,

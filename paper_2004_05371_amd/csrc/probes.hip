@@ -162,7 +162,7 @@ __global__ void k_reset_words(BarrierWords* w) {
 
 // Read-only bandwidth proxy (Section VII-B): grid-stride 16-byte loads, two
 // adds per load.
-template <int IPT>
+template <int IPT, bool NT>
 __global__ __launch_bounds__(1024) void k_bw_proxy(const v4u* x, int64_t nvec, unsigned* sink) {
   const int64_t bs = blockDim.x;
   const int64_t tile = bs * IPT;
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(1024) void k_bw_proxy(const v4u* x, int64_t nvec, u
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     v4u v[IPT];
 #pragma unroll
-    for (int u = 0; u < IPT; ++u) v[u] = x[t * tile + u * bs + threadIdx.x];
+    for (int u = 0; u < IPT; ++u) v[u] = load_vec<NT>(x + t * tile + u * bs + threadIdx.x);
     __builtin_amdgcn_sched_barrier(0);  // all IPT loads in flight before use
 #pragma unroll
     for (int u = 0; u < IPT; ++u) acc += v[u].x + v[u].y;
@@ -344,12 +344,14 @@ int coresident(const void* fn, int wg, const DeviceInfo& dev, int* n) {
 
 }  // namespace
 
-int bw_proxy_launch(const void* x, int64_t nbytes, int n_wg, int wg, Workspace* ws, hipStream_t s) {
+int bw_proxy_launch(const void* x, int64_t nbytes, int n_wg, int wg, bool nt, Workspace* ws, hipStream_t s) {
   const v4u* xv = static_cast<const v4u*>(x);
   int64_t nvec = nbytes / 16;
   unsigned* sink = ws->sink;
   void* args[] = {&xv, &nvec, &sink};
-  return launch(reinterpret_cast<const void*>(&k_bw_proxy<4>), n_wg, wg, args, s, false);
+  const void* fn = nt ? reinterpret_cast<const void*>(&k_bw_proxy<4, true>)
+                      : reinterpret_cast<const void*>(&k_bw_proxy<4, false>);
+  return launch(fn, n_wg, wg, args, s, false);
 }
 
 // Wavefront-probe kernel of `op` on values of Op's type.
@@ -705,6 +707,11 @@ int sync_xcc_map(int n_wg, int wg_size, int32_t* host_xcc, void* stream) {
 }
 
 int red_bw_proxy(const void* x, int64_t nbytes, int n_wg, int wg_size, void* stream) {
+  return red_bw_proxy_ex(x, nbytes, n_wg, wg_size, 0, stream);
+}
+
+int red_bw_proxy_ex(const void* x, int64_t nbytes, int n_wg, int wg_size, int flags, void* stream) {
+  if (flags & ~RED_FLAG_NONTEMPORAL) return set_error(RED_EINVAL, "unknown flags 0x%x", flags);
   if (!x || nbytes < 0) return set_error(RED_EINVAL, "bad buffer");
   if (reinterpret_cast<uintptr_t>(x) & 15) return set_error(RED_EINVAL, "x must be 16-byte aligned");
   if (wg_size < 64 || wg_size > 1024 || wg_size % 64) return set_error(RED_EINVAL, "bad wg_size %d", wg_size);
@@ -715,7 +722,7 @@ int red_bw_proxy(const void* x, int64_t nbytes, int n_wg, int wg_size, void* str
   if (rc) return rc;
   Workspace* ws;
   if ((rc = get_workspace(s, &ws))) return rc;
-  return bw_proxy_launch(x, nbytes, n_wg, wg_size, ws, s);
+  return bw_proxy_launch(x, nbytes, n_wg, wg_size, (flags & RED_FLAG_NONTEMPORAL) != 0, ws, s);
 }
 
 }  // extern "C"

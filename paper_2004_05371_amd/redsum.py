@@ -51,7 +51,7 @@ EXPORTS = [
     "sync_check_grid_visibility",
     "sync_check_watchdog", "sync_xcc_map", "red_max_coresident", "red_max_coresident_segmented",
     "red_device_info",
-    "red_bw_proxy", "red_eq6_overhead", "red_eq7_latency", "red_eq8_sigma", "stencil_jacobi_1d",
+    "red_bw_proxy", "red_bw_proxy_ex", "red_eq6_overhead", "red_eq7_latency", "red_eq8_sigma", "stencil_jacobi_1d",
 ]
 
 
@@ -113,6 +113,7 @@ _SIGS = {
     "red_device_info": ([_i32p, _i64p, _i64p, _i64p, _i64p, _i32p], _i32),
     "sync_xcc_map": ([_i32, _i32, _i32p, _vp], _i32),
     "red_bw_proxy": ([_vp, _i64, _i32, _i32, _vp], _i32),
+    "red_bw_proxy_ex": ([_vp, _i64, _i32, _i32, _i32, _vp], _i32),
     "red_eq6_overhead": ([_d, _d, _i32, _i32], _d),
     "red_eq7_latency": ([_d, _d, _i64, _i64], _d),
     "red_eq8_sigma": ([_dp, _dp, _i32, _i64, _i64], _d),
@@ -360,6 +361,10 @@ def jacobi(t, steps: int, r: float, scratch=None, steps_per_sync: int = 0, opts:
 
 def red_bw_proxy(x: int, nbytes: int, n_wg: int, wg_size: int, stream: int = 0) -> int:
     return _check(load().red_bw_proxy(x, nbytes, n_wg, wg_size, stream), "red_bw_proxy")
+
+
+def red_bw_proxy_ex(x: int, nbytes: int, n_wg: int, wg_size: int, flags: int = 0, stream: int = 0) -> int:
+    return _check(load().red_bw_proxy_ex(x, nbytes, n_wg, wg_size, flags, stream), "red_bw_proxy_ex")
 
 
 def red_eq6_overhead(lat_ij: float, lat_ji: float, i: int, j: int) -> float:

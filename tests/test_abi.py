@@ -91,6 +91,7 @@ def test_validation_before_hip(lib):
     for kind in (-1, 3):  # launch types are 0 ordinary, 1 cooperative, 2 graph
         assert lib.sync_bench_relaunch(8, 64, kind, 10, ctypes.byref(d), ctypes.byref(d), None, None) == R.RED_EINVAL
     assert lib.sync_check_watchdog(4, 64, 9, 100, None) == R.RED_EINVAL
+    assert lib.red_bw_proxy_ex(ctypes.c_void_p(64), 1024, 4, 256, 2, None) == R.RED_EINVAL  # unknown flag
     e = ctypes.c_int64()
     assert lib.sync_check_grid_visibility(0, 256, 0, 10, ctypes.byref(e), None) == R.RED_EINVAL
     assert lib.sync_check_grid_visibility(4, 256, -2, 10, ctypes.byref(e), None) == R.RED_EINVAL

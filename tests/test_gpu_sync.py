@@ -44,6 +44,16 @@ def test_grid_barrier_visibility(lib, n_wg, groups):
     assert lib.sync_check_grid_visibility(n, 256, groups, rounds=200) == 0
 
 
+@pytest.mark.parametrize("flags", [0, 1])
+def test_bw_proxy_runs(lib, flags):
+    """The read-only bandwidth proxy, with ordinary and nontemporal loads,
+    over a buffer that is not a multiple of its tile."""
+    x = torch.ones((1 << 24) + 20, dtype=torch.float32, device="cuda")
+    lib.red_bw_proxy_ex(x.data_ptr(), x.numel() * 4, 512, 256, flags, lib.current_stream())
+    torch.cuda.synchronize()
+    assert lib.red_check_error(lib.current_stream()) == lib.RED_OK
+
+
 def test_watchdog_fires_and_recovers(lib):
     rc = lib.sync_check_watchdog(8, 64, skip_wg=3, spin_limit=2000)
     assert rc == lib.RED_ETIMEOUT
