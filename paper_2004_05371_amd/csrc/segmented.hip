@@ -841,18 +841,7 @@ __global__ __launch_bounds__(kSegMaxWG) void k_segmented(SegArgs a) {
   if (form == kSegWorkgroup) {
     seg_workgroup_slices<IPT, NT, FIX>(a, lds.wg);
   } else if (form == kSegWaveRuns) {
-    if constexpr (IPT == 4) {
-      // Under a mean of 8 values a quarter tile (256 values) holds 32 or
-      // more starts and a tile more offsets than the ring refills: walk the
-      // slice in tiles of 2 rows instead (the slices do not depend on the
-      // tile size).
-      if (offset_at(a.offsets, a.nseg) < 8 * a.nseg)
-        seg_wave_runs<2, NT, FIX>(a, lds.runs);
-      else
-        seg_wave_runs<4, NT, FIX>(a, lds.runs);
-    } else if constexpr (IPT <= 2) {
-      seg_wave_runs<IPT, NT, FIX>(a, lds.runs);
-    }
+    if constexpr (IPT <= 4) seg_wave_runs<IPT, NT, FIX>(a, lds.runs);
   } else {
     seg_wave_slices<IPT, NT, FIX>(a);
   }
