@@ -11,10 +11,12 @@ namespace redsum {
 struct BarrierWords;
 
 // One carry slot of the segmented reduction: the binary64 sum of the piece
-// of segment `seg` that falls in one workgroup's slice.
+// of segment `seg` that falls in one slice, and the number of slices the
+// segment spans (written with the first piece, for the fix-up kernel).
 struct SegCarry {
   long long seg;
   double val;
+  long long np;
 };
 
 struct DeviceInfo {

@@ -109,25 +109,25 @@ __device__ __forceinline__ void finish_piece(const SegArgs& a, int64_t s, int64_
   if constexpr (FIX == kFixRelaunch) {
     if (lane == 0) {
       if (sa < lo)
-        a.carry_in[w] = SegCarry{s, v};
+        a.carry_in[w] = SegCarry{s, v, np};
       else
-        a.carry_out[w] = SegCarry{s, v};
+        a.carry_out[w] = SegCarry{s, v, np};
     }
   } else if constexpr (FIX == kFixBarrier) {
     if (lane == 0) {
       if (sa < lo)
-        a.carry_in[w] = SegCarry{s, v};
+        a.carry_in[w] = SegCarry{s, v, np};
       else
-        a.carry_out[w] = SegCarry{s, v};
+        a.carry_out[w] = SegCarry{s, v, np};
     }
     if (sa >= lo) *own_fix = s;
   } else {
     int last = 0;
     if (lane == 0) {
       if (sa < lo)
-        a.carry_in[w] = SegCarry{s, v};
+        a.carry_in[w] = SegCarry{s, v, np};
       else
-        a.carry_out[w] = SegCarry{s, v};
+        a.carry_out[w] = SegCarry{s, v, np};
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       const unsigned tk = __hip_atomic_fetch_add(&a.tickets[o], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       last = tk == (unsigned)(np - 1);
@@ -258,7 +258,7 @@ __device__ __forceinline__ void seg_wave_slices(const SegArgs& a) {
   // Relaunch fix-up: the slot says "no cut segment starts here" unless a
   // later store by the same lane replaces it.
   if constexpr (FIX == kFixRelaunch)
-    if (lane == 0) a.carry_out[w] = SegCarry{-1, 0.0};
+    if (lane == 0) a.carry_out[w] = SegCarry{-1, 0.0, 0};
 
   int64_t s = first_segment(a, lo);
   int64_t sa = 0, sb = 0;
@@ -401,7 +401,7 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
   // Relaunch fix-up: the slot says "no cut segment starts here" unless a
   // later store by the same lane replaces it.
   if constexpr (FIX == kFixRelaunch)
-    if (lane == 0) a.carry_out[w] = SegCarry{-1, 0.0};
+    if (lane == 0) a.carry_out[w] = SegCarry{-1, 0.0, 0};
 
   int64_t s = first_segment(a, lo);
   int64_t sa = 0, sb = 0;
@@ -719,9 +719,13 @@ __device__ __forceinline__ void seg_workgroup_slices(const SegArgs& a, Workgroup
   const int nwaves = (int)bs / kWave;
   if (tid == 0) own_fix = -1;
   // Relaunch fix-up: "no cut segment starts here" unless a store after the
-  // first batch barrier replaces it.
-  if constexpr (FIX == kFixRelaunch)
-    if (tid == 0) a.carry_out[g] = SegCarry{-1, 0.0};
+  // first batch barrier replaces it.  The fix-up kernel looks at one slot
+  // per wavefront of the grid, so the other waves also clear the slots
+  // [G, G * nwaves) that workgroup slices do not use.
+  if constexpr (FIX == kFixRelaunch) {
+    if (tid == 0) a.carry_out[g] = SegCarry{-1, 0.0, 0};
+    if (wave > 0 && lane == 0) a.carry_out[G + g * (nwaves - 1) + (wave - 1)] = SegCarry{-1, 0.0, 0};
+  }
 
   // Completes the batched pieces: wave w finishes pieces w, w + nwaves, ...
   auto flush = [&]() {
@@ -847,24 +851,22 @@ __global__ __launch_bounds__(kSegMaxWG) void k_segmented(SegArgs a) {
   }
 }
 
-// Relaunch fix-up: wavefront w of this grid looks at slice w of the slice
-// kernel; if a cut segment starts there it sums the segment's pieces in
-// slice order (the same combine as the ticket and barrier fix-ups) and
-// writes it.
+// Relaunch fix-up: wavefront w of this grid looks at carry slot w, which
+// the slice kernel wrote for every w below its grid's wavefront count
+// (slice w's slot in the wavefront forms; in the workgroup form, the slots
+// past the grid say "none"); if a cut segment starts in slice w, it sums
+// the segment's pieces in slice order (the same combine as the ticket and
+// barrier fix-ups) and writes it.  The slot holds the segment and its
+// piece count, so the fix-up reads no offsets.
 constexpr int kFixupWG = 256;
 
-template <int IPT>
 __global__ __launch_bounds__(kFixupWG) void k_seg_fixup(SegArgs a) {
-  const int64_t W = seg_form<IPT>(a) == kSegWorkgroup ? (int64_t)a.grid : (int64_t)a.grid * (a.wg / kWave);
   const int64_t w = (int64_t)blockIdx.x * (kFixupWG / kWave) + threadIdx.x / kWave;
-  if (w >= W) return;
-  const int64_t seg = a.carry_out[w].seg;
-  if (seg < 0) return;
-  const int64_t E = offset_at(a.offsets, a.nseg);
-  const int64_t chunk = std::max<int64_t>(64, (((E + W - 1) / W) + 63) & ~(int64_t)63);
-  const int64_t np = (offset_at(a.offsets, seg + 1) - 1) / chunk - w + 1;
-  const double v = combine_pieces(a, w, np);
-  if (__lane_id() == 0) a.out[seg] = v;
+  if (w >= (int64_t)a.grid * (a.wg / kWave)) return;
+  const SegCarry c = a.carry_out[w];
+  if (c.seg < 0) return;
+  const double v = combine_pieces(a, w, c.np);
+  if (__lane_id() == 0) a.out[c.seg] = v;
 }
 
 namespace {
@@ -873,7 +875,6 @@ int ipt_index(int ipt) { return ipt == 1 ? 0 : ipt == 2 ? 1 : ipt == 4 ? 2 : ipt
 
 struct SegTable {
   const void* k[3][2][4];  // SegFix, nontemporal, ipt index
-  const void* fixup[4];    // ipt index
   template <int F, bool NT>
   void fill() {
     k[F][NT][0] = reinterpret_cast<const void*>(&k_segmented<1, NT, F>);
@@ -888,10 +889,6 @@ struct SegTable {
     fill<kFixBarrier, true>();
     fill<kFixRelaunch, false>();
     fill<kFixRelaunch, true>();
-    fixup[0] = reinterpret_cast<const void*>(&k_seg_fixup<1>);
-    fixup[1] = reinterpret_cast<const void*>(&k_seg_fixup<2>);
-    fixup[2] = reinterpret_cast<const void*>(&k_seg_fixup<4>);
-    fixup[3] = reinterpret_cast<const void*>(&k_seg_fixup<8>);
   }
 };
 
@@ -983,7 +980,7 @@ int seg_launch(const SegLaunch& sl, const float* x, const int64_t* offsets, int6
     // workgroup-slice count).
     const int64_t waves = (int64_t)grid * (p.wg / kWave);
     const int fix_grid = (int)((waves + kFixupWG / kWave - 1) / (kFixupWG / kWave));
-    rc = launch(seg_table().fixup[ii], fix_grid, kFixupWG, args, s, false);
+    rc = launch(reinterpret_cast<const void*>(&k_seg_fixup), fix_grid, kFixupWG, args, s, false);
   }
   timer_end(s, slot);
   return rc;
