@@ -278,9 +278,11 @@ int red_sum_segmented_loop(const float *x, const int64_t *host_offsets, int64_t 
  *            RED_VARIANT_AUTO        persistent when the array fits the
  *                                    co-resident workgroups' LDS, else
  *                                    relaunch.
- *            plan.wg (default 512), plan.grid (default one workgroup per
- *            CU, or as many 64 KB LDS windows as the array needs, capped at
- *            the co-resident limit) and flags
+ *            plan.wg (default: 1024 when one 64 KB LDS window per CU
+ *            holds the array and n >= 4096 x CUs, else 512), plan.grid
+ *            (default one workgroup per CU, or as many 64 KB LDS windows
+ *            as the array needs rounded up to a whole number per CU,
+ *            capped at the co-resident limit) and flags
  *            RED_FLAG_PLAIN_LAUNCH / RED_FLAG_XCD as for red_sum.
  * Asynchronous on `stream`.  RED_EINVAL for bad arguments, overlapping
  * arrays, or a persistent request whose block does not fit one LDS window;

@@ -674,7 +674,7 @@ int stencil_jacobi_1d(float* u, float* scratch, int64_t n, int32_t steps, float 
     const uintptr_t bytes = (uintptr_t)n * 4;
     if (a0 < b0 + bytes && b0 < a0 + bytes) return set_error(RED_EINVAL, "u and scratch overlap");
   }
-  red_plan p{RED_VARIANT_AUTO, 512, 1, 0, 0};
+  red_plan p{RED_VARIANT_AUTO, 0, 1, 0, 0};  // wg 0: chosen by stencil_launch
   if (opts) {
     if (opts->flags & ~(RED_FLAG_PLAIN_LAUNCH | RED_FLAG_XCD))
       return set_error(RED_EINVAL, "unknown flags 0x%x", opts->flags);

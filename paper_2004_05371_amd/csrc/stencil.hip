@@ -196,13 +196,28 @@ int stencil_coresident(int wg, size_t lds_bytes, const DeviceInfo& dev, int* n_w
 int stencil_launch(float* u, float* scratch, int64_t n, int steps, float r, int steps_per_sync, const red_plan& p,
                    Workspace* ws, hipStream_t s, const DeviceInfo& dev) {
   if (n < 3 || steps == 0) return RED_OK;
-  const int wg = p.wg;
   int variant = p.variant;
   const int k_req = steps_per_sync > 0 ? steps_per_sync : 8;
   // LDS window: the 64 KB a workgroup gets without opting in to more, less
   // a margin for the barrier's static LDS.
-  const int64_t lds_floats =
-      std::min<int64_t>((std::min<int64_t>(dev.lds_per_wg, 65536) - 256) / 4 - 8, (int64_t)4 * kStencilRows * wg);
+  auto window_floats = [&](int threads) {
+    return std::min<int64_t>((std::min<int64_t>(dev.lds_per_wg, 65536) - 256) / 4 - 8,
+                             (int64_t)4 * kStencilRows * threads);
+  };
+  // Threads per workgroup when the caller leaves them open: 16 wavefronts
+  // per CU either way, as one 1024-thread workgroup when one window per CU
+  // holds the array with at least 4 values per thread (measured on MI355X:
+  // 0.87 against 1.11 us per step at 1 M values, k = 32), else 512-thread
+  // workgroups, two per CU when the array needs more windows than CUs.
+  int wg = p.wg;
+  if (wg == 0) {
+    const int64_t cap1024 = std::max<int64_t>(1, window_floats(1024) - 2 * (int64_t)k_req);
+    wg = (variant != RED_VARIANT_RELAUNCH && n >= (int64_t)4 * 1024 * dev.cus &&
+          (n + cap1024 - 1) / cap1024 <= dev.cus)
+             ? 1024
+             : 512;
+  }
+  const int64_t lds_floats = window_floats(wg);
 
   // Persistent geometry: one workgroup per CU unless the array needs more
   // LDS windows, never more than are co-resident with the largest window,
@@ -216,7 +231,12 @@ int stencil_launch(float* u, float* scratch, int64_t n, int steps, float r, int 
     int rc = stencil_coresident(wg, (size_t)stencil_window_alloc((int)lds_floats) * 4, dev, &g_max);
     if (rc) return rc;
     const int64_t cap = std::max<int64_t>(1, lds_floats - 2 * (int64_t)k_req);  // block values per window
-    int64_t g = p.grid > 0 ? p.grid : std::max<int64_t>(dev.cus, (n + cap - 1) / cap);
+    // More windows than CUs: a whole number of workgroups per CU, so that no
+    // CU holds one block more than the others (4 M values need 259 windows
+    // of 64 KB: 512 of half the size keep every CU equally loaded).
+    const int64_t need = (n + cap - 1) / cap;
+    int64_t g = p.grid > 0 ? p.grid
+                           : need <= dev.cus ? (int64_t)dev.cus : (need + dev.cus - 1) / dev.cus * dev.cus;
     g = std::max<int64_t>(1, std::min<int64_t>({g, (int64_t)g_max, (n + 63) / 64}));
     m = (n + g - 1) / g;
     grid = (int)((n + m - 1) / m);
