@@ -218,7 +218,8 @@ def summarize_extensions(rows, line, out_dir):
           "python3 bench.py --summarize-trace <dir> <bench line of that run>", "```", "",
           "Workloads: %d fp32 values in %d log-uniform segments, plan `%s` (graph replay and direct "
           "launches); a 1D Jacobi stencil on %d values, %d steps per call, one launch per step and "
-          "the persistent form with a grid barrier every 32 steps."
+          "the persistent form with a grid barrier every 32 steps, and every k steps for the halo "
+          "width k the library picks."
           % (seg["values"], seg["segments"], json.dumps(seg["plan"]), st["n"], st["steps"]), "",
           "| Kernel | Calls | Average (us) | Min (us) | Max (us) |", "|---|---|---|---|---|"]
     for r in pick:
@@ -236,7 +237,9 @@ def summarize_extensions(rows, line, out_dir):
                "- The bench line's own event timing of a whole call: %.1f us replayed from the graph, %.1f us "
                "launched directly." % (seg["graph_us"], seg["direct_us"])]
     md += ["- Stencil, from the bench line: %.3f us per step with one launch per step, %.3f us in the "
-           "persistent form." % (st["relaunch_us_per_step"], st["persistent_k32_us_per_step"]),
+           "persistent form at k = 32%s." % (st["relaunch_us_per_step"], st["persistent_k32_us_per_step"],
+                                             ", %.3f us with the library's halo" % st["persistent_auto_us_per_step"]
+                                             if "persistent_auto_us_per_step" in st else ""),
            "- The bench-line figures of this run were taken under the profiler, which adds time to every "
            "launch (most visible in the one-launch-per-step stencil)."]
     with open(os.path.join(out_dir, "k_segmented_and_stencil_kernel_trace.md"), "w") as fh:
@@ -397,7 +400,8 @@ def stencil_configs(R, dev, stream, emit, timed):
     sh = stream.cuda_stream
     forms = [("relaunch", R.RED_VARIANT_RELAUNCH, 0, 0), ("persistent_k1", R.RED_VARIANT_PERSISTENT, 1, 0),
              ("persistent_k8", R.RED_VARIANT_PERSISTENT, 8, 0), ("persistent_k32", R.RED_VARIANT_PERSISTENT, 32, 0),
-             ("persistent_xcd_k8", R.RED_VARIANT_PERSISTENT, 8, R.FLAG_XCD)]
+             ("persistent_xcd_k8", R.RED_VARIANT_PERSISTENT, 8, R.FLAG_XCD),
+             ("persistent_auto", R.RED_VARIANT_PERSISTENT, 0, 0)]
     for n in (1 << 16, 1 << 20, 1 << 22, 8_000_000):
         steps = 1000 if n <= (1 << 20) else 200
         x = torch.from_numpy(inputs.normal_f32(n, sub=66)).to("cuda")
@@ -918,7 +922,8 @@ def headline(args, R, dev, stream, sh, plans, inputs):
         u = torch.from_numpy(inputs.normal_f32(n_st, sub=66)).to("cuda")
         sc = torch.empty_like(u)
         st = {"n": n_st, "steps": steps_st}
-        for name, variant, k in (("relaunch", R.RED_VARIANT_RELAUNCH, 0), ("persistent_k32", R.RED_VARIANT_PERSISTENT, 32)):
+        for name, variant, k in (("relaunch", R.RED_VARIANT_RELAUNCH, 0), ("persistent_k32", R.RED_VARIANT_PERSISTENT, 32),
+                                 ("persistent_auto", R.RED_VARIANT_PERSISTENT, 0)):
             o = R.make_opts(variant=variant)
             fn = lambda: R.stencil_jacobi_1d(u.data_ptr(), sc.data_ptr(), n_st, steps_st, 0.25, k, sh, o)
             fn()

@@ -265,7 +265,9 @@ int red_sum_segmented_loop(const float *x, const int64_t *host_offsets, int64_t 
  *   r        the step's coefficient (stable for 0 <= r <= 1/2).
  *   steps_per_sync  persistent form: steps between grid barriers, which
  *            is also the halo width each workgroup keeps (1 = a barrier
- *            every step); 0 = 8.  Any value gives the same result.
+ *            every step); 0 = chosen by the library: the widest halo up to
+ *            128 that the LDS window holds beside the block (the block
+ *            length is set as for 8).  Any value gives the same result.
  *   opts     NULL or plan.variant:
  *            RED_VARIANT_RELAUNCH    one kernel launch per step (the
  *                                    implicit barrier), u and scratch
