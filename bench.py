@@ -157,7 +157,7 @@ def summarize_pmc(fetch_dir, write_dir, bench_json, out_dir):
     log("traffic %d B per launch (%.5fx algorithmic)" % (traffic, traffic / algo))
 
 
-def summarize_trace(trace_dir, bench_json, out_dir):
+def summarize_trace(trace_dir, bench_json, out_dir, plain_json=None):
     """Kernel-trace summary of a profiled bench run: the per-kernel
     statistics of rocprofv3 --kernel-trace --stats beside the bench line's
     own event timing of the dominant kernel."""
@@ -175,7 +175,8 @@ def summarize_trace(trace_dir, bench_json, out_dir):
     md = ["# Kernel trace: fp32 2^28 compensated sum (headline workload)", "",
           "Command (repository root, plans from `paper_2004_05371_amd/tuned_plans.json`), then the summary:", "",
           "```", "rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- python3 bench.py",
-          "python3 bench.py --summarize-trace <dir> <bench line of that run>", "```", "",
+          "python3 bench.py --summarize-trace <dir> <bench line of that run> [<bench line of a run of python3 bench.py>]",
+          "```", "",
           "Device: %s. Plan `%s`." % ("MI355X (gfx950, 256 CUs, 8 XCDs)", json.dumps(plan)), "",
           "| Kernel | Calls | Average (us) | Min (us) | Max (us) |", "|---|---|---|---|---|"]
     for r in rows[:12]:
@@ -189,10 +190,16 @@ def summarize_trace(trace_dir, bench_json, out_dir):
            % (name.split("(")[0].replace("void redsum::", ""), dom[0]["Calls"], avg_ns / 1e3),
            "  %.1f GB/s for %d algorithmic bytes (%.1f %% of 8 TB/s)."
            % (algo / avg_ns, algo, 100 * algo / avg_ns / 8000),
-           "- The bench line of the same run: HIP events around that kernel on its stream, mean %.2f us"
+           "- The bench line of the same run: HIP events carried by that kernel's dispatch on its stream, mean %.2f us"
            % line["extra"]["dominant_kernel_mean_us"],
-           "  (roofline.achieved %.1f GB/s); wall rate %.1f GB/s. Events include the dispatch latency."
-           % (line["roofline"]["achieved"], line["value"]),
+           "  (roofline.achieved %.1f GB/s); wall rate %.1f GB/s." % (line["roofline"]["achieved"], line["value"])]
+    if plain_json:
+        plain = last_json_line(plain_json)
+        md += ["- The same command without the profiler (a separate run): events mean %.2f us, roofline.achieved"
+               " %.1f GB/s (frac %.4f); the profiler adds time to the events of every dispatch."
+               % (plain["extra"]["dominant_kernel_mean_us"], plain["roofline"]["achieved"],
+                  plain["roofline"]["frac"])]
+    md += [
            "- Other rows come from the variant table and the probes of the same bench run."]
     with open(os.path.join(out_dir, "k_partials_f32_2p28_kernel_trace.md"), "w") as fh:
         fh.write("\n".join(md) + "\n")
@@ -768,8 +775,9 @@ def main():
                     help="after the headline, copy the 1 GiB input 3 times (byte-counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "BENCH_JSON"),
                     help="no GPU: write the HBM traffic summary from two rocprofv3 --pmc runs")
-    ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "BENCH_JSON"),
-                    help="no GPU: write the kernel-trace summary of a profiled bench run")
+    ap.add_argument("--summarize-trace", nargs="+", metavar="TRACE_DIR BENCH_JSON [PLAIN_BENCH_JSON]",
+                    help="no GPU: write the kernel-trace summary of a profiled bench run (optionally beside "
+                         "the bench line of a run without the profiler)")
     ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles"), metavar="DIR")
     args = ap.parse_args()
     if args.summarize_pmc or args.summarize_trace:
@@ -777,7 +785,10 @@ def main():
         if args.summarize_pmc:
             summarize_pmc(*args.summarize_pmc, args.summary_out)
         if args.summarize_trace:
-            summarize_trace(*args.summarize_trace, args.summary_out)
+            if len(args.summarize_trace) not in (2, 3):
+                ap.error("--summarize-trace takes TRACE_DIR BENCH_JSON [PLAIN_BENCH_JSON]")
+            summarize_trace(*args.summarize_trace[:2], args.summary_out,
+                            args.summarize_trace[2] if len(args.summarize_trace) == 3 else None)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -828,8 +839,8 @@ def headline(args, R, dev, stream, sh, plans, inputs):
     for _ in range(args.warmup):
         step()
     # Timed region: K steps between two synchronizations, with the library
-    # recording HIP events around the dominant kernel of every
-    # TIMER_PERIOD-th step (on the stream it runs on) for the roofline.
+    # timing the dominant kernel of every TIMER_PERIOD-th step by HIP events
+    # carried in its own dispatch (on the stream it runs on) for the roofline.
     torch.cuda.synchronize()
     R.red_kernel_timer(sh, TIMER_PERIOD)
     t0 = time.perf_counter()

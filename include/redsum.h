@@ -425,12 +425,17 @@ int sync_xcc_map(int n_wg, int wg_size, int32_t *host_xcc, void *stream);
  * Measurement helpers (not part of a reduction)
  * ------------------------------------------------------------------- */
 
-/* While enabled on `stream`, reduction / segmented launches on it record a
- * pair of HIP events (without system-scope fences) around their dominant
- * streaming kernel (the partials kernel of the relaunch variant, the single
- * kernel otherwise).  enable = 0 turns the timer off; enable = k > 0 times
- * every k-th launch (k > 1 keeps the events' own cost off most launches).
- * Enabling clears earlier records.  Not recorded inside stream capture. */
+/* While enabled on `stream`, reduction / segmented / stencil launches on it
+ * time their dominant streaming kernel (the partials kernel of the relaunch
+ * variant, the single kernel otherwise) with a pair of HIP events without
+ * system-scope fences.  An ordinary launch of a reduction kernel carries
+ * the events in its own dispatch (hipExtLaunchKernel), so they take the
+ * kernel's start and end as a kernel trace does; a cooperative launch, the
+ * segmented batch (slice and fix-up kernels) and the persistent stencil
+ * are bracketed by events recorded before and after them.  enable = 0
+ * turns the timer off; enable = k > 0 times every k-th launch (k > 1 keeps
+ * the events' own cost off most launches).  Enabling clears earlier
+ * records.  Not recorded inside stream capture. */
 int red_kernel_timer(void *stream, int enable);
 
 /* Synchronize `stream` and report the timed launches: mean and minimum

@@ -73,10 +73,16 @@ bool stream_capturing(hipStream_t s);
 unsigned watchdog_spins();
 unsigned barrier_groups(int grid);  // REDSUM_BARRIER_GROUPS, else the default policy
 
-// Dominant-kernel timer: timer_begin returns a slot (or -1 when the timer
-// is off / the stream is capturing), timer_end closes it.
+// Dominant-kernel timer: timer_begin records a slot's start event and
+// returns the slot (or -1 when the timer is off / the stream is
+// capturing), timer_end records its stop event; the two bracket whatever
+// is launched between them.  launch_timed launches one kernel whose
+// events, when a slot is due, are the kernel's own start and end
+// (hipExtLaunchKernel); a cooperative launch is bracketed instead.
 int timer_begin(hipStream_t s);
 void timer_end(hipStream_t s, int slot);
+int launch_timed(const void* fn, int grid, int block, void** args, hipStream_t s, bool cooperative,
+                 size_t lds_bytes = 0);
 
 // Kernel launch (uniform signature: one argument struct by value).
 int launch(const void* fn, int grid, int block, void** args, hipStream_t s, bool cooperative, size_t lds_bytes = 0);

@@ -460,9 +460,7 @@ int reduce_launch(const ReduceLaunch& rl, const void* x, int64_t n, void* out, W
   void* args[] = {&a};
   switch (p.variant) {
     case RED_VARIANT_RELAUNCH: {
-      const int slot = timer_begin(s);
-      int rc = launch(ks.partials, grid, p.wg, args, s, false);
-      timer_end(s, slot);
+      int rc = launch_timed(ks.partials, grid, p.wg, args, s, false);
       if (rc) return rc;
       // Up to 1024 partials: one wavefront (at most 16 loads per lane);
       // beyond: one 256-thread workgroup.
@@ -476,16 +474,10 @@ int reduce_launch(const ReduceLaunch& rl, const void* x, int64_t n, void* out, W
       return launch(fn, 1, wave ? kWave : kFinalWG, fargs, s, false);
     }
     case RED_VARIANT_SINGLE: {
-      const int slot = timer_begin(s);
-      int rc = launch(ks.single, 1, p.wg, args, s, false);
-      timer_end(s, slot);
-      return rc;
+      return launch_timed(ks.single, 1, p.wg, args, s, false);
     }
     case RED_VARIANT_ATOMIC: {
-      const int slot = timer_begin(s);
-      int rc = launch(ks.atomic, grid, p.wg, args, s, false);
-      timer_end(s, slot);
-      return rc;
+      return launch_timed(ks.atomic, grid, p.wg, args, s, false);
     }
     case RED_VARIANT_PERSISTENT: {
       int maxg = 0;
@@ -497,10 +489,7 @@ int reduce_launch(const ReduceLaunch& rl, const void* x, int64_t n, void* out, W
       grid = std::min(grid, maxg);
       if (grid < 1) return set_error(RED_EINVAL, "persistent kernel cannot be resident");
       a.bar_groups = xcd ? (kBarrierXcd | (unsigned)dev.nxcc) : barrier_groups(grid);
-      const int slot = timer_begin(s);
-      rc = launch(ks.persistent, grid, p.wg, args, s, (p.flags & RED_FLAG_PLAIN_LAUNCH) == 0);
-      timer_end(s, slot);
-      return rc;
+      return launch_timed(ks.persistent, grid, p.wg, args, s, (p.flags & RED_FLAG_PLAIN_LAUNCH) == 0);
     }
   }
   return set_error(RED_EINVAL, "unknown variant %d", p.variant);

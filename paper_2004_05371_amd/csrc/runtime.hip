@@ -13,6 +13,8 @@
 #include <tuple>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "device_prims.h"
 #include "internal.h"
 
@@ -220,7 +222,11 @@ struct KernelTimer {
 std::map<std::pair<int, hipStream_t>, KernelTimer> g_timers;
 }  // namespace
 
-int timer_begin(hipStream_t s) {
+namespace {
+// A slot of the stream's timer for this launch (every period-th launch
+// while the timer is on), or -1; with `record`, its start event is
+// recorded on the stream now.
+int timer_acquire(hipStream_t s, bool record, hipEvent_t* start = nullptr, hipEvent_t* stop = nullptr) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -1;
   std::lock_guard<std::mutex> lk(g_mu);
@@ -239,12 +245,17 @@ int timer_begin(hipStream_t s) {
     t.ev.emplace_back(a, b);
   }
   const int slot = (int)t.used++;
-  if (hipEventRecord(t.ev[slot].first, s) != hipSuccess) {
+  if (record && hipEventRecord(t.ev[slot].first, s) != hipSuccess) {
     --t.used;
     return -1;
   }
+  if (start) *start = t.ev[slot].first;
+  if (stop) *stop = t.ev[slot].second;
   return slot;
 }
+}  // namespace
+
+int timer_begin(hipStream_t s) { return timer_acquire(s, true); }
 
 void timer_end(hipStream_t s, int slot) {
   if (slot < 0) return;
@@ -254,6 +265,26 @@ void timer_end(hipStream_t s, int slot) {
   auto it = g_timers.find(std::make_pair(dev, s));
   if (it == g_timers.end() || (size_t)slot >= it->second.ev.size()) return;
   (void)hipEventRecord(it->second.ev[slot].second, s);
+}
+
+int launch_timed(const void* fn, int grid, int block, void** args, hipStream_t s, bool cooperative,
+                 size_t lds_bytes) {
+  if (cooperative) {
+    const int slot = timer_begin(s);
+    const int rc = launch(fn, grid, block, args, s, true, lds_bytes);
+    timer_end(s, slot);
+    return rc;
+  }
+  hipEvent_t a = nullptr, b = nullptr;
+  if (timer_acquire(s, false, &a, &b) < 0) return launch(fn, grid, block, args, s, false, lds_bytes);
+  // The events ride on the kernel's own dispatch: they take its start and
+  // end, as a kernel trace reports them.
+  const hipError_t e = hipExtLaunchKernel(fn, dim3(grid), dim3(block), args, lds_bytes, s, a, b, 0);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return hip_fail(e, "hipExtLaunchKernel");
+  }
+  return RED_OK;
 }
 
 int launch(const void* fn, int grid, int block, void** args, hipStream_t s, bool cooperative, size_t lds_bytes) {

@@ -189,6 +189,19 @@ def test_kernel_timer(lib):
     mean_us, min_us, count = lib.red_kernel_timer_read(s)
     lib.red_kernel_timer(s, False)
     assert count == 3 and 0 < min_us <= mean_us < 1e5
+    # A plain launch carries the events in its own dispatch: the partials
+    # kernel takes no longer than the whole call (both kernels) timed by
+    # events recorded around it on the same stream.
+    for v in (1, 2):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        lib.red_kernel_timer(s, True)
+        a.record()
+        lib.sum(x, opts=lib.make_opts(variant=v))
+        b.record()
+        torch.cuda.synchronize()
+        k_us, _, count = lib.red_kernel_timer_read(s)
+        lib.red_kernel_timer(s, False)
+        assert count == 1 and 0 < k_us <= a.elapsed_time(b) * 1e3, (v, k_us, a.elapsed_time(b))
 
 
 def test_dispatch_is_round_robin_over_xcds(lib):
