@@ -212,16 +212,17 @@ int red_sum_ex(int dtype, const void *x, int64_t n, void *out, void *stream, con
  *           offsets[0] == 0 (not checked on the device).
  *   nseg    number of segments, 0 <= nseg < 2^31.
  *   out     device pointer to nseg doubles.  Empty segments give 0.
- * One launch of a fixed grid: every workgroup (long segments) or every
- * wavefront (short ones) owns an equal slice of the elements and sums the
- * pieces of the segments that meet its slice; for very short segments a
- * wavefront reduces by key over runs of consecutive values with a
- * segmented scan across its lanes.  The pieces of segments that cross slice
- * boundaries are combined in slice order in binary64 (see
- * red_sum_segmented_ex for the ways of doing so; the default plan's).  The launch is captured in a hipGraph
- * on the first call for a given (x, offsets, nseg, out, stream, plan) and
- * replayed afterwards; when the stream is already being captured by the
- * caller the kernel is simply launched into that capture.
+ * A fixed grid: every workgroup (long segments) or every wavefront (short
+ * ones) owns an equal slice of the elements and sums the pieces of the
+ * segments that meet its slice; for very short segments a wavefront
+ * reduces by key over runs of consecutive values with a segmented scan
+ * across its lanes.  The pieces of segments that cross slice boundaries
+ * are combined in slice order in binary64, by default by a second, small
+ * kernel (red_sum_segmented_ex lists the other ways).  The kernels are
+ * captured in a hipGraph on the first call for a given (x, offsets, nseg,
+ * out, stream, plan) and replayed afterwards; when the stream is already
+ * being captured by the caller they are simply launched into that
+ * capture.
  * Errors: RED_EINVAL, RED_EHIP, RED_ENOMEM. */
 int red_sum_segmented(const float *x, const int64_t *offsets, int64_t nseg, double *out, void *stream);
 
@@ -231,8 +232,9 @@ int red_sum_segmented(const float *x, const int64_t *offsets, int64_t nseg, doub
  * between launches; both kernels go into the graph), RED_VARIANT_ATOMIC
  * (the last contributor, found by an atomic ticket after a release fence)
  * or RED_VARIANT_PERSISTENT (the owning slice after a grid barrier;
- * co-resident grid, launched directly, not from a graph).  plan.wg is at most 512 here (RED_EINVAL
- * otherwise); grid x wg / 64 wavefront slices are capped at 65536.
+ * co-resident grid, launched directly, not from a graph).  plan.wg is at
+ * most 512 here (RED_EINVAL otherwise); grid x wg / 64 wavefront slices
+ * are capped at 65536.
  * RED_FLAG_NO_GRAPH disables graph capture; RED_FLAG_SEG_WORKGROUP,
  * RED_FLAG_SEG_PIECES or RED_FLAG_SEG_RUNS forces one form (RED_EINVAL for
  * two of them, or for RED_FLAG_SEG_RUNS with plan.ipt > 4). */
