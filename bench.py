@@ -932,18 +932,21 @@ def headline(args, R, dev, stream, sh, plans, inputs):
         od = R.make_opts(variant=sp.variant, wg=sp.wg, ipt=sp.ipt, grid=sp.grid, flags=sp.flags | R.FLAG_NO_GRAPH)
         seg_bytes = xst.numel() * 4 + ot.numel() * 8 + nseg * 8
         seg = {"values": int(off[-1]), "segments": nseg, "plan": sp.as_dict()}
-        for name, fn in (("graph", lambda: R.red_sum_segmented(xst.data_ptr(), ot.data_ptr(), nseg, so.data_ptr(), sh)),
-                         ("direct", lambda: R.red_sum_segmented_ex(xst.data_ptr(), ot.data_ptr(), nseg, so.data_ptr(),
-                                                                   sh, od))):
-            for _ in range(3):
-                fn()
-            # back-to-back calls (batch throughput), and each call between
-            # its own pair of events (which delays the next graph replay)
-            ms = time_loop(fn, 20, stream)
-            seg[name + "_us"] = round(ms * 1e3, 1)
-            seg[name + "_GBps"] = gbps(seg_bytes, ms)
-            tt, _ = time_steps(fn, 20, stream)
-            seg[name + "_us_events_per_call"] = round(statistics.median(tt) * 1e3, 1)
+        forms = (("graph", lambda: R.red_sum_segmented(xst.data_ptr(), ot.data_ptr(), nseg, so.data_ptr(), sh)),
+                 ("direct", lambda: R.red_sum_segmented_ex(xst.data_ptr(), ot.data_ptr(), nseg, so.data_ptr(), sh, od)))
+        # Two rounds over both forms, the second one kept (the first series
+        # after a pause runs slower): back-to-back calls (batch throughput),
+        # and each call between its own pair of events (which delays the
+        # next graph replay).
+        for _ in range(2):
+            for name, fn in forms:
+                for _ in range(3):
+                    fn()
+                ms = time_loop(fn, 20, stream)
+                seg[name + "_us"] = round(ms * 1e3, 1)
+                seg[name + "_GBps"] = gbps(seg_bytes, ms)
+                tt, _ = time_steps(fn, 20, stream)
+                seg[name + "_us_events_per_call"] = round(statistics.median(tt) * 1e3, 1)
         extra["segmented_10000"] = seg
         del xst, ot, so
         torch.cuda.empty_cache()
