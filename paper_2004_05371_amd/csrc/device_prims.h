@@ -527,7 +527,9 @@ __device__ __forceinline__ bool xcd_top(BarrierWords* w, Line& top, unsigned nbl
 //   kBarrierXcd | nxcc
 //            XCD-aggregated: the first level is the XCD, with one L2
 //            write-back per XCD (xcd_arrive above).
-// Thread 0 of each workgroup reads the generation first; the last top-level
+// Thread 0 of each workgroup keeps the generation in `gen` (read once per
+// launch with grid_barrier_gen, then advanced by each barrier, so no
+// barrier waits for a load of it before arriving); the last top-level
 // arrival resets the counter, acquires, releases and bumps the generation;
 // the others poll it with relaxed device-scope loads (s_sleep between
 // polls, so polling neither invalidates the L2 nor floods the atomic unit)
@@ -539,8 +541,16 @@ __device__ __forceinline__ bool xcd_top(BarrierWords* w, Line& top, unsigned nbl
 // VIII-B of the paper).  Counters are back at zero after every completed
 // barrier.  Returns false on timeout.
 // ---------------------------------------------------------------------------
+// The barrier generation at the start of a launch, for thread 0 of each
+// workgroup to pass to its grid_barrier calls.  A barrier completes only
+// once every workgroup has arrived, so every workgroup that reads this
+// before its first arrival reads the same value.
+__device__ __forceinline__ unsigned grid_barrier_gen(BarrierWords* w) {
+  return threadIdx.x == 0 ? __hip_atomic_load(&w->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+}
+
 __device__ __forceinline__ bool grid_barrier(BarrierWords* w, unsigned nblocks, unsigned groups,
-                                             unsigned spin_limit) {
+                                             unsigned spin_limit, unsigned& gen) {
   __shared__ int timed_out;
   const bool xcd = (groups & kBarrierXcd) != 0;
   // Every wave drains its own stores first, so they are in its XCD's L2
@@ -550,7 +560,7 @@ __device__ __forceinline__ bool grid_barrier(BarrierWords* w, unsigned nblocks, 
   __syncthreads();
   if (threadIdx.x == 0) {
     int to = 0;
-    const unsigned g = __hip_atomic_load(&w->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned g = gen;
     bool last = false;
     if (xcd) {
       const unsigned nxcc = groups & 0xFFu;
@@ -587,6 +597,7 @@ __device__ __forceinline__ bool grid_barrier(BarrierWords* w, unsigned nblocks, 
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    gen = g + 1u;
     timed_out = to;
   }
   __syncthreads();

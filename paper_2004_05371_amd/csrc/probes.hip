@@ -94,9 +94,10 @@ __global__ __launch_bounds__(1024) void k_block_chain(int r, long long* cycles) 
 
 __global__ __launch_bounds__(1024) void k_grid_chain(int r, BarrierWords* w, unsigned groups,
                                                     unsigned spin_limit, long long* stamps) {
+  unsigned gen = grid_barrier_gen(w);
   __syncthreads();
   const long long t0 = __builtin_amdgcn_s_memrealtime();
-  for (int i = 0; i < r; ++i) grid_barrier(w, gridDim.x, groups, spin_limit);
+  for (int i = 0; i < r; ++i) grid_barrier(w, gridDim.x, groups, spin_limit, gen);
   const long long t1 = __builtin_amdgcn_s_memrealtime();
   if (blockIdx.x == 0 && threadIdx.x == 0) stamps[0] = t1 - t0;
 }
@@ -111,9 +112,10 @@ __global__ __launch_bounds__(1024) void k_spin(long long ticks) {
 
 __global__ __launch_bounds__(1024) void k_grid_order(BarrierWords* w, unsigned groups, unsigned spin_limit,
                                                     long long* before, long long* after) {
+  unsigned gen = grid_barrier_gen(w);
   __syncthreads();
   if (threadIdx.x == 0) before[blockIdx.x] = __builtin_amdgcn_s_memrealtime();
-  grid_barrier(w, gridDim.x, groups, spin_limit);
+  grid_barrier(w, gridDim.x, groups, spin_limit, gen);
   if (threadIdx.x == 0) after[blockIdx.x] = __builtin_amdgcn_s_memrealtime();
 }
 
@@ -128,11 +130,12 @@ __global__ __launch_bounds__(1024) void k_grid_visibility(BarrierWords* w, unsig
                                                          int rounds) {
   const unsigned G = gridDim.x;
   unsigned long long bad = 0;
+  unsigned gen = grid_barrier_gen(w);
   for (int r = 0; r < rounds; ++r) {
     if (threadIdx.x == 0) data[blockIdx.x] = (long long)r * G + blockIdx.x;
-    if (!grid_barrier(w, G, groups, spin_limit)) break;
+    if (!grid_barrier(w, G, groups, spin_limit, gen)) break;
     for (unsigned i = threadIdx.x; i < G; i += blockDim.x) bad += data[i] != (long long)r * G + i;
-    if (!grid_barrier(w, G, groups, spin_limit)) break;
+    if (!grid_barrier(w, G, groups, spin_limit, gen)) break;
   }
   if (bad) atomicAdd(errors, bad);
 }
@@ -141,7 +144,8 @@ __global__ __launch_bounds__(1024) void k_grid_visibility(BarrierWords* w, unsig
 __global__ __launch_bounds__(1024) void k_watchdog(BarrierWords* w, int skip, unsigned groups,
                                                   unsigned spin_limit) {
   if ((int)blockIdx.x == skip) return;
-  grid_barrier(w, gridDim.x, groups, spin_limit);
+  unsigned gen = grid_barrier_gen(w);
+  grid_barrier(w, gridDim.x, groups, spin_limit, gen);
 }
 
 // XCD of every workgroup (thread 0 records it).

@@ -239,9 +239,10 @@ __global__ __launch_bounds__(1024) void k_atomic(ReduceArgs a) {
 template <class M, int IPT, bool NT, bool PIPE>
 __global__ __launch_bounds__(1024) void k_persistent(ReduceArgs a) {
   using Part = typename M::Part;
+  unsigned gen = grid_barrier_gen(a.words);
   Part p = workgroup_partial<M, IPT, NT, PIPE>(a);
   if (threadIdx.x == 0) static_cast<Part*>(a.partials)[blockIdx.x] = p;
-  grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit);
+  grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit, gen);
   if (blockIdx.x != 0) return;
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   Part s = combine_partials<Part>(static_cast<const Part*>(a.partials), gridDim.x);

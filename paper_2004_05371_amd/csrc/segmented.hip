@@ -242,6 +242,8 @@ constexpr int64_t kRunsMeanLen = 1024;
 // w and streams it as tiles of 64 x IPT vectors.
 template <int IPT, bool NT, int FIX>
 __device__ __forceinline__ void seg_wave_slices(const SegArgs& a) {
+  // Barrier fix-up: thread 0 holds the barrier generation of this launch.
+  unsigned gen = FIX == kFixBarrier ? grid_barrier_gen(a.words) : 0u;
   using M = ModeF32Comp;
   const int nwaves = blockDim.x / kWave;
   const int lane = __lane_id();
@@ -331,7 +333,7 @@ __device__ __forceinline__ void seg_wave_slices(const SegArgs& a) {
     for (int u = 0; u < IPT; ++u) cur[u] = nxt[u];
   }
   if constexpr (FIX == kFixBarrier) {
-    grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit);
+    grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit, gen);
     if (own_fix >= 0) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       const int64_t o = offset_at(a.offsets, own_fix) / chunk;
@@ -384,6 +386,8 @@ __device__ __forceinline__ int run_swz(int i) {
 
 template <int IPT, bool NT, int FIX>
 __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all) {
+  // Barrier fix-up: thread 0 holds the barrier generation of this launch.
+  unsigned gen = FIX == kFixBarrier ? grid_barrier_gen(a.words) : 0u;
   static_assert(IPT <= 4, "runs of at most 16 values");
   using M = ModeF32Comp;
   const int nwaves = blockDim.x / kWave;
@@ -652,7 +656,7 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
     seek_segment(a, s, hi, E, end_slice, sa, sb, lane == 0);  // empty segments at E
   }
   if constexpr (FIX == kFixBarrier) {
-    grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit);
+    grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit, gen);
     if (own_fix >= 0) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       const int64_t o = offset_at(a.offsets, own_fix) / chunk;
@@ -680,6 +684,8 @@ struct WorkgroupLds {
 
 template <int IPT, bool NT, int FIX>
 __device__ __forceinline__ void seg_workgroup_slices(const SegArgs& a, WorkgroupLds& lds) {
+  // Barrier fix-up: thread 0 holds the barrier generation of this launch.
+  unsigned gen = FIX == kFixBarrier ? grid_barrier_gen(a.words) : 0u;
   using M = ModeF32Comp;
   auto& part = lds.part;
   auto& info = lds.info;
@@ -802,7 +808,7 @@ __device__ __forceinline__ void seg_workgroup_slices(const SegArgs& a, Workgroup
   }
   if (nb > 0) flush();
   if constexpr (FIX == kFixBarrier) {
-    grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit);  // also a workgroup barrier
+    grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit, gen);  // also a workgroup barrier
     const int64_t os = own_fix;
     if (os >= 0 && wave == 0) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");

@@ -81,6 +81,7 @@ __host__ __device__ inline int stencil_window_alloc(int len) { return ((len + 3)
 
 template <int ROWS>
 __global__ __launch_bounds__(1024) void k_jacobi_persistent(StencilArgs a) {
+  unsigned gen = grid_barrier_gen(a.words);  // thread 0: the barrier generation of this launch
   extern __shared__ v4f win4[];  // 16-byte aligned window
   float* win = reinterpret_cast<float*>(win4);  // win[j] = element lo - k + j, j in [0, len)
   const int64_t n = a.n;
@@ -156,7 +157,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_persistent(StencilArgs a) {
         pub[lo + j] = win[k + j];
         pub[hi - 1 - j] = win[k + blen - 1 - j];
       }
-      grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit);
+      grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit, gen);
       for (int j = tid; j < k; j += bs) {
         const int64_t el = lo - k + j;  // left halo: the left neighbour's last k values
         if (el >= 0) win[j] = pub[el];
@@ -170,7 +171,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_persistent(StencilArgs a) {
   // Neighbours read u for their initial halos and, at odd exchanges, as the
   // publication buffer: the block is written back only once every
   // workgroup is past its last read of u.
-  grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit);
+  grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit, gen);
   for (int j = tid; j < blen; j += bs) a.u[lo + j] = win[k + j];
 }
 
