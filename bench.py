@@ -41,7 +41,7 @@ CSRC = os.path.join(ROOT, "paper_2004_05371_amd", "csrc")
 # Sources of the dominant streaming kernel (the traffic summary is tied to them).
 KERNEL_SOURCES = ("device_prims.h", "reduce.hip")
 # The timed loop records kernel events on every TIMER_PERIOD-th step.
-TIMER_PERIOD = 8
+TIMER_PERIOD = 20
 
 
 def log(*a):
