@@ -29,8 +29,9 @@ def run(lib, x, off, variant=0, wg=0, ipt=0, grid=0, flags=0):
     return out.cpu().numpy()[:nseg]
 
 
-def check(res, x, off):
-    sums = oracle.segmented_sums(x, off)
+def check(res, x, off, sums=None):
+    if sums is None:
+        sums = oracle.segmented_sums(x, off)
     for k, ex in enumerate(sums):
         if ex.fraction == 0:
             a = float(oracle.exact_abs_sum(x[off[k]:off[k + 1]], "f32").fraction)
@@ -313,12 +314,16 @@ def test_loop_baseline_matches(lib):
 
 
 def test_full_batch_config(lib):
-    """10,000 log-uniform segments in [1, 2^20] (about 7.4e8 values)."""
+    """10,000 log-uniform segments in [1, 2^20] (about 7.4e8 values): the
+    default plan, the cached plan the bench line times (relaunch fix-up,
+    256 x 4, grid 1024, nontemporal, graph replay) and the barrier fix-up."""
     x, off = inputs.segments(10000)
     say("segments total", int(off[-1]))
-    for p in (dict(), dict(variant=3, wg=512, ipt=4, grid=256)):
+    sums = oracle.segmented_sums(x, off)
+    for p in (dict(), dict(variant=1, wg=256, ipt=4, grid=1024, flags=1), dict(variant=3, wg=512, ipt=4, grid=256)):
+        say("plan", p)
         res = run(lib, x, off, **p)
-        check(res, x, off)
+        check(res, x, off, sums)
 
 
 @pytest.mark.parametrize("L", [64, 768])

@@ -100,6 +100,19 @@ def test_large_persistent_and_auto_fallback(lib):
     assert np.array_equal(t.cpu().numpy(), oracle.jacobi_1d_f32(big, 3, 0.25))
 
 
+@pytest.mark.parametrize("n,steps,spsync,flags", [(1 << 22, 200, 0, 0), (1 << 22, 200, 32, 0), (1 << 22, 130, 0, 16),
+                                                  (8_000_000, 60, 0, 0)])
+def test_bench_sizes_default_geometry(lib, n, steps, spsync, flags):
+    """The 4 M-value workload of the bench line and the 8 M-value table size
+    in the default geometry (a whole number of workgroups per CU, the
+    library's halo, or k = 32; XCD-aggregated barrier), bit for bit."""
+    x = inputs.normal_f32(n, sub=66)
+    say("stencil", n, "values,", steps, "steps, steps_per_sync", spsync, "flags", flags)
+    want = oracle.jacobi_1d_f32(x, steps, 0.25)
+    got = run(lib, x, steps, 0.25, variant=PERSISTENT, spsync=spsync, flags=flags)
+    assert np.array_equal(got, want), np.flatnonzero(got != want)[:5]
+
+
 def test_repeat_and_graph_capture(lib):
     """The persistent launch recorded into a caller's graph and replayed:
     each replay continues from the previous state, like eager calls."""
