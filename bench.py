@@ -40,8 +40,14 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_f32_2p28.json")
 CSRC = os.path.join(ROOT, "paper_2004_05371_amd", "csrc")
 # Sources of the dominant streaming kernel (the traffic summary is tied to them).
 KERNEL_SOURCES = ("device_prims.h", "reduce.hip")
-# The timed loop records kernel events on every TIMER_PERIOD-th step.
-TIMER_PERIOD = 20
+# The timed loop records kernel events on every timer_period(steps)-th
+# step: at least this many launches of the dominant kernel are timed.
+KERNEL_LAUNCHES_TIMED = 10
+
+
+def timer_period(steps: int) -> int:
+    return max(1, steps // KERNEL_LAUNCHES_TIMED)
+
 
 
 def log(*a):
@@ -853,10 +859,11 @@ def headline(args, R, dev, stream, sh, plans, inputs):
     for _ in range(args.warmup):
         step()
     # Timed region: K steps between two synchronizations, with the library
-    # timing the dominant kernel of every TIMER_PERIOD-th step by HIP events
+    # timing the dominant kernel of every period-th step by HIP events
     # carried in its own dispatch (on the stream it runs on) for the roofline.
     torch.cuda.synchronize()
-    R.red_kernel_timer(sh, TIMER_PERIOD)
+    period = timer_period(args.steps)
+    R.red_kernel_timer(sh, period)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
@@ -864,6 +871,8 @@ def headline(args, R, dev, stream, sh, plans, inputs):
     wall = time.perf_counter() - t0
     k_mean_us, k_min_us, k_count = R.red_kernel_timer_read(sh)
     R.red_kernel_timer(sh, False)
+    if k_count < min(KERNEL_LAUNCHES_TIMED, args.steps):
+        raise RuntimeError("only %d launches of the dominant kernel were timed" % k_count)
     ms_per_step = wall * 1e3 / args.steps
     value = nbytes / (ms_per_step * 1e-3) / 1e9
     result = out.item()
@@ -882,7 +891,7 @@ def headline(args, R, dev, stream, sh, plans, inputs):
         (ms_per_step, wall_plain * 1e3 / args.steps, statistics.fmean(times), k_mean_us, k_min_us, k_count))
 
     extra = {"GBps_without_kernel_events": round(nbytes / (wall_plain / args.steps) / 1e9, 1),
-             "kernel_events_every_n_steps": TIMER_PERIOD, "kernel_launches_timed": k_count,
+             "kernel_events_every_n_steps": period, "kernel_launches_timed": k_count,
              "step_event_mean_us": round(statistics.fmean(times) * 1e3, 2),
              "dominant_kernel_mean_us": round(k_mean_us, 2), "dominant_kernel_min_us": round(k_min_us, 2)}
     extra["variants_GBps"] = variant_table(R, plan, R.RED_F32, xt, N, out, sh, stream, dev)
@@ -947,6 +956,14 @@ def headline(args, R, dev, stream, sh, plans, inputs):
                 seg[name + "_GBps"] = gbps(seg_bytes, ms)
                 tt, _ = time_steps(fn, 20, stream)
                 seg[name + "_us_events_per_call"] = round(statistics.median(tt) * 1e3, 1)
+        # The baseline the batch replaces: one red_sum launch per segment
+        # (10,000 launches, offsets read on the host).
+        loop = lambda: R.red_sum_segmented_loop(xst.data_ptr(), off, nseg, so.data_ptr(), sh)
+        loop()
+        ms = time_loop(loop, 3, stream)
+        seg["per_segment_launches_us"] = round(ms * 1e3, 1)
+        seg["per_segment_launches_GBps"] = gbps(seg_bytes, ms)
+        seg["graph_speedup_vs_per_segment_launches"] = round(ms * 1e3 / seg["graph_us"], 1)
         extra["segmented_10000"] = seg
         del xst, ot, so
         torch.cuda.empty_cache()

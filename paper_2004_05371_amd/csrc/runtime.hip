@@ -415,19 +415,33 @@ int red_init(int device) {
 
 void red_shutdown(void) {
   std::lock_guard<std::mutex> lk(g_mu);
+  // A process that never reached a device has nothing to release (and
+  // makes no HIP call here).
+  if (g_dev.empty() && g_ws.empty() && g_graphs.empty() && g_timers.empty() && g_capture_streams.empty())
+    return;
   int cur = 0;
   (void)hipGetDevice(&cur);
-  // Nothing of the library may still run: graphs and workspaces go below.
+  // Nothing of the library may still run: graphs, events and workspaces go
+  // below.
   for (auto& kv : g_dev) {
     (void)hipSetDevice(kv.first);
     (void)hipDeviceSynchronize();
   }
   for (auto& kv : g_graphs) {
+    (void)hipSetDevice(kv.first.dev);
     if (kv.second.e) (void)hipGraphExecDestroy(kv.second.e);
     if (kv.second.g) (void)hipGraphDestroy(kv.second.g);
   }
   g_graphs.clear();
   g_graph_lru.clear();
+  for (auto& kv : g_timers) {
+    (void)hipSetDevice(kv.first.first);
+    for (auto& ab : kv.second.ev) {
+      (void)hipEventDestroy(ab.first);
+      (void)hipEventDestroy(ab.second);
+    }
+  }
+  g_timers.clear();
   for (auto& kv : g_ws) {
     (void)hipSetDevice(kv.first.first);
     (void)hipFree(kv.second.base);
@@ -438,7 +452,9 @@ void red_shutdown(void) {
     (void)hipStreamDestroy(kv.second);
   }
   g_capture_streams.clear();
+  // Device records are kept: they hold no HIP object.
   (void)hipSetDevice(cur);
+  (void)hipGetLastError();
 }
 
 int red_check_error(void* stream) {

@@ -12,6 +12,7 @@ fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 from typing import Optional
@@ -134,6 +135,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
             fn.argtypes = args
             fn.restype = res
         _lib = lib
+        # Release the library's graphs, events, streams and workspaces while
+        # the HIP runtime is still whole: Python's exit handlers run before
+        # the runtime's own teardown (and before a profiler's).
+        atexit.register(lib.red_shutdown)
     return _lib
 
 
@@ -396,6 +401,19 @@ def dtype_code(t) -> int:
     return _DTYPE_CODES[t.dtype]
 
 
+def _check_out(out, dtype, count: int, device) -> None:
+    """A caller's output tensor: `dtype`, contiguous, on `device`, with room
+    for `count` results (checked before any launch writes into it)."""
+    if not out.is_cuda or not out.is_contiguous():
+        raise ValueError("out must be a contiguous CUDA tensor")
+    if out.dtype != dtype:
+        raise ValueError("out must be %s, not %s" % (dtype, out.dtype))
+    if out.device != device:
+        raise ValueError("out is on %s, the input on %s" % (out.device, device))
+    if out.numel() < count:
+        raise ValueError("out holds %d elements, %d are written" % (out.numel(), count))
+
+
 def current_stream() -> int:
     import torch
     return torch.cuda.current_stream().cuda_stream
@@ -408,8 +426,11 @@ def sum(t, out=None, opts: Optional[Opts] = None):
     if not t.is_cuda or not t.is_contiguous():
         raise ValueError("expected a contiguous CUDA tensor")
     code = dtype_code(t)
+    want = torch.int64 if code == RED_I32 else torch.float64
     if out is None:
-        out = torch.empty((), dtype=torch.int64 if code == RED_I32 else torch.float64, device=t.device)
+        out = torch.empty((), dtype=want, device=t.device)
+    else:
+        _check_out(out, want, 1, t.device)
     red_sum_ex(code, t.data_ptr(), t.numel(), out.data_ptr(), current_stream(), opts)
     return out
 
@@ -419,8 +440,17 @@ def segmented_sum(values, offsets, out=None, opts: Optional[Opts] = None):
     import torch
     if values.dtype != torch.float32 or offsets.dtype != torch.int64:
         raise TypeError("values must be float32 and offsets int64")
+    for name, t in (("values", values), ("offsets", offsets)):
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous CUDA tensor" % name)
+    if offsets.device != values.device:
+        raise ValueError("values and offsets are on different devices")
+    if offsets.dim() != 1 or offsets.numel() < 1:
+        raise ValueError("offsets must be 1-D with nseg + 1 entries")
     nseg = offsets.numel() - 1
     if out is None:
-        out = torch.empty(max(nseg, 0), dtype=torch.float64, device=values.device)
+        out = torch.empty(nseg, dtype=torch.float64, device=values.device)
+    else:
+        _check_out(out, torch.float64, nseg, values.device)
     red_sum_segmented_ex(values.data_ptr(), offsets.data_ptr(), nseg, out.data_ptr(), current_stream(), opts)
     return out

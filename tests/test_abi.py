@@ -138,3 +138,62 @@ def test_default_plan_follows_model_switch_point(lib):
     assert large.variant == R.RED_VARIANT_RELAUNCH
     # the same switch point in bytes for 16-bit inputs
     assert R.red_get_plan(R.RED_BF16, R.RED_ACC_COMPENSATED, 2000).variant == R.RED_VARIANT_SINGLE
+
+
+class _FakeCudaTensor:
+    """Stand-in for a CUDA tensor: the fields the wrappers check, and a
+    data_ptr that must never be reached when a check fails."""
+
+    def __init__(self, dtype, numel, device="cuda:0", contiguous=True, cuda=True):
+        import torch
+        self.dtype = dtype
+        self._n = numel
+        self.device = torch.device(device)
+        self._contig = contiguous
+        self.is_cuda = cuda
+
+    def is_contiguous(self):
+        return self._contig
+
+    def numel(self):
+        return self._n
+
+    def dim(self):
+        return 1
+
+    def data_ptr(self):
+        raise AssertionError("a wrapper passed a pointer on after a failed check")
+
+
+def test_wrappers_reject_bad_tensors_before_any_launch():
+    import torch
+    f32, f64, i64 = torch.float32, torch.float64, torch.int64
+    T = _FakeCudaTensor
+    # sum: out of the wrong dtype, size, device or layout
+    with pytest.raises(ValueError, match="float64"):
+        R.sum(T(f32, 100), out=T(f32, 1))
+    with pytest.raises(ValueError, match="int64"):
+        R.sum(T(torch.int32, 100), out=T(f64, 1))
+    with pytest.raises(ValueError, match="holds 0"):
+        R.sum(T(f32, 100), out=T(f64, 0))
+    with pytest.raises(ValueError, match="is on"):
+        R.sum(T(f32, 100), out=T(f64, 1, device="cuda:1"))
+    with pytest.raises(ValueError, match="contiguous"):
+        R.sum(T(f32, 100), out=T(f64, 1, contiguous=False))
+    with pytest.raises(ValueError):
+        R.sum(T(f32, 100, cuda=False))
+    # segmented: host offsets, non-contiguous values, devices, out
+    with pytest.raises(ValueError, match="offsets"):
+        R.segmented_sum(T(f32, 100), T(i64, 11, device="cpu", cuda=False))
+    with pytest.raises(ValueError, match="values"):
+        R.segmented_sum(T(f32, 100, contiguous=False), T(i64, 11))
+    with pytest.raises(ValueError, match="devices"):
+        R.segmented_sum(T(f32, 100), T(i64, 11, device="cuda:1"))
+    with pytest.raises(ValueError, match="nseg"):
+        R.segmented_sum(T(f32, 100), T(i64, 0))
+    with pytest.raises(ValueError, match="holds 9"):
+        R.segmented_sum(T(f32, 100), T(i64, 11), out=T(f64, 9))
+    with pytest.raises(ValueError, match="float64"):
+        R.segmented_sum(T(f32, 100), T(i64, 11), out=T(f32, 10))
+    with pytest.raises(TypeError):
+        R.segmented_sum(T(f32, 100), T(torch.int32, 11))
