@@ -205,6 +205,34 @@ int red_sum(int dtype, const void *x, int64_t n, void *out, void *stream);
 /* red_sum with explicit options (variant, plan, accumulation). */
 int red_sum_ex(int dtype, const void *x, int64_t n, void *out, void *stream, const red_opts *opts);
 
+/* Largest grid (workgroups, hence per-workgroup partials) of
+ * red_sum_noalloc. */
+#define RED_NOALLOC_MAX_GRID 2048
+
+/* red_sum_ex that allocates nothing, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, plans, kernels and results as
+ * red_sum_ex (the same plan gives the same bits).
+ *   Scratch: the partials and barrier words live in one static device
+ *   array of the library (8 KiB of words + RED_NOALLOC_MAX_GRID x 8 bytes,
+ *   held by every device the library runs on until the process ends), not
+ *   in a per-stream workspace.  Its address on each device is looked up
+ *   once, by red_init or by the first call on that device (a lookup, not an
+ *   allocation; that first call must not be under capture).
+ *   Limit: an explicit opts->plan.grid above RED_NOALLOC_MAX_GRID is
+ *   rejected with RED_EINVAL; an automatic grid is capped there.
+ *   Sharing: every call on one device uses that device's one array, and the
+ *   array keeps the last call's contents.  Calls that overlap on one
+ *   device (two streams, two threads) race; serialize them.  The barrier
+ *   and ticket words are cleared by a small kernel at the start of each
+ *   call of the atomic-ticket and persistent variants, which alone use them.
+ *   No kernel-timer events are recorded (red_kernel_timer does not see
+ *   these calls), and a persistent variant's watchdog is not reported by
+ *   red_check_error (which reads the stream's workspace).
+ * Errors: RED_EINVAL (validation, grid above the limit), RED_ENODEV,
+ * RED_EHIP. */
+int red_sum_noalloc(int dtype, const void *x, int64_t n, void *out, void *stream, const red_opts *opts);
+
 /* Per-segment sums of a CSR batch: out[k] = sum of x[offsets[k] ..
  * offsets[k+1]) for k in [0, nseg).
  *   x       device pointer to binary32 values (aligned to 4 bytes).

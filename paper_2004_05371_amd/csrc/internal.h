@@ -91,6 +91,8 @@ int launch(const void* fn, int grid, int block, void** args, hipStream_t s, bool
 struct ReduceLaunch {
   int dtype, acc;
   red_plan plan;  // plan.flags: RED_FLAG_NONTEMPORAL | RED_FLAG_PLAIN_LAUNCH
+  bool timed = true;             // may carry the stream's kernel-timer events
+  int max_grid = RED_MAX_GRID;   // partial slots the workspace holds
 };
 int validate_plan(const red_plan& p);
 red_plan default_plan(int dtype, int64_t n, const DeviceInfo& dev);

@@ -457,11 +457,15 @@ int reduce_launch(const ReduceLaunch& rl, const void* x, int64_t n, void* out, W
   const int64_t tile = (int64_t)p.wg * p.ipt;
   int64_t want = std::max<int64_t>(1, (a.nvec + tile - 1) / tile);
   int grid = (int)std::min<int64_t>(want, p.grid > 0 ? (int64_t)p.grid : 4LL * dev.cus);
-  grid = std::max(1, std::min(grid, RED_MAX_GRID));
+  grid = std::max(1, std::min(grid, std::min(rl.max_grid, RED_MAX_GRID)));
   void* args[] = {&a};
+  // The stream's kernel timer, unless the caller rules out its events.
+  auto launch_k = [&](const void* fn, int g, bool coop) {
+    return rl.timed ? launch_timed(fn, g, p.wg, args, s, coop) : launch(fn, g, p.wg, args, s, coop);
+  };
   switch (p.variant) {
     case RED_VARIANT_RELAUNCH: {
-      int rc = launch_timed(ks.partials, grid, p.wg, args, s, false);
+      int rc = launch_k(ks.partials, grid, false);
       if (rc) return rc;
       // Up to 1024 partials: one wavefront (at most 16 loads per lane);
       // beyond: one 256-thread workgroup.
@@ -475,10 +479,10 @@ int reduce_launch(const ReduceLaunch& rl, const void* x, int64_t n, void* out, W
       return launch(fn, 1, wave ? kWave : kFinalWG, fargs, s, false);
     }
     case RED_VARIANT_SINGLE: {
-      return launch_timed(ks.single, 1, p.wg, args, s, false);
+      return launch_k(ks.single, 1, false);
     }
     case RED_VARIANT_ATOMIC: {
-      return launch_timed(ks.atomic, grid, p.wg, args, s, false);
+      return launch_k(ks.atomic, grid, false);
     }
     case RED_VARIANT_PERSISTENT: {
       int maxg = 0;
@@ -490,7 +494,7 @@ int reduce_launch(const ReduceLaunch& rl, const void* x, int64_t n, void* out, W
       grid = std::min(grid, maxg);
       if (grid < 1) return set_error(RED_EINVAL, "persistent kernel cannot be resident");
       a.bar_groups = xcd ? (kBarrierXcd | (unsigned)dev.nxcc) : barrier_groups(grid);
-      return launch_timed(ks.persistent, grid, p.wg, args, s, (p.flags & RED_FLAG_PLAIN_LAUNCH) == 0);
+      return launch_k(ks.persistent, grid, (p.flags & RED_FLAG_PLAIN_LAUNCH) == 0);
     }
   }
   return set_error(RED_EINVAL, "unknown variant %d", p.variant);

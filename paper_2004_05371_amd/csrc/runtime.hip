@@ -302,6 +302,58 @@ int launch(const void* fn, int grid, int block, void** args, hipStream_t s, bool
   return RED_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the no-allocation entry point: barrier words, then one partial
+// slot per workgroup, in one static device array per device.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = kWordsBytes + (size_t)RED_NOALLOC_MAX_GRID * 8;
+static_assert(sizeof(BarrierWords) <= kWordsBytes, "barrier words fit their region");
+
+}  // namespace redsum
+
+// The array itself.  In host code its name is only a stand-in for the
+// device symbol: every host use goes through the device address that
+// scratch_address() looked up for the current device.
+static __device__ __align__(256) unsigned char scratch[redsum::kScratchBytes];
+
+namespace redsum {
+namespace {
+
+std::map<int, void*> g_scratch;  // device -> address of `scratch` on it
+
+// Device address of `scratch` on the current device (looked up once per
+// device, with that device current).
+int scratch_address(void** out) {
+  int dev = 0;
+  RED_HIP(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_scratch.find(dev);
+    if (it != g_scratch.end()) {
+      *out = it->second;
+      return RED_OK;
+    }
+  }
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return set_error(RED_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                     hipGetErrorString(e));
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_scratch[dev] = ptr;
+  *out = ptr;
+  return RED_OK;
+}
+
+// Zeroes n 32-bit words (a kernel, not a memset, so it also records as an
+// ordinary kernel node under capture).
+__global__ void k_zero_words(unsigned* w, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) w[i] = 0u;
+}
+
+}  // namespace
 }  // namespace redsum
 
 using namespace redsum;
@@ -409,6 +461,8 @@ int red_init(int device) {
   const DeviceInfo* d;
   int rc = ensure_device(&d);
   if (rc) return rc;
+  void* sp = nullptr;
+  if ((rc = scratch_address(&sp))) return rc;
   Workspace* ws;
   return get_workspace(nullptr, &ws);
 }
@@ -507,6 +561,40 @@ int red_sum_ex(int dtype, const void* x, int64_t n, void* out, void* stream, con
 
 int red_sum(int dtype, const void* x, int64_t n, void* out, void* stream) {
   return red_sum_ex(dtype, x, n, out, stream, nullptr);
+}
+
+int red_sum_noalloc(int dtype, const void* x, int64_t n, void* out, void* stream, const red_opts* opts) {
+  int rc = validate_sum_args(dtype, x, n, out, opts);
+  if (rc) return rc;
+  if (opts && opts->plan.variant != RED_VARIANT_AUTO && opts->plan.grid > RED_NOALLOC_MAX_GRID)
+    return set_error(RED_EINVAL, "red_sum_noalloc: grid %d exceeds the %d workgroups its scratch holds",
+                     opts->plan.grid, RED_NOALLOC_MAX_GRID);
+  const DeviceInfo* dev;
+  if ((rc = ensure_device(&dev))) return rc;
+  void* sp = nullptr;
+  if ((rc = scratch_address(&sp))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace ws;  // views into the scratch; nothing else of a workspace is used
+  ws.words = reinterpret_cast<BarrierWords*>(sp);
+  ws.partials = static_cast<char*>(sp) + kWordsBytes;
+  ReduceLaunch rl;
+  rl.dtype = dtype;
+  rl.acc = opts ? opts->acc : RED_ACC_COMPENSATED;
+  rl.plan = (opts && opts->plan.variant != RED_VARIANT_AUTO)
+                ? complete_plan(opts->plan, default_plan(dtype, n, *dev))
+                : lookup_plan(dtype, rl.acc, n, *dev);
+  if (opts) rl.plan.flags |= opts->flags & (RED_FLAG_NONTEMPORAL | RED_FLAG_PLAIN_LAUNCH | RED_FLAG_PIPELINE | RED_FLAG_XCD);
+  rl.timed = false;
+  rl.max_grid = RED_NOALLOC_MAX_GRID;
+  if (n > 0 && (rl.plan.variant == RED_VARIANT_ATOMIC || rl.plan.variant == RED_VARIANT_PERSISTENT)) {
+    // The ticket, counters and accumulator start at zero (the array keeps
+    // whatever the last call, or an abandoned barrier, left).
+    unsigned* w = static_cast<unsigned*>(sp);
+    int nw = (int)(sizeof(BarrierWords) / 4);
+    void* zargs[] = {&w, &nw};
+    if ((rc = launch(reinterpret_cast<const void*>(&k_zero_words), 1, 256, zargs, s, false))) return rc;
+  }
+  return reduce_launch(rl, x, n, out, &ws, s, *dev);
 }
 
 int red_set_plan(int dtype, int acc, int64_t n, const red_plan* plan) {

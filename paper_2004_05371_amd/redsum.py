@@ -28,6 +28,7 @@ RED_VARIANT_SINGLE = 4
 RED_ACC_COMPENSATED, RED_ACC_PLAIN = 0, 1
 RED_WAVE_DPP, RED_WAVE_SWIZZLE, RED_WAVE_BPERMUTE, RED_WAVE_DPP_STEP = 0, 1, 2, 3
 RED_MAX_GRID = 8192
+RED_NOALLOC_MAX_GRID = 2048
 FLAG_NONTEMPORAL = 1
 FLAG_NO_GRAPH = 2
 FLAG_PLAIN_LAUNCH = 4
@@ -44,7 +45,7 @@ VARIANT_NAMES = {1: "relaunch", 2: "atomic", 3: "persistent", 4: "single"}
 # every symbol declared in include/redsum.h
 EXPORTS = [
     "red_init", "red_shutdown", "red_last_error", "red_check_error",
-    "red_sum", "red_sum_ex", "red_sum_segmented", "red_sum_segmented_ex",
+    "red_sum", "red_sum_ex", "red_sum_noalloc", "red_sum_segmented", "red_sum_segmented_ex",
     "red_sum_segmented_loop", "red_set_plan", "red_get_plan", "red_autotune",
     "red_autotune_segmented", "red_set_segmented_plan", "red_get_segmented_plan",
     "red_kernel_timer", "red_kernel_timer_read", "sync_bench_wave", "sync_bench_wave_ex", "sync_bench_block",
@@ -89,6 +90,7 @@ _SIGS = {
     "red_check_error": ([_vp], _i32),
     "red_sum": ([_i32, _vp, _i64, _vp, _vp], _i32),
     "red_sum_ex": ([_i32, _vp, _i64, _vp, _vp, ctypes.POINTER(Opts)], _i32),
+    "red_sum_noalloc": ([_i32, _vp, _i64, _vp, _vp, ctypes.POINTER(Opts)], _i32),
     "red_sum_segmented": ([_vp, _vp, _i64, _vp, _vp], _i32),
     "red_sum_segmented_ex": ([_vp, _vp, _i64, _vp, _vp, ctypes.POINTER(Opts)], _i32),
     "red_sum_segmented_loop": ([_vp, _i64p, _i64, _vp, _vp], _i32),
@@ -181,6 +183,13 @@ def opts_from_plan(plan: Plan, acc: int = RED_ACC_COMPENSATED, flags: int = 0) -
 def red_sum_ex(dtype: int, x: int, n: int, out: int, stream: int = 0, opts: Optional[Opts] = None) -> int:
     return _check(load().red_sum_ex(dtype, x, n, out, stream,
                                     ctypes.byref(opts) if opts is not None else None), "red_sum_ex")
+
+
+def red_sum_noalloc(dtype: int, x: int, n: int, out: int, stream: int = 0, opts: Optional[Opts] = None) -> int:
+    """red_sum_ex with its partials and barrier words in the library's static
+    device scratch (no allocation; calls on one device must not overlap)."""
+    return _check(load().red_sum_noalloc(dtype, x, n, out, stream,
+                                         ctypes.byref(opts) if opts is not None else None), "red_sum_noalloc")
 
 
 def red_sum_segmented(x: int, offsets: int, nseg: int, out: int, stream: int = 0) -> int:

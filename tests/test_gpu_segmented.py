@@ -326,13 +326,15 @@ def test_full_batch_config(lib):
         check(res, x, off, sums)
 
 
-@pytest.mark.parametrize("L", [64, 768])
+@pytest.mark.parametrize("L", [3, 4, 5, 8, 64, 768])
 def test_full_size_uniform_segments(lib, L):
-    """2^28 N(0,1) values in segments of 64 values (reduce-by-key form, 4M
-    segments) and of 768 values (a segment cut at every slice edge), default
-    plan through the graph path: 3000 sampled segments against the oracle's
-    exact sums, every segment within 1e-12 of its sum of magnitudes of a
-    binary64 row sum, and the ticket fix-up bit-identical."""
+    """2^28 N(0,1) values in segments of 3 to 8 values (reduce-by-key form
+    with quarter-tile parts and the per-piece walk; up to 89M segments), of
+    64 values (reduce-by-key form, 4M segments) and of 768 values (a segment
+    cut at every slice edge), default plan through the graph path: 3000
+    sampled segments against the oracle's exact sums, every segment within
+    1e-12 of its sum of magnitudes of a binary64 row sum, and the ticket
+    fix-up bit-identical."""
     n = (1 << 28) // L * L
     x = inputs.normal_f32(1 << 28, sub=19)[:n]
     nseg = n // L
