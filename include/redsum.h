@@ -342,6 +342,27 @@ int red_get_plan(int dtype, int acc, int64_t n, red_plan *plan);
 int red_autotune(int dtype, int acc, const void *x, int64_t n, void *out, void *stream, int budget,
                  red_plan *best, double *best_us);
 
+/* Cost of one candidate plan in microseconds (lower is better), or a
+ * negative red_status to stop the search.  It may lower plan->grid (the
+ * plan kept is the one it was given back). */
+typedef double (*red_cost_fn)(red_plan *plan, void *ctx);
+
+/* The candidate search of red_autotune on its own, with the cost of each
+ * candidate supplied by the caller (red_autotune times it on the GPU; a
+ * model or a test may supply another), for a device of `cus` compute units
+ * and `nxcc` XCDs.  Candidates, in order: the default plan without and with
+ * the nontemporal hint; every relaunch shape (pipelined or not) x wg {128,
+ * 256, 512, 1024} x ipt {1, 2, 4, 8} x grid {1, 2, 3, 4, 6, 8, 12, 16} x
+ * cus (up to the work's tile count); one-workgroup plans when n is within
+ * 64 times the Eq. 4/5 switch point; then the atomic-ticket and persistent
+ * (cooperative and plain launch) variants of the best shape, with and
+ * without RED_FLAG_XCD when allow_xcd and nxcc > 1.  The first candidate
+ * of the lowest cost wins; nothing is installed.  budget > 0 caps the
+ * number of candidates costed.  No HIP call.
+ * Errors: RED_EINVAL, or the cost function's negative status. */
+int red_autotune_search(int dtype, int64_t n, int cus, int nxcc, int allow_xcd, int budget, red_cost_fn cost,
+                        void *ctx, red_plan *best, double *best_us);
+
 /* Install / read the plan of segmented batches whose nseg has the same
  * bit length as `nseg` (variant RED_VARIANT_ATOMIC or _PERSISTENT, wg at
  * most 512). */
@@ -397,6 +418,13 @@ int sync_bench_grid(int n_wg, int wg_size, int reps, double *ns, double *sigma_n
 int sync_bench_grid_ex(int n_wg, int wg_size, int groups, int reps, double *ns, double *sigma_ns,
                        double *cycles, void *stream);
 
+/* sync_bench_grid_ex with the two repetition counts of Eq. 7 fixed by the
+ * caller (r1 > r2 > 0, r1 <= 65536) instead of calibrated: the
+ * repeat-count invariance check of Section IX-C (the latency of one
+ * barrier must not depend on r1, r2).  r1 = r2 = 0 calibrates. */
+int sync_bench_grid_r(int n_wg, int wg_size, int groups, int64_t r1, int64_t r2, int reps, double *ns,
+                      double *sigma_ns, double *cycles, void *stream);
+
 /* Launch overhead of a kernel boundary (the implicit barrier) by kernel
  * fusion, Eq. 6, with (i, j) = (8, 1) launches of n_wg x wg_size kernels
  * that wait 5 us per unit.  cooperative selects the launch type: 0 ordinary
@@ -404,10 +432,39 @@ int sync_bench_grid_ex(int n_wg, int wg_size, int groups, int reps, double *ns, 
  * a captured hipGraph (i kernels in one graph against j in another; the
  * graphs are captured on a private stream and replayed on `stream`, which
  * must not be capturing); other values: RED_EINVAL.  null_kernel_ns (if
- * non-NULL) receives the total latency of one null kernel in ns (Section IV
- * formula, host clock around 1 and 5 launches, or graphs of 1 and 5). */
+ * non-NULL) receives the total latency of one null kernel in ns: for
+ * ordinary and cooperative launches by the Section IV formula (host clock
+ * around 1 and around 5 launches, each followed by a synchronization); for
+ * the graph type, where one replay launches every kernel of the graph, by
+ * the Eq. 7 differential between graphs of 40 and of 5 null kernels timed
+ * with events (the cost of one more null kernel inside a graph). */
 int sync_bench_relaunch(int n_wg, int wg_size, int cooperative, int reps, double *ns,
                         double *sigma_ns, double *null_kernel_ns, void *stream);
+
+/* sync_bench_relaunch with the launch counts (i, j) of Eq. 6 (1 <= i, j <=
+ * 64, i != j) and the wait unit in ticks of the device's 100 MHz wall
+ * clock (0 = 5 us) chosen by the caller: the overhead per launch must not
+ * depend on (i, j). */
+int sync_bench_relaunch_ex(int n_wg, int wg_size, int cooperative, int i, int j, int64_t unit_ticks, int reps,
+                           double *ns, double *sigma_ns, double *null_kernel_ns, void *stream);
+
+/* Method check of Eq. 7 with a known answer: one workgroup of a kernel
+ * that waits r x unit_ticks ticks of the 100 MHz wall clock, with r = r1
+ * and r = r2 (r1 > r2 >= 1, r1 x unit_ticks <= 1e8); *ns receives Eq. 7's
+ * latency per unit, which must come out as unit_ticks x 10 ns, and
+ * *sigma_ns its Eq. 8 uncertainty. */
+int sync_bench_spin(int64_t unit_ticks, int64_t r1, int64_t r2, int reps, double *ns, double *sigma_ns,
+                    void *stream);
+
+/* Values of one wavefront combine (the warp reduction of Section VII-D):
+ * host_in holds 64 values of red_wave_type `type` (4 bytes each for
+ * float / int32, 8 for double / int64 / the compensated pair), value l for
+ * lane l; after combine `op` every lane's result is written to host_out
+ * (64 values, same layout).  The full combines (DPP, ds_swizzle,
+ * ds_bpermute) return the sum of the 64 values to every lane (integers
+ * wrap modulo 2^32 or 2^64); RED_WAVE_DPP_STEP returns v[l] + v[l-1]
+ * inside each 16-lane row and v[l] at a row's first lane.  Synchronous. */
+int sync_check_wave(int op, int type, const void *host_in, void *host_out, void *stream);
 
 /* Grid-barrier ordering check: every workgroup of a cooperative kernel
  * records the 100 MHz wall clock before and after one grid barrier; writes

@@ -82,6 +82,26 @@ __global__ __launch_bounds__(1024) void k_wave_chain(int r, unsigned* sink, long
   if (w0 == (unsigned)r * 0x9E3779B9u + 0x7F7F1234u) sink[threadIdx.x] = w0;
 }
 
+// One wavefront combine of `op` on the 64 values in[0..64) (one per lane);
+// lane l writes the value the combine returns to it to out[l].  The one
+// DPP step returns v[l] + v[l - 1] inside each 16-lane row (0 from outside
+// the row).
+template <int OP, class Op>
+__global__ __launch_bounds__(64) void k_wave_once(const typename Op::T* in, typename Op::T* out) {
+  using T = typename Op::T;
+  const int lane = __lane_id();
+  T v = in[lane];
+  if constexpr (OP == RED_WAVE_DPP)
+    v = wave_reduce_dpp<Op>(v);
+  else if constexpr (OP == RED_WAVE_SWIZZLE)
+    v = wave_reduce_swizzle<Op>(v);
+  else if constexpr (OP == RED_WAVE_BPERMUTE)
+    v = wave_reduce_bpermute<Op>(v);
+  else
+    v = Op::add(v, dpp_move<kRowShr1, 0xF, 0xF>(v));
+  out[lane] = v;
+}
+
 __global__ __launch_bounds__(1024) void k_block_chain(int r, long long* cycles) {
   __builtin_amdgcn_sched_barrier(0);
   const long long t0 = __builtin_amdgcn_s_memtime();
@@ -276,17 +296,49 @@ double sdev(const std::vector<double>& v) {
   return v.size() > 1 ? std::sqrt(s / (v.size() - 1)) : 0.0;
 }
 
+// `reps` timed pairs of one launch with r1 and one with r2 repetitions:
+// Eq. 7 on the mean latencies, Eq. 8 on their spreads.
+template <class SetR, class ReadCycles>
+int differential_pairs(const void* fn, int grid, int block, void** args, bool coop, int reps, hipStream_t s,
+                       SetR set_r, ReadCycles read_cycles, int64_t r1, int64_t r2, Events& ev, double* ns,
+                       double* sigma, double* per_op_counter) {
+  std::vector<double> l1, l2, c1, c2;
+  double ms = 0;
+  int rc = RED_OK;
+  for (int i = 0; i < reps; ++i) {
+    set_r(r1);
+    if ((rc = time_launches(fn, grid, block, args, coop, 1, s, ev, &ms))) return rc;
+    l1.push_back(ms * 1e6);
+    if (per_op_counter) c1.push_back(read_cycles());
+    set_r(r2);
+    if ((rc = time_launches(fn, grid, block, args, coop, 1, s, ev, &ms))) return rc;
+    l2.push_back(ms * 1e6);
+    if (per_op_counter) c2.push_back(read_cycles());
+  }
+  *ns = red_eq7_latency(mean(l1), mean(l2), r1, r2);
+  *sigma = red_eq8_sigma(l1.data(), l2.data(), (int)l1.size(), r1, r2);
+  if (per_op_counter) *per_op_counter = (mean(c1) - mean(c2)) / (double)(r1 - r2);
+  return RED_OK;
+}
+
 // Runs the Eq. 7 / Eq. 8 differential between r1 and r2 repetitions.
 // `set_r` rewrites the repetition argument; `read_cycles` (optional)
 // returns the in-kernel counter of the last launch.
+// r1 > r2 > 0 fixes the two repetition counts; r1 = r2 = 0 calibrates them.
 template <class SetR, class ReadCycles>
 int differential(const void* fn, int grid, int block, void** args, bool coop, int reps, hipStream_t s,
                  SetR set_r, ReadCycles read_cycles, double target_us, int64_t r_max, double* ns,
-                 double* sigma, double* per_op_counter) {
+                 double* sigma, double* per_op_counter, int64_t r1_fixed = 0, int64_t r2_fixed = 0) {
   Events ev;
   int rc = ev.init();
   if (rc) return rc;
   double ms = 0;
+  if (r1_fixed > 0) {
+    set_r(r1_fixed);  // warm-up
+    if ((rc = time_launches(fn, grid, block, args, coop, 1, s, ev, &ms))) return rc;
+    return differential_pairs(fn, grid, block, args, coop, reps, s, set_r, read_cycles, r1_fixed, r2_fixed, ev,
+                              ns, sigma, per_op_counter);
+  }
   // Warm-up and calibration: choose r2 so that the r2 kernel runs about
   // target_us beyond its fixed cost, r1 = 8 r2 (Section IX-B: kernels must
   // be long enough to saturate the launch pipeline).
@@ -302,21 +354,8 @@ int differential(const void* fn, int grid, int block, void** args, bool coop, in
   int64_t r2 = (int64_t)std::ceil(target_us / per);
   r2 = std::max<int64_t>(4, std::min<int64_t>(r2, r_max / 8));
   const int64_t r1 = 8 * r2;
-  std::vector<double> l1, l2, c1, c2;
-  for (int i = 0; i < reps; ++i) {
-    set_r(r1);
-    if ((rc = time_launches(fn, grid, block, args, coop, 1, s, ev, &ms))) return rc;
-    l1.push_back(ms * 1e6);
-    c1.push_back(read_cycles());
-    set_r(r2);
-    if ((rc = time_launches(fn, grid, block, args, coop, 1, s, ev, &ms))) return rc;
-    l2.push_back(ms * 1e6);
-    c2.push_back(read_cycles());
-  }
-  *ns = red_eq7_latency(mean(l1), mean(l2), r1, r2);
-  *sigma = red_eq8_sigma(l1.data(), l2.data(), (int)l1.size(), r1, r2);
-  if (per_op_counter) *per_op_counter = (mean(c1) - mean(c2)) / (double)(r1 - r2);
-  return RED_OK;
+  return differential_pairs(fn, grid, block, args, coop, reps, s, set_r, read_cycles, r1, r2, ev, ns, sigma,
+                            per_op_counter);
 }
 
 int read_i64(const long long* dptr, long long* h) {
@@ -366,6 +405,16 @@ const void* wave_chain_fn(int op) {
     case RED_WAVE_SWIZZLE: return reinterpret_cast<const void*>(&k_wave_chain<RED_WAVE_SWIZZLE, Op>);
     case RED_WAVE_BPERMUTE: return reinterpret_cast<const void*>(&k_wave_chain<RED_WAVE_BPERMUTE, Op>);
     default: return reinterpret_cast<const void*>(&k_wave_chain<RED_WAVE_DPP_STEP, Op>);
+  }
+}
+
+template <class Op>
+const void* wave_once_fn(int op) {
+  switch (op) {
+    case RED_WAVE_DPP: return reinterpret_cast<const void*>(&k_wave_once<RED_WAVE_DPP, Op>);
+    case RED_WAVE_SWIZZLE: return reinterpret_cast<const void*>(&k_wave_once<RED_WAVE_SWIZZLE, Op>);
+    case RED_WAVE_BPERMUTE: return reinterpret_cast<const void*>(&k_wave_once<RED_WAVE_BPERMUTE, Op>);
+    default: return reinterpret_cast<const void*>(&k_wave_once<RED_WAVE_DPP_STEP, Op>);
   }
 }
 
@@ -451,6 +500,13 @@ int sync_bench_block(int wg_size, int n_wg, int reps, double* ns, double* sigma_
 
 int sync_bench_grid_ex(int n_wg, int wg_size, int groups, int reps, double* ns, double* sigma_ns,
                        double* cycles, void* stream) {
+  return sync_bench_grid_r(n_wg, wg_size, groups, 0, 0, reps, ns, sigma_ns, cycles, stream);
+}
+
+int sync_bench_grid_r(int n_wg, int wg_size, int groups, int64_t r1, int64_t r2, int reps, double* ns,
+                      double* sigma_ns, double* cycles, void* stream) {
+  if (!((r1 == 0 && r2 == 0) || (r1 > r2 && r2 > 0 && r1 <= (1 << 16))))
+    return set_error(RED_EINVAL, "repetitions: r1 = r2 = 0, or r1 > r2 > 0 and r1 <= 65536");
   if (wg_size < 64 || wg_size > 1024 || wg_size % 64) return set_error(RED_EINVAL, "bad wg_size %d", wg_size);
   if (n_wg < 1 || n_wg > RED_MAX_GRID) return set_error(RED_EINVAL, "bad n_wg %d", n_wg);
   if (groups < -1 || groups > kMaxBarrierGroups) return set_error(RED_EINVAL, "bad groups %d", groups);
@@ -483,7 +539,7 @@ int sync_bench_grid_ex(int n_wg, int wg_size, int groups, int reps, double* ns, 
         read_i64(st, &h);
         return (double)h * tick_ns;
       },
-      50.0, 1 << 16, ns, sigma_ns, cycles);
+      50.0, 1 << 16, ns, sigma_ns, cycles, r1, r2);
   if (rc) return rc;
   unsigned err = 0;
   RED_HIP(hipMemcpy(&err, &ws->words->err.v, 4, hipMemcpyDeviceToHost));
@@ -502,6 +558,16 @@ int sync_bench_grid(int n_wg, int wg_size, int reps, double* ns, double* sigma_n
 
 int sync_bench_relaunch(int n_wg, int wg_size, int cooperative, int reps, double* ns, double* sigma_ns,
                         double* null_kernel_ns, void* stream) {
+  // (i, j) = (8, 1) with a 5 us wait unit (Section IX-B: about 5 us keeps
+  // one GPU's launch pipeline saturated); 0 ticks: 5 us of this device's
+  // wall clock.
+  return sync_bench_relaunch_ex(n_wg, wg_size, cooperative, 8, 1, 0, reps, ns, sigma_ns, null_kernel_ns, stream);
+}
+
+int sync_bench_relaunch_ex(int n_wg, int wg_size, int cooperative, int i, int j, int64_t unit_ticks, int reps,
+                           double* ns, double* sigma_ns, double* null_kernel_ns, void* stream) {
+  if (i < 1 || j < 1 || i == j || i > 64 || j > 64) return set_error(RED_EINVAL, "launch counts: 1 <= i, j <= 64, i != j");
+  if (unit_ticks < 0 || unit_ticks > 100000000) return set_error(RED_EINVAL, "unit_ticks out of range");
   if (wg_size < 64 || wg_size > 1024 || wg_size % 64) return set_error(RED_EINVAL, "bad wg_size %d", wg_size);
   if (n_wg < 1 || n_wg > RED_MAX_GRID) return set_error(RED_EINVAL, "bad n_wg %d", n_wg);
   if (cooperative < 0 || cooperative > 2)
@@ -526,10 +592,7 @@ int sync_bench_relaunch(int n_wg, int wg_size, int cooperative, int reps, double
   if ((rc = ev.init())) return rc;
   long long ticks = 0;
   void* args[] = {&ticks};
-  // 5 us wait unit (Section IX-B: about 5 us keeps one GPU's launch
-  // pipeline saturated).
-  const long long unit = std::max<long long>(1, dev->wallclock_khz * 5 / 1000);
-  const int i = 8, j = 1;
+  const long long unit = unit_ticks > 0 ? unit_ticks : std::max<long long>(1, dev->wallclock_khz * 5 / 1000);
   double ms = 0;
   // Graph form: i kernels of j units and j kernels of i units, each one graph.
   LaunchGraph g_ij, g_ji;
@@ -558,19 +621,31 @@ int sync_bench_relaunch(int n_wg, int wg_size, int cooperative, int reps, double
   }
   *ns = red_eq6_overhead(mean(lij), mean(lji), i, j);
   *sigma_ns = red_eq8_sigma(lij.data(), lji.data(), (int)lij.size(), i, j);
-  if (null_kernel_ns) {
-    // Section IV: host clock around 1 launch and around 5 launches of a
-    // null kernel, each followed by a device synchronization (graph form:
-    // one graph of 1 and one of 5 null kernels).
-    LaunchGraph g1, g5;
-    if (graph) {
-      if ((rc = g1.build(fn, n_wg, wg_size, 0, 1))) return rc;
-      if ((rc = g5.build(fn, n_wg, wg_size, 0, 5))) return rc;
+  if (null_kernel_ns && graph) {
+    // One replay launches the whole graph, so the host clock around a
+    // replay does not separate its kernels: the per-kernel latency of a
+    // null kernel inside a graph is the Eq. 7 differential between graphs
+    // of 40 and of 5 null kernels, timed with events.
+    constexpr int kBig = 40, kSmall = 5;
+    LaunchGraph gb, gs;
+    if ((rc = gb.build(fn, n_wg, wg_size, 0, kBig))) return rc;
+    if ((rc = gs.build(fn, n_wg, wg_size, 0, kSmall))) return rc;
+    if ((rc = time_graph(gb, s, ev, &ms))) return rc;  // warm-up
+    if ((rc = time_graph(gs, s, ev, &ms))) return rc;
+    std::vector<double> lb, ls;
+    for (int k = 0; k < reps; ++k) {
+      if ((rc = time_graph(gb, s, ev, &ms))) return rc;
+      lb.push_back(ms * 1e6);
+      if ((rc = time_graph(gs, s, ev, &ms))) return rc;
+      ls.push_back(ms * 1e6);
     }
+    *null_kernel_ns = red_eq7_latency(mean(lb), mean(ls), kBig, kSmall);
+  } else if (null_kernel_ns) {
+    // Section IV: host clock around 1 launch and around 5 launches of a
+    // null kernel, each followed by a device synchronization.
     ticks = 0;
-    auto one = [&]() { return graph ? hip_check(hipGraphLaunch(g1.exec, s)) : launch(fn, n_wg, wg_size, args, s, coop); };
+    auto one = [&]() { return launch(fn, n_wg, wg_size, args, s, coop); };
     auto five = [&]() {
-      if (graph) return hip_check(hipGraphLaunch(g5.exec, s));
       for (int q = 0; q < 5; ++q) {
         int r = launch(fn, n_wg, wg_size, args, s, coop);
         if (r) return r;
@@ -592,6 +667,49 @@ int sync_bench_relaunch(int n_wg, int wg_size, int cooperative, int reps, double
     }
     *null_kernel_ns = mean(tot);
   }
+  return RED_OK;
+}
+
+int sync_bench_spin(int64_t unit_ticks, int64_t r1, int64_t r2, int reps, double* ns, double* sigma_ns,
+                    void* stream) {
+  if (unit_ticks < 1 || r2 < 1 || r1 <= r2 || r1 * unit_ticks > 100000000)
+    return set_error(RED_EINVAL, "need unit_ticks >= 1, r1 > r2 >= 1, r1 * unit_ticks <= 1e8");
+  if (reps < 2 || !ns || !sigma_ns) return set_error(RED_EINVAL, "reps >= 2 and non-null outputs required");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DeviceInfo* dev;
+  Workspace* ws;
+  int rc = probe_prologue(s, &dev, &ws);
+  if (rc) return rc;
+  long long ticks = 0;
+  void* args[] = {&ticks};
+  return differential(
+      reinterpret_cast<const void*>(&k_spin), 1, 64, args, false, reps, s,
+      [&](int64_t v) { ticks = (long long)(v * unit_ticks); }, [&]() { return 0.0; }, 0.0, 0, ns, sigma_ns,
+      nullptr, r1, r2);
+}
+
+int sync_check_wave(int op, int type, const void* host_in, void* host_out, void* stream) {
+  if (op < RED_WAVE_DPP || op > RED_WAVE_DPP_STEP) return set_error(RED_EINVAL, "bad wave op %d", op);
+  if (type < RED_WAVE_T_F32 || type > RED_WAVE_T_COMP) return set_error(RED_EINVAL, "bad wave type %d", type);
+  if (!host_in || !host_out) return set_error(RED_EINVAL, "null buffer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DeviceInfo* dev;
+  Workspace* ws;
+  int rc = probe_prologue(s, &dev, &ws);
+  if (rc) return rc;
+  const size_t esz = (type == RED_WAVE_T_F32 || type == RED_WAVE_T_I32) ? 4 : 8;
+  char* in = reinterpret_cast<char*>(ws->stamps);  // 64 values in, 64 out
+  char* out = in + kWave * 8;
+  RED_HIP(hipMemcpyAsync(in, host_in, kWave * esz, hipMemcpyHostToDevice, s));
+  const void* fn = type == RED_WAVE_T_F32   ? wave_once_fn<OpF32>(op)
+                   : type == RED_WAVE_T_I32 ? wave_once_fn<OpU32>(op)
+                   : type == RED_WAVE_T_F64 ? wave_once_fn<OpF64>(op)
+                   : type == RED_WAVE_T_I64 ? wave_once_fn<OpU64>(op)
+                                            : wave_once_fn<OpComp>(op);
+  void* args[] = {&in, &out};
+  if ((rc = launch(fn, 1, kWave, args, s, false))) return rc;
+  RED_HIP(hipMemcpyAsync(host_out, out, kWave * esz, hipMemcpyDeviceToHost, s));
+  RED_HIP(hipStreamSynchronize(s));
   return RED_OK;
 }
 

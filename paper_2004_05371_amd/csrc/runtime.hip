@@ -698,39 +698,31 @@ static int time_plan(int dtype, int acc, const red_plan& plan, const void* x, in
   return RED_OK;
 }
 
-int red_autotune(int dtype, int acc, const void* x, int64_t n, void* out, void* stream, int budget,
-                 red_plan* best, double* best_us) {
-  red_opts vo;
-  memset(&vo, 0, sizeof vo);
-  vo.acc = acc;
-  int rc = validate_sum_args(dtype, x, n, out, &vo);
+int red_autotune_search(int dtype, int64_t n, int cus, int nxcc, int allow_xcd, int budget, red_cost_fn cost,
+                        void* ctx, red_plan* best, double* best_us) {
+  int rc = check_dtype(dtype);
   if (rc) return rc;
-  const DeviceInfo* dev;
-  if ((rc = ensure_device(&dev))) return rc;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  if (stream_capturing(s)) return set_error(RED_EINVAL, "autotuning cannot run inside stream capture");
+  if (n < 0 || cus < 1 || nxcc < 1 || !cost) return set_error(RED_EINVAL, "bad search arguments");
+  DeviceInfo d;
+  d.cus = cus;
+  d.nxcc = nxcc;
   // Search: (1) nontemporal hint on the default shape; (2) every
   // (pipelined?, wg, ipt, grid) of the relaunch variant with that hint;
-  // (3) the other synchronization variants on the best shape.  `budget` caps the number
-  // of timed candidates (0 = no cap).  The grid candidates start at one
-  // workgroup per CU; the in-flight bytes per CU (wg * ipt * 16 * grid /
-  // CUs) is what the shapes trade off.
+  // (3) one workgroup for small inputs; (4) the other synchronization
+  // variants on the best shape.  `budget` caps the number of timed
+  // candidates (0 = no cap).  The grid candidates start at one workgroup
+  // per CU; the in-flight bytes per CU (wg * ipt * 16 * grid / CUs) is what
+  // the shapes trade off.  The cost function may lower a candidate's grid
+  // (co-residency of the persistent variant); the plan kept is the one it
+  // timed.  The first candidate of the lowest cost wins.
   int timed = 0;
-  red_plan cur = default_plan(dtype, n, *dev);
+  red_plan cur = default_plan(dtype, n, d);
   double cur_us = 1e300;
   auto consider = [&](red_plan p) -> int {
     if (budget > 0 && timed >= budget) return RED_OK;
-    if (p.variant == RED_VARIANT_PERSISTENT) {
-      int maxg = 0;
-      int r = reduce_max_coresident(dtype, acc, p.ipt, (p.flags & RED_FLAG_NONTEMPORAL) != 0,
-                                    (p.flags & RED_FLAG_PIPELINE) != 0, p.wg, *dev, &maxg);
-      if (r) return r;
-      if (p.grid == 0 || p.grid > maxg) p.grid = maxg;
-    }
-    double us = 0;
-    int r = time_plan(dtype, acc, p, x, n, out, s, &us);
+    const double us = cost(&p, ctx);
     ++timed;
-    if (r) return r;
+    if (us < 0) return (int)us;  // the cost function's status
     if (us < cur_us) {
       cur_us = us;
       cur = p;
@@ -753,7 +745,7 @@ int red_autotune(int dtype, int acc, const void* x, int64_t n, void* out, void* 
         const int64_t tile = (int64_t)wg * ipt;
         const int64_t want = std::max<int64_t>(1, (nvec + tile - 1) / tile);
         for (int m : mults) {
-          const int64_t g = std::min<int64_t>({(int64_t)m * dev->cus, want, (int64_t)RED_MAX_GRID});
+          const int64_t g = std::min<int64_t>({(int64_t)m * cus, want, (int64_t)RED_MAX_GRID});
           if ((rc = consider(red_plan{RED_VARIANT_RELAUNCH, wg, ipt, (int)g, nt_flag | pipe}))) return rc;
           if (g == want) break;
         }
@@ -766,9 +758,8 @@ int red_autotune(int dtype, int acc, const void* x, int64_t n, void* out, void* 
           if ((rc = consider(red_plan{RED_VARIANT_SINGLE, wg, ipt, 1, nt_flag | pipe}))) return rc;
   const red_plan shape = cur;
   // XCD-aggregated publication relies on the dispatch order (checked in the
-  // kernels); it is a candidate only when REDSUM_ALLOW_XCD=1.
-  const char* allow = getenv("REDSUM_ALLOW_XCD");
-  const bool try_xcd = dev->nxcc > 1 && allow && atoi(allow) == 1;
+  // kernels); it is a candidate only when the caller allows it.
+  const bool try_xcd = nxcc > 1 && allow_xcd;
   for (int v : {RED_VARIANT_ATOMIC, RED_VARIANT_PERSISTENT})
     for (int xcd : {0, try_xcd ? RED_FLAG_XCD : 0}) {
       if (shape.variant == RED_VARIANT_SINGLE) break;
@@ -782,6 +773,56 @@ int red_autotune(int dtype, int acc, const void* x, int64_t n, void* out, void* 
       }
       if (!xcd && !try_xcd) break;
     }
+  if (timed == 0) return set_error(RED_EINVAL, "no candidate timed");
+  if (best) *best = cur;
+  if (best_us) *best_us = cur_us;
+  return RED_OK;
+}
+
+namespace {
+// Cost of a candidate on the GPU: the median of 10 timed calls on the
+// caller's data (a persistent candidate's grid capped at co-residency).
+struct GpuCost {
+  int dtype, acc;
+  const void* x;
+  int64_t n;
+  void* out;
+  hipStream_t s;
+  const DeviceInfo* dev;
+};
+double gpu_cost(red_plan* p, void* c) {
+  const GpuCost& k = *static_cast<const GpuCost*>(c);
+  if (p->variant == RED_VARIANT_PERSISTENT) {
+    int maxg = 0;
+    int r = reduce_max_coresident(k.dtype, k.acc, p->ipt, (p->flags & RED_FLAG_NONTEMPORAL) != 0,
+                                  (p->flags & RED_FLAG_PIPELINE) != 0, p->wg, *k.dev, &maxg);
+    if (r) return (double)r;
+    if (p->grid == 0 || p->grid > maxg) p->grid = maxg;
+  }
+  double us = 0;
+  const int r = time_plan(k.dtype, k.acc, *p, k.x, k.n, k.out, k.s, &us);
+  return r ? (double)r : us;
+}
+}  // namespace
+
+int red_autotune(int dtype, int acc, const void* x, int64_t n, void* out, void* stream, int budget,
+                 red_plan* best, double* best_us) {
+  red_opts vo;
+  memset(&vo, 0, sizeof vo);
+  vo.acc = acc;
+  int rc = validate_sum_args(dtype, x, n, out, &vo);
+  if (rc) return rc;
+  const DeviceInfo* dev;
+  if ((rc = ensure_device(&dev))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (stream_capturing(s)) return set_error(RED_EINVAL, "autotuning cannot run inside stream capture");
+  const char* allow = getenv("REDSUM_ALLOW_XCD");
+  GpuCost ctx{dtype, acc, x, n, out, s, dev};
+  red_plan cur;
+  double cur_us = 0;
+  if ((rc = red_autotune_search(dtype, n, dev->cus, dev->nxcc, allow && atoi(allow) == 1, budget, gpu_cost, &ctx,
+                                &cur, &cur_us)))
+    return rc;
   if ((rc = red_set_plan(dtype, acc, n, &cur))) return rc;
   if (best) *best = cur;
   if (best_us) *best_us = cur_us;

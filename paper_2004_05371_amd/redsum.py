@@ -46,10 +46,11 @@ VARIANT_NAMES = {1: "relaunch", 2: "atomic", 3: "persistent", 4: "single"}
 EXPORTS = [
     "red_init", "red_shutdown", "red_last_error", "red_check_error",
     "red_sum", "red_sum_ex", "red_sum_noalloc", "red_sum_segmented", "red_sum_segmented_ex",
-    "red_sum_segmented_loop", "red_set_plan", "red_get_plan", "red_autotune",
+    "red_sum_segmented_loop", "red_set_plan", "red_get_plan", "red_autotune", "red_autotune_search",
     "red_autotune_segmented", "red_set_segmented_plan", "red_get_segmented_plan",
     "red_kernel_timer", "red_kernel_timer_read", "sync_bench_wave", "sync_bench_wave_ex", "sync_bench_block",
-    "sync_bench_grid", "sync_bench_grid_ex", "sync_bench_relaunch", "sync_check_grid_order",
+    "sync_bench_grid", "sync_bench_grid_ex", "sync_bench_grid_r", "sync_bench_relaunch",
+    "sync_bench_relaunch_ex", "sync_bench_spin", "sync_check_wave", "sync_check_grid_order",
     "sync_check_grid_visibility",
     "sync_check_watchdog", "sync_xcc_map", "red_max_coresident", "red_max_coresident_segmented",
     "red_device_info",
@@ -78,6 +79,9 @@ class RedError(RuntimeError):
 
 _lib: Optional[ctypes.CDLL] = None
 
+# double (*red_cost_fn)(red_plan *plan, void *ctx)
+COST_FN = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.POINTER(Plan), ctypes.c_void_p)
+
 _vp, _i32, _i64, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
 _dp = ctypes.POINTER(ctypes.c_double)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -98,6 +102,7 @@ _SIGS = {
     "red_get_plan": ([_i32, _i32, _i64, ctypes.POINTER(Plan)], _i32),
     "red_autotune": ([_i32, _i32, _vp, _i64, _vp, _vp, _i32, ctypes.POINTER(Plan), _dp], _i32),
     "red_autotune_segmented": ([_vp, _vp, _i64, _vp, _vp, _i32, ctypes.POINTER(Plan), _dp], _i32),
+    "red_autotune_search": ([_i32, _i64, _i32, _i32, _i32, _i32, COST_FN, _vp, ctypes.POINTER(Plan), _dp], _i32),
     "red_set_segmented_plan": ([_i64, ctypes.POINTER(Plan)], _i32),
     "red_get_segmented_plan": ([_i64, ctypes.POINTER(Plan)], _i32),
     "red_kernel_timer": ([_vp, _i32], _i32),
@@ -108,6 +113,10 @@ _SIGS = {
     "sync_bench_grid": ([_i32, _i32, _i32, _dp, _dp, _dp, _vp], _i32),
     "sync_bench_grid_ex": ([_i32, _i32, _i32, _i32, _dp, _dp, _dp, _vp], _i32),
     "sync_bench_relaunch": ([_i32, _i32, _i32, _i32, _dp, _dp, _dp, _vp], _i32),
+    "sync_bench_grid_r": ([_i32, _i32, _i32, _i64, _i64, _i32, _dp, _dp, _dp, _vp], _i32),
+    "sync_bench_relaunch_ex": ([_i32, _i32, _i32, _i32, _i32, _i64, _i32, _dp, _dp, _dp, _vp], _i32),
+    "sync_bench_spin": ([_i64, _i64, _i64, _i32, _dp, _dp, _vp], _i32),
+    "sync_check_wave": ([_i32, _i32, _vp, _vp, _vp], _i32),
     "sync_check_grid_order": ([_i32, _i32, _i64p, _i64p, _vp], _i32),
     "sync_check_grid_visibility": ([_i32, _i32, _i32, _i32, _i64p, _vp], _i32),
     "sync_check_watchdog": ([_i32, _i32, _i32, _i32, _vp], _i32),
@@ -228,6 +237,31 @@ def red_autotune(dtype: int, acc: int, x: int, n: int, out: int, stream: int = 0
     return p, us.value
 
 
+def red_autotune_search(dtype: int, n: int, cost, cus: int = 256, nxcc: int = 8, allow_xcd: bool = False,
+                        budget: int = 0):
+    """The library's candidate search with a caller-supplied cost: `cost`
+    takes a Plan (it may lower plan.grid) and returns microseconds, or a
+    negative status to stop.  -> (best Plan, its cost)."""
+    errors = []
+
+    def trampoline(pp, _ctx):
+        try:
+            return float(cost(pp.contents))
+        except Exception as e:  # an exception must not cross the C frames
+            errors.append(e)
+            return float(RED_EINVAL)
+
+    fn = COST_FN(trampoline)
+    p = Plan()
+    us = ctypes.c_double()
+    rc = load().red_autotune_search(dtype, n, cus, nxcc, int(allow_xcd), budget, fn, None, ctypes.byref(p),
+                                    ctypes.byref(us))
+    if errors:
+        raise errors[0]
+    _check(rc, "red_autotune_search")
+    return p, us.value
+
+
 def red_autotune_segmented(x: int, offsets: int, nseg: int, out: int, stream: int = 0, budget: int = 0):
     p = Plan()
     us = ctypes.c_double()
@@ -294,6 +328,11 @@ def sync_bench_grid_ex(n_wg: int, wg_size: int = 256, groups: int = 0, reps: int
     return _probe3("sync_bench_grid_ex", n_wg, wg_size, groups, reps, stream=stream)
 
 
+def sync_bench_grid_r(n_wg: int, wg_size: int, groups: int, r1: int, r2: int, reps: int = 20, stream: int = 0):
+    """Grid barrier with the two repetition counts of Eq. 7 fixed (r1 > r2 > 0)."""
+    return _probe3("sync_bench_grid_r", n_wg, wg_size, groups, r1, r2, reps, stream=stream)
+
+
 LAUNCH_ORDINARY, LAUNCH_COOPERATIVE, LAUNCH_GRAPH = 0, 1, 2
 
 
@@ -303,6 +342,44 @@ def sync_bench_relaunch(n_wg: int = 256, wg_size: int = 256, cooperative=False, 
     cooperative: False/True, or a launch type LAUNCH_ORDINARY /
     LAUNCH_COOPERATIVE / LAUNCH_GRAPH."""
     return _probe3("sync_bench_relaunch", n_wg, wg_size, int(cooperative), reps, stream=stream)
+
+
+def sync_bench_relaunch_ex(n_wg: int, wg_size: int, launch_type: int, i: int, j: int, unit_ticks: int = 0,
+                           reps: int = 20, stream: int = 0):
+    """Eq. 6 with launch counts (i, j) and a wait unit of unit_ticks 100 MHz
+    ticks (0 = 5 us) -> (overhead ns, sigma ns, null-kernel ns)."""
+    return _probe3("sync_bench_relaunch_ex", n_wg, wg_size, launch_type, i, j, unit_ticks, reps, stream=stream)
+
+
+def sync_bench_spin(unit_ticks: int, r1: int, r2: int, reps: int = 20, stream: int = 0):
+    """Eq. 7 over a wait kernel of r x unit_ticks ticks -> (ns per unit, sigma ns)."""
+    ns, sg = ctypes.c_double(), ctypes.c_double()
+    _check(load().sync_bench_spin(unit_ticks, r1, r2, reps, ctypes.byref(ns), ctypes.byref(sg), stream),
+           "sync_bench_spin")
+    return ns.value, sg.value
+
+
+_WAVE_CTYPES = {0: ctypes.c_float, 1: ctypes.c_uint32, 2: ctypes.c_double, 3: ctypes.c_uint64}
+
+
+def sync_check_wave(op: int, vtype: int, values, stream: int = 0):
+    """One wavefront combine of 64 values (list; for the compensated type
+    a list of (s, c) pairs) -> the 64 per-lane results."""
+    if len(values) != 64:
+        raise ValueError("64 values, one per lane")
+    if vtype == WAVE_TYPES["comp"]:
+        flat = [float(v) for pair in values for v in pair]
+        buf_in = (ctypes.c_float * 128)(*flat)
+        buf_out = (ctypes.c_float * 128)()
+    else:
+        ct = _WAVE_CTYPES[vtype]
+        buf_in = (ct * 64)(*values)
+        buf_out = (ct * 64)()
+    _check(load().sync_check_wave(op, vtype, ctypes.cast(buf_in, _vp), ctypes.cast(buf_out, _vp), stream),
+           "sync_check_wave")
+    if vtype == WAVE_TYPES["comp"]:
+        return [(buf_out[2 * k], buf_out[2 * k + 1]) for k in range(64)]
+    return list(buf_out)
 
 
 def sync_check_grid_visibility(n_wg: int, wg_size: int = 256, groups: int = 0, rounds: int = 50,

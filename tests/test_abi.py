@@ -98,6 +98,27 @@ def test_validation_before_hip(lib):
     assert lib.sync_check_grid_visibility(4, 256, 0, 0, ctypes.byref(e), None) == R.RED_EINVAL
     p = R.Plan(R.RED_VARIANT_PERSISTENT, 256, 16, 0, 0)
     assert lib.red_set_plan(R.RED_F32, 0, 100, ctypes.byref(p)) == R.RED_EINVAL
+    # the no-allocation entry point: its grid limit, before any HIP call
+    big = R.make_opts(variant=R.RED_VARIANT_RELAUNCH, wg=256, ipt=4, grid=R.RED_NOALLOC_MAX_GRID + 1)
+    assert lib.red_sum_noalloc(R.RED_F32, ctypes.c_void_p(64), 4, ctypes.c_void_p(64), None,
+                               ctypes.byref(big)) == R.RED_EINVAL
+    assert "scratch" in R.last_error()
+    assert lib.red_sum_noalloc(R.RED_F32, ctypes.c_void_p(64), -3, ctypes.c_void_p(64), None, None) == R.RED_EINVAL
+    # probe validation: repetition counts, launch counts, wait units, wave ops
+    dd = ctypes.byref(d)
+    assert lib.sync_bench_grid_r(8, 256, 0, 16, 16, 5, dd, dd, None, None) == R.RED_EINVAL  # r1 == r2
+    assert lib.sync_bench_grid_r(8, 256, 0, 0, 5, 5, dd, dd, None, None) == R.RED_EINVAL
+    assert lib.sync_bench_grid_r(8, 256, 0, 1 << 20, 5, 5, dd, dd, None, None) == R.RED_EINVAL
+    assert lib.sync_bench_relaunch_ex(8, 64, 0, 4, 4, 0, 10, dd, dd, None, None) == R.RED_EINVAL  # i == j
+    assert lib.sync_bench_relaunch_ex(8, 64, 0, 65, 1, 0, 10, dd, dd, None, None) == R.RED_EINVAL
+    assert lib.sync_bench_relaunch_ex(8, 64, 0, 8, 1, -1, 10, dd, dd, None, None) == R.RED_EINVAL
+    assert lib.sync_bench_spin(0, 8, 1, 10, dd, dd, None) == R.RED_EINVAL
+    assert lib.sync_bench_spin(100, 8, 8, 10, dd, dd, None) == R.RED_EINVAL
+    assert lib.sync_bench_spin(10**7, 100, 1, 10, dd, dd, None) == R.RED_EINVAL  # > 1 s of waiting
+    buf = (ctypes.c_double * 64)()
+    assert lib.sync_check_wave(7, 0, buf, buf, None) == R.RED_EINVAL
+    assert lib.sync_check_wave(0, 9, buf, buf, None) == R.RED_EINVAL
+    assert lib.sync_check_wave(0, 0, None, buf, None) == R.RED_EINVAL
     # host-side loop baseline validates host offsets
     off = (ctypes.c_int64 * 3)(0, 5, 2)
     assert lib.red_sum_segmented_loop(ctypes.c_void_p(64), off, 2, ctypes.c_void_p(64), None) == R.RED_EINVAL

@@ -292,3 +292,30 @@ def test_full_half_config(lib, kind):
         assert e <= BOUND[kind]
     del t
     torch.cuda.empty_cache()
+
+
+def test_budgeted_tune_sum_installs_the_plan_it_returns(lib):
+    """autotune.tune_sum (red_autotune, Section VII-A/B's search over launch
+    shapes and variants, timed on the data) with a budget: the plan it
+    returns is the one installed for that size, red_sum without options
+    then gives the same bits as that plan given explicitly, and the result
+    is within the bound of the exact oracle."""
+    from paper_2004_05371_amd import autotune
+    n = 3_000_017
+    before = lib.red_get_plan(lib.RED_F32, lib.RED_ACC_COMPENSATED, n)
+    x = inputs.normal_f32(n, sub=61)
+    t = torch.from_numpy(x).to("cuda")
+    out = torch.empty((), dtype=torch.float64, device="cuda")
+    try:
+        entry = autotune.tune_sum(t, out, budget=12)
+        say("tuned", entry)
+        got = lib.red_get_plan(lib.RED_F32, lib.RED_ACC_COMPENSATED, n)
+        assert got.as_dict() == entry["plan"]
+        assert entry["us"] > 0
+        auto = lib.sum(t)
+        explicit = lib.sum(t, opts=lib.opts_from_plan(got))
+        torch.cuda.synchronize()
+        assert auto.item() == explicit.item()
+        assert oracle.rel_err(auto.item(), oracle.exact_sum(x, "f32")) <= BOUND["f32"]
+    finally:
+        lib.red_set_plan(lib.RED_F32, lib.RED_ACC_COMPENSATED, n, before)
