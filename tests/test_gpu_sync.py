@@ -142,12 +142,15 @@ def test_grid_probe_repeat_count_invariance(lib, n_wg, groups):
     assert lib.red_check_error(lib.current_stream()) == lib.RED_OK
 
 
-@pytest.mark.parametrize("unit_ticks,r1,r2", [(100, 64, 8), (37, 96, 16), (500, 40, 4)])
+@pytest.mark.parametrize("unit_ticks,r1,r2", [(100, 512, 32), (37, 1536, 96), (500, 128, 8)])
 def test_eq7_recovers_an_injected_duration(lib, unit_ticks, r1, r2):
     """Section IX's method check with a known answer: kernels that wait r
     units of a known number of 100 MHz ticks; Eq. 7 over r1 and r2 units
     returns the unit's duration within 2 %, with an Eq. 8 uncertainty
-    below 2 % of it."""
+    below 2 % of it.  The two kernels differ by about half a millisecond,
+    so the launch-to-launch jitter (about a microsecond) stays well inside
+    the bound (the paper's rule: a large r1 - r2 makes the estimate's
+    uncertainty small)."""
     tick_ns = 1e6 / lib.red_device_info()["wallclock_khz"]
     want = unit_ticks * tick_ns
     ns, sigma = lib.sync_bench_spin(unit_ticks, r1, r2, reps=10)
