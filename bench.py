@@ -213,6 +213,95 @@ def summarize_trace(trace_dir, bench_json, out_dir, plain_json=None):
     summarize_extensions(rows, line, out_dir)
 
 
+def summarize_configs(paths, out_dir):
+    """Write profiles/sync_characterization.md from the probe records of
+    `bench.py --configs` runs (Sections IV, V and IX: every level of the
+    synchronization hierarchy, Tables I, II and V and the grid-barrier heat
+    map)."""
+    recs = []
+    for p in paths:
+        with open(p) as fh:
+            recs += [json.loads(l) for l in fh if l.strip()]
+    machine = next((r for r in recs if r.get("config") == "machine"), None)
+    by = lambda kind: [r for r in recs if r.get("probe") == kind]
+    out = ["# Synchronization characterization: MI355X (gfx950), one GPU", "",
+           "Commands (repository root), then the summary:", "", "```",
+           "python3 bench.py --only-configs --configs <jsonl> --config-sections machine,probes",
+           "python3 bench.py --summarize-configs <jsonl>", "```", ""]
+    if machine:
+        d = machine["device"]
+        out += ["Device: %d CUs, %d XCDs, shader clock %.2f GHz, wall clock %d kHz; host CPUs %s." %
+                (d["cus"], d["nxcc"], d["clock_khz"] / 1e6, d["wallclock_khz"], machine.get("host_cpus")), ""]
+    out += ["Latencies are the Eq. 7 differential between kernels of r1 and r2 repetitions (host-side HIP events), "
+            "sigma by Eq. 8; cycles are the in-kernel shader clock per operation (Section IX-C's method). "
+            "Block throughput is measured as barriers completed in a 200 us window by every co-resident workgroup.",
+            ""]
+    w = by("wave")
+    if w:
+        out += ["## Wavefront combines (Section VII-D, Table V)", "",
+                "| Op | Type | ns | sigma ns | cycles |", "|---|---|---|---|---|"]
+        out += ["| %s | %s | %.2f | %.2f | %.1f |" % (r["op"], r["type"], r["ns"], r["sigma_ns"], r["cycles"]) for r in w]
+        out.append("")
+    b = by("block")
+    if b:
+        out += ["## Workgroup barrier latency (Section V, Table II)", "",
+                "| Threads per WG | Workgroups | Waves per CU | ns | sigma ns | cycles |", "|---|---|---|---|---|---|"]
+        out += ["| %d | %d | %.2f | %.2f | %.2f | %.1f |" % (r["wg"], r["n_wg"], r["waves_per_cu"], r["ns"], r["sigma_ns"],
+                                                         r["cycles"]) for r in b]
+        out.append("")
+    t = by("block_tput")
+    if t:
+        out += ["## Workgroup barrier throughput under load, measured (Section V, Table II)", "",
+                "| Threads per WG | WGs per CU | Waves per CU | Barriers per us per CU | Cycles per barrier (one WG) |",
+                "|---|---|---|---|---|"]
+        out += ["| %d | %d | %d | %.1f | %.1f |" % (r["wg"], r["wg_per_cu"], r["waves_per_cu"], r["barriers_per_us_per_cu"],
+                                                 r["cycles_per_barrier"]) for r in t]
+        out.append("")
+    g = by("grid")
+    if g:
+        out += ["## Grid barrier heat map (Section V, grid synchronization)", "",
+                "Latency of one grid barrier in ns, by grid size (rows) and workgroup size (columns), one table per "
+                "barrier shape: flat (one counter), 8 groups and the default two-level shape (groups of blockIdx mod "
+                "g), and the XCD-aggregated shape.", ""]
+        wgs = sorted({r["wg"] for r in g})
+        for shape in ("1", "8", "default", "xcd"):
+            rows = [r for r in g if str(r["groups"]) == shape]
+            if not rows:
+                continue
+            out += ["### Shape: %s" % {"1": "flat", "8": "8 groups"}.get(shape, shape), "",
+                    "| Workgroups | " + " | ".join("%d threads (WG/CU)" % x for x in wgs) + " |",
+                    "|---|" + "---|" * len(wgs)]
+            for n in sorted({r["n_wg"] for r in rows}):
+                cells = []
+                for x in wgs:
+                    m = [r for r in rows if r["n_wg"] == n and r["wg"] == x]
+                    cells.append("%.0f (%.2f)" % (m[0]["ns"], m[0]["wg_per_cu"]) if m else "-")
+                out.append("| %d | %s |" % (n, " | ".join(cells)))
+            out.append("")
+    rl = by("relaunch")
+    if rl:
+        out += ["## Kernel boundary (Section IV, Table I; Eq. 6)", "",
+                "| Launch | Workgroups | Overhead ns (Eq. 6) | sigma ns | Null kernel ns |", "|---|---|---|---|---|"]
+        out += ["| %s | %d | %.1f | %.1f | %.1f |" % (r["launch"], r["n_wg"], r["overhead_ns"], r["sigma_ns"],
+                                                  r["null_kernel_total_ns"]) for r in rl]
+        out += ["", "Null kernel: the Section IV host-clock formula for ordinary and cooperative launches; for the graph "
+                "type, the Eq. 7 differential between graphs of 40 and 5 null kernels.", ""]
+        ordinary = {r["n_wg"]: r["overhead_ns"] for r in rl if r["launch"] == "ordinary"}
+        if ordinary and g:
+            out += ["## Grid barrier against a kernel boundary", "",
+                    "| Workgroups (256 threads) | Barrier shape | Barrier ns | Ordinary launch overhead ns | Difference ns |",
+                    "|---|---|---|---|---|"]
+            for n, ov in sorted(ordinary.items()):
+                for r in g:
+                    if r["wg"] == 256 and r["n_wg"] == n:
+                        out.append("| %d | %s | %.0f | %.0f | %.0f |" % (n, r["groups"], r["ns"], ov, r["ns"] - ov))
+            out.append("")
+    path = os.path.join(out_dir, "sync_characterization.md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    log("wrote", path)
+
+
 def summarize_extensions(rows, line, out_dir):
     """Kernel-trace rows of the extension figures of the same bench run:
     the segmented batch (slice kernel and fix-up) and the stencil."""
@@ -542,10 +631,14 @@ def model_check(R, stream, emit, lo=10, hi=26):
     del big
 
 
-def run_configs(R, dev, stream, path, plans):
+CONFIG_SECTIONS = ("machine", "small", "int", "f32", "half", "segments", "uniform", "stencil", "model", "probes")
+
+
+def run_configs(R, dev, stream, path, plans, sections=CONFIG_SECTIONS):
     """Every workload of the study, one JSON record per measurement,
     appended to `path` (JSONL).  Timed regions hold only library calls; the
-    oracle timings and errors are the CPU-baseline leg of each record."""
+    oracle timings and errors are the CPU-baseline leg of each record.
+    `sections` selects which of CONFIG_SECTIONS run."""
     import numpy as np
     import torch
 
@@ -559,12 +652,6 @@ def run_configs(R, dev, stream, path, plans):
         log(json.dumps(rec))
         with open(path, "a") as fh:
             fh.write(json.dumps(rec) + "\n")
-
-    # -- the machine: device properties, partition mode, clocks and power
-    #    (amd-smi, read-only queries), host CPUs available to this process
-    emit({"config": "machine", "device": dev, "host_cpus": len(os.sched_getaffinity(0)),
-          "amd_smi": {k: smi_query(v) for k, v in (("partition", ["static", "--partition"]),
-                                                   ("clock_power", ["metric", "--clock", "--power"]))}})
 
     last = {}  # statistics of the latest timed() call, in microseconds
 
@@ -585,200 +672,233 @@ def run_configs(R, dev, stream, path, plans):
         ex = oracle.exact_sum(x, kind) if kind != "i32" else oracle.sum_i32(x)
         return ex, time.perf_counter() - c0
 
-    # -- small: 2^20 fp32 U[-1,1] and int32 U[-1000,1000]; the two-launch
-    #    variant, and the tuned plan
-    for kind, x in (("f32", inputs.uniform_f32(1 << 20)), ("i32", inputs.uniform_i32(1 << 20))):
+    def sec_machine():
+        # -- the machine: device properties, partition mode, clocks and power
+        #    (amd-smi, read-only queries), host CPUs available to this process
+        emit({"config": "machine", "device": dev, "host_cpus": len(os.sched_getaffinity(0)),
+              "amd_smi": {k: smi_query(v) for k, v in (("partition", ["static", "--partition"]),
+                                                       ("clock_power", ["metric", "--clock", "--power"]))}})
+
+    def sec_small():
+        # -- small: 2^20 fp32 U[-1,1] and int32 U[-1000,1000]; the two-launch
+        #    variant, and the tuned plan
+        for kind, x in (("f32", inputs.uniform_f32(1 << 20)), ("i32", inputs.uniform_i32(1 << 20))):
+            t = torch.from_numpy(x).to("cuda")
+            code = R.RED_F32 if kind == "f32" else R.RED_I32
+            out = torch.empty((), dtype=torch.float64 if kind == "f32" else torch.int64, device="cuda")
+            o = R.make_opts(variant=R.RED_VARIANT_RELAUNCH)
+            fn = lambda: R.red_sum_ex(code, t.data_ptr(), t.numel(), out.data_ptr(), sh, o)
+            warm, cold = timed(fn, 200), timed(fn, 50, flushed=True)
+            dev_t = statistics.median(time_gpu_side(fn, 100, stream))
+            plan = plans.sum_plan(t, out, R.RED_ACC_COMPENSATED, sh)
+            ot = R.opts_from_plan(plan)
+            tuned = timed(lambda: R.red_sum_ex(code, t.data_ptr(), t.numel(), out.data_ptr(), sh, ot), 200)
+            fn()
+            torch.cuda.synchronize()
+            ex, tc = cpu_exact(x, kind)
+            ok = (out.item() == ex) if kind == "i32" else (oracle.rel_err(out.item(), ex) <= 1e-6)
+            emit({"config": "small", "dtype": kind, "n": x.size, "variant": "relaunch", "us_warm": round(warm * 1e3, 2),
+                  "us_device": round(dev_t * 1e3, 2),
+                  "us_flushed": round(cold * 1e3, 2), "tuned_plan": plan.as_dict(), "us_tuned": round(tuned * 1e3, 2),
+                  "matches_oracle": bool(ok), "cpu_oracle_s": round(tc, 4)})
+
+    def sec_int():
+        # -- int: 2^26 int32, three synchronization variants, flushed and warm
+        x = inputs.uniform_i32(1 << 26)
         t = torch.from_numpy(x).to("cuda")
-        code = R.RED_F32 if kind == "f32" else R.RED_I32
-        out = torch.empty((), dtype=torch.float64 if kind == "f32" else torch.int64, device="cuda")
-        o = R.make_opts(variant=R.RED_VARIANT_RELAUNCH)
-        fn = lambda: R.red_sum_ex(code, t.data_ptr(), t.numel(), out.data_ptr(), sh, o)
-        warm, cold = timed(fn, 200), timed(fn, 50, flushed=True)
-        dev_t = statistics.median(time_gpu_side(fn, 100, stream))
+        out = torch.empty((), dtype=torch.int64, device="cuda")
         plan = plans.sum_plan(t, out, R.RED_ACC_COMPENSATED, sh)
-        ot = R.opts_from_plan(plan)
-        tuned = timed(lambda: R.red_sum_ex(code, t.data_ptr(), t.numel(), out.data_ptr(), sh, ot), 200)
-        fn()
-        torch.cuda.synchronize()
-        ex, tc = cpu_exact(x, kind)
-        ok = (out.item() == ex) if kind == "i32" else (oracle.rel_err(out.item(), ex) <= 1e-6)
-        emit({"config": "small", "dtype": kind, "n": x.size, "variant": "relaunch", "us_warm": round(warm * 1e3, 2),
-              "us_device": round(dev_t * 1e3, 2),
-              "us_flushed": round(cold * 1e3, 2), "tuned_plan": plan.as_dict(), "us_tuned": round(tuned * 1e3, 2),
-              "matches_oracle": bool(ok), "cpu_oracle_s": round(tc, 4)})
-
-    # -- int: 2^26 int32, three synchronization variants, flushed and warm
-    x = inputs.uniform_i32(1 << 26)
-    t = torch.from_numpy(x).to("cuda")
-    out = torch.empty((), dtype=torch.int64, device="cuda")
-    plan = plans.sum_plan(t, out, R.RED_ACC_COMPENSATED, sh)
-    warm = variant_table(R, plan, R.RED_I32, t, t.numel(), out, sh, stream, dev)
-    cold = variant_table(R, plan, R.RED_I32, t, t.numel(), out, sh, stream, dev, reps=30, flush=flush)
-    exact, tc = cpu_exact(x, "i32")
-    bit_exact = {}
-    for v in (1, 2, 3):
-        R.red_sum_ex(R.RED_I32, t.data_ptr(), t.numel(), out.data_ptr(), sh,
-                     R.make_opts(variant=v, wg=plan.wg, ipt=plan.ipt,
-                                 grid=min(plan.grid or 1024, R.red_max_coresident(plan.wg))))
-        torch.cuda.synchronize()
-        bit_exact[R.VARIANT_NAMES[v]] = out.item() == exact
-    emit({"config": "int", "dtype": "i32", "n": x.size, "plan": plan.as_dict(), "GBps_warm": warm,
-          "GBps_flushed": cold, "bit_exact": bit_exact, "cpu_oracle_s": round(tc, 4)})
-    del t
-
-    # -- f32: 2^28 in two distributions, plain vs compensated
-    for gen in ("normal", "mixed"):
-        x = inputs.normal_f32(1 << 28) if gen == "normal" else inputs.mixed_f32(1 << 28)
-        t = torch.from_numpy(x).to("cuda")
-        out = torch.empty((), dtype=torch.float64, device="cuda")
-        ex, tc = cpu_exact(x, "f32")
-        absx = float(oracle.exact_abs_sum(x, "f32").fraction)
-        for acc, name in ((0, "compensated"), (1, "plain")):
-            plan = plans.sum_plan(t, out, acc, sh)
-            o = R.opts_from_plan(plan, acc=acc)
-            ms = timed(lambda: R.red_sum_ex(R.RED_F32, t.data_ptr(), t.numel(), out.data_ptr(), sh, o), 50)
-            stats = dict(last)
+        warm = variant_table(R, plan, R.RED_I32, t, t.numel(), out, sh, stream, dev)
+        cold = variant_table(R, plan, R.RED_I32, t, t.numel(), out, sh, stream, dev, reps=30, flush=flush)
+        exact, tc = cpu_exact(x, "i32")
+        bit_exact = {}
+        for v in (1, 2, 3):
+            R.red_sum_ex(R.RED_I32, t.data_ptr(), t.numel(), out.data_ptr(), sh,
+                         R.make_opts(variant=v, wg=plan.wg, ipt=plan.ipt,
+                                     grid=min(plan.grid or 1024, R.red_max_coresident(plan.wg))))
             torch.cuda.synchronize()
-            r = out.item()
-            emit({"config": "f32", "dist": gen, "acc": name, "n": x.size, "plan": plan.as_dict(),
-                  "GBps": gbps(x.nbytes, ms), "timing_us": stats, "rel_err": oracle.rel_err(r, ex),
-                  "err_over_sum_abs": abs(float(ex.fraction) - r) / absx, "cpu_oracle_s": round(tc, 3)})
+            bit_exact[R.VARIANT_NAMES[v]] = out.item() == exact
+        emit({"config": "int", "dtype": "i32", "n": x.size, "plan": plan.as_dict(), "GBps_warm": warm,
+              "GBps_flushed": cold, "bit_exact": bit_exact, "cpu_oracle_s": round(tc, 4)})
         del t
 
-    # -- half: bf16 / fp16 2^29 N(0,1), compensated (and plain for contrast)
-    for kind in ("bf16", "f16"):
-        bits = inputs.normal_half_bits(1 << 29, kind)
-        tdt = torch.bfloat16 if kind == "bf16" else torch.float16
-        t = torch.from_numpy(bits.view(np.int16)).view(tdt).to("cuda")
-        code = R.RED_BF16 if kind == "bf16" else R.RED_F16
-        out = torch.empty((), dtype=torch.float64, device="cuda")
-        ex, tc = cpu_exact(bits, kind)
-        res = {}
-        for acc, name in ((0, "compensated"), (1, "plain")):
-            plan = plans.sum_plan(t, out, acc, sh)
-            o = R.opts_from_plan(plan, acc=acc)
-            ms = timed(lambda: R.red_sum_ex(code, t.data_ptr(), t.numel(), out.data_ptr(), sh, o), 50)
-            torch.cuda.synchronize()
-            res[name] = {"plan": plan.as_dict(), "GBps": gbps(bits.nbytes, ms), "timing_us": dict(last),
-                         "Gelem_per_s": round(bits.size / (ms * 1e-3) / 1e9, 1),
-                         "rel_err": oracle.rel_err(out.item(), ex)}
-        emit({"config": "half", "dtype": kind, "n": bits.size, **res, "cpu_oracle_s": round(tc, 3)})
-        del t
-        torch.cuda.empty_cache()
+    def sec_f32():
+        # -- f32: 2^28 in two distributions, plain vs compensated
+        for gen in ("normal", "mixed"):
+            x = inputs.normal_f32(1 << 28) if gen == "normal" else inputs.mixed_f32(1 << 28)
+            t = torch.from_numpy(x).to("cuda")
+            out = torch.empty((), dtype=torch.float64, device="cuda")
+            ex, tc = cpu_exact(x, "f32")
+            absx = float(oracle.exact_abs_sum(x, "f32").fraction)
+            for acc, name in ((0, "compensated"), (1, "plain")):
+                plan = plans.sum_plan(t, out, acc, sh)
+                o = R.opts_from_plan(plan, acc=acc)
+                ms = timed(lambda: R.red_sum_ex(R.RED_F32, t.data_ptr(), t.numel(), out.data_ptr(), sh, o), 50)
+                stats = dict(last)
+                torch.cuda.synchronize()
+                r = out.item()
+                emit({"config": "f32", "dist": gen, "acc": name, "n": x.size, "plan": plan.as_dict(),
+                      "GBps": gbps(x.nbytes, ms), "timing_us": stats, "rel_err": oracle.rel_err(r, ex),
+                      "err_over_sum_abs": abs(float(ex.fraction) - r) / absx, "cpu_oracle_s": round(tc, 3)})
+            del t
 
-    # -- segmented: 10,000 log-uniform segments, one graph launch vs a loop;
-    #    the drawn lengths (about 7.4e8 elements) and the same draws scaled
-    #    to a total of about 2^28
-    for label, total in (("segments", None), ("segments_2p28", 1 << 28)):
-        x, off = inputs.segments(10000, total=total)
-        xt = torch.from_numpy(x).to("cuda")
-        ot = torch.from_numpy(off).to("cuda")
-        nseg = off.size - 1
-        out = torch.empty(nseg, dtype=torch.float64, device="cuda")
-        plan = plans.seg_plan(xt, ot, out, sh)
-        nbytes = x.nbytes + off.nbytes + out.numel() * 8
-        ms_graph = timed(lambda: R.red_sum_segmented(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh), 30)
-        graph_stats = dict(last)
-        o = R.make_opts(variant=R.RED_VARIANT_PERSISTENT, wg=plan.wg, ipt=plan.ipt,
-                        grid=min(plan.grid, R.red_max_coresident_segmented(plan.ipt, plan.wg)),
-                        flags=R.FLAG_PLAIN_LAUNCH | (plan.flags & R.FLAG_NONTEMPORAL))
-        ms_barrier = timed(lambda: R.red_sum_segmented_ex(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh, o),
-                           30)
-        fixups = {}
-        for vname, v in (("relaunch", R.RED_VARIANT_RELAUNCH), ("ticket", R.RED_VARIANT_ATOMIC)):
-            ov = R.make_opts(variant=v, wg=plan.wg, ipt=plan.ipt, grid=plan.grid, flags=plan.flags)
-            fixups[vname] = round(timed(lambda: R.red_sum_segmented_ex(xt.data_ptr(), ot.data_ptr(), nseg,
-                                                                       out.data_ptr(), sh, ov), 30) * 1e3, 1)
-        ms_loop = timed(lambda: R.red_sum_segmented_loop(xt.data_ptr(), off, nseg, out.data_ptr(), sh), 3)
-        R.red_sum_segmented(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh)
-        torch.cuda.synchronize()
-        got = out.cpu().numpy()
-        c0 = time.perf_counter()
-        sums = oracle.segmented_sums(x, off)
-        tc = time.perf_counter() - c0
-        worst = max(oracle.rel_err(float(got[k]), e) if e.fraction != 0 else abs(got[k]) for k, e in enumerate(sums))
-        emit({"config": label, "nseg": nseg, "total_elems": int(off[-1]), "bytes": nbytes, "plan": plan.as_dict(),
-              "graph_us": round(ms_graph * 1e3, 1), "graph_GBps": gbps(nbytes, ms_graph), "graph_timing_us": graph_stats,
-              "grid_barrier_fixup_us": round(ms_barrier * 1e3, 1), "plan_with_fixup_us": fixups,
-              "loop_per_segment_us": round(ms_loop * 1e3, 1), "speedup_vs_loop": round(ms_loop / ms_graph, 1),
-              "max_rel_err": worst, "cpu_oracle_s": round(tc, 2)})
-        del xt, ot
-        torch.cuda.empty_cache()
+    def sec_half():
+        # -- half: bf16 / fp16 2^29 N(0,1), compensated (and plain for contrast)
+        for kind in ("bf16", "f16"):
+            bits = inputs.normal_half_bits(1 << 29, kind)
+            tdt = torch.bfloat16 if kind == "bf16" else torch.float16
+            t = torch.from_numpy(bits.view(np.int16)).view(tdt).to("cuda")
+            code = R.RED_BF16 if kind == "bf16" else R.RED_F16
+            out = torch.empty((), dtype=torch.float64, device="cuda")
+            ex, tc = cpu_exact(bits, kind)
+            res = {}
+            for acc, name in ((0, "compensated"), (1, "plain")):
+                plan = plans.sum_plan(t, out, acc, sh)
+                o = R.opts_from_plan(plan, acc=acc)
+                ms = timed(lambda: R.red_sum_ex(code, t.data_ptr(), t.numel(), out.data_ptr(), sh, o), 50)
+                torch.cuda.synchronize()
+                res[name] = {"plan": plan.as_dict(), "GBps": gbps(bits.nbytes, ms), "timing_us": dict(last),
+                             "Gelem_per_s": round(bits.size / (ms * 1e-3) / 1e9, 1),
+                             "rel_err": oracle.rel_err(out.item(), ex)}
+            emit({"config": "half", "dtype": kind, "n": bits.size, **res, "cpu_oracle_s": round(tc, 3)})
+            del t
+            torch.cuda.empty_cache()
 
-    # -- segmented batches of uniform lengths over 2^28 values: the cost of
-    #    short segments, the slice granularity switch
-    xs = torch.from_numpy(inputs.normal_f32(1 << 28, sub=3)).to("cuda")
-    splan = dict(wg=512, ipt=4, grid=2 * dev["cus"])
-    forms = {"workgroup": R.FLAG_SEG_WORKGROUP, "pieces": R.FLAG_SEG_PIECES, "runs": R.FLAG_SEG_RUNS}
-    for L in (16, 32, 64, 256, 768, 1024, 4096, 16384, 65536, 262144, 1 << 28):
-        nseg = (1 << 28) // L
-        ntot = nseg * L
-        offs = torch.arange(0, ntot + 1, L, dtype=torch.int64, device="cuda")
-        outs = torch.empty(nseg, dtype=torch.float64, device="cuda")
-        nb = ntot * 4 + (nseg + 1) * 8 + nseg * 8
-        row = {}
-        for fname, ff in [("auto", 0)] + list(forms.items()):
-            if (fname == "workgroup" and L < 4096) or (fname == "pieces" and L < 64) or (fname == "runs" and L > 16384):
-                continue
+    def sec_segments():
+        # -- segmented: 10,000 log-uniform segments, one graph launch vs a loop;
+        #    the drawn lengths (about 7.4e8 elements) and the same draws scaled
+        #    to a total of about 2^28
+        for label, total in (("segments", None), ("segments_2p28", 1 << 28)):
+            x, off = inputs.segments(10000, total=total)
+            xt = torch.from_numpy(x).to("cuda")
+            ot = torch.from_numpy(off).to("cuda")
+            nseg = off.size - 1
+            out = torch.empty(nseg, dtype=torch.float64, device="cuda")
+            plan = plans.seg_plan(xt, ot, out, sh)
+            nbytes = x.nbytes + off.nbytes + out.numel() * 8
+            ms_graph = timed(lambda: R.red_sum_segmented(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh), 30)
+            graph_stats = dict(last)
+            o = R.make_opts(variant=R.RED_VARIANT_PERSISTENT, wg=plan.wg, ipt=plan.ipt,
+                            grid=min(plan.grid, R.red_max_coresident_segmented(plan.ipt, plan.wg)),
+                            flags=R.FLAG_PLAIN_LAUNCH | (plan.flags & R.FLAG_NONTEMPORAL))
+            ms_barrier = timed(lambda: R.red_sum_segmented_ex(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh, o),
+                               30)
+            fixups = {}
             for vname, v in (("relaunch", R.RED_VARIANT_RELAUNCH), ("ticket", R.RED_VARIANT_ATOMIC)):
-                if fname != "auto" and vname == "ticket":
+                ov = R.make_opts(variant=v, wg=plan.wg, ipt=plan.ipt, grid=plan.grid, flags=plan.flags)
+                fixups[vname] = round(timed(lambda: R.red_sum_segmented_ex(xt.data_ptr(), ot.data_ptr(), nseg,
+                                                                           out.data_ptr(), sh, ov), 30) * 1e3, 1)
+            ms_loop = timed(lambda: R.red_sum_segmented_loop(xt.data_ptr(), off, nseg, out.data_ptr(), sh), 3)
+            R.red_sum_segmented(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), sh)
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            c0 = time.perf_counter()
+            sums = oracle.segmented_sums(x, off)
+            tc = time.perf_counter() - c0
+            worst = max(oracle.rel_err(float(got[k]), e) if e.fraction != 0 else abs(got[k]) for k, e in enumerate(sums))
+            emit({"config": label, "nseg": nseg, "total_elems": int(off[-1]), "bytes": nbytes, "plan": plan.as_dict(),
+                  "graph_us": round(ms_graph * 1e3, 1), "graph_GBps": gbps(nbytes, ms_graph), "graph_timing_us": graph_stats,
+                  "grid_barrier_fixup_us": round(ms_barrier * 1e3, 1), "plan_with_fixup_us": fixups,
+                  "loop_per_segment_us": round(ms_loop * 1e3, 1), "speedup_vs_loop": round(ms_loop / ms_graph, 1),
+                  "max_rel_err": worst, "cpu_oracle_s": round(tc, 2)})
+            del xt, ot
+            torch.cuda.empty_cache()
+
+    def sec_uniform():
+        # -- segmented batches of uniform lengths over 2^28 values: the cost of
+        #    short segments, the slice granularity switch
+        xs = torch.from_numpy(inputs.normal_f32(1 << 28, sub=3)).to("cuda")
+        splan = dict(wg=512, ipt=4, grid=2 * dev["cus"])
+        forms = {"workgroup": R.FLAG_SEG_WORKGROUP, "pieces": R.FLAG_SEG_PIECES, "runs": R.FLAG_SEG_RUNS}
+        for L in (16, 32, 64, 256, 768, 1024, 4096, 16384, 65536, 262144, 1 << 28):
+            nseg = (1 << 28) // L
+            ntot = nseg * L
+            offs = torch.arange(0, ntot + 1, L, dtype=torch.int64, device="cuda")
+            outs = torch.empty(nseg, dtype=torch.float64, device="cuda")
+            nb = ntot * 4 + (nseg + 1) * 8 + nseg * 8
+            row = {}
+            for fname, ff in [("auto", 0)] + list(forms.items()):
+                if (fname == "workgroup" and L < 4096) or (fname == "pieces" and L < 64) or (fname == "runs" and L > 16384):
                     continue
-                o = R.make_opts(variant=v, flags=R.FLAG_NONTEMPORAL | ff, **splan)
-                ms = timed(lambda: R.red_sum_segmented_ex(xs.data_ptr(), offs.data_ptr(), nseg, outs.data_ptr(),
-                                                          sh, o), 20)
-                row["%s_%s_us" % (fname, vname)] = round(ms * 1e3, 1)
-        ms = row["auto_relaunch_us"] / 1e3
-        ref = xs[:ntot].view(nseg, L).double().sum(1)  # torch check on the GPU (the oracle covers parity in the tests)
-        emit({"config": "segments_uniform", "length": L, "nseg": nseg, "plan": splan, "us": row["auto_relaunch_us"],
-              "GBps": gbps(nb, ms), "by_form_and_fixup_us": row,
-              "form": "workgroup" if L >= 16384 else "runs" if L < 1024 else "pieces",
-              "max_abs_diff_vs_fp64_torch": float((outs - ref).abs().max())})
-        del offs, outs, ref
-    del xs
-    torch.cuda.empty_cache()
+                for vname, v in (("relaunch", R.RED_VARIANT_RELAUNCH), ("ticket", R.RED_VARIANT_ATOMIC)):
+                    if fname != "auto" and vname == "ticket":
+                        continue
+                    o = R.make_opts(variant=v, flags=R.FLAG_NONTEMPORAL | ff, **splan)
+                    ms = timed(lambda: R.red_sum_segmented_ex(xs.data_ptr(), offs.data_ptr(), nseg, outs.data_ptr(),
+                                                              sh, o), 20)
+                    row["%s_%s_us" % (fname, vname)] = round(ms * 1e3, 1)
+            ms = row["auto_relaunch_us"] / 1e3
+            ref = xs[:ntot].view(nseg, L).double().sum(1)  # torch check on the GPU (the oracle covers parity in the tests)
+            emit({"config": "segments_uniform", "length": L, "nseg": nseg, "plan": splan, "us": row["auto_relaunch_us"],
+                  "GBps": gbps(nb, ms), "by_form_and_fixup_us": row,
+                  "form": "workgroup" if L >= 16384 else "runs" if L < 1024 else "pieces",
+                  "max_abs_diff_vs_fp64_torch": float((outs - ref).abs().max())})
+            del offs, outs, ref
+        del xs
+        torch.cuda.empty_cache()
 
-    # -- iterative stencil: one launch per step against the time loop inside
-    #    one persistent kernel (values kept in LDS across grid barriers)
-    stencil_configs(R, dev, stream, emit, timed)
+    def sec_stencil():
+        # -- iterative stencil: one launch per step against the time loop inside
+        #    one persistent kernel (values kept in LDS across grid barriers)
+        stencil_configs(R, dev, stream, emit, timed)
 
-    # -- model: the Eq. 1-5 switch point between one workgroup ("basic")
-    #    and the whole device ("more") from constants fitted on this GPU,
-    #    against the crossover measured directly
-    model_check(R, stream, emit)
+    def sec_model():
+        # -- model: the Eq. 1-5 switch point between one workgroup ("basic")
+        #    and the whole device ("more") from constants fitted on this GPU,
+        #    against the crossover measured directly
+        model_check(R, stream, emit)
 
-    # -- probes
-    for vname, vt in R.WAVE_TYPES.items():
-        for op, name in ((0, "dpp_reduce"), (1, "swizzle_reduce"), (2, "bpermute_reduce"), (3, "dpp_step")):
-            ns, sg, cyc = R.sync_bench_wave_ex(op, vt, 64, reps=20)
-            emit({"probe": "wave", "op": name, "type": vname, "ns": round(ns, 2), "sigma_ns": round(sg, 2),
-                  "cycles": round(cyc, 1)})
-    for wg in (64, 128, 256, 512, 1024):
-        for n_wg in (1, dev["cus"], 4 * dev["cus"]):
-            ns, sg, cyc = R.sync_bench_block(wg, n_wg, reps=20)
-            # Table II's throughput view: barriers completed per CU per
-            # microsecond with n_wg / cus resident workgroups per CU
-            emit({"probe": "block", "wg": wg, "n_wg": n_wg, "waves_per_wg": wg // 64,
-                  "waves_per_cu": round(n_wg / dev["cus"] * wg / 64, 2), "ns": round(ns, 2),
-                  "sigma_ns": round(sg, 2), "cycles": round(cyc, 1),
-                  "barriers_per_us_per_cu": round(n_wg / dev["cus"] / (ns * 1e-3), 2) if ns > 0 else None})
-    for wg in (64, 256, 1024):
-        cores = R.red_max_coresident(wg)
-        n = 1
-        while n <= min(2048, cores):
-            for groups in ((1, 8, 0, -1) if n >= 64 else (1, -1)):
-                ns, sg, wall = R.sync_bench_grid_ex(n, wg, groups, reps=20)
-                emit({"probe": "grid", "wg": wg, "n_wg": n, "wg_per_cu": round(n / dev["cus"], 3),
-                      "groups": {0: "default", -1: "xcd"}.get(groups, groups), "ns": round(ns, 1),
-                      "sigma_ns": round(sg, 1), "in_kernel_ns": round(wall, 1)})
-            n *= 2
-    for kind, name in ((0, "ordinary"), (1, "cooperative"), (2, "graph")):
-        for n_wg in (1, dev["cus"], 4 * dev["cus"]):
-            if kind == 1 and n_wg > R.red_max_coresident(256):
-                continue
-            ns, sg, null_ns = R.sync_bench_relaunch(n_wg, 256, cooperative=kind, reps=30)
-            emit({"probe": "relaunch", "launch": name, "n_wg": n_wg, "overhead_ns": round(ns, 1),
-                  "sigma_ns": round(sg, 1), "null_kernel_total_ns": round(null_ns, 1)})
+    def sec_probes():
+        # -- probes
+        for vname, vt in R.WAVE_TYPES.items():
+            for op, name in ((0, "dpp_reduce"), (1, "swizzle_reduce"), (2, "bpermute_reduce"), (3, "dpp_step")):
+                ns, sg, cyc = R.sync_bench_wave_ex(op, vt, 64, reps=20)
+                emit({"probe": "wave", "op": name, "type": vname, "ns": round(ns, 2), "sigma_ns": round(sg, 2),
+                      "cycles": round(cyc, 1)})
+        for wg in (64, 128, 256, 512, 1024):
+            for n_wg in (1, dev["cus"], 4 * dev["cus"]):
+                ns, sg, cyc = R.sync_bench_block(wg, n_wg, reps=20)
+                # Table II's throughput view: barriers completed per CU per
+                # microsecond with n_wg / cus resident workgroups per CU
+                emit({"probe": "block", "wg": wg, "n_wg": n_wg, "waves_per_wg": wg // 64,
+                      "waves_per_cu": round(n_wg / dev["cus"] * wg / 64, 2), "ns": round(ns, 2),
+                      "sigma_ns": round(sg, 2), "cycles": round(cyc, 1),
+                      "barriers_per_us_per_cu_from_latency": round(n_wg / dev["cus"] / (ns * 1e-3), 2)
+                      if ns > 0 else None})
+        # Table II's throughput, measured: barriers completed per CU per
+        # microsecond with 1..8 co-resident workgroups per CU
+        for wg in (64, 128, 256, 512, 1024):
+            for k in (1, 2, 4, 8):
+                if k * dev["cus"] > R.red_max_coresident(wg):
+                    continue
+                rate, cyc = R.sync_bench_block_tput(wg, k, window_ticks=20000)
+                emit({"probe": "block_tput", "wg": wg, "wg_per_cu": k, "waves_per_cu": k * wg // 64,
+                      "barriers_per_us_per_cu": round(rate, 2), "cycles_per_barrier": round(cyc, 1)})
+        for wg in (64, 256, 1024):
+            cores = R.red_max_coresident(wg)
+            n = 1
+            while n <= min(2048, cores):
+                for groups in ((1, 8, 0, -1) if n >= 64 else (1, -1)):
+                    ns, sg, wall = R.sync_bench_grid_ex(n, wg, groups, reps=20)
+                    emit({"probe": "grid", "wg": wg, "n_wg": n, "wg_per_cu": round(n / dev["cus"], 3),
+                          "groups": {0: "default", -1: "xcd"}.get(groups, groups), "ns": round(ns, 1),
+                          "sigma_ns": round(sg, 1), "in_kernel_ns": round(wall, 1)})
+                n *= 2
+        for kind, name in ((0, "ordinary"), (1, "cooperative"), (2, "graph")):
+            for n_wg in (1, dev["cus"], 4 * dev["cus"]):
+                if kind == 1 and n_wg > R.red_max_coresident(256):
+                    continue
+                ns, sg, null_ns = R.sync_bench_relaunch(n_wg, 256, cooperative=kind, reps=30)
+                emit({"probe": "relaunch", "launch": name, "n_wg": n_wg, "overhead_ns": round(ns, 1),
+                      "sigma_ns": round(sg, 1), "null_kernel_total_ns": round(null_ns, 1)})
 
+    run = {"machine": sec_machine, "small": sec_small, "int": sec_int, "f32": sec_f32, "half": sec_half,
+           "segments": sec_segments, "uniform": sec_uniform, "stencil": sec_stencil, "model": sec_model,
+           "probes": sec_probes}
+    for name in CONFIG_SECTIONS:
+        if name in sections:
+            log("configs section", name)
+            run[name]()
 
 def main():
     ap = argparse.ArgumentParser()
@@ -789,6 +909,10 @@ def main():
     ap.add_argument("--no-probes", action="store_true")
     ap.add_argument("--configs", metavar="JSONL", help="also measure every workload and probe sweep into JSONL")
     ap.add_argument("--only-configs", action="store_true", help="skip the headline (with --configs)")
+    ap.add_argument("--config-sections", default=",".join(CONFIG_SECTIONS),
+                    help="comma-separated sections of --configs to run (default: all of %s)" % ",".join(CONFIG_SECTIONS))
+    ap.add_argument("--summarize-configs", nargs="+", metavar="JSONL",
+                    help="no GPU: write the synchronization characterization summary from configs records")
     ap.add_argument("--retune", action="store_true", help="ignore the plan cache and autotune")
     ap.add_argument("--save-plans", metavar="JSON", help="write the plans tuned in this run")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -800,8 +924,10 @@ def main():
                          "the bench line of a run without the profiler)")
     ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles"), metavar="DIR")
     args = ap.parse_args()
-    if args.summarize_pmc or args.summarize_trace:
+    if args.summarize_pmc or args.summarize_trace or args.summarize_configs:
         os.makedirs(args.summary_out, exist_ok=True)
+        if args.summarize_configs:
+            summarize_configs(args.summarize_configs, args.summary_out)
         if args.summarize_pmc:
             summarize_pmc(*args.summarize_pmc, args.summary_out)
         if args.summarize_trace:
@@ -829,7 +955,11 @@ def main():
     log("device", dev, "cached plans installed:", plans.installed)
 
     if args.configs:
-        run_configs(R, dev, stream, args.configs, plans)
+        sections = [x for x in args.config_sections.split(",") if x]
+        bad = [x for x in sections if x not in CONFIG_SECTIONS]
+        if bad:
+            ap.error("unknown config sections %s" % bad)
+        run_configs(R, dev, stream, args.configs, plans, sections)
     if not args.only_configs:
         headline(args, R, dev, stream, sh, plans, inputs)
     if args.save_plans and plans.recorded:
@@ -941,8 +1071,16 @@ def headline(args, R, dev, stream, sh, plans, inputs):
         od = R.make_opts(variant=sp.variant, wg=sp.wg, ipt=sp.ipt, grid=sp.grid, flags=sp.flags | R.FLAG_NO_GRAPH)
         seg_bytes = xst.numel() * 4 + ot.numel() * 8 + nseg * 8
         seg = {"values": int(off[-1]), "segments": nseg, "plan": sp.as_dict()}
+        # the same shape as one persistent kernel (grid-barrier fix-up,
+        # ordinary occupancy-capped launch) replayed from a graph
+        pg = min(sp.grid or 2 * dev["cus"], R.red_max_coresident_segmented(sp.ipt, sp.wg))
+        opg = R.make_opts(variant=R.RED_VARIANT_PERSISTENT, wg=sp.wg, ipt=sp.ipt, grid=pg,
+                          flags=R.FLAG_PLAIN_LAUNCH | (sp.flags & R.FLAG_NONTEMPORAL))
+        seg["persistent_graph_grid"] = pg
         forms = (("graph", lambda: R.red_sum_segmented(xst.data_ptr(), ot.data_ptr(), nseg, so.data_ptr(), sh)),
-                 ("direct", lambda: R.red_sum_segmented_ex(xst.data_ptr(), ot.data_ptr(), nseg, so.data_ptr(), sh, od)))
+                 ("direct", lambda: R.red_sum_segmented_ex(xst.data_ptr(), ot.data_ptr(), nseg, so.data_ptr(), sh, od)),
+                 ("persistent_graph",
+                  lambda: R.red_sum_segmented_ex(xst.data_ptr(), ot.data_ptr(), nseg, so.data_ptr(), sh, opg)))
         # Two rounds over both forms, the second one kept (the first series
         # after a pause runs slower): back-to-back calls (batch throughput),
         # and each call between its own pair of events (which delays the
@@ -964,6 +1102,8 @@ def headline(args, R, dev, stream, sh, plans, inputs):
         seg["per_segment_launches_us"] = round(ms * 1e3, 1)
         seg["per_segment_launches_GBps"] = gbps(seg_bytes, ms)
         seg["graph_speedup_vs_per_segment_launches"] = round(ms * 1e3 / seg["graph_us"], 1)
+        if R.red_check_error(sh) != R.RED_OK:
+            raise RuntimeError("segmented batch: " + R.last_error())
         extra["segmented_10000"] = seg
         del xst, ot, so
         torch.cuda.empty_cache()

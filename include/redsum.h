@@ -260,7 +260,11 @@ int red_sum_segmented(const float *x, const int64_t *offsets, int64_t nseg, doub
  * between launches; both kernels go into the graph), RED_VARIANT_ATOMIC
  * (the last contributor, found by an atomic ticket after a release fence)
  * or RED_VARIANT_PERSISTENT (the owning slice after a grid barrier;
- * co-resident grid, launched directly, not from a graph).  plan.wg is at
+ * co-resident grid: a cooperative launch is made directly, not from a
+ * graph; with RED_FLAG_PLAIN_LAUNCH the grid, capped at the co-resident
+ * count, is an ordinary launch, and that one persistent kernel is captured
+ * and replayed like the other fix-ups; a grid that does not stay resident
+ * ends on the barrier watchdog, reported by red_check_error).  plan.wg is at
  * most 512 here (RED_EINVAL otherwise); grid x wg / 64 wavefront slices
  * are capped at 65536.
  * RED_FLAG_NO_GRAPH disables graph capture; RED_FLAG_SEG_WORKGROUP,
@@ -404,6 +408,17 @@ int sync_bench_wave_ex(int op, int type, int wg_size, int reps, double *ns, doub
  * threads. */
 int sync_bench_block(int wg_size, int n_wg, int reps, double *ns, double *sigma_ns, double *cycles,
                      void *stream);
+
+/* Block-barrier throughput under load (Table II's throughput column, as
+ * barriers completed rather than derived from a latency): wg_per_cu x CUs
+ * workgroups of wg_size threads, all co-resident (RED_EINVAL otherwise),
+ * each running barriers back to back for window_ticks ticks of the 100 MHz
+ * wall clock (100 .. 1e8).  *barriers_per_us_per_cu receives the barriers
+ * completed per microsecond per CU (summed over its workgroups), and
+ * *cycles_per_barrier (if non-NULL) the mean shader-clock cycles between
+ * one workgroup's barriers. */
+int sync_bench_block_tput(int wg_size, int wg_per_cu, int64_t window_ticks, double *barriers_per_us_per_cu,
+                          double *cycles_per_barrier, void *stream);
 
 /* One grid barrier inside a cooperative kernel of n_wg workgroups of
  * wg_size threads (n_wg must be co-resident: RED_EINVAL otherwise). */

@@ -112,6 +112,33 @@ __global__ __launch_bounds__(1024) void k_block_chain(int r, long long* cycles) 
   if (threadIdx.x == 0) cycles[blockIdx.x] = t1 - t0;
 }
 
+// Block-barrier throughput under load: every workgroup runs barriers
+// (s_barrier) back to back for `window` ticks of the 100 MHz wall clock and
+// records how many it completed and over how many ticks.  Thread 0 reads
+// the clock after every 64 barriers and broadcasts the decision through
+// LDS behind one more barrier, so every thread runs the same count.
+__global__ __launch_bounds__(1024) void k_block_tput(long long window, long long* counts, long long* ticks) {
+  __shared__ int stop;
+  long long t0 = 0;
+  if (threadIdx.x == 0) {
+    stop = 0;
+    t0 = __builtin_amdgcn_s_memrealtime();
+  }
+  __syncthreads();
+  long long n = 0;
+  for (;;) {
+    for (int k = 0; k < 64; ++k) __syncthreads();
+    if (threadIdx.x == 0) stop = __builtin_amdgcn_s_memrealtime() - t0 >= window;
+    __syncthreads();
+    n += 65;
+    if (stop) break;
+  }
+  if (threadIdx.x == 0) {
+    counts[blockIdx.x] = n;
+    ticks[blockIdx.x] = __builtin_amdgcn_s_memrealtime() - t0;
+  }
+}
+
 __global__ __launch_bounds__(1024) void k_grid_chain(int r, BarrierWords* w, unsigned groups,
                                                     unsigned spin_limit, long long* stamps) {
   unsigned gen = grid_barrier_gen(w);
@@ -667,6 +694,46 @@ int sync_bench_relaunch_ex(int n_wg, int wg_size, int cooperative, int i, int j,
     }
     *null_kernel_ns = mean(tot);
   }
+  return RED_OK;
+}
+
+int sync_bench_block_tput(int wg_size, int wg_per_cu, int64_t window_ticks, double* barriers_per_us_per_cu,
+                          double* cycles_per_barrier, void* stream) {
+  if (wg_size < 64 || wg_size > 1024 || wg_size % 64) return set_error(RED_EINVAL, "bad wg_size %d", wg_size);
+  if (wg_per_cu < 1 || wg_per_cu > 32) return set_error(RED_EINVAL, "bad wg_per_cu %d", wg_per_cu);
+  if (window_ticks < 100 || window_ticks > 100000000) return set_error(RED_EINVAL, "window_ticks out of range");
+  if (!barriers_per_us_per_cu) return set_error(RED_EINVAL, "null output");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DeviceInfo* dev;
+  Workspace* ws;
+  int rc = probe_prologue(s, &dev, &ws);
+  if (rc) return rc;
+  const void* fn = reinterpret_cast<const void*>(&k_block_tput);
+  int maxg = 0;
+  if ((rc = coresident(fn, wg_size, *dev, &maxg))) return rc;
+  const int n_wg = wg_per_cu * dev->cus;
+  if (n_wg > maxg || n_wg > RED_MAX_GRID)
+    return set_error(RED_EINVAL, "%d workgroups of %d threads per CU are not co-resident", wg_per_cu, wg_size);
+  long long* counts = ws->stamps;
+  long long* ticks = ws->stamps + RED_MAX_GRID;
+  long long window = (long long)window_ticks;
+  void* args[] = {&window, &counts, &ticks};
+  if ((rc = launch(fn, n_wg, wg_size, args, s, false))) return rc;  // warm-up
+  if ((rc = launch(fn, n_wg, wg_size, args, s, false))) return rc;
+  RED_HIP(hipStreamSynchronize(s));
+  std::vector<long long> hc(n_wg), ht(n_wg);
+  RED_HIP(hipMemcpy(hc.data(), counts, n_wg * sizeof(long long), hipMemcpyDeviceToHost));
+  RED_HIP(hipMemcpy(ht.data(), ticks, n_wg * sizeof(long long), hipMemcpyDeviceToHost));
+  const double tick_us = 1e3 / (double)dev->wallclock_khz;
+  double rate = 0, per = 0;  // barriers per microsecond, summed over workgroups; microseconds per barrier
+  for (int k = 0; k < n_wg; ++k) {
+    const double us = (double)ht[k] * tick_us;
+    if (hc[k] <= 0 || us <= 0) return set_error(RED_EHIP, "block throughput probe: empty record %d", k);
+    rate += (double)hc[k] / us;
+    per += us / (double)hc[k];
+  }
+  *barriers_per_us_per_cu = rate / dev->cus;
+  if (cycles_per_barrier) *cycles_per_barrier = per / n_wg * (double)dev->clock_khz * 1e-3;
   return RED_OK;
 }
 

@@ -902,11 +902,13 @@ int red_sum_segmented_ex(const float* x, const int64_t* offsets, int64_t nseg, d
                                     RED_FLAG_SEG_WORKGROUP | RED_FLAG_SEG_PIECES | RED_FLAG_SEG_RUNS);
   if ((sl.plan.flags & RED_FLAG_SEG_RUNS) && sl.plan.ipt > 4)
     return set_error(RED_EINVAL, "segmented: the reduce-by-key form takes at most 4 loads per thread");
-  // Persistent (co-resident) launches, the null stream and a caller's own
-  // capture launch directly; otherwise the launch is replayed from a cached
-  // graph.
-  if (no_graph || !s || sl.plan.variant == RED_VARIANT_PERSISTENT || stream_capturing(s))
-    return seg_direct(sl, x, offsets, nseg, out, ws, s, *dev);
+  // Cooperative launches, the null stream and a caller's own capture
+  // launch directly; otherwise the launch is replayed from a cached graph.
+  // The persistent (grid-barrier) form goes into the graph too when it is
+  // launched as an ordinary, occupancy-capped grid: one persistent kernel
+  // per replay.
+  const bool coop = sl.plan.variant == RED_VARIANT_PERSISTENT && !(sl.plan.flags & RED_FLAG_PLAIN_LAUNCH);
+  if (no_graph || !s || coop || stream_capturing(s)) return seg_direct(sl, x, offsets, nseg, out, ws, s, *dev);
   GraphKey key{dev->id, s, x, offsets, nseg, out, sl.plan.variant, sl.plan.wg, sl.plan.ipt, sl.plan.grid,
                sl.plan.flags};
   hipGraphExec_t exec = nullptr;

@@ -50,7 +50,7 @@ EXPORTS = [
     "red_autotune_segmented", "red_set_segmented_plan", "red_get_segmented_plan",
     "red_kernel_timer", "red_kernel_timer_read", "sync_bench_wave", "sync_bench_wave_ex", "sync_bench_block",
     "sync_bench_grid", "sync_bench_grid_ex", "sync_bench_grid_r", "sync_bench_relaunch",
-    "sync_bench_relaunch_ex", "sync_bench_spin", "sync_check_wave", "sync_check_grid_order",
+    "sync_bench_relaunch_ex", "sync_bench_spin", "sync_bench_block_tput", "sync_check_wave", "sync_check_grid_order",
     "sync_check_grid_visibility",
     "sync_check_watchdog", "sync_xcc_map", "red_max_coresident", "red_max_coresident_segmented",
     "red_device_info",
@@ -116,6 +116,7 @@ _SIGS = {
     "sync_bench_grid_r": ([_i32, _i32, _i32, _i64, _i64, _i32, _dp, _dp, _dp, _vp], _i32),
     "sync_bench_relaunch_ex": ([_i32, _i32, _i32, _i32, _i32, _i64, _i32, _dp, _dp, _dp, _vp], _i32),
     "sync_bench_spin": ([_i64, _i64, _i64, _i32, _dp, _dp, _vp], _i32),
+    "sync_bench_block_tput": ([_i32, _i32, _i64, _dp, _dp, _vp], _i32),
     "sync_check_wave": ([_i32, _i32, _vp, _vp, _vp], _i32),
     "sync_check_grid_order": ([_i32, _i32, _i64p, _i64p, _vp], _i32),
     "sync_check_grid_visibility": ([_i32, _i32, _i32, _i32, _i64p, _vp], _i32),
@@ -316,6 +317,14 @@ def sync_bench_wave(op: int, wg_size: int = 64, reps: int = 20, stream: int = 0)
 def sync_bench_block(wg_size: int, n_wg: int = 1, reps: int = 20, stream: int = 0):
     """-> (ns per barrier, sigma ns, cycles per barrier)"""
     return _probe3("sync_bench_block", wg_size, n_wg, reps, stream=stream)
+
+
+def sync_bench_block_tput(wg_size: int, wg_per_cu: int, window_ticks: int = 20000, stream: int = 0):
+    """-> (barriers completed per microsecond per CU, cycles per barrier of one workgroup)"""
+    r, c = ctypes.c_double(), ctypes.c_double()
+    _check(load().sync_bench_block_tput(wg_size, wg_per_cu, window_ticks, ctypes.byref(r), ctypes.byref(c), stream),
+           "sync_bench_block_tput")
+    return r.value, c.value
 
 
 def sync_bench_grid(n_wg: int, wg_size: int = 256, reps: int = 20, stream: int = 0):

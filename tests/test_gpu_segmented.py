@@ -388,3 +388,33 @@ def test_graph_cache_eviction(lib):
     res = outs.cpu().numpy()
     assert (res == res[0]).all()
     check(res[0], x, off)
+
+
+def test_persistent_batch_replays_from_a_graph(lib):
+    """The grid-barrier fix-up as one persistent kernel, launched as an
+    ordinary occupancy-capped grid: captured into the library's graph on the
+    first call and replayed after, every replay bit-identical to the
+    two-kernel relaunch graph of the same shape (the fix-ups sum the pieces
+    in the same order) and to the oracle; no watchdog fired."""
+    lens = inputs.segment_lengths(400, max_len=1 << 16)
+    off = inputs.offsets_from_lengths(lens)
+    x = inputs.mixed_f32(int(off[-1]), sub=23)
+    xt = torch.from_numpy(x).to("cuda")
+    ot = torch.from_numpy(off).to("cuda")
+    nseg = off.size - 1
+    g = min(512, lib.red_max_coresident_segmented(4, 512))
+    pers = lib.make_opts(variant=3, wg=512, ipt=4, grid=g, flags=lib.FLAG_PLAIN_LAUNCH | lib.FLAG_NONTEMPORAL)
+    rel = lib.make_opts(variant=1, wg=512, ipt=4, grid=g, flags=lib.FLAG_NONTEMPORAL)
+    s = lib.current_stream()
+    ref = torch.full((nseg,), float("nan"), dtype=torch.float64, device="cuda")
+    lib.red_sum_segmented_ex(xt.data_ptr(), ot.data_ptr(), nseg, ref.data_ptr(), s, rel)
+    torch.cuda.synchronize()
+    want = ref.cpu().numpy()
+    check(want, x, off)
+    out = torch.empty(nseg, dtype=torch.float64, device="cuda")
+    for i in range(4):  # capture, then three replays
+        out.fill_(float("nan"))
+        lib.red_sum_segmented_ex(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), s, pers)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), want), i
+    assert lib.red_check_error(s) == lib.RED_OK

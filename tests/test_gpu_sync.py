@@ -367,3 +367,17 @@ def test_grid_probe_rejects_grids_that_cannot_be_resident(lib):
     with pytest.raises(lib.RedError):
         lib.sum(x, opts=lib.make_opts(variant=3, wg=1024, ipt=1, grid=too_many))
     assert lib.red_check_error(lib.current_stream()) == lib.RED_OK
+
+
+@pytest.mark.parametrize("wg,k", [(64, 1), (64, 8), (256, 2), (1024, 1)])
+def test_block_throughput_is_measured_and_consistent(lib, wg, k):
+    """Barriers completed per CU per microsecond with k co-resident
+    workgroups per CU (measured by counting), positive, and consistent with
+    the mean spacing of one workgroup's barriers: k / (cycles / clock)."""
+    if k * lib.red_device_info()["cus"] > lib.red_max_coresident(wg):
+        pytest.skip("not co-resident")
+    rate, cyc = lib.sync_bench_block_tput(wg, k, window_ticks=20000)
+    clock_mhz = lib.red_device_info()["clock_khz"] / 1e3
+    say("block tput wg %d x %d per CU: %.1f barriers/us/CU, %.1f cycles per barrier" % (wg, k, rate, cyc))
+    assert rate > 0 and cyc > 0
+    assert abs(rate - k * clock_mhz / cyc) <= 0.1 * rate
