@@ -116,13 +116,18 @@ typedef enum {
                                    current tile's arithmetic                */
 #define RED_FLAG_XCD 16         /* atomic / persistent variants: publish the
                                    partials with one L2 write-back per XCD
-                                   (the last workgroup of each XCD releases
-                                   for all of them) instead of one per
-                                   workgroup.  Relies on the round-robin
+                                   (the workgroups count themselves on an
+                                   arrival tree, and the last of each XCD
+                                   releases for all of them) instead of one
+                                   per workgroup.  Relies on the round-robin
                                    dispatch of workgroups over the XCDs,
-                                   which every workgroup checks against its
-                                   XCC_ID register; a mismatch is reported
-                                   by red_check_error as RED_ENOTSUP        */
+                                   which the tree checks against every
+                                   workgroup's XCC_ID register: a grid
+                                   barrier that finds a mismatch falls back
+                                   to a release by every workgroup (correct,
+                                   slower); the atomic-ticket variant, whose
+                                   workgroups have left, reports it through
+                                   red_check_error as RED_ENOTSUP           */
 /* Segmented batches: force one way of cutting and walking the slices
  * (at most one of the three; by default the device picks from the mean
  * segment length).  For experiments and tests. */
@@ -176,10 +181,11 @@ const char *red_last_error(void);
 
 /* Synchronize `stream`, then report a grid-barrier watchdog timeout raised
  * by an earlier persistent kernel on that stream (RED_ETIMEOUT), or a
- * workgroup that ran on another XCD than round-robin dispatch implies under
- * RED_FLAG_XCD (RED_ENOTSUP: flagged by a tally, or arrival counters left
- * incomplete, in which case that call's output was not written), clearing
- * the flag and the barrier words.  RED_OK if none. */
+ * workgroup that ran on another XCD than round-robin dispatch implies in
+ * an atomic-ticket call under RED_FLAG_XCD (RED_ENOTSUP: its output may
+ * miss partials still held in another XCD's L2), or arrival counters left
+ * incomplete (RED_ENOTSUP), clearing the flag and the barrier words.
+ * RED_OK if none. */
 int red_check_error(void *stream);
 
 /* ---------------------------------------------------------------------
@@ -214,7 +220,7 @@ int red_sum_ex(int dtype, const void *x, int64_t n, void *out, void *stream, con
  * forbid hipMalloc.  Same arguments, plans, kernels and results as
  * red_sum_ex (the same plan gives the same bits).
  *   Scratch: the partials and barrier words live in one static device
- *   array of the library (8 KiB of words + RED_NOALLOC_MAX_GRID x 8 bytes,
+ *   array of the library (80 KiB of words + RED_NOALLOC_MAX_GRID x 8 bytes,
  *   held by every device the library runs on until the process ends), not
  *   in a per-stream workspace.  Its address on each device is looked up
  *   once, by red_init or by the first call on that device (a lookup, not an
@@ -428,8 +434,11 @@ int sync_bench_grid(int n_wg, int wg_size, int reps, double *ns, double *sigma_n
 /* sync_bench_grid with an explicit barrier shape: groups = 1 is the flat
  * centralized barrier, groups = 2..32 the two-level barrier whose first
  * level counts the workgroups with blockIdx % groups equal, -1 the
- * XCD-aggregated barrier (first level per XCD with one L2 write-back per
- * XCD, see RED_FLAG_XCD), 0 the default policy. */
+ * XCD-aggregated barrier (an arrival tree over the workgroups of each XCD
+ * with one L2 write-back per XCD, see RED_FLAG_XCD), 0 the default policy.
+ * -2 is the XCD-aggregated barrier with odd workgroups reporting the next
+ * XCD: it drives the barrier's fall-back (every workgroup releases its own
+ * stores when one ran off its XCD) from the host, for tests. */
 int sync_bench_grid_ex(int n_wg, int wg_size, int groups, int reps, double *ns, double *sigma_ns,
                        double *cycles, void *stream);
 

@@ -408,6 +408,9 @@ __device__ __forceinline__ unsigned xcc_id() {
 // by atomics sits on its own 128-byte line.
 // ---------------------------------------------------------------------------
 constexpr int kMaxBarrierGroups = 32;
+constexpr unsigned kTreeFanIn = 16;       // arrivals per first-level node of the XCD tree
+constexpr int kMaxTreeClasses = 16;       // residue classes (XCDs) of the XCD tree
+constexpr int kMaxTreeNodes = 528;        // first-level nodes: 8192 / kTreeFanIn + kMaxTreeClasses
 
 struct alignas(128) Line {
   unsigned v;
@@ -415,11 +418,16 @@ struct alignas(128) Line {
 };
 struct BarrierWords {
   Line count;   // arrivals at the current grid barrier (top level)
-  Line gen;     // grid-barrier generation (incremented by the last arrival)
+  Line gen;     // grid-barrier generation (v, incremented by the last
+                // arrival); pad[0]: the generation whose fall-back release
+                // the last arrival requests (XCD tree)
   Line ticket;  // atomic-final variant: workgroups that have stored a partial
   Line err;     // watchdog flag (nonzero after a timeout)
   Line acc_lo;  // atomic-final int accumulator (int64 in acc_lo.v/acc_lo.pad[0])
-  Line group[kMaxBarrierGroups];  // arrivals per group (two-level / per-XCD barrier)
+  Line group[kMaxBarrierGroups];  // arrivals per group (two-level barrier)
+  Line cls[kMaxTreeClasses];      // XCD tree, second level: node completions per class
+  Line node[kMaxTreeNodes];       // XCD tree, first level: arrivals per node
+  Line fb;                        // XCD tree: fall-back releases done (v)
 };
 
 __device__ __forceinline__ long long* acc_i64(BarrierWords* w) {
@@ -431,32 +439,52 @@ __device__ __forceinline__ unsigned relaxed_add(unsigned* p, unsigned v) {
 }
 
 // ---------------------------------------------------------------------------
-// XCD-aggregated publication.
+// XCD-aggregated publication over an arrival tree.
 //
 // The dispatcher hands workgroups to the XCDs round-robin: within one
 // launch workgroup g runs on XCD (g + off) mod nxcc for a launch-wide offset
-// off (measured on MI355X).  All workgroups of one XCD share that XCD's L2,
-// and a store is in that L2 once the issuing wave's vector-memory counter
-// has drained.  So instead of one L2 write-back per workgroup (an
-// agent-scope release fence), each workgroup drains its stores and counts
-// itself on the counter of the XCD it runs on (its XCC_ID register); the
-// number of workgroups on that XCD is the number of g' with
-// g' = g (mod nxcc), whatever the offset.  The last arrival of the XCD
-// performs ONE agent-scope release (write-back of that L2, which holds every
-// member's stores) before it signals onward.
+// off (measured on MI355X), so the workgroups of one residue class
+// r = g mod nxcc share one XCD and its L2.  A store is in that L2 once the
+// issuing wave's memory counter has drained.  So instead of one L2
+// write-back per workgroup (an agent-scope release fence), the workgroups
+// of a class drain their stores and count themselves, and the last of the
+// class performs ONE agent-scope release (write-back of that L2, which holds
+// every member's stores) before it arrives at the top level.
+//
+// Counting is by workgroup index, so every level completes whatever the
+// dispatch; atomics on one line serialize (about 60 ns each on MI355X), so
+// the count is a tree:
+//   level 1  nodes of kTreeFanIn consecutive members of class r (member
+//            j = g / nxcc in node j / kTreeFanIn), one line per node;
+//   level 2  the last arrival of each node of class r, on the class line
+//            (skipped when the class has one node);
+//   level 3  the last arrival of each class, on the top line.
+// At 512 workgroups that is 16 + 4 + 8 serialized arrivals instead of
+// 64 + 8 with one counter per XCD.
 //
 // The dispatch rule is checked on the way, at no extra atomic: every counter
 // is a 64-bit tally that adds (1, k, k^2) for a key k in three fields
-// (count: bits 0-15, sum of k: bits 16-31, sum of k^2: bits 32-63).  At the
-// XCD level k = g mod nxcc, at the top level k = the offset the XCD implies.
-// By the Cauchy-Schwarz inequality, count * sum(k^2) = sum(k)^2 exactly when
-// all keys are equal, so the last arrival at each level sees whether one
-// rule held for all of its members and otherwise reports err = kErrDispatch.
-// Fields stay in range for up to 9362 workgroups per XCD.
+// (count: bits 0-15, sum of k: bits 16-31, sum of k^2: bits 32-63).  By the
+// Cauchy-Schwarz inequality, count * sum(k^2) = sum(k)^2 exactly when all
+// keys are equal.  Keys: the physical XCD (XCC_ID register) at levels 1 and
+// 2, the dispatch offset that XCD implies at level 3, and kTreeBad for an
+// arrival whose own subtree was not uniform.  The last arrival of the tree
+// thus learns whether every workgroup ran on the XCD its class implies; if
+// one did not, its stores may sit in another XCD's L2, and the caller falls
+// back (the grid barrier asks every workgroup to release on its own).
 // ---------------------------------------------------------------------------
 constexpr unsigned kErrTimeout = 1u;
 constexpr unsigned kErrDispatch = 2u;
-constexpr unsigned kBarrierXcd = 0x100u;  // groups value: XCD-aggregated barrier (| nxcc)
+constexpr unsigned kBarrierXcd = 0x100u;   // groups value: XCD-aggregated barrier (| nxcc)
+constexpr unsigned kBarrierSkew = 0x200u;  // with kBarrierXcd: odd workgroups report the next XCD
+                                           // (drives the fall-back from the host in tests)
+constexpr unsigned kTreeBad = 15u;         // key of an arrival whose subtree saw two XCDs
+
+// Whether the XCD tree serves a device of nxcc XCDs (more than one, each
+// with its own class line and a key below kTreeBad).
+__host__ __device__ constexpr bool xcd_tree_fits(int nxcc) {
+  return nxcc > 1 && nxcc < (int)kTreeBad && nxcc <= kMaxTreeClasses;
+}
 
 __device__ __forceinline__ unsigned long long* tally_word(Line& l) {
   return reinterpret_cast<unsigned long long*>(&l.v);  // v and pad[0]
@@ -472,47 +500,51 @@ __device__ __forceinline__ bool tally_uniform(unsigned long long t) {
 }
 
 // Adds key k to the tally in `l`; true for the arrival that completes
-// `expected` arrivals, which also resets the tally and checks the keys.
-__device__ __forceinline__ bool tally_arrive(BarrierWords* w, Line& l, unsigned k, unsigned expected) {
+// `expected` arrivals, which also resets the tally and sets *uniform to
+// whether every key of the tally was k, and k is not kTreeBad.
+__device__ __forceinline__ bool tally_arrive(Line& l, unsigned k, unsigned expected, bool* uniform) {
   const unsigned long long t =
       __hip_atomic_fetch_add(tally_word(l), tally_term(k), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if ((unsigned)(t & 0xFFFFull) != expected - 1) return false;
   __hip_atomic_store(tally_word(l), 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (!tally_uniform(t + tally_term(k)))
-    __hip_atomic_store(&w->err.v, kErrDispatch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  *uniform = tally_uniform(t + tally_term(k)) && k != kTreeBad;
   return true;
 }
 
-// Makes this workgroup's earlier global stores visible to the other
-// workgroups of its XCD and counts it there; returns true for the last
-// arrival of the XCD, which has then released agent-wide for all of them
-// and must call xcd_top with *off.  Thread 0 only; every wave of the
-// workgroup must have drained its stores (s_waitcnt) before the workgroup
-// barrier that precedes this call.
-__device__ __forceinline__ bool xcd_arrive(BarrierWords* w, unsigned nblocks, unsigned nxcc, unsigned* off) {
-  const unsigned r = blockIdx.x % nxcc;
-  const unsigned members = (nblocks - r + nxcc - 1) / nxcc;
-  unsigned phys = xcc_id();
+// Counts this workgroup on the XCD tree whose top line is `top`; returns
+// true for the one last arrival of the grid, which has then seen every
+// workgroup arrive, with *ok telling whether every workgroup ran on the XCD
+// its class implies (then every class's stores have been released).
+// Thread 0 only; every wave of the workgroup must have drained its stores
+// (s_waitcnt) before the workgroup barrier that precedes this call.
+__device__ __forceinline__ bool xcd_tree_arrive(BarrierWords* w, Line& top, unsigned nblocks, unsigned groups,
+                                                bool* ok) {
+  const unsigned nxcc = groups & 0xFFu;
+  const unsigned g = blockIdx.x, r = g % nxcc, j = g / nxcc;
+  const unsigned members = (nblocks - r + nxcc - 1) / nxcc;  // of class r
+  const unsigned nodes = (members + kTreeFanIn - 1) / kTreeFanIn;
+  const unsigned node = j / kTreeFanIn;
+  const unsigned nsize = members - node * kTreeFanIn < kTreeFanIn ? members - node * kTreeFanIn : kTreeFanIn;
+  unsigned key = xcc_id();
+  if ((groups & kBarrierSkew) && (g & 1u)) key = (key + 1u) % nxcc;
+  if (key >= nxcc) key = kTreeBad;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_s_waitcnt(0);
-  if (phys >= nxcc) {  // not a valid XCD index for this grid: publish alone, report
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_store(&w->err.v, kErrDispatch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    phys = r;
+  bool u = true;
+  if (!tally_arrive(w->node[r + nxcc * node], key, nsize, &u)) return false;
+  if (!u) key = kTreeBad;
+  if (nodes > 1) {
+    if (!tally_arrive(w->cls[r], key, nodes, &u)) return false;
+    if (!u) key = kTreeBad;
   }
-  *off = (phys + nxcc - r) % nxcc;
-  if (!tally_arrive(w, w->group[phys], r, members)) return false;
+  // The class is complete: one write-back of this XCD's L2 publishes the
+  // stores of every member that ran here.
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-  return true;
-}
-
-// Top-level arrival of an XCD's last workgroup on `top` (a counter of
-// min(nblocks, nxcc) XCDs); true for the last XCD, after the check that
-// every XCD implied the same dispatch offset.  Leaves `top` at zero.
-__device__ __forceinline__ bool xcd_top(BarrierWords* w, Line& top, unsigned nblocks, unsigned nxcc,
-                                        unsigned off) {
+  const unsigned off = key == kTreeBad ? kTreeBad : (key + nxcc - r) % nxcc;
   const unsigned active = nblocks < nxcc ? nblocks : nxcc;
-  return tally_arrive(w, top, off, active);
+  if (!tally_arrive(top, off, active, &u)) return false;
+  *ok = u;
+  return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -525,8 +557,12 @@ __device__ __forceinline__ bool xcd_top(BarrierWords* w, Line& top, unsigned nbl
 //            blockIdx.x % groups (each still releasing on its own), the
 //            last of a group acquires and increments the top counter;
 //   kBarrierXcd | nxcc
-//            XCD-aggregated: the first level is the XCD, with one L2
-//            write-back per XCD (xcd_arrive above).
+//            XCD-aggregated: the arrival tree above, one L2 write-back per
+//            XCD.  When the tree reports a workgroup off its class's XCD,
+//            the last arrival requests a fall-back before it opens the
+//            barrier: every other workgroup, still waiting, releases its
+//            own stores and acknowledges on the `fb` line; the last arrival
+//            waits for all acknowledgements (bounded like every wait here).
 // Thread 0 of each workgroup keeps the generation in `gen` (read once per
 // launch with grid_barrier_gen, then advanced by each barrier, so no
 // barrier waits for a load of it before arriving); the last top-level
@@ -535,11 +571,11 @@ __device__ __forceinline__ bool xcd_top(BarrierWords* w, Line& top, unsigned nbl
 // polls, so polling neither invalidates the L2 nor floods the atomic unit)
 // and acquire once after the wait.  Each hop is a release / relaxed RMW /
 // acquire chain, so every workgroup's stores happen before every
-// workgroup's loads after the barrier.  The poll is bounded by `spin_limit`:
-// on expiry the workgroup sets the error word and leaves, so the kernel
-// always ends (a grid in which not every block arrives deadlocks, Section
-// VIII-B of the paper).  Counters are back at zero after every completed
-// barrier.  Returns false on timeout.
+// workgroup's loads after the barrier.  Every wait is bounded by
+// `spin_limit` polls: on expiry the workgroup sets the error word and
+// leaves, so the kernel always ends (a grid in which not every block
+// arrives deadlocks, Section VIII-B of the paper).  Counters are back at
+// zero after every completed barrier.  Returns false on timeout.
 // ---------------------------------------------------------------------------
 // The barrier generation at the start of a launch, for thread 0 of each
 // workgroup to pass to its grid_barrier calls.  A barrier completes only
@@ -561,11 +597,9 @@ __device__ __forceinline__ bool grid_barrier(BarrierWords* w, unsigned nblocks, 
   if (threadIdx.x == 0) {
     int to = 0;
     const unsigned g = gen;
-    bool last = false;
+    bool last = false, ok = true;
     if (xcd) {
-      const unsigned nxcc = groups & 0xFFu;
-      unsigned off;
-      last = xcd_arrive(w, nblocks, nxcc, &off) && xcd_top(w, w->count, nblocks, nxcc, off);
+      last = xcd_tree_arrive(w, w->count, nblocks, groups, &ok);
     } else {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       if (groups <= 1) {
@@ -583,11 +617,42 @@ __device__ __forceinline__ bool grid_barrier(BarrierWords* w, unsigned nblocks, 
     }
     if (last) {
       __hip_atomic_store(&w->count.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (!ok && nblocks > 1) {
+        // Fall-back: every other workgroup releases its own stores.
+        __hip_atomic_store(&w->gen.pad[0], g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned spins = 0;
+        while (__hip_atomic_load(&w->fb.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != nblocks - 1) {
+          if (++spins > spin_limit) {
+            __hip_atomic_store(&w->err.v, kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            to = 1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+        __hip_atomic_store(&w->fb.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
       relaxed_add(&w->gen.v, 1u);
     } else {
       unsigned spins = 0;
-      while (__hip_atomic_load(&w->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+      bool released = false;
+      for (;;) {
+        unsigned cur, req;
+        if (xcd) {
+          const unsigned long long both = __hip_atomic_load(reinterpret_cast<unsigned long long*>(&w->gen.v),
+                                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          cur = (unsigned)both;
+          req = (unsigned)(both >> 32);
+        } else {
+          cur = __hip_atomic_load(&w->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          req = 0u;
+        }
+        if (cur != g) break;
+        if (xcd && !released && req == g + 1u) {  // fall-back requested for this barrier
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          relaxed_add(&w->fb.v, 1u);
+          released = true;
+        }
         if (++spins > spin_limit) {
           __hip_atomic_store(&w->err.v, kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           to = 1;

@@ -48,7 +48,7 @@ struct Workspace {
 constexpr int64_t kMaxChunks = 65536;
 
 // Workspace layout sizes.
-constexpr size_t kWordsBytes = 8192;
+constexpr size_t kWordsBytes = 81920;  // BarrierWords (the XCD tree's lines), rounded up
 constexpr size_t kPartialBytes = (size_t)RED_MAX_GRID * 8;
 constexpr size_t kCarryBytes = (size_t)kMaxChunks * sizeof(SegCarry);
 constexpr size_t kTicketBytes = (size_t)kMaxChunks * 4;

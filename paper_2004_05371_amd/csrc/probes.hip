@@ -203,12 +203,15 @@ __global__ __launch_bounds__(1024) void k_xcc_map(int* out) {
 __global__ void k_reset_words(BarrierWords* w) {
   if (threadIdx.x == 0) {
     *tally_word(w->count) = 0;
-    w->gen.v = 0;
+    *tally_word(w->gen) = 0;  // generation and fall-back request
     *tally_word(w->ticket) = 0;
     w->err.v = 0;
     *acc_i64(w) = 0;
-    for (int i = 0; i < kMaxBarrierGroups; ++i) *tally_word(w->group[i]) = 0;
+    w->fb.v = 0;
   }
+  for (int i = threadIdx.x; i < kMaxBarrierGroups; i += blockDim.x) *tally_word(w->group[i]) = 0;
+  for (int i = threadIdx.x; i < kMaxTreeClasses; i += blockDim.x) *tally_word(w->cls[i]) = 0;
+  for (int i = threadIdx.x; i < kMaxTreeNodes; i += blockDim.x) *tally_word(w->node[i]) = 0;
 }
 
 // Read-only bandwidth proxy (Section VII-B): grid-stride 16-byte loads, two
@@ -405,6 +408,14 @@ int reset_words(Workspace* ws, hipStream_t s) {
   return RED_OK;
 }
 
+// The XCD-aggregated barrier shape of the device (flat on one XCD); with
+// `skew` odd workgroups report the next XCD, which drives the barrier's
+// fall-back path from the host.
+unsigned xcd_groups(const DeviceInfo& dev, bool skew) {
+  if (!xcd_tree_fits(dev.nxcc)) return 1u;
+  return kBarrierXcd | (unsigned)dev.nxcc | (skew ? kBarrierSkew : 0u);
+}
+
 int coresident(const void* fn, int wg, const DeviceInfo& dev, int* n) {
   int per_cu = 0;
   RED_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, wg, 0));
@@ -536,7 +547,7 @@ int sync_bench_grid_r(int n_wg, int wg_size, int groups, int64_t r1, int64_t r2,
     return set_error(RED_EINVAL, "repetitions: r1 = r2 = 0, or r1 > r2 > 0 and r1 <= 65536");
   if (wg_size < 64 || wg_size > 1024 || wg_size % 64) return set_error(RED_EINVAL, "bad wg_size %d", wg_size);
   if (n_wg < 1 || n_wg > RED_MAX_GRID) return set_error(RED_EINVAL, "bad n_wg %d", n_wg);
-  if (groups < -1 || groups > kMaxBarrierGroups) return set_error(RED_EINVAL, "bad groups %d", groups);
+  if (groups < -2 || groups > kMaxBarrierGroups) return set_error(RED_EINVAL, "bad groups %d", groups);
   if (reps < 2 || !ns || !sigma_ns) return set_error(RED_EINVAL, "reps >= 2 and non-null outputs required");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const DeviceInfo* dev;
@@ -553,7 +564,7 @@ int sync_bench_grid_r(int n_wg, int wg_size, int groups, int64_t r1, int64_t r2,
   int r = 0;
   BarrierWords* w = ws->words;
   unsigned grp = groups > 0 ? (unsigned)groups
-                 : groups < 0 ? (dev->nxcc > 1 ? (kBarrierXcd | (unsigned)dev->nxcc) : 1u)
+                 : groups < 0 ? xcd_groups(*dev, groups == -2)
                               : barrier_groups(n_wg);
   unsigned spin = watchdog_spins();
   long long* st = ws->stamps;
@@ -819,7 +830,7 @@ int sync_check_grid_order(int n_wg, int wg_size, int64_t* max_before, int64_t* m
 int sync_check_grid_visibility(int n_wg, int wg_size, int groups, int rounds, int64_t* errors, void* stream) {
   if (wg_size < 64 || wg_size > 1024 || wg_size % 64) return set_error(RED_EINVAL, "bad wg_size %d", wg_size);
   if (n_wg < 1 || n_wg > RED_MAX_GRID) return set_error(RED_EINVAL, "bad n_wg %d", n_wg);
-  if (groups < -1 || groups > kMaxBarrierGroups) return set_error(RED_EINVAL, "bad groups %d", groups);
+  if (groups < -2 || groups > kMaxBarrierGroups) return set_error(RED_EINVAL, "bad groups %d", groups);
   if (rounds < 1 || rounds > 100000) return set_error(RED_EINVAL, "bad rounds %d", rounds);
   if (!errors) return set_error(RED_EINVAL, "null output");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -834,7 +845,7 @@ int sync_check_grid_visibility(int n_wg, int wg_size, int groups, int rounds, in
   if ((rc = reset_words(ws, s))) return rc;
   BarrierWords* w = ws->words;
   unsigned grp = groups > 0 ? (unsigned)groups
-                 : groups < 0 ? (dev->nxcc > 1 ? (kBarrierXcd | (unsigned)dev->nxcc) : 1u)
+                 : groups < 0 ? xcd_groups(*dev, groups == -2)
                               : barrier_groups(n_wg);
   unsigned spin = watchdog_spins();
   long long* data = ws->stamps;  // RED_MAX_GRID slots

@@ -199,10 +199,14 @@ __global__ __launch_bounds__(1024) void k_atomic(ReduceArgs a) {
       static_cast<Part*>(a.partials)[blockIdx.x] = p;
     bool last;
     if (a.xcd_nxcc > 1) {
-      // One L2 write-back per XCD: the last member of each XCD releases and
-      // takes the ticket for the whole XCD.
-      unsigned off;
-      last = xcd_arrive(w, gridDim.x, a.xcd_nxcc, &off) && xcd_top(w, w->ticket, gridDim.x, a.xcd_nxcc, off);
+      // One L2 write-back per XCD: the workgroups count themselves on the
+      // XCD arrival tree, whose last arrival takes the ticket.  Here the
+      // other workgroups have left, so a workgroup found off its class's
+      // XCD cannot be asked to release: the call is reported (RED_ENOTSUP
+      // from red_check_error).
+      bool ok = true;
+      last = xcd_tree_arrive(w, w->ticket, gridDim.x, kBarrierXcd | a.xcd_nxcc, &ok);
+      if (last && !ok) __hip_atomic_store(&w->err.v, kErrDispatch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       // Release (one L2 write-back) publishes the partial; the ticket itself
       // is relaxed, and only the last workgroup pays an acquire.
@@ -443,7 +447,7 @@ int reduce_launch(const ReduceLaunch& rl, const void* x, int64_t n, void* out, W
   a.out = out;
   a.spin_limit = watchdog_spins();
   a.bar_groups = 1;
-  const bool xcd = (rl.plan.flags & RED_FLAG_XCD) != 0 && dev.nxcc > 1;
+  const bool xcd = (rl.plan.flags & RED_FLAG_XCD) != 0 && xcd_tree_fits(dev.nxcc);
   a.xcd_nxcc = xcd ? (unsigned)dev.nxcc : 0u;
 
   const red_plan& p = rl.plan;

@@ -347,10 +347,12 @@ int scratch_address(void** out) {
   return RED_OK;
 }
 
-// Zeroes n 32-bit words (a kernel, not a memset, so it also records as an
-// ordinary kernel node under capture).
-__global__ void k_zero_words(unsigned* w, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) w[i] = 0u;
+// Zeroes the first 8 bytes (the counter or tally, and the fall-back
+// request of the generation line) of each of n lines of barrier words (a
+// kernel, not a memset, so it also records as an ordinary kernel node
+// under capture).
+__global__ void k_zero_lines(Line* lines, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) *reinterpret_cast<unsigned long long*>(&lines[i].v) = 0ull;
 }
 
 }  // namespace
@@ -519,22 +521,24 @@ int red_check_error(void* stream) {
   Workspace* ws;
   if ((rc = get_workspace(s, &ws))) return rc;
   RED_HIP(hipStreamSynchronize(s));
-  BarrierWords hw;
+  std::vector<BarrierWords> hw_buf(1);  // about 73 KB: on the heap
+  BarrierWords& hw = hw_buf[0];
   RED_HIP(hipMemcpy(&hw, ws->words, sizeof(hw), hipMemcpyDeviceToHost));
   const unsigned err = hw.err.v;
   // Every completed launch leaves its arrival counters at zero; a counter
   // left over means some workgroups never completed an arrival (on the
   // XCD-aggregated path: a dispatch order other than round-robin).
   bool stale = hw.count.v || hw.count.pad[0] || hw.ticket.v || hw.ticket.pad[0] || hw.acc_lo.v ||
-               hw.acc_lo.pad[0];
+               hw.acc_lo.pad[0] || hw.fb.v;
   for (const Line& g : hw.group) stale = stale || g.v || g.pad[0];
+  for (const Line& g : hw.cls) stale = stale || g.v || g.pad[0];
+  for (const Line& g : hw.node) stale = stale || g.v || g.pad[0];
   if (!err && !stale) return RED_OK;
   // Clear the error and every barrier word (the barrier was abandoned).
   RED_HIP(hipMemset(ws->words, 0, kWordsBytes));
   RED_HIP(hipMemset(ws->seg_tickets, 0, kTicketBytes));
   if (!err)
-    return set_error(RED_ENOTSUP, "arrival counters were left incomplete (a workgroup ran on another XCD "
-                                  "than round-robin dispatch implies)");
+    return set_error(RED_ENOTSUP, "arrival counters were left incomplete (an abandoned barrier or ticket)");
   if (err == kErrDispatch)
     return set_error(RED_ENOTSUP, "a workgroup ran on another XCD than round-robin dispatch implies "
                                   "(XCD-aggregated publication is not valid on this device)");
@@ -589,10 +593,10 @@ int red_sum_noalloc(int dtype, const void* x, int64_t n, void* out, void* stream
   if (n > 0 && (rl.plan.variant == RED_VARIANT_ATOMIC || rl.plan.variant == RED_VARIANT_PERSISTENT)) {
     // The ticket, counters and accumulator start at zero (the array keeps
     // whatever the last call, or an abandoned barrier, left).
-    unsigned* w = static_cast<unsigned*>(sp);
-    int nw = (int)(sizeof(BarrierWords) / 4);
-    void* zargs[] = {&w, &nw};
-    if ((rc = launch(reinterpret_cast<const void*>(&k_zero_words), 1, 256, zargs, s, false))) return rc;
+    Line* lines = static_cast<Line*>(sp);
+    int nl = (int)(sizeof(BarrierWords) / sizeof(Line));
+    void* zargs[] = {&lines, &nl};
+    if ((rc = launch(reinterpret_cast<const void*>(&k_zero_lines), 1, 256, zargs, s, false))) return rc;
   }
   return reduce_launch(rl, x, n, out, &ws, s, *dev);
 }

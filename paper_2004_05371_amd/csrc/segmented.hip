@@ -966,7 +966,7 @@ int seg_launch(const SegLaunch& sl, const float* x, const int64_t* offsets, int6
   a.tickets = ws->seg_tickets;
   a.words = ws->words;
   a.spin_limit = watchdog_spins();
-  a.bar_groups = ((p.flags & RED_FLAG_XCD) && dev.nxcc > 1) ? (kBarrierXcd | (unsigned)dev.nxcc)
+  a.bar_groups = ((p.flags & RED_FLAG_XCD) && xcd_tree_fits(dev.nxcc)) ? (kBarrierXcd | (unsigned)dev.nxcc)
                                                             : barrier_groups(grid);
   a.form = (p.flags & RED_FLAG_SEG_WORKGROUP) ? kSegWorkgroup
            : (p.flags & RED_FLAG_SEG_PIECES)  ? kSegWavePieces

@@ -295,7 +295,7 @@ int stencil_launch(float* u, float* scratch, int64_t n, int steps, float r, int 
   a.r = r;
   a.words = ws->words;
   a.spin_limit = watchdog_spins();
-  a.bar_groups = ((p.flags & RED_FLAG_XCD) && dev.nxcc > 1) ? (kBarrierXcd | (unsigned)dev.nxcc)
+  a.bar_groups = ((p.flags & RED_FLAG_XCD) && xcd_tree_fits(dev.nxcc)) ? (kBarrierXcd | (unsigned)dev.nxcc)
                                                             : barrier_groups(grid);
   void* args[] = {&a};
   const bool coop = (p.flags & RED_FLAG_PLAIN_LAUNCH) == 0;

@@ -94,7 +94,7 @@ def test_validation_before_hip(lib):
     assert lib.red_bw_proxy_ex(ctypes.c_void_p(64), 1024, 4, 256, 2, None) == R.RED_EINVAL  # unknown flag
     e = ctypes.c_int64()
     assert lib.sync_check_grid_visibility(0, 256, 0, 10, ctypes.byref(e), None) == R.RED_EINVAL
-    assert lib.sync_check_grid_visibility(4, 256, -2, 10, ctypes.byref(e), None) == R.RED_EINVAL
+    assert lib.sync_check_grid_visibility(4, 256, -3, 10, ctypes.byref(e), None) == R.RED_EINVAL
     assert lib.sync_check_grid_visibility(4, 256, 0, 0, ctypes.byref(e), None) == R.RED_EINVAL
     p = R.Plan(R.RED_VARIANT_PERSISTENT, 256, 16, 0, 0)
     assert lib.red_set_plan(R.RED_F32, 0, 100, ctypes.byref(p)) == R.RED_EINVAL
@@ -218,3 +218,26 @@ def test_wrappers_reject_bad_tensors_before_any_launch():
         R.segmented_sum(T(f32, 100), T(i64, 11), out=T(f32, 10))
     with pytest.raises(TypeError):
         R.segmented_sum(T(f32, 100), T(torch.int32, 11))
+
+
+def test_xcd_tree_layout_covers_every_grid():
+    """The arrival tree's first-level lines (class r = g mod nxcc, node
+    (g / nxcc) / 16, line r + nxcc * node) for every grid the library
+    launches: every line index is inside the 528 lines, and each node's
+    expected count is the number of workgroups that map to it."""
+    import numpy as np
+    fan, max_lines = 16, 528
+    for nxcc in (2, 4, 8, 14):
+        for n in list(range(1, 70)) + [100, 255, 256, 257, 511, 512, 1000, 1024, 2047, 2048, 4096, 8191, 8192]:
+            g = np.arange(n)
+            r, j = g % nxcc, g // nxcc
+            members = (n - r + nxcc - 1) // nxcc
+            node = j // fan
+            line = r + nxcc * node
+            assert line.max() < max_lines, (nxcc, n)
+            nsize = np.minimum(fan, members - node * fan)
+            counts = np.bincount(line, minlength=max_lines)
+            assert (counts[line] == nsize).all(), (nxcc, n)
+            nodes = (members + fan - 1) // fan
+            for cls in range(min(n, nxcc)):
+                assert len(set(node[r == cls])) == nodes[r == cls][0]

@@ -33,12 +33,14 @@ def test_grid_barrier_ordering(lib, n_wg, wg):
         assert before <= after, (n_wg, wg, before, after)
 
 
-@pytest.mark.parametrize("groups", [1, 0, 8, -1])
-@pytest.mark.parametrize("n_wg", [2, 64, 256, 512])
+@pytest.mark.parametrize("groups", [1, 0, 8, -1, -2])
+@pytest.mark.parametrize("n_wg", [2, 64, 256, 512, 1024])
 def test_grid_barrier_visibility(lib, n_wg, groups):
     """Ordinary stores before a grid barrier are seen by ordinary loads of
     every workgroup after it, round after round on the same addresses, for
-    the flat, default, 8-group and XCD-aggregated barriers."""
+    the flat, default, 8-group and XCD-aggregated (arrival tree) barriers,
+    and for the XCD barrier's fall-back (-2: odd workgroups report another
+    XCD, so every barrier asks every workgroup to release on its own)."""
     n = min(n_wg, lib.red_max_coresident(256))
     say("visibility", n, "workgroups, groups", groups)
     assert lib.sync_check_grid_visibility(n, 256, groups, rounds=200) == 0
@@ -337,12 +339,31 @@ def test_xcd_publication_sums(lib, variant):
     assert lib.red_check_error(lib.current_stream()) == lib.RED_OK
 
 
-@pytest.mark.parametrize("n_wg", [1, 8, 9, 256, 1024])
-def test_xcd_barrier_probe(lib, n_wg):
-    n_wg = min(n_wg, lib.red_max_coresident(256))
-    ns, sigma, wall = lib.sync_bench_grid_ex(n_wg, 256, -1, reps=5)
-    say("grid %d WGs, XCD-aggregated: %.1f ns" % (n_wg, ns))
+@pytest.mark.parametrize("n_wg", [1, 8, 9, 17, 129, 256, 1024, 2048])
+@pytest.mark.parametrize("groups", [-1, -2])
+def test_xcd_barrier_probe(lib, n_wg, groups):
+    """The XCD arrival tree (one, two and three levels) and its fall-back:
+    every barrier completes, no watchdog fires, and the fall-back costs
+    more than the aggregated path."""
+    n_wg = min(n_wg, lib.red_max_coresident(64))
+    ns, sigma, wall = lib.sync_bench_grid_ex(n_wg, 64, groups, reps=5)
+    say("grid %d WGs, XCD-aggregated%s: %.1f ns" % (n_wg, " (fall-back)" if groups == -2 else "", ns))
     assert 0 < ns < 1e6
+    assert lib.red_check_error(lib.current_stream()) == lib.RED_OK
+
+
+def test_xcd_fallback_keeps_ordering(lib):
+    """Stores before a fall-back barrier are seen after it at grids of one
+    class per XCD and more, and the XCD tree inside the persistent
+    reduction gives the exact int sum."""
+    x = inputs.uniform_i32(2_000_003, lo=-2**31, hi=2**31 - 1, sub=19)
+    t = torch.from_numpy(x).to("cuda")
+    ref = oracle.sum_i32(x)
+    for n_wg in (8, 9, 256):
+        assert lib.sync_check_grid_visibility(n_wg, 256, -2, rounds=100) == 0
+    out = lib.sum(t, opts=lib.make_opts(variant=3, wg=256, ipt=4, grid=256, flags=lib.FLAG_XCD))
+    torch.cuda.synchronize()
+    assert out.item() == ref
     assert lib.red_check_error(lib.current_stream()) == lib.RED_OK
 
 
