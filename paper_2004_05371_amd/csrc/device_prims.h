@@ -585,58 +585,48 @@ __device__ __forceinline__ unsigned grid_barrier_gen(BarrierWords* w) {
   return threadIdx.x == 0 ? __hip_atomic_load(&w->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
 }
 
-__device__ __forceinline__ bool grid_barrier(BarrierWords* w, unsigned nblocks, unsigned groups,
-                                             unsigned spin_limit, unsigned& gen) {
-  __shared__ int timed_out;
+// Thread 0's part of one grid barrier: arrive, then open the barrier (last
+// arrival) or wait for it; returns 1 on timeout.  One polling loop serves
+// the waiting workgroups and, during a fall-back, the last arrival (which
+// then waits for the other workgroups' release acknowledgements before it
+// opens the barrier); a second loop for the last arrival raised the
+// register count of the persistent kernels that hold 8 loads per lane
+// from 59 to 107 VGPRs.
+__device__ __forceinline__ int grid_barrier_thread0(BarrierWords* w, unsigned nblocks, unsigned groups,
+                                                    unsigned spin_limit, unsigned g) {
   const bool xcd = (groups & kBarrierXcd) != 0;
-  // Every wave drains its own stores first, so they are in its XCD's L2
-  // when thread 0's release writes that L2 back (the stores of a workgroup
-  // may come from any of its waves).
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int to = 0;
-    const unsigned g = gen;
-    bool last = false, ok = true;
-    if (xcd) {
-      last = xcd_tree_arrive(w, w->count, nblocks, groups, &ok);
+  int to = 0;
+  bool last = false, ok = true;
+  if (xcd) {
+    last = xcd_tree_arrive(w, w->count, nblocks, groups, &ok);
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (groups <= 1) {
+      last = relaxed_add(&w->count.v, 1u) == nblocks - 1;
     } else {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      if (groups <= 1) {
-        last = relaxed_add(&w->count.v, 1u) == nblocks - 1;
-      } else {
-        const unsigned grp = blockIdx.x % groups;
-        const unsigned members = (nblocks - grp + groups - 1) / groups;
-        const unsigned active = nblocks < groups ? nblocks : groups;
-        if (relaxed_add(&w->group[grp].v, 1u) == members - 1) {
-          __hip_atomic_store(&w->group[grp].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-          last = relaxed_add(&w->count.v, 1u) == active - 1;
-        }
+      const unsigned grp = blockIdx.x % groups;
+      const unsigned members = (nblocks - grp + groups - 1) / groups;
+      const unsigned active = nblocks < groups ? nblocks : groups;
+      if (relaxed_add(&w->group[grp].v, 1u) == members - 1) {
+        __hip_atomic_store(&w->group[grp].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        last = relaxed_add(&w->count.v, 1u) == active - 1;
       }
     }
-    if (last) {
-      __hip_atomic_store(&w->count.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (!ok && nblocks > 1) {
-        // Fall-back: every other workgroup releases its own stores.
-        __hip_atomic_store(&w->gen.pad[0], g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned spins = 0;
-        while (__hip_atomic_load(&w->fb.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != nblocks - 1) {
-          if (++spins > spin_limit) {
-            __hip_atomic_store(&w->err.v, kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            to = 1;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
-        __hip_atomic_store(&w->fb.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-      relaxed_add(&w->gen.v, 1u);
-    } else {
-      unsigned spins = 0;
-      bool released = false;
-      for (;;) {
+  }
+  // The last arrival opens the barrier now, or after a fall-back: it asks
+  // every other workgroup to release its own stores, then waits below for
+  // their acknowledgements.
+  const bool fallback = last && !ok && nblocks > 1;
+  if (last) __hip_atomic_store(&w->count.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (fallback) __hip_atomic_store(&w->gen.pad[0], g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!last || fallback) {
+    unsigned spins = 0;
+    bool released = false;
+    for (;;) {
+      if (fallback) {
+        if (__hip_atomic_load(&w->fb.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == nblocks - 1) break;
+      } else {
         unsigned cur, req;
         if (xcd) {
           const unsigned long long both = __hip_atomic_load(reinterpret_cast<unsigned long long*>(&w->gen.v),
@@ -653,17 +643,35 @@ __device__ __forceinline__ bool grid_barrier(BarrierWords* w, unsigned nblocks, 
           relaxed_add(&w->fb.v, 1u);
           released = true;
         }
-        if (++spins > spin_limit) {
-          __hip_atomic_store(&w->err.v, kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          to = 1;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
       }
+      if (++spins > spin_limit) {
+        __hip_atomic_store(&w->err.v, kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        to = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    gen = g + 1u;
-    timed_out = to;
+    if (fallback) __hip_atomic_store(&w->fb.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (last) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+    relaxed_add(&w->gen.v, 1u);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return to;
+}
+
+__device__ __forceinline__ bool grid_barrier(BarrierWords* w, unsigned nblocks, unsigned groups,
+                                             unsigned spin_limit, unsigned& gen) {
+  __shared__ int timed_out;
+  // Every wave drains its own stores first, so they are in its XCD's L2
+  // when thread 0's release writes that L2 back (the stores of a workgroup
+  // may come from any of its waves).
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    timed_out = grid_barrier_thread0(w, nblocks, groups, spin_limit, gen);
+    gen = gen + 1u;
   }
   __syncthreads();
   return timed_out == 0;
