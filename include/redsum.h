@@ -71,7 +71,9 @@ typedef enum {
     RED_VARIANT_ATOMIC = 2,     /* one kernel; the last workgroup to take an
                                    atomic ticket does the final combine        */
     RED_VARIANT_PERSISTENT = 3, /* one cooperative kernel; grid barrier, then
-                                   workgroup 0 does the final combine          */
+                                   workgroup 0 does the final combine (the
+                                   barrier is split: workgroup 0 alone waits
+                                   for every arrival; the others leave)        */
     RED_VARIANT_SINGLE = 4      /* one workgroup, no device-wide
                                    synchronization at all: the "use fewer
                                    workers" side of the performance model

@@ -408,9 +408,9 @@ __device__ __forceinline__ unsigned xcc_id() {
 // by atomics sits on its own 128-byte line.
 // ---------------------------------------------------------------------------
 constexpr int kMaxBarrierGroups = 32;
-constexpr unsigned kTreeFanIn = 16;       // arrivals per first-level node of the XCD tree
+constexpr unsigned kTreeFanIn = 64;       // arrivals per first-level node of the XCD tree
 constexpr int kMaxTreeClasses = 16;       // residue classes (XCDs) of the XCD tree
-constexpr int kMaxTreeNodes = 528;        // first-level nodes: 8192 / kTreeFanIn + kMaxTreeClasses
+constexpr int kMaxTreeNodes = 144;        // first-level nodes: 8192 / kTreeFanIn + kMaxTreeClasses
 
 struct alignas(128) Line {
   unsigned v;
@@ -459,8 +459,11 @@ __device__ __forceinline__ unsigned relaxed_add(unsigned* p, unsigned v) {
 //   level 2  the last arrival of each node of class r, on the class line
 //            (skipped when the class has one node);
 //   level 3  the last arrival of each class, on the top line.
-// At 512 workgroups that is 16 + 4 + 8 serialized arrivals instead of
-// 64 + 8 with one counter per XCD.
+// Measured on MI355X, a level costs about as much as 16 serialized
+// arrivals, and the agent-scope acquire that every waiting workgroup needs
+// after the barrier (an L2 invalidation, about 56 ns each, queued per XCD)
+// dominates beyond that; so nodes hold 64 members, one level per class up
+// to 512 workgroups.
 //
 // The dispatch rule is checked on the way, at no extra atomic: every counter
 // is a 64-bit tally that adds (1, k, k^2) for a key k in three fields
@@ -592,8 +595,13 @@ __device__ __forceinline__ unsigned grid_barrier_gen(BarrierWords* w) {
 // opens the barrier); a second loop for the last arrival raised the
 // register count of the persistent kernels that hold 8 loads per lane
 // from 59 to 107 VGPRs.
+// ONE_SIDED: only the workgroups with `waiter` set wait for the barrier
+// (and acquire); the others arrive and return at once.  No fall-back is
+// possible then (the others may have left): an XCD tree that finds a
+// workgroup off its class's XCD reports kErrDispatch instead.
+template <bool ONE_SIDED = false>
 __device__ __forceinline__ int grid_barrier_thread0(BarrierWords* w, unsigned nblocks, unsigned groups,
-                                                    unsigned spin_limit, unsigned g) {
+                                                    unsigned spin_limit, unsigned g, bool waiter = true) {
   const bool xcd = (groups & kBarrierXcd) != 0;
   int to = 0;
   bool last = false, ok = true;
@@ -617,7 +625,9 @@ __device__ __forceinline__ int grid_barrier_thread0(BarrierWords* w, unsigned nb
   // The last arrival opens the barrier now, or after a fall-back: it asks
   // every other workgroup to release its own stores, then waits below for
   // their acknowledgements.
-  const bool fallback = last && !ok && nblocks > 1;
+  const bool fallback = !ONE_SIDED && last && !ok && nblocks > 1;
+  if (ONE_SIDED && last && !ok) __hip_atomic_store(&w->err.v, kErrDispatch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (ONE_SIDED && !last && !waiter) return 0;
   if (last) __hip_atomic_store(&w->count.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (fallback) __hip_atomic_store(&w->gen.pad[0], g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (!last || fallback) {
@@ -657,8 +667,29 @@ __device__ __forceinline__ int grid_barrier_thread0(BarrierWords* w, unsigned nb
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
     relaxed_add(&w->gen.v, 1u);
   }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (!ONE_SIDED || waiter) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return to;
+}
+
+// One-sided grid barrier: every workgroup arrives (its stores released as
+// in grid_barrier), and only the workgroups with `waiter` set wait for all
+// arrivals and acquire; the others return at once (they must not read what
+// other workgroups stored before the barrier).  For a persistent reduction
+// whose workgroup 0 alone combines the partials: the other workgroups skip
+// the wait and the agent-scope acquire, whose L2 invalidations queue up per
+// XCD.  `waiter` is uniform across the workgroup.  Returns false on timeout
+// (waiters).
+__device__ __forceinline__ bool grid_barrier_to(BarrierWords* w, unsigned nblocks, unsigned groups,
+                                                unsigned spin_limit, unsigned& gen, bool waiter) {
+  __shared__ int timed_out;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    timed_out = grid_barrier_thread0<true>(w, nblocks, groups, spin_limit, gen, waiter);
+    gen = gen + 1u;
+  }
+  __syncthreads();
+  return timed_out == 0;
 }
 
 __device__ __forceinline__ bool grid_barrier(BarrierWords* w, unsigned nblocks, unsigned groups,

@@ -237,8 +237,10 @@ __global__ __launch_bounds__(1024) void k_atomic(ReduceArgs a) {
 
 // ---------------------------------------------------------------------------
 // Variant 3, explicit barrier: one cooperative (co-resident) kernel; every
-// workgroup stores its partial, all meet at the grid barrier, workgroup 0
-// combines.
+// workgroup stores its partial and arrives at the grid barrier, workgroup 0
+// waits for all of them and combines.  Only workgroup 0 reads after the
+// barrier, so it is split (arrive / wait): the others leave on arrival and
+// skip the agent-scope acquire.
 // ---------------------------------------------------------------------------
 template <class M, int IPT, bool NT, bool PIPE>
 __global__ __launch_bounds__(1024) void k_persistent(ReduceArgs a) {
@@ -246,7 +248,8 @@ __global__ __launch_bounds__(1024) void k_persistent(ReduceArgs a) {
   unsigned gen = grid_barrier_gen(a.words);
   Part p = workgroup_partial<M, IPT, NT, PIPE>(a);
   if (threadIdx.x == 0) static_cast<Part*>(a.partials)[blockIdx.x] = p;
-  grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit, gen);
+  // Workgroup 0 alone reads the partials: the others arrive and leave.
+  grid_barrier_to(a.words, gridDim.x, a.bar_groups, a.spin_limit, gen, blockIdx.x == 0);
   if (blockIdx.x != 0) return;
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   Part s = combine_partials<Part>(static_cast<const Part*>(a.partials), gridDim.x);

@@ -222,11 +222,11 @@ def test_wrappers_reject_bad_tensors_before_any_launch():
 
 def test_xcd_tree_layout_covers_every_grid():
     """The arrival tree's first-level lines (class r = g mod nxcc, node
-    (g / nxcc) / 16, line r + nxcc * node) for every grid the library
-    launches: every line index is inside the 528 lines, and each node's
+    (g / nxcc) / 64, line r + nxcc * node) for every grid the library
+    launches: every line index is inside the 144 lines, and each node's
     expected count is the number of workgroups that map to it."""
     import numpy as np
-    fan, max_lines = 16, 528
+    fan, max_lines = 64, 144
     for nxcc in (2, 4, 8, 14):
         for n in list(range(1, 70)) + [100, 255, 256, 257, 511, 512, 1000, 1024, 2047, 2048, 4096, 8191, 8192]:
             g = np.arange(n)
