@@ -173,10 +173,15 @@ def test_relaunch_probe(lib, kind):
     assert 0 < null_ns < 1e5
 
 
-@pytest.mark.parametrize("kind", [0, 2])
+@pytest.mark.parametrize("kind", [0, 1])
 def test_eq6_overhead_does_not_depend_on_launch_counts(lib, kind):
     """Eq. 6 (kernel fusion): (i, j) = (8, 1) and (4, 2) give the same
-    overhead per launch within 30 %."""
+    overhead per launch within 30 %, for ordinary and cooperative launches.
+    (Replayed from a graph, the kernels of one replay are dispatched without
+    the host, and the cost of a boundary depends on how many kernels the
+    graph holds: (8, 1) and (4, 2) differed by a factor of four in one run,
+    so Eq. 6's assumption does not hold there; the graph figure is reported,
+    not pinned.)"""
     a, sa, _ = lib.sync_bench_relaunch_ex(256, 256, kind, 8, 1, 0, reps=30)
     b, sb, _ = lib.sync_bench_relaunch_ex(256, 256, kind, 4, 2, 0, reps=30)
     say("Eq. 6 kind %d: (8,1) %.1f ns (sigma %.1f), (4,2) %.1f ns (sigma %.1f)" % (kind, a, sa, b, sb))
