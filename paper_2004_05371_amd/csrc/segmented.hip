@@ -375,6 +375,36 @@ struct RunLds {
   int64_t ring[kRing];   // offsets[i] at i mod kRing, for i in [fill - kRing, fill)
 };
 
+// LDS words written by one lane and read by another inside a wavefront.
+// The wavefront's LDS instructions execute in program order, so ordinary
+// LDS loads and stores suffice; the accesses are relaxed atomics on
+// LDS-space pointers (no compiler may forward a lane's own store to its
+// load, as it could for plain data) behind compiler-only fences (keeping
+// program order).  A volatile access through a generic pointer would be
+// compiled as a flat access with a wait for every outstanding global load.
+template <class T>
+using LdsPtr = __attribute__((address_space(3))) T*;
+
+template <class T>
+__device__ __forceinline__ LdsPtr<T> lds_ptr(T* p) {
+  return (LdsPtr<T>)p;
+}
+
+template <class T>
+__device__ __forceinline__ void lds_put(LdsPtr<T> p, int i, T v) {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __atomic_store_n(p + i, v, __ATOMIC_RELAXED);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+template <class T>
+__device__ __forceinline__ T lds_get(LdsPtr<T> p, int i) {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  const T v = __atomic_load_n(p + i, __ATOMIC_RELAXED);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  return v;
+}
+
 // Position of vector i of the transposition buffer: within each group of 16
 // vectors the low bits are XOR-ed so that both the row writes (lane l, vector
 // 64 u + l) and the run reads (lane l, vector IPT l + j) of 16 consecutive
@@ -426,15 +456,17 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
   // many as fit without overwriting entries from s + 1 on.  A (sub-)tile
   // reads entries s + 1 .. s + 64, those that are in the ring.
   auto off_entry = [&](int64_t i) -> int64_t { return i <= nseg ? a.offsets[i] : INT64_MAX; };
-  volatile int64_t* ring = L.ring;
+  const LdsPtr<int64_t> ring = lds_ptr(L.ring);
   int64_t fill = 0;
   int npend = 0;
   int64_t pend0 = 0, pend1 = 0, pend2 = 0;
-  auto ring_pos = [&](int64_t base) {  // (base + lane) mod kRing; base is wave-uniform
-    const int h = __builtin_amdgcn_readfirstlane((int)(base % kRing)) + lane;
+  // (base + lane) mod kRing; base is wave-uniform and below 2^31 + 4 kRing
+  // (nseg < 2^31), so the modulo is a 32-bit one.
+  auto ring_pos = [&](int64_t base) {
+    const int h = (int)((unsigned)__builtin_amdgcn_readfirstlane((int)base) % (unsigned)kRing) + lane;
     return h >= kRing ? h - kRing : h;
   };
-  auto put = [&](int64_t v, int64_t base) { ring[ring_pos(base)] = v; };
+  auto put = [&](int64_t v, int64_t base) { lds_put(ring, ring_pos(base), v); };
   auto refill = [&]() {
     if (npend > 0) put(pend0, fill);
     if (npend > 1) put(pend1, fill + kWave);
@@ -496,7 +528,7 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
       // must end past the rows to show every start in them.
       const int vis = (int)std::min<int64_t>(kWave, fill - (s + 1));
       if (vis <= 0) return false;
-      const int64_t O = lane < vis ? ring[ring_pos(s + 1)] : INT64_MAX;  // start of segment s + 1 + lane
+      const int64_t O = lane < vis ? lds_get(ring, ring_pos(s + 1)) : INT64_MAX;  // start of segment s + 1 + lane
       const bool valid = O < std::min(f1, hi);
       const int m = __popcll(__ballot(valid));  // the valid lanes are 0 .. m-1
       if (m >= vis) return false;
@@ -506,10 +538,10 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
       const bool clash = valid && lane + 1 < m && rn == r;
       if (__ballot(clash) != 0) return false;
       // Start k (lane k) tells lane r_k where it lies.
-      volatile unsigned* slot = L.slot;
-      slot[lane] = 0u;
-      if (valid) slot[r] = ((unsigned)(lane + 1) << 16) | (unsigned)rel;
-      const unsigned word = slot[lane];
+      const LdsPtr<unsigned> slot = lds_ptr(L.slot);
+      lds_put(slot, lane, 0u);
+      if (valid) lds_put(slot, r, ((unsigned)(lane + 1) << 16) | (unsigned)rel);
+      const unsigned word = lds_get(slot, lane);
       // Transpose: row u of the rows in, a run of RL values out.
 #pragma unroll
       for (int u = 0; u < RS; ++u) L.tile[run_swz<RS>(u * kWave + lane)] = cur[Q * RS + u];
