@@ -349,11 +349,11 @@ __device__ __forceinline__ void seg_wave_slices(const SegArgs& a) {
 // Each tile of 64 x IPT 16-byte vectors (256 IPT contiguous values) is
 // transposed through LDS so that lane l holds the run of RL = 4 IPT
 // consecutive values that starts at value RL l of the tile.  The starts of
-// the segments that follow the open one come from a window of the offsets
-// held in registers (entries j0 .. j0 + 63 of two 64-entry windows, a third
-// one prefetched).  When fewer than 64 segments start in the tile and no
-// run holds two starts:
-//   * each lane sums its run with fp32 TwoSum, cut at the start it holds (if
+// the segments that follow the open one come from a ring of the offsets
+// held in LDS (kRing entries ahead of the walk, refilled a tile ahead).
+// When fewer than 64 segments start in the tile and no run holds two
+// starts:
+//   * each lane sums its run in binary64, cut at the start it holds (if
 //     any) into a head, the end of the segment open on its left, and a
 //     tail;
 //   * a segmented inclusive scan of the tails in binary64 across the lanes,
@@ -563,24 +563,24 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
       }
       const bool has = word != 0u;
       const int b = has ? (int)(word & 0xFFFFu) - RL * lane : RL;  // the start's place in the run
-      CompF32 run = M::zero(), head = M::zero();
+      // The run's head and tail in binary64: an fp32 value widens exactly,
+      // and each of the at most RL - 1 additions rounds once, at 2^-53.
+      double run = 0.0, head = 0.0;
 #pragma unroll
       for (int i = 0; i < RL; ++i) {
         if (i > 0) {
           const bool at = i == b;
-          head.s = at ? run.s : head.s;
-          head.c = at ? run.c : head.c;
-          run.s = at ? 0.0f : run.s;
-          run.c = at ? 0.0f : run.c;
+          head = at ? run : head;
+          run = at ? 0.0 : run;
         }
-        M::add_elem(run, xr[i]);
+        run += (double)xr[i];
       }
-      double v = comp_to_double(run);
+      double v = run;
       int f = has ? 1 : 0;
       wave_segscan(v, f);
       if (!f) v = C + v;  // lanes 0 .. l hold no start: the open segment continues
       const double left = bpermute_move(v, (lane - 1) & (kWave - 1));
-      const double total = (lane == 0 ? C : left) + comp_to_double(head);
+      const double total = (lane == 0 ? C : left) + head;
       const int k = (int)(word >> 16) - 1;
       if (has && k > 0 && k < m) a.out[s + k] = total;  // segment s + k lies in the rows
       const double c_next = read_lane(v, kWave - 1);
