@@ -116,20 +116,24 @@ typedef enum {
 #define RED_FLAG_PIPELINE 8     /* reductions: double-buffered loop that
                                    issues the next tile's loads before the
                                    current tile's arithmetic                */
-#define RED_FLAG_XCD 16         /* atomic / persistent variants: publish the
-                                   partials with one L2 write-back per XCD
-                                   (the workgroups count themselves on an
-                                   arrival tree, and the last of each XCD
-                                   releases for all of them) instead of one
-                                   per workgroup.  Relies on the round-robin
-                                   dispatch of workgroups over the XCDs,
-                                   which the tree checks against every
-                                   workgroup's XCC_ID register: a grid
+#define RED_FLAG_XCD 16         /* workgroups count their arrivals on an
+                                   XCD arrival tree (nodes of 64, one line
+                                   per XCD, then one top line) instead of
+                                   one counter per group.  Grid barriers
+                                   (stencil, segmented grid-barrier
+                                   fix-up) then release with one L2
+                                   write-back per XCD instead of one per
+                                   workgroup; that relies on the
+                                   round-robin dispatch of workgroups over
+                                   the XCDs, which the tree checks against
+                                   every workgroup's XCC_ID register, and a
                                    barrier that finds a mismatch falls back
                                    to a release by every workgroup (correct,
-                                   slower); the atomic-ticket variant, whose
-                                   workgroups have left, reports it through
-                                   red_check_error as RED_ENOTSUP           */
+                                   slower).  The atomic and persistent
+                                   reductions publish their partials with
+                                   device-scope atomic stores (no L2
+                                   write-back at all), so for them the flag
+                                   only changes how arrivals are counted   */
 /* Segmented batches: force one way of cutting and walking the slices
  * (at most one of the three; by default the device picks from the mean
  * segment length).  For experiments and tests. */
@@ -182,12 +186,9 @@ void red_shutdown(void);
 const char *red_last_error(void);
 
 /* Synchronize `stream`, then report a grid-barrier watchdog timeout raised
- * by an earlier persistent kernel on that stream (RED_ETIMEOUT), or a
- * workgroup that ran on another XCD than round-robin dispatch implies in
- * an atomic-ticket call under RED_FLAG_XCD (RED_ENOTSUP: its output may
- * miss partials still held in another XCD's L2), or arrival counters left
- * incomplete (RED_ENOTSUP), clearing the flag and the barrier words.
- * RED_OK if none. */
+ * by an earlier persistent kernel on that stream (RED_ETIMEOUT), or arrival
+ * counters left incomplete (RED_ENOTSUP: an abandoned barrier or ticket),
+ * clearing the flag and the barrier words.  RED_OK if none. */
 int red_check_error(void *stream);
 
 /* ---------------------------------------------------------------------
@@ -506,7 +507,7 @@ int sync_check_grid_order(int n_wg, int wg_size, int64_t *max_before, int64_t *m
  * (host) receives the number of reads that did not see the round's value;
  * a correct barrier gives 0.  groups as in sync_bench_grid_ex.  Errors:
  * RED_EINVAL (bad arguments, grid not co-resident), RED_ETIMEOUT (watchdog),
- * RED_ENOTSUP (XCD dispatch rule broken), RED_EHIP. */
+ * RED_EHIP. */
 int sync_check_grid_visibility(int n_wg, int wg_size, int groups, int rounds, int64_t *errors, void *stream);
 
 /* Watchdog check: a cooperative kernel in which workgroup `skip_wg` never

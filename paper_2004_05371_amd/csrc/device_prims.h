@@ -477,7 +477,6 @@ __device__ __forceinline__ unsigned relaxed_add(unsigned* p, unsigned v) {
 // back (the grid barrier asks every workgroup to release on its own).
 // ---------------------------------------------------------------------------
 constexpr unsigned kErrTimeout = 1u;
-constexpr unsigned kErrDispatch = 2u;
 constexpr unsigned kBarrierXcd = 0x100u;   // groups value: XCD-aggregated barrier (| nxcc)
 constexpr unsigned kBarrierSkew = 0x200u;  // with kBarrierXcd: odd workgroups report the next XCD
                                            // (drives the fall-back from the host in tests)
@@ -550,6 +549,26 @@ __device__ __forceinline__ bool xcd_tree_arrive(BarrierWords* w, Line& top, unsi
   return true;
 }
 
+// Publication by device-scope atomic stores.  A relaxed agent-scope atomic
+// store is coherent across the XCDs (the store carries device scope, so it
+// is written through this XCD's L2), so a value published this way needs no
+// L2 write-back (buffer_wbl2) before the arrival that announces it: it only
+// has to be complete, which a wait on the store counter ensures.  What the
+// reader loads after its acquire is then the published value.  Only for
+// data that every writer publishes this way.
+template <class T>
+__device__ __forceinline__ void publish(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Waits until every store of this wave (published values included) is
+// complete; no compiler reordering of memory accesses across it.
+__device__ __forceinline__ void drain_stores() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // ---------------------------------------------------------------------------
 // Grid barrier for a launch of `nblocks` co-resident workgroups.
 //
@@ -596,9 +615,10 @@ __device__ __forceinline__ unsigned grid_barrier_gen(BarrierWords* w) {
 // register count of the persistent kernels that hold 8 loads per lane
 // from 59 to 107 VGPRs.
 // ONE_SIDED: only the workgroups with `waiter` set wait for the barrier
-// (and acquire); the others arrive and return at once.  No fall-back is
-// possible then (the others may have left): an XCD tree that finds a
-// workgroup off its class's XCD reports kErrDispatch instead.
+// (and acquire); the others arrive and return at once.  What the waiters
+// read was stored with publish() and drained, so no arrival releases (no
+// L2 write-back), and no fall-back is needed (nor possible: the others may
+// have left) when the XCD tree finds a workgroup off its class's XCD.
 template <bool ONE_SIDED = false>
 __device__ __forceinline__ int grid_barrier_thread0(BarrierWords* w, unsigned nblocks, unsigned groups,
                                                     unsigned spin_limit, unsigned g, bool waiter = true) {
@@ -608,7 +628,7 @@ __device__ __forceinline__ int grid_barrier_thread0(BarrierWords* w, unsigned nb
   if (xcd) {
     last = xcd_tree_arrive(w, w->count, nblocks, groups, &ok);
   } else {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if constexpr (!ONE_SIDED) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (groups <= 1) {
       last = relaxed_add(&w->count.v, 1u) == nblocks - 1;
     } else {
@@ -617,7 +637,7 @@ __device__ __forceinline__ int grid_barrier_thread0(BarrierWords* w, unsigned nb
       const unsigned active = nblocks < groups ? nblocks : groups;
       if (relaxed_add(&w->group[grp].v, 1u) == members - 1) {
         __hip_atomic_store(&w->group[grp].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        if constexpr (!ONE_SIDED) __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
         last = relaxed_add(&w->count.v, 1u) == active - 1;
       }
     }
@@ -626,7 +646,6 @@ __device__ __forceinline__ int grid_barrier_thread0(BarrierWords* w, unsigned nb
   // every other workgroup to release its own stores, then waits below for
   // their acknowledgements.
   const bool fallback = !ONE_SIDED && last && !ok && nblocks > 1;
-  if (ONE_SIDED && last && !ok) __hip_atomic_store(&w->err.v, kErrDispatch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (ONE_SIDED && !last && !waiter) return 0;
   if (last) __hip_atomic_store(&w->count.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (fallback) __hip_atomic_store(&w->gen.pad[0], g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -664,25 +683,33 @@ __device__ __forceinline__ int grid_barrier_thread0(BarrierWords* w, unsigned nb
     if (fallback) __hip_atomic_store(&w->fb.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   if (last) {
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+    // One-sided: nothing to pass on (the data is published, the last
+    // arrival reads none of it); the counter's reset completes first.
+    if constexpr (ONE_SIDED)
+      drain_stores();
+    else
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
     relaxed_add(&w->gen.v, 1u);
   }
   if (!ONE_SIDED || waiter) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return to;
 }
 
-// One-sided grid barrier: every workgroup arrives (its stores released as
-// in grid_barrier), and only the workgroups with `waiter` set wait for all
-// arrivals and acquire; the others return at once (they must not read what
-// other workgroups stored before the barrier).  For a persistent reduction
-// whose workgroup 0 alone combines the partials: the other workgroups skip
-// the wait and the agent-scope acquire, whose L2 invalidations queue up per
-// XCD.  `waiter` is uniform across the workgroup.  Returns false on timeout
+// One-sided grid barrier: every workgroup arrives, and only the workgroups
+// with `waiter` set wait for all arrivals and acquire; the others return at
+// once (they must not read what other workgroups stored before the
+// barrier).  What the waiters read must have been stored with publish():
+// every wave drains its stores before the workgroup barrier that precedes
+// the arrival, so no arrival writes back an L2 and no XCD placement
+// matters.  For a persistent reduction whose workgroup 0 alone combines
+// the partials: the other workgroups skip the L2 write-back, the wait and
+// the agent-scope acquire (write-backs and invalidations queue up per XCD).
+// `waiter` is uniform across the workgroup.  Returns false on timeout
 // (waiters).
 __device__ __forceinline__ bool grid_barrier_to(BarrierWords* w, unsigned nblocks, unsigned groups,
                                                 unsigned spin_limit, unsigned& gen, bool waiter) {
   __shared__ int timed_out;
-  __builtin_amdgcn_s_waitcnt(0);
+  drain_stores();
   __syncthreads();
   if (threadIdx.x == 0) {
     timed_out = grid_barrier_thread0<true>(w, nblocks, groups, spin_limit, gen, waiter);

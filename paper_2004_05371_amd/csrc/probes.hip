@@ -583,8 +583,7 @@ int sync_bench_grid_r(int n_wg, int wg_size, int groups, int64_t r1, int64_t r2,
   RED_HIP(hipMemcpy(&err, &ws->words->err.v, 4, hipMemcpyDeviceToHost));
   if (err) {
     reset_words(ws, s);
-    return err == kErrDispatch ? set_error(RED_ENOTSUP, "grid probe: workgroup not on its round-robin XCD")
-                               : set_error(RED_ETIMEOUT, "grid probe: barrier watchdog fired");
+    return set_error(RED_ETIMEOUT, "grid probe: barrier watchdog fired");
   }
   return RED_OK;
 }

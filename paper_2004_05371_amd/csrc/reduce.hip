@@ -179,12 +179,13 @@ __global__ __launch_bounds__(64) void k_final_wave(const Part* partials, int cou
 
 // ---------------------------------------------------------------------------
 // Variant 2, one kernel with an atomic ticket: each workgroup publishes its
-// partial (int: atomic int64 add into one word; float: its partial slot),
-// then, after a device-scope release fence, takes a ticket with a relaxed
-// atomic; the workgroup that draws the last ticket acquires, does the final
-// combine and resets the ticket (and the int accumulator) for the next
-// launch.  With XCD-aggregated publication the release and the ticket are
-// taken once per XCD by its last workgroup.
+// partial with a device-scope atomic (int: an int64 add into one word;
+// float: a store to its partial slot), waits for it to complete, then takes
+// a ticket with a relaxed atomic; the workgroup that draws the last ticket
+// acquires, does the final combine and resets the ticket (and the int
+// accumulator) for the next launch.  The partials being atomics, no
+// workgroup writes back its L2.  Under RED_FLAG_XCD the tickets are counted
+// on the XCD arrival tree instead of one counter.
 // ---------------------------------------------------------------------------
 template <class M, int IPT, bool NT, bool PIPE>
 __global__ __launch_bounds__(1024) void k_atomic(ReduceArgs a) {
@@ -196,21 +197,18 @@ __global__ __launch_bounds__(1024) void k_atomic(ReduceArgs a) {
     if constexpr (__is_same(Part, long long))
       __hip_atomic_fetch_add(acc_i64(w), p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else
-      static_cast<Part*>(a.partials)[blockIdx.x] = p;
+      publish(static_cast<Part*>(a.partials) + blockIdx.x, p);
+    // The partial is complete before the ticket: only the last workgroup
+    // pays a fence (its acquire).
+    drain_stores();
     bool last;
     if (a.xcd_nxcc > 1) {
-      // One L2 write-back per XCD: the workgroups count themselves on the
-      // XCD arrival tree, whose last arrival takes the ticket.  Here the
-      // other workgroups have left, so a workgroup found off its class's
-      // XCD cannot be asked to release: the call is reported (RED_ENOTSUP
-      // from red_check_error).
+      // The workgroups count themselves on the XCD arrival tree, whose last
+      // arrival takes the ticket (its uniformity check does not matter: the
+      // partials need no L2 write-back).
       bool ok = true;
       last = xcd_tree_arrive(w, w->ticket, gridDim.x, kBarrierXcd | a.xcd_nxcc, &ok);
-      if (last && !ok) __hip_atomic_store(&w->err.v, kErrDispatch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      // Release (one L2 write-back) publishes the partial; the ticket itself
-      // is relaxed, and only the last workgroup pays an acquire.
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       last = relaxed_add(&w->ticket.v, 1u) == gridDim.x - 1;
     }
     is_last = last;
@@ -237,17 +235,17 @@ __global__ __launch_bounds__(1024) void k_atomic(ReduceArgs a) {
 
 // ---------------------------------------------------------------------------
 // Variant 3, explicit barrier: one cooperative (co-resident) kernel; every
-// workgroup stores its partial and arrives at the grid barrier, workgroup 0
-// waits for all of them and combines.  Only workgroup 0 reads after the
-// barrier, so it is split (arrive / wait): the others leave on arrival and
-// skip the agent-scope acquire.
+// workgroup publishes its partial (device-scope atomic store) and arrives
+// at the grid barrier, workgroup 0 waits for all of them and combines.
+// Only workgroup 0 reads after the barrier, so it is split (arrive / wait):
+// the others leave on arrival, with no L2 write-back and no acquire.
 // ---------------------------------------------------------------------------
 template <class M, int IPT, bool NT, bool PIPE>
 __global__ __launch_bounds__(1024) void k_persistent(ReduceArgs a) {
   using Part = typename M::Part;
   unsigned gen = grid_barrier_gen(a.words);
   Part p = workgroup_partial<M, IPT, NT, PIPE>(a);
-  if (threadIdx.x == 0) static_cast<Part*>(a.partials)[blockIdx.x] = p;
+  if (threadIdx.x == 0) publish(static_cast<Part*>(a.partials) + blockIdx.x, p);
   // Workgroup 0 alone reads the partials: the others arrive and leave.
   grid_barrier_to(a.words, gridDim.x, a.bar_groups, a.spin_limit, gen, blockIdx.x == 0);
   if (blockIdx.x != 0) return;

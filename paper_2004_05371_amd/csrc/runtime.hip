@@ -526,8 +526,7 @@ int red_check_error(void* stream) {
   RED_HIP(hipMemcpy(&hw, ws->words, sizeof(hw), hipMemcpyDeviceToHost));
   const unsigned err = hw.err.v;
   // Every completed launch leaves its arrival counters at zero; a counter
-  // left over means some workgroups never completed an arrival (on the
-  // XCD-aggregated path: a dispatch order other than round-robin).
+  // left over means some workgroups never completed an arrival.
   bool stale = hw.count.v || hw.count.pad[0] || hw.ticket.v || hw.ticket.pad[0] || hw.acc_lo.v ||
                hw.acc_lo.pad[0] || hw.fb.v;
   for (const Line& g : hw.group) stale = stale || g.v || g.pad[0];
@@ -539,9 +538,6 @@ int red_check_error(void* stream) {
   RED_HIP(hipMemset(ws->seg_tickets, 0, kTicketBytes));
   if (!err)
     return set_error(RED_ENOTSUP, "arrival counters were left incomplete (an abandoned barrier or ticket)");
-  if (err == kErrDispatch)
-    return set_error(RED_ENOTSUP, "a workgroup ran on another XCD than round-robin dispatch implies "
-                                  "(XCD-aggregated publication is not valid on this device)");
   return set_error(RED_ETIMEOUT, "a grid-barrier watchdog fired on this stream");
 }
 
