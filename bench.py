@@ -328,8 +328,11 @@ def summarize_extensions(rows, line, out_dir):
         k = r["Name"].replace("|", "/")
         md.append("| `%s` | %s | %.2f | %.2f | %.2f |" % (k[:95], r["Calls"], float(r["AverageNs"]) / 1e3,
                                                           float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3))
-    sk = [r for r in pick if "k_segmented<" in r["Name"]]
-    fx = [r for r in pick if "k_seg_fixup" in r["Name"]]
+    # the slice kernel of the bench plan: k_segmented<ipt, nontemporal, fix-up>
+    fix = {"atomic": 0, "persistent": 1, "relaunch": 2}.get(seg["plan"]["variant"], 2)
+    tmpl = "k_segmented<%d, %s, %d>" % (seg["plan"]["ipt"], "true" if seg["plan"]["flags"] & 1 else "false", fix)
+    sk = [r for r in pick if tmpl in r["Name"]]
+    fx = [r for r in pick if "k_seg_fixup" in r["Name"]] if fix == 2 else []
     if sk:
         a = float(sk[0]["AverageNs"])
         md += ["", "- Slice kernel: average %.1f us = %.1f GB/s for %d algorithmic bytes (values, offsets, "

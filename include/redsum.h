@@ -254,8 +254,9 @@ int red_sum_noalloc(int dtype, const void *x, int64_t n, void *out, void *stream
  * segments that meet its slice; for very short segments a wavefront
  * reduces by key over runs of consecutive values with a segmented scan
  * across its lanes.  The pieces of segments that cross slice boundaries
- * are combined in slice order in binary64, by default by a second, small
- * kernel (red_sum_segmented_ex lists the other ways).  The kernels are
+ * are combined in slice order in binary64, by default by the wavefront
+ * that publishes a segment's last piece, found with an atomic ticket
+ * (red_sum_segmented_ex lists the other ways).  The kernels are
  * captured in a hipGraph on the first call for a given (x, offsets, nseg,
  * out, stream, plan) and replayed afterwards; when the stream is already
  * being captured by the caller they are simply launched into that
@@ -267,8 +268,10 @@ int red_sum_segmented(const float *x, const int64_t *offsets, int64_t nseg, doub
  * the pieces of segments cut by slice boundaries are summed:
  * RED_VARIANT_RELAUNCH (a second, small kernel after the implicit barrier
  * between launches; both kernels go into the graph), RED_VARIANT_ATOMIC
- * (the last contributor, found by an atomic ticket after a release fence)
- * or RED_VARIANT_PERSISTENT (the owning slice after a grid barrier;
+ * (the last contributor, found by an atomic ticket; the pieces are
+ * published with device-scope atomic stores, no L2 write-back) or
+ * RED_VARIANT_PERSISTENT (the owning slice after a grid barrier that
+ * neither writes back nor invalidates an L2, the pieces being published;
  * co-resident grid: a cooperative launch is made directly, not from a
  * graph; with RED_FLAG_PLAIN_LAUNCH the grid, capped at the co-resident
  * count, is an ordinary launch, and that one persistent kernel is captured

@@ -516,9 +516,12 @@ __device__ __forceinline__ bool tally_arrive(Line& l, unsigned k, unsigned expec
 // Counts this workgroup on the XCD tree whose top line is `top`; returns
 // true for the one last arrival of the grid, which has then seen every
 // workgroup arrive, with *ok telling whether every workgroup ran on the XCD
-// its class implies (then every class's stores have been released).
+// its class implies (then, with RELEASE, every class's stores have been
+// released; without, the caller's data is published by device-scope atomic
+// stores and only the count matters).
 // Thread 0 only; every wave of the workgroup must have drained its stores
 // (s_waitcnt) before the workgroup barrier that precedes this call.
+template <bool RELEASE = true>
 __device__ __forceinline__ bool xcd_tree_arrive(BarrierWords* w, Line& top, unsigned nblocks, unsigned groups,
                                                 bool* ok) {
   const unsigned nxcc = groups & 0xFFu;
@@ -541,7 +544,7 @@ __device__ __forceinline__ bool xcd_tree_arrive(BarrierWords* w, Line& top, unsi
   }
   // The class is complete: one write-back of this XCD's L2 publishes the
   // stores of every member that ran here.
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+  if constexpr (RELEASE) __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
   const unsigned off = key == kTreeBad ? kTreeBad : (key + nxcc - r) % nxcc;
   const unsigned active = nblocks < nxcc ? nblocks : nxcc;
   if (!tally_arrive(top, off, active, &u)) return false;
@@ -559,6 +562,13 @@ __device__ __forceinline__ bool xcd_tree_arrive(BarrierWords* w, Line& top, unsi
 template <class T>
 __device__ __forceinline__ void publish(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Loads a value stored with publish() by another workgroup (device scope:
+// no stale copy in this XCD's L2 is returned).
+template <class T>
+__device__ __forceinline__ T load_published(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Waits until every store of this wave (published values included) is
@@ -607,28 +617,42 @@ __device__ __forceinline__ unsigned grid_barrier_gen(BarrierWords* w) {
   return threadIdx.x == 0 ? __hip_atomic_load(&w->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
 }
 
+// How a grid barrier passes data between workgroups.
+enum BarrierMode {
+  // Ordinary stores before, ordinary loads after: every arrival releases
+  // (on the XCD tree, one L2 write-back per XCD, with the fall-back below),
+  // every workgroup acquires after the wait.
+  kBarFenced = 0,
+  // One-sided: only the workgroups with `waiter` set wait (and acquire);
+  // what they read was stored with publish() and drained, so no arrival
+  // releases and no fall-back is needed (nor possible: the others may have
+  // left).
+  kBarOneSided = 1,
+  // Two-sided, with every value that crosses the barrier stored with
+  // publish() (drained before the arrival) and loaded with a device-scope
+  // atomic load: no workgroup releases or acquires.
+  kBarPublished = 2,
+};
+
 // Thread 0's part of one grid barrier: arrive, then open the barrier (last
 // arrival) or wait for it; returns 1 on timeout.  One polling loop serves
 // the waiting workgroups and, during a fall-back, the last arrival (which
 // then waits for the other workgroups' release acknowledgements before it
 // opens the barrier); a second loop for the last arrival raised the
 // register count of the persistent kernels that hold 8 loads per lane
-// from 59 to 107 VGPRs.
-// ONE_SIDED: only the workgroups with `waiter` set wait for the barrier
-// (and acquire); the others arrive and return at once.  What the waiters
-// read was stored with publish() and drained, so no arrival releases (no
-// L2 write-back), and no fall-back is needed (nor possible: the others may
-// have left) when the XCD tree finds a workgroup off its class's XCD.
-template <bool ONE_SIDED = false>
+// from 59 to 107 VGPRs.  `waiter` matters in kBarOneSided only.
+template <int MODE = kBarFenced>
 __device__ __forceinline__ int grid_barrier_thread0(BarrierWords* w, unsigned nblocks, unsigned groups,
                                                     unsigned spin_limit, unsigned g, bool waiter = true) {
+  constexpr bool ONE_SIDED = MODE == kBarOneSided;
+  constexpr bool FENCED = MODE == kBarFenced;
   const bool xcd = (groups & kBarrierXcd) != 0;
   int to = 0;
   bool last = false, ok = true;
   if (xcd) {
-    last = xcd_tree_arrive(w, w->count, nblocks, groups, &ok);
+    last = xcd_tree_arrive<FENCED>(w, w->count, nblocks, groups, &ok);
   } else {
-    if constexpr (!ONE_SIDED) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if constexpr (FENCED) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (groups <= 1) {
       last = relaxed_add(&w->count.v, 1u) == nblocks - 1;
     } else {
@@ -637,7 +661,7 @@ __device__ __forceinline__ int grid_barrier_thread0(BarrierWords* w, unsigned nb
       const unsigned active = nblocks < groups ? nblocks : groups;
       if (relaxed_add(&w->group[grp].v, 1u) == members - 1) {
         __hip_atomic_store(&w->group[grp].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if constexpr (!ONE_SIDED) __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        if constexpr (FENCED) __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
         last = relaxed_add(&w->count.v, 1u) == active - 1;
       }
     }
@@ -645,7 +669,7 @@ __device__ __forceinline__ int grid_barrier_thread0(BarrierWords* w, unsigned nb
   // The last arrival opens the barrier now, or after a fall-back: it asks
   // every other workgroup to release its own stores, then waits below for
   // their acknowledgements.
-  const bool fallback = !ONE_SIDED && last && !ok && nblocks > 1;
+  const bool fallback = FENCED && last && !ok && nblocks > 1;
   if (ONE_SIDED && !last && !waiter) return 0;
   if (last) __hip_atomic_store(&w->count.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (fallback) __hip_atomic_store(&w->gen.pad[0], g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -683,15 +707,15 @@ __device__ __forceinline__ int grid_barrier_thread0(BarrierWords* w, unsigned nb
     if (fallback) __hip_atomic_store(&w->fb.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   if (last) {
-    // One-sided: nothing to pass on (the data is published, the last
-    // arrival reads none of it); the counter's reset completes first.
-    if constexpr (ONE_SIDED)
-      drain_stores();
-    else
+    // Published data: nothing to pass on; the counter's reset completes
+    // first.
+    if constexpr (FENCED)
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+    else
+      drain_stores();
     relaxed_add(&w->gen.v, 1u);
   }
-  if (!ONE_SIDED || waiter) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (FENCED || (ONE_SIDED && waiter)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return to;
 }
 
@@ -712,7 +736,23 @@ __device__ __forceinline__ bool grid_barrier_to(BarrierWords* w, unsigned nblock
   drain_stores();
   __syncthreads();
   if (threadIdx.x == 0) {
-    timed_out = grid_barrier_thread0<true>(w, nblocks, groups, spin_limit, gen, waiter);
+    timed_out = grid_barrier_thread0<kBarOneSided>(w, nblocks, groups, spin_limit, gen, waiter);
+    gen = gen + 1u;
+  }
+  __syncthreads();
+  return timed_out == 0;
+}
+
+// Grid barrier for data that crosses it only by publish() and device-scope
+// atomic loads (kBarPublished): no L2 write-back at any arrival and no L2
+// invalidation after the wait.  Returns false on timeout.
+__device__ __forceinline__ bool grid_barrier_published(BarrierWords* w, unsigned nblocks, unsigned groups,
+                                                       unsigned spin_limit, unsigned& gen) {
+  __shared__ int timed_out;
+  drain_stores();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    timed_out = grid_barrier_thread0<kBarPublished>(w, nblocks, groups, spin_limit, gen);
     gen = gen + 1u;
   }
   __syncthreads();

@@ -207,7 +207,7 @@ __global__ __launch_bounds__(1024) void k_atomic(ReduceArgs a) {
       // arrival takes the ticket (its uniformity check does not matter: the
       // partials need no L2 write-back).
       bool ok = true;
-      last = xcd_tree_arrive(w, w->ticket, gridDim.x, kBarrierXcd | a.xcd_nxcc, &ok);
+      last = xcd_tree_arrive<false>(w, w->ticket, gridDim.x, kBarrierXcd | a.xcd_nxcc, &ok);
     } else {
       last = relaxed_add(&w->ticket.v, 1u) == gridDim.x - 1;
     }

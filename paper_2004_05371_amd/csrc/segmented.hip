@@ -81,11 +81,21 @@ __device__ __forceinline__ int64_t offset_at(const int64_t* offsets, int64_t i) 
 // Sum of the np pieces of a cut segment (owning slice o: carry_out[o], then
 // carry_in[o+1 .. o+np-1]) by one wavefront: lane l adds pieces o+l,
 // o+l+64, ... in order, then the fixed binary64 wavefront combine
-// (returned to every lane).
+// (returned to every lane).  The pieces are read with device-scope atomic
+// loads: the ticket and grid-barrier fix-ups read them in the launch that
+// published them, with no acquire.
 __device__ __forceinline__ double combine_pieces(const SegArgs& a, int64_t o, int64_t np) {
   double v = 0.0;
-  for (int64_t k = o + __lane_id(); k < o + np; k += kWave) v += k == o ? a.carry_out[o].val : a.carry_in[k].val;
+  for (int64_t k = o + __lane_id(); k < o + np; k += kWave)
+    v += load_published(k == o ? &a.carry_out[o].val : &a.carry_in[k].val);
   return wave_reduce_dpp<OpF64>(v);
+}
+
+// A carry slot published to the other workgroups of the same launch.
+__device__ __forceinline__ void publish_carry(SegCarry* slot, int64_t s, double v, int64_t np) {
+  publish(&slot->seg, (long long)s);
+  publish(&slot->val, v);
+  publish(&slot->np, (long long)np);
 }
 
 // Completes, by one wavefront, the piece [max(sa, lo), min(sb, hi)) of
@@ -95,7 +105,9 @@ __device__ __forceinline__ double combine_pieces(const SegArgs& a, int64_t o, in
 // the owning wavefront does so after the grid barrier (barrier fix-up:
 // *own_fix records the segment), or the fix-up kernel that follows does
 // (relaunch fix-up: the slot is an ordinary store, made visible by the
-// kernel boundary).
+// kernel boundary).  Within one launch the slots are published with
+// device-scope atomic stores, waited for before the ticket or the barrier,
+// so no workgroup writes back its L2 or invalidates it.
 template <int FIX>
 __device__ __forceinline__ void finish_piece(const SegArgs& a, int64_t s, int64_t sa, int64_t sb, double v,
                                              int64_t lo, int64_t hi, int64_t w, int64_t chunk, int64_t* own_fix) {
@@ -114,26 +126,18 @@ __device__ __forceinline__ void finish_piece(const SegArgs& a, int64_t s, int64_
         a.carry_out[w] = SegCarry{s, v, np};
     }
   } else if constexpr (FIX == kFixBarrier) {
-    if (lane == 0) {
-      if (sa < lo)
-        a.carry_in[w] = SegCarry{s, v, np};
-      else
-        a.carry_out[w] = SegCarry{s, v, np};
-    }
+    if (lane == 0) publish_carry(sa < lo ? &a.carry_in[w] : &a.carry_out[w], s, v, np);
     if (sa >= lo) *own_fix = s;
   } else {
     int last = 0;
     if (lane == 0) {
-      if (sa < lo)
-        a.carry_in[w] = SegCarry{s, v, np};
-      else
-        a.carry_out[w] = SegCarry{s, v, np};
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      publish_carry(sa < lo ? &a.carry_in[w] : &a.carry_out[w], s, v, np);
+      drain_stores();
       const unsigned tk = __hip_atomic_fetch_add(&a.tickets[o], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       last = tk == (unsigned)(np - 1);
     }
     if (__builtin_amdgcn_readfirstlane(last)) {  // this wave published the last piece
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
       const double t = combine_pieces(a, o, np);
       if (lane == 0) {
         a.out[s] = t;
@@ -333,9 +337,9 @@ __device__ __forceinline__ void seg_wave_slices(const SegArgs& a) {
     for (int u = 0; u < IPT; ++u) cur[u] = nxt[u];
   }
   if constexpr (FIX == kFixBarrier) {
-    grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit, gen);
+    grid_barrier_published(a.words, gridDim.x, a.bar_groups, a.spin_limit, gen);
     if (own_fix >= 0) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);  // the pieces are loaded as published
       const int64_t o = offset_at(a.offsets, own_fix) / chunk;
       const int64_t np = (offset_at(a.offsets, own_fix + 1) - 1) / chunk - o + 1;
       const double v = combine_pieces(a, o, np);
@@ -688,9 +692,9 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
     seek_segment(a, s, hi, E, end_slice, sa, sb, lane == 0);  // empty segments at E
   }
   if constexpr (FIX == kFixBarrier) {
-    grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit, gen);
+    grid_barrier_published(a.words, gridDim.x, a.bar_groups, a.spin_limit, gen);
     if (own_fix >= 0) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);  // the pieces are loaded as published
       const int64_t o = offset_at(a.offsets, own_fix) / chunk;
       const int64_t np = (offset_at(a.offsets, own_fix + 1) - 1) / chunk - o + 1;
       const double v = combine_pieces(a, o, np);
@@ -840,10 +844,10 @@ __device__ __forceinline__ void seg_workgroup_slices(const SegArgs& a, Workgroup
   }
   if (nb > 0) flush();
   if constexpr (FIX == kFixBarrier) {
-    grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit, gen);  // also a workgroup barrier
+    grid_barrier_published(a.words, gridDim.x, a.bar_groups, a.spin_limit, gen);  // also a workgroup barrier
     const int64_t os = own_fix;
     if (os >= 0 && wave == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);  // the pieces are loaded as published
       const int64_t o = offset_at(a.offsets, os) / chunk;
       const int64_t np = (offset_at(a.offsets, os + 1) - 1) / chunk - o + 1;
       const double v = combine_pieces(a, o, np);
@@ -937,18 +941,18 @@ const SegTable& seg_table() {
 
 }  // namespace
 
-// Default (measured on MI355X over uniform segment lengths from 16 to
-// 65536 values and 10,000 log-uniform ones): the relaunch fix-up, whose
-// slices publish their cut pieces with ordinary stores (a release fence
-// per cut piece writes back the XCD's L2: 768-value segments cut at every
-// one of 4096 slice boundaries took 405 us with tickets, 194 us with the
-// second launch); two 512-thread workgroups per CU, the most the
+// Default (measured on MI355X over uniform segment lengths and 10,000
+// log-uniform ones): the atomic-ticket fix-up.  With the cut pieces
+// published by device-scope atomic stores it is one kernel and 1 to 4 %
+// faster than the relaunch fix-up's two (768-value segments, every slice
+// boundary a cut: 188 against 196 us; with a release fence per cut piece
+// it had taken 405 us); two 512-thread workgroups per CU, the most the
 // reduce-by-key form keeps resident; 4 loads of 16 bytes per thread per
 // tile.
 red_plan default_seg_plan(int64_t nseg, const DeviceInfo& dev) {
   (void)nseg;
   red_plan p;
-  p.variant = RED_VARIANT_RELAUNCH;
+  p.variant = RED_VARIANT_ATOMIC;
   p.wg = 512;
   p.ipt = 4;
   p.grid = 2 * dev.cus;

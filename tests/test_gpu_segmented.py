@@ -315,12 +315,14 @@ def test_loop_baseline_matches(lib):
 
 def test_full_batch_config(lib):
     """10,000 log-uniform segments in [1, 2^20] (about 7.4e8 values): the
-    default plan, the cached plan the bench line times (relaunch fix-up,
-    256 x 4, grid 1024, nontemporal, graph replay) and the barrier fix-up."""
+    default plan, the cached plan the bench line times (ticket fix-up,
+    256 x 4, grid 768, nontemporal, graph replay), the relaunch fix-up and
+    the barrier fix-up."""
     x, off = inputs.segments(10000)
     say("segments total", int(off[-1]))
     sums = oracle.segmented_sums(x, off)
-    for p in (dict(), dict(variant=1, wg=256, ipt=4, grid=1024, flags=1), dict(variant=3, wg=512, ipt=4, grid=256)):
+    for p in (dict(), dict(variant=2, wg=256, ipt=4, grid=768, flags=1), dict(variant=1, wg=256, ipt=4, grid=1024, flags=1),
+              dict(variant=3, wg=512, ipt=4, grid=256)):
         say("plan", p)
         res = run(lib, x, off, **p)
         check(res, x, off, sums)
