@@ -262,13 +262,17 @@ def summarize_configs(paths, out_dir):
         out += ["## Grid barrier heat map (Section V, grid synchronization)", "",
                 "Latency of one grid barrier in ns, by grid size (rows) and workgroup size (columns), one table per "
                 "barrier shape: flat (one counter), 8 groups and the default two-level shape (groups of blockIdx mod "
-                "g), and the XCD-aggregated shape.", ""]
+                "g), and the XCD-aggregated shape; then the default and XCD shapes of the barrier for published data "
+                "(values stored and loaded with device-scope atomics: no L2 write-back at arrival, no invalidation "
+                "after the wait).", ""]
         wgs = sorted({r["wg"] for r in g})
-        for shape in ("1", "8", "default", "xcd"):
+        titles = {"1": "flat", "8": "8 groups", "default_published": "default, published data",
+                  "xcd_published": "xcd, published data"}
+        for shape in ("1", "8", "default", "xcd", "default_published", "xcd_published"):
             rows = [r for r in g if str(r["groups"]) == shape]
             if not rows:
                 continue
-            out += ["### Shape: %s" % {"1": "flat", "8": "8 groups"}.get(shape, shape), "",
+            out += ["### Shape: %s" % titles.get(shape, shape), "",
                     "| Workgroups | " + " | ".join("%d threads (WG/CU)" % x for x in wgs) + " |",
                     "|---|" + "---|" * len(wgs)]
             for n in sorted({r["n_wg"] for r in rows}):
@@ -881,10 +885,15 @@ def run_configs(R, dev, stream, path, plans, sections=CONFIG_SECTIONS):
             cores = R.red_max_coresident(wg)
             n = 1
             while n <= min(2048, cores):
-                for groups in ((1, 8, 0, -1) if n >= 64 else (1, -1)):
-                    ns, sg, wall = R.sync_bench_grid_ex(n, wg, groups, reps=20)
+                shapes = [(g, False) for g in ((1, 8, 0, -1) if n >= 64 else (1, -1))] + [(0, True), (-1, True)]
+                for groups, pub in shapes:
+                    if pub:
+                        ns, sg, wall = R.sync_bench_grid_published(n, wg, groups, reps=20)
+                    else:
+                        ns, sg, wall = R.sync_bench_grid_ex(n, wg, groups, reps=20)
+                    name = {0: "default", -1: "xcd"}.get(groups, groups)
                     emit({"probe": "grid", "wg": wg, "n_wg": n, "wg_per_cu": round(n / dev["cus"], 3),
-                          "groups": {0: "default", -1: "xcd"}.get(groups, groups), "ns": round(ns, 1),
+                          "groups": "%s_published" % name if pub else name, "ns": round(ns, 1),
                           "sigma_ns": round(sg, 1), "in_kernel_ns": round(wall, 1)})
                 n *= 2
         for kind, name in ((0, "ordinary"), (1, "cooperative"), (2, "graph")):
@@ -1042,10 +1051,14 @@ def headline(args, R, dev, stream, sh, plans, inputs):
     if not args.no_probes:
         cus = dev["cus"]
         gb = {}
-        for n_wg in (cus, 4 * cus):
+        for n_wg in (cus, 2 * cus, 4 * cus):
             n = min(n_wg, R.red_max_coresident(256))
-            for groups, name in ((1, "flat"), (0, "two_level"), (-1, "xcd")):
-                ns, sg, wall_ns = R.sync_bench_grid_ex(n, 256, groups, reps=20)
+            # fenced barriers (ordinary data) at 1 and 4 workgroups per CU;
+            # the barrier for published data (device-scope atomics) at 1, 2, 4
+            shapes = ([(1, "flat", False), (0, "two_level", False), (-1, "xcd", False)] if n_wg != 2 * cus else [])
+            for groups, name, pub in shapes + [(0, "two_level_published", True), (-1, "xcd_published", True)]:
+                probe = R.sync_bench_grid_published if pub else R.sync_bench_grid_ex
+                ns, sg, wall_ns = probe(n, 256, groups, reps=20)
                 gb["%d_wg_%s" % (n, name)] = {"ns": round(ns, 1), "sigma_ns": round(sg, 1),
                                               "in_kernel_ns": round(wall_ns, 1)}
         ro, ro_sg, null_ns = R.sync_bench_relaunch(cus, 256, cooperative=0, reps=20)

@@ -455,6 +455,16 @@ int sync_bench_grid_ex(int n_wg, int wg_size, int groups, int reps, double *ns, 
 int sync_bench_grid_r(int n_wg, int wg_size, int groups, int64_t r1, int64_t r2, int reps, double *ns,
                       double *sigma_ns, double *cycles, void *stream);
 
+/* sync_bench_grid_r for the grid barrier that carries only data published
+ * with device-scope atomic stores and read with device-scope atomic loads
+ * (the barrier of the persistent reduction's partials and of the segmented
+ * grid-barrier fix-up): no arrival writes back an L2 and no workgroup
+ * invalidates one after the wait, so it measures the arrival counting and
+ * the wait alone.  Arguments, shapes (groups) and errors as in
+ * sync_bench_grid_r. */
+int sync_bench_grid_published(int n_wg, int wg_size, int groups, int64_t r1, int64_t r2, int reps, double *ns,
+                              double *sigma_ns, double *cycles, void *stream);
+
 /* Launch overhead of a kernel boundary (the implicit barrier) by kernel
  * fusion, Eq. 6, with (i, j) = (8, 1) launches of n_wg x wg_size kernels
  * that wait 5 us per unit.  cooperative selects the launch type: 0 ordinary
@@ -512,6 +522,12 @@ int sync_check_grid_order(int n_wg, int wg_size, int64_t *max_before, int64_t *m
  * RED_EINVAL (bad arguments, grid not co-resident), RED_ETIMEOUT (watchdog),
  * RED_EHIP. */
 int sync_check_grid_visibility(int n_wg, int wg_size, int groups, int rounds, int64_t *errors, void *stream);
+
+/* sync_check_grid_visibility for the barrier of sync_bench_grid_published:
+ * every value is stored with a device-scope atomic store and read with
+ * device-scope atomic loads.  Arguments and errors as there. */
+int sync_check_grid_visibility_published(int n_wg, int wg_size, int groups, int rounds, int64_t *errors,
+                                         void *stream);
 
 /* Watchdog check: a cooperative kernel in which workgroup `skip_wg` never
  * arrives at the grid barrier while the others wait with a spin limit of

@@ -139,12 +139,20 @@ __global__ __launch_bounds__(1024) void k_block_tput(long long window, long long
   }
 }
 
+// r grid barriers back to back; PUB: the barrier for data published by
+// device-scope atomics (no L2 write-back at arrival, no invalidation after).
+template <bool PUB>
 __global__ __launch_bounds__(1024) void k_grid_chain(int r, BarrierWords* w, unsigned groups,
                                                     unsigned spin_limit, long long* stamps) {
   unsigned gen = grid_barrier_gen(w);
   __syncthreads();
   const long long t0 = __builtin_amdgcn_s_memrealtime();
-  for (int i = 0; i < r; ++i) grid_barrier(w, gridDim.x, groups, spin_limit, gen);
+  for (int i = 0; i < r; ++i) {
+    if constexpr (PUB)
+      grid_barrier_published(w, gridDim.x, groups, spin_limit, gen);
+    else
+      grid_barrier(w, gridDim.x, groups, spin_limit, gen);
+  }
   const long long t1 = __builtin_amdgcn_s_memrealtime();
   if (blockIdx.x == 0 && threadIdx.x == 0) stamps[0] = t1 - t0;
 }
@@ -171,18 +179,36 @@ __global__ __launch_bounds__(1024) void k_grid_order(BarrierWords* w, unsigned g
 // every thread reads its share of data[0 .. G) with ordinary loads (the
 // same addresses every round, so a stale line in either cache level would
 // show) and counts the slots that do not hold this round's value; a second
-// barrier keeps round r + 1's stores after every read of round r.
+// barrier keeps round r + 1's stores after every read of round r.  PUB:
+// device-scope atomic stores and loads around the barrier for published
+// data.
+template <bool PUB>
 __global__ __launch_bounds__(1024) void k_grid_visibility(BarrierWords* w, unsigned groups, unsigned spin_limit,
                                                          long long* data, unsigned long long* errors,
                                                          int rounds) {
   const unsigned G = gridDim.x;
   unsigned long long bad = 0;
   unsigned gen = grid_barrier_gen(w);
+  auto barrier = [&]() {
+    if constexpr (PUB)
+      return grid_barrier_published(w, G, groups, spin_limit, gen);
+    else
+      return grid_barrier(w, G, groups, spin_limit, gen);
+  };
   for (int r = 0; r < rounds; ++r) {
-    if (threadIdx.x == 0) data[blockIdx.x] = (long long)r * G + blockIdx.x;
-    if (!grid_barrier(w, G, groups, spin_limit, gen)) break;
-    for (unsigned i = threadIdx.x; i < G; i += blockDim.x) bad += data[i] != (long long)r * G + i;
-    if (!grid_barrier(w, G, groups, spin_limit, gen)) break;
+    const long long mine = (long long)r * G + blockIdx.x;
+    if (threadIdx.x == 0) {
+      if constexpr (PUB)
+        publish(&data[blockIdx.x], mine);
+      else
+        data[blockIdx.x] = mine;
+    }
+    if (!barrier()) break;
+    for (unsigned i = threadIdx.x; i < G; i += blockDim.x) {
+      const long long v = PUB ? load_published(&data[i]) : data[i];
+      bad += v != (long long)r * G + i;
+    }
+    if (!barrier()) break;
   }
   if (bad) atomicAdd(errors, bad);
 }
@@ -541,8 +567,10 @@ int sync_bench_grid_ex(int n_wg, int wg_size, int groups, int reps, double* ns, 
   return sync_bench_grid_r(n_wg, wg_size, groups, 0, 0, reps, ns, sigma_ns, cycles, stream);
 }
 
-int sync_bench_grid_r(int n_wg, int wg_size, int groups, int64_t r1, int64_t r2, int reps, double* ns,
-                      double* sigma_ns, double* cycles, void* stream) {
+namespace {
+
+int grid_probe(bool pub, int n_wg, int wg_size, int groups, int64_t r1, int64_t r2, int reps, double* ns,
+               double* sigma_ns, double* cycles, void* stream) {
   if (!((r1 == 0 && r2 == 0) || (r1 > r2 && r2 > 0 && r1 <= (1 << 16))))
     return set_error(RED_EINVAL, "repetitions: r1 = r2 = 0, or r1 > r2 > 0 and r1 <= 65536");
   if (wg_size < 64 || wg_size > 1024 || wg_size % 64) return set_error(RED_EINVAL, "bad wg_size %d", wg_size);
@@ -554,7 +582,8 @@ int sync_bench_grid_r(int n_wg, int wg_size, int groups, int64_t r1, int64_t r2,
   Workspace* ws;
   int rc = probe_prologue(s, &dev, &ws);
   if (rc) return rc;
-  const void* fn = reinterpret_cast<const void*>(&k_grid_chain);
+  const void* fn = pub ? reinterpret_cast<const void*>(&k_grid_chain<true>)
+                       : reinterpret_cast<const void*>(&k_grid_chain<false>);
   int maxg = 0;
   if ((rc = coresident(fn, wg_size, *dev, &maxg))) return rc;
   if (n_wg > maxg)
@@ -586,6 +615,18 @@ int sync_bench_grid_r(int n_wg, int wg_size, int groups, int64_t r1, int64_t r2,
     return set_error(RED_ETIMEOUT, "grid probe: barrier watchdog fired");
   }
   return RED_OK;
+}
+
+}  // namespace
+
+int sync_bench_grid_r(int n_wg, int wg_size, int groups, int64_t r1, int64_t r2, int reps, double* ns,
+                      double* sigma_ns, double* cycles, void* stream) {
+  return grid_probe(false, n_wg, wg_size, groups, r1, r2, reps, ns, sigma_ns, cycles, stream);
+}
+
+int sync_bench_grid_published(int n_wg, int wg_size, int groups, int64_t r1, int64_t r2, int reps, double* ns,
+                              double* sigma_ns, double* cycles, void* stream) {
+  return grid_probe(true, n_wg, wg_size, groups, r1, r2, reps, ns, sigma_ns, cycles, stream);
 }
 
 int sync_bench_grid(int n_wg, int wg_size, int reps, double* ns, double* sigma_ns, double* cycles,
@@ -826,7 +867,9 @@ int sync_check_grid_order(int n_wg, int wg_size, int64_t* max_before, int64_t* m
   return RED_OK;
 }
 
-int sync_check_grid_visibility(int n_wg, int wg_size, int groups, int rounds, int64_t* errors, void* stream) {
+namespace {
+
+int grid_visibility(bool pub, int n_wg, int wg_size, int groups, int rounds, int64_t* errors, void* stream) {
   if (wg_size < 64 || wg_size > 1024 || wg_size % 64) return set_error(RED_EINVAL, "bad wg_size %d", wg_size);
   if (n_wg < 1 || n_wg > RED_MAX_GRID) return set_error(RED_EINVAL, "bad n_wg %d", n_wg);
   if (groups < -2 || groups > kMaxBarrierGroups) return set_error(RED_EINVAL, "bad groups %d", groups);
@@ -837,7 +880,8 @@ int sync_check_grid_visibility(int n_wg, int wg_size, int groups, int rounds, in
   Workspace* ws;
   int rc = probe_prologue(s, &dev, &ws);
   if (rc) return rc;
-  const void* fn = reinterpret_cast<const void*>(&k_grid_visibility);
+  const void* fn = pub ? reinterpret_cast<const void*>(&k_grid_visibility<true>)
+                       : reinterpret_cast<const void*>(&k_grid_visibility<false>);
   int maxg = 0;
   if ((rc = coresident(fn, wg_size, *dev, &maxg))) return rc;
   if (n_wg > maxg) return set_error(RED_EINVAL, "visibility check: grid too large (max %d)", maxg);
@@ -863,6 +907,17 @@ int sync_check_grid_visibility(int n_wg, int wg_size, int groups, int rounds, in
   }
   *errors = (int64_t)h;
   return RED_OK;
+}
+
+}  // namespace
+
+int sync_check_grid_visibility(int n_wg, int wg_size, int groups, int rounds, int64_t* errors, void* stream) {
+  return grid_visibility(false, n_wg, wg_size, groups, rounds, errors, stream);
+}
+
+int sync_check_grid_visibility_published(int n_wg, int wg_size, int groups, int rounds, int64_t* errors,
+                                         void* stream) {
+  return grid_visibility(true, n_wg, wg_size, groups, rounds, errors, stream);
 }
 
 int sync_check_watchdog(int n_wg, int wg_size, int skip_wg, int spin_limit, void* stream) {

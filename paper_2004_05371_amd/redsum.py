@@ -51,7 +51,7 @@ EXPORTS = [
     "red_kernel_timer", "red_kernel_timer_read", "sync_bench_wave", "sync_bench_wave_ex", "sync_bench_block",
     "sync_bench_grid", "sync_bench_grid_ex", "sync_bench_grid_r", "sync_bench_relaunch",
     "sync_bench_relaunch_ex", "sync_bench_spin", "sync_bench_block_tput", "sync_check_wave", "sync_check_grid_order",
-    "sync_check_grid_visibility",
+    "sync_check_grid_visibility", "sync_bench_grid_published", "sync_check_grid_visibility_published",
     "sync_check_watchdog", "sync_xcc_map", "red_max_coresident", "red_max_coresident_segmented",
     "red_device_info",
     "red_bw_proxy", "red_bw_proxy_ex", "red_eq6_overhead", "red_eq7_latency", "red_eq8_sigma", "stencil_jacobi_1d",
@@ -120,6 +120,8 @@ _SIGS = {
     "sync_check_wave": ([_i32, _i32, _vp, _vp, _vp], _i32),
     "sync_check_grid_order": ([_i32, _i32, _i64p, _i64p, _vp], _i32),
     "sync_check_grid_visibility": ([_i32, _i32, _i32, _i32, _i64p, _vp], _i32),
+    "sync_bench_grid_published": ([_i32, _i32, _i32, _i64, _i64, _i32, _dp, _dp, _dp, _vp], _i32),
+    "sync_check_grid_visibility_published": ([_i32, _i32, _i32, _i32, _i64p, _vp], _i32),
     "sync_check_watchdog": ([_i32, _i32, _i32, _i32, _vp], _i32),
     "red_max_coresident": ([_i32, _i32p], _i32),
     "red_max_coresident_segmented": ([_i32, _i32, _i32p], _i32),
@@ -342,6 +344,13 @@ def sync_bench_grid_r(n_wg: int, wg_size: int, groups: int, r1: int, r2: int, re
     return _probe3("sync_bench_grid_r", n_wg, wg_size, groups, r1, r2, reps, stream=stream)
 
 
+def sync_bench_grid_published(n_wg: int, wg_size: int = 256, groups: int = 0, r1: int = 0, r2: int = 0,
+                              reps: int = 20, stream: int = 0):
+    """Grid barrier for data published by device-scope atomics (no L2
+    write-back or invalidation); r1 = r2 = 0 calibrates."""
+    return _probe3("sync_bench_grid_published", n_wg, wg_size, groups, r1, r2, reps, stream=stream)
+
+
 LAUNCH_ORDINARY, LAUNCH_COOPERATIVE, LAUNCH_GRAPH = 0, 1, 2
 
 
@@ -397,6 +406,15 @@ def sync_check_grid_visibility(n_wg: int, wg_size: int = 256, groups: int = 0, r
     e = ctypes.c_int64()
     _check(load().sync_check_grid_visibility(n_wg, wg_size, groups, rounds, ctypes.byref(e), stream),
            "sync_check_grid_visibility")
+    return e.value
+
+
+def sync_check_grid_visibility_published(n_wg: int, wg_size: int = 256, groups: int = 0, rounds: int = 50,
+                                         stream: int = 0) -> int:
+    """As sync_check_grid_visibility, with device-scope atomic stores and loads."""
+    e = ctypes.c_int64()
+    _check(load().sync_check_grid_visibility_published(n_wg, wg_size, groups, rounds, ctypes.byref(e), stream),
+           "sync_check_grid_visibility_published")
     return e.value
 
 

@@ -96,6 +96,9 @@ def test_validation_before_hip(lib):
     assert lib.sync_check_grid_visibility(0, 256, 0, 10, ctypes.byref(e), None) == R.RED_EINVAL
     assert lib.sync_check_grid_visibility(4, 256, -3, 10, ctypes.byref(e), None) == R.RED_EINVAL
     assert lib.sync_check_grid_visibility(4, 256, 0, 0, ctypes.byref(e), None) == R.RED_EINVAL
+    assert lib.sync_check_grid_visibility_published(0, 256, 0, 10, ctypes.byref(e), None) == R.RED_EINVAL
+    assert lib.sync_check_grid_visibility_published(4, 256, 33, 10, ctypes.byref(e), None) == R.RED_EINVAL
+    assert lib.sync_check_grid_visibility_published(4, 100, 0, 10, ctypes.byref(e), None) == R.RED_EINVAL
     p = R.Plan(R.RED_VARIANT_PERSISTENT, 256, 16, 0, 0)
     assert lib.red_set_plan(R.RED_F32, 0, 100, ctypes.byref(p)) == R.RED_EINVAL
     # the no-allocation entry point: its grid limit, before any HIP call
@@ -109,6 +112,9 @@ def test_validation_before_hip(lib):
     assert lib.sync_bench_grid_r(8, 256, 0, 16, 16, 5, dd, dd, None, None) == R.RED_EINVAL  # r1 == r2
     assert lib.sync_bench_grid_r(8, 256, 0, 0, 5, 5, dd, dd, None, None) == R.RED_EINVAL
     assert lib.sync_bench_grid_r(8, 256, 0, 1 << 20, 5, 5, dd, dd, None, None) == R.RED_EINVAL
+    assert lib.sync_bench_grid_published(8, 256, 0, 16, 16, 5, dd, dd, None, None) == R.RED_EINVAL
+    assert lib.sync_bench_grid_published(8, 256, -3, 0, 0, 5, dd, dd, None, None) == R.RED_EINVAL
+    assert lib.sync_bench_grid_published(0, 256, 0, 0, 0, 5, dd, dd, None, None) == R.RED_EINVAL
     assert lib.sync_bench_relaunch_ex(8, 64, 0, 4, 4, 0, 10, dd, dd, None, None) == R.RED_EINVAL  # i == j
     assert lib.sync_bench_relaunch_ex(8, 64, 0, 65, 1, 0, 10, dd, dd, None, None) == R.RED_EINVAL
     assert lib.sync_bench_relaunch_ex(8, 64, 0, 8, 1, -1, 10, dd, dd, None, None) == R.RED_EINVAL

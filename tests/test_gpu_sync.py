@@ -46,6 +46,34 @@ def test_grid_barrier_visibility(lib, n_wg, groups):
     assert lib.sync_check_grid_visibility(n, 256, groups, rounds=200) == 0
 
 
+@pytest.mark.parametrize("groups", [1, 0, 8, -1, -2])
+@pytest.mark.parametrize("n_wg", [2, 64, 256, 512, 1024])
+def test_published_grid_barrier_visibility(lib, n_wg, groups):
+    """The barrier for published data (no L2 write-back at arrival, no
+    invalidation after the wait): values stored with device-scope atomic
+    stores before it are seen by device-scope atomic loads of every
+    workgroup after it, round after round on the same addresses, for every
+    shape (the XCD placement, -2's skewed keys included, does not matter)."""
+    n = min(n_wg, lib.red_max_coresident(256))
+    say("published visibility", n, "workgroups, groups", groups)
+    assert lib.sync_check_grid_visibility_published(n, 256, groups, rounds=200) == 0
+
+
+@pytest.mark.parametrize("n_wg,groups", [(256, 0), (512, 0), (512, -1), (1024, -1)])
+def test_published_grid_barrier_is_cheaper(lib, n_wg, groups):
+    """Without the L2 write-backs and invalidations the barrier costs less
+    than the fenced one of the same shape, and its latency does not depend
+    on the repetition counts of Eq. 7 (two pairs within 10 %)."""
+    n = min(n_wg, lib.red_max_coresident(256))
+    pa, _, _ = lib.sync_bench_grid_published(n, 256, groups, 512, 64, reps=10)
+    pb, _, _ = lib.sync_bench_grid_published(n, 256, groups, 192, 16, reps=10)
+    f, _, _ = lib.sync_bench_grid_r(n, 256, groups, 512, 64, reps=10)
+    say("grid %d WGs groups %d: published %.1f / %.1f ns, fenced %.1f ns" % (n, groups, pa, pb, f))
+    assert 0 < pa < f and 0 < pb < f
+    assert abs(pa - pb) <= 0.1 * max(pa, pb), (pa, pb)
+    assert lib.red_check_error(lib.current_stream()) == lib.RED_OK
+
+
 @pytest.mark.parametrize("flags", [0, 1])
 def test_bw_proxy_runs(lib, flags):
     """The read-only bandwidth proxy, with ordinary and nontemporal loads,
