@@ -150,19 +150,21 @@ __global__ __launch_bounds__(1024) void k_jacobi_persistent(StencilArgs a) {
       // Publish the first and last k values of the block (time `step`) to
       // the buffer of this barrier's parity, meet, read the neighbours'.
       // The first publication goes to scratch: u is still being read for
-      // the initial halos.
+      // the initial halos.  The edges cross the barrier as device-scope
+      // atomic stores and loads, so the barrier neither writes back nor
+      // invalidates an L2.
       float* pub = (sync & 1) ? a.u : a.scratch;
       const int w = std::min(k, blen);
       for (int j = tid; j < w; j += bs) {
-        pub[lo + j] = win[k + j];
-        pub[hi - 1 - j] = win[k + blen - 1 - j];
+        publish(&pub[lo + j], win[k + j]);
+        publish(&pub[hi - 1 - j], win[k + blen - 1 - j]);
       }
-      grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit, gen);
+      grid_barrier_published(a.words, gridDim.x, a.bar_groups, a.spin_limit, gen);
       for (int j = tid; j < k; j += bs) {
         const int64_t el = lo - k + j;  // left halo: the left neighbour's last k values
-        if (el >= 0) win[j] = pub[el];
+        if (el >= 0) win[j] = load_published(&pub[el]);
         const int64_t er = hi + j;      // right halo: the right neighbour's first k values
-        if (er < n) win[k + blen + j] = pub[er];
+        if (er < n) win[k + blen + j] = load_published(&pub[er]);
       }
       __syncthreads();
       ++sync;
@@ -170,8 +172,9 @@ __global__ __launch_bounds__(1024) void k_jacobi_persistent(StencilArgs a) {
   }
   // Neighbours read u for their initial halos and, at odd exchanges, as the
   // publication buffer: the block is written back only once every
-  // workgroup is past its last read of u.
-  grid_barrier(a.words, gridDim.x, a.bar_groups, a.spin_limit, gen);
+  // workgroup is past its last read of u (each workgroup's loads complete
+  // before it arrives; no data crosses this barrier).
+  grid_barrier_published(a.words, gridDim.x, a.bar_groups, a.spin_limit, gen);
   for (int j = tid; j < blen; j += bs) a.u[lo + j] = win[k + j];
 }
 
