@@ -438,6 +438,40 @@ __device__ __forceinline__ unsigned relaxed_add(unsigned* p, unsigned v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Relaxed device-scope increment that wraps: returns the old value and
+// stores old + 1, or 0 when old >= last (the last of last + 1 arrivals
+// leaves the counter at zero in the same atomic).
+__device__ __forceinline__ unsigned wrap_inc(unsigned* p, unsigned last) {
+  return __builtin_amdgcn_atomic_inc32(p, last, __ATOMIC_RELAXED, "agent");
+}
+
+// Publication by device-scope atomic stores.  A relaxed agent-scope atomic
+// store is coherent across the XCDs (the store carries device scope, so it
+// is written through this XCD's L2), so a value published this way needs no
+// L2 write-back (buffer_wbl2) before the arrival that announces it: it only
+// has to be complete, which a wait on the store counter ensures.  What the
+// reader loads after its acquire is then the published value.  Only for
+// data that every writer publishes this way.
+template <class T>
+__device__ __forceinline__ void publish(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Loads a value stored with publish() by another workgroup (device scope:
+// no stale copy in this XCD's L2 is returned).
+template <class T>
+__device__ __forceinline__ T load_published(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Waits until every store of this wave (published values included) is
+// complete; no compiler reordering of memory accesses across it.
+__device__ __forceinline__ void drain_stores() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // ---------------------------------------------------------------------------
 // XCD-aggregated publication over an arrival tree.
 //
@@ -543,40 +577,17 @@ __device__ __forceinline__ bool xcd_tree_arrive(BarrierWords* w, Line& top, unsi
     if (!u) key = kTreeBad;
   }
   // The class is complete: one write-back of this XCD's L2 publishes the
-  // stores of every member that ran here.
-  if constexpr (RELEASE) __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+  // stores of every member that ran here.  Either way the resets of the
+  // lines below complete before the arrival above (a barrier reuses them).
+  if constexpr (RELEASE)
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+  else
+    drain_stores();
   const unsigned off = key == kTreeBad ? kTreeBad : (key + nxcc - r) % nxcc;
   const unsigned active = nblocks < nxcc ? nblocks : nxcc;
   if (!tally_arrive(top, off, active, &u)) return false;
   *ok = u;
   return true;
-}
-
-// Publication by device-scope atomic stores.  A relaxed agent-scope atomic
-// store is coherent across the XCDs (the store carries device scope, so it
-// is written through this XCD's L2), so a value published this way needs no
-// L2 write-back (buffer_wbl2) before the arrival that announces it: it only
-// has to be complete, which a wait on the store counter ensures.  What the
-// reader loads after its acquire is then the published value.  Only for
-// data that every writer publishes this way.
-template <class T>
-__device__ __forceinline__ void publish(T* p, T v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Loads a value stored with publish() by another workgroup (device scope:
-// no stale copy in this XCD's L2 is returned).
-template <class T>
-__device__ __forceinline__ T load_published(const T* p) {
-  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Waits until every store of this wave (published values included) is
-// complete; no compiler reordering of memory accesses across it.
-__device__ __forceinline__ void drain_stores() {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_waitcnt(0);
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 // ---------------------------------------------------------------------------
@@ -597,8 +608,10 @@ __device__ __forceinline__ void drain_stores() {
 //            waits for all acknowledgements (bounded like every wait here).
 // Thread 0 of each workgroup keeps the generation in `gen` (read once per
 // launch with grid_barrier_gen, then advanced by each barrier, so no
-// barrier waits for a load of it before arriving); the last top-level
-// arrival resets the counter, acquires, releases and bumps the generation;
+// barrier waits for a load of it before arriving); the counters of the
+// flat and two-level shapes wrap to zero on their last arrival (the XCD
+// tree's tallies are reset by theirs); the last top-level arrival
+// acquires, releases and bumps the generation;
 // the others poll it with relaxed device-scope loads (s_sleep between
 // polls, so polling neither invalidates the L2 nor floods the atomic unit)
 // and acquire once after the wait.  Each hop is a release / relaxed RMW /
@@ -653,16 +666,17 @@ __device__ __forceinline__ int grid_barrier_thread0(BarrierWords* w, unsigned nb
     last = xcd_tree_arrive<FENCED>(w, w->count, nblocks, groups, &ok);
   } else {
     if constexpr (FENCED) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // Counters wrap to zero on their last arrival (atomic increment with a
+    // limit), so no reset store has to complete before the next barrier.
     if (groups <= 1) {
-      last = relaxed_add(&w->count.v, 1u) == nblocks - 1;
+      last = wrap_inc(&w->count.v, nblocks - 1) == nblocks - 1;
     } else {
       const unsigned grp = blockIdx.x % groups;
       const unsigned members = (nblocks - grp + groups - 1) / groups;
       const unsigned active = nblocks < groups ? nblocks : groups;
-      if (relaxed_add(&w->group[grp].v, 1u) == members - 1) {
-        __hip_atomic_store(&w->group[grp].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (wrap_inc(&w->group[grp].v, members - 1) == members - 1) {
         if constexpr (FENCED) __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-        last = relaxed_add(&w->count.v, 1u) == active - 1;
+        last = wrap_inc(&w->count.v, active - 1) == active - 1;
       }
     }
   }
@@ -671,7 +685,6 @@ __device__ __forceinline__ int grid_barrier_thread0(BarrierWords* w, unsigned nb
   // their acknowledgements.
   const bool fallback = FENCED && last && !ok && nblocks > 1;
   if (ONE_SIDED && !last && !waiter) return 0;
-  if (last) __hip_atomic_store(&w->count.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (fallback) __hip_atomic_store(&w->gen.pad[0], g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (!last || fallback) {
     unsigned spins = 0;
@@ -707,8 +720,8 @@ __device__ __forceinline__ int grid_barrier_thread0(BarrierWords* w, unsigned nb
     if (fallback) __hip_atomic_store(&w->fb.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   if (last) {
-    // Published data: nothing to pass on; the counter's reset completes
-    // first.
+    // Published data: nothing to pass on; the XCD tree's line resets
+    // complete first.
     if constexpr (FENCED)
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
     else
