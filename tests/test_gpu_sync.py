@@ -74,6 +74,19 @@ def test_published_grid_barrier_is_cheaper(lib, n_wg, groups):
     assert lib.red_check_error(lib.current_stream()) == lib.RED_OK
 
 
+@pytest.mark.parametrize("groups", [1, 0, -1])
+def test_published_grid_barrier_chain_stress(lib, groups):
+    """16,384 published-data grid barriers back to back in one kernel over
+    1024 workgroups (every counter wraps to zero in its last arrival's own
+    atomic and is counted on again at once by the next barrier): no
+    watchdog fires and no counter is left over."""
+    n = min(1024, lib.red_max_coresident(256))
+    ns, sigma, wall = lib.sync_bench_grid_published(n, 256, groups, 16384, 1024, reps=3)
+    say("published chain %d WGs groups %d: %.1f ns" % (n, groups, ns))
+    assert 0 < ns < 1e5
+    assert lib.red_check_error(lib.current_stream()) == lib.RED_OK
+
+
 @pytest.mark.parametrize("flags", [0, 1])
 def test_bw_proxy_runs(lib, flags):
     """The read-only bandwidth proxy, with ordinary and nontemporal loads,
