@@ -421,18 +421,14 @@ struct BarrierWords {
   Line gen;     // grid-barrier generation (v, incremented by the last
                 // arrival); pad[0]: the generation whose fall-back release
                 // the last arrival requests (XCD tree)
-  Line ticket;  // atomic-final variant: workgroups that have stored a partial
+  Line ticket;  // atomic-final variant: groups (or workgroups) done, or the XCD tree's top
   Line err;     // watchdog flag (nonzero after a timeout)
-  Line acc_lo;  // atomic-final int accumulator (int64 in acc_lo.v/acc_lo.pad[0])
-  Line group[kMaxBarrierGroups];  // arrivals per group (two-level barrier)
+  Line group[kMaxBarrierGroups];  // arrivals per group (two-level barrier and ticket)
   Line cls[kMaxTreeClasses];      // XCD tree, second level: node completions per class
   Line node[kMaxTreeNodes];       // XCD tree, first level: arrivals per node
   Line fb;                        // XCD tree: fall-back releases done (v)
 };
 
-__device__ __forceinline__ long long* acc_i64(BarrierWords* w) {
-  return reinterpret_cast<long long*>(&w->acc_lo.v);
-}
 
 __device__ __forceinline__ unsigned relaxed_add(unsigned* p, unsigned v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

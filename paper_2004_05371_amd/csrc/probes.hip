@@ -232,7 +232,6 @@ __global__ void k_reset_words(BarrierWords* w) {
     *tally_word(w->gen) = 0;  // generation and fall-back request
     *tally_word(w->ticket) = 0;
     w->err.v = 0;
-    *acc_i64(w) = 0;
     w->fb.v = 0;
   }
   for (int i = threadIdx.x; i < kMaxBarrierGroups; i += blockDim.x) *tally_word(w->group[i]) = 0;

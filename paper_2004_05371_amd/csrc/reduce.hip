@@ -179,13 +179,14 @@ __global__ __launch_bounds__(64) void k_final_wave(const Part* partials, int cou
 
 // ---------------------------------------------------------------------------
 // Variant 2, one kernel with an atomic ticket: each workgroup publishes its
-// partial with a device-scope atomic (int: an int64 add into one word;
-// float: a store to its partial slot), waits for it to complete, then takes
-// a ticket with a relaxed atomic; the workgroup that draws the last ticket
-// acquires, does the final combine and resets the ticket (and the int
-// accumulator) for the next launch.  The partials being atomics, no
-// workgroup writes back its L2.  Under RED_FLAG_XCD the tickets are counted
-// on the XCD arrival tree instead of one counter.
+// partial (int64 or binary64) to its slot with a device-scope atomic store,
+// waits for it to complete, then takes a ticket; the workgroup that draws
+// the last ticket acquires and does the ordered final combine.  The
+// partials being atomics, no workgroup writes back its L2.  The ticket is
+// two-level (one line per group of blockIdx % g, then the ticket line),
+// every line wrapping to zero on its last arrival, so the tail of a launch
+// does not queue all of its workgroups on one line; under RED_FLAG_XCD the
+// XCD arrival tree counts instead.
 // ---------------------------------------------------------------------------
 template <class M, int IPT, bool NT, bool PIPE>
 __global__ __launch_bounds__(1024) void k_atomic(ReduceArgs a) {
@@ -194,10 +195,7 @@ __global__ __launch_bounds__(1024) void k_atomic(ReduceArgs a) {
   Part p = workgroup_partial<M, IPT, NT, PIPE>(a);
   BarrierWords* w = a.words;
   if (threadIdx.x == 0) {
-    if constexpr (__is_same(Part, long long))
-      __hip_atomic_fetch_add(acc_i64(w), p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else
-      publish(static_cast<Part*>(a.partials) + blockIdx.x, p);
+    publish(static_cast<Part*>(a.partials) + blockIdx.x, p);
     // The partial is complete before the ticket: only the last workgroup
     // pays a fence (its acquire).
     drain_stores();
@@ -209,7 +207,17 @@ __global__ __launch_bounds__(1024) void k_atomic(ReduceArgs a) {
       bool ok = true;
       last = xcd_tree_arrive<false>(w, w->ticket, gridDim.x, kBarrierXcd | a.xcd_nxcc, &ok);
     } else {
-      last = relaxed_add(&w->ticket.v, 1u) == gridDim.x - 1;
+      // Two-level ticket: the workgroups with equal blockIdx % g count on
+      // one line per group, the last of each group on the ticket line;
+      // every line wraps to zero on its last arrival.
+      const unsigned G = gridDim.x;
+      const unsigned g = default_barrier_groups(G);
+      const unsigned grp = blockIdx.x % g;
+      const unsigned members = (G - grp + g - 1) / g;
+      const unsigned active = G < g ? G : g;
+      last = false;
+      if (g <= 1 || wrap_inc(&w->group[grp].v, members - 1) == members - 1)
+        last = wrap_inc(&w->ticket.v, (g <= 1 ? G : active) - 1) == (g <= 1 ? G : active) - 1;
     }
     is_last = last;
   }
@@ -217,20 +225,8 @@ __global__ __launch_bounds__(1024) void k_atomic(ReduceArgs a) {
   if (!is_last) return;
   // Last workgroup: every thread acquires before reading the others' data.
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  if constexpr (__is_same(Part, long long)) {
-    if (threadIdx.x == 0) {
-      long long s = __hip_atomic_load(acc_i64(w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      *static_cast<Part*>(a.out) = s;
-      __hip_atomic_store(acc_i64(w), 0LL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&w->ticket.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  } else {
-    Part s = combine_partials<Part>(static_cast<const Part*>(a.partials), gridDim.x);
-    if (threadIdx.x == 0) {
-      *static_cast<Part*>(a.out) = s;
-      __hip_atomic_store(&w->ticket.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
+  Part s = combine_partials<Part>(static_cast<const Part*>(a.partials), gridDim.x);
+  if (threadIdx.x == 0) *static_cast<Part*>(a.out) = s;
 }
 
 // ---------------------------------------------------------------------------

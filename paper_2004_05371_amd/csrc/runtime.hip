@@ -527,8 +527,7 @@ int red_check_error(void* stream) {
   const unsigned err = hw.err.v;
   // Every completed launch leaves its arrival counters at zero; a counter
   // left over means some workgroups never completed an arrival.
-  bool stale = hw.count.v || hw.count.pad[0] || hw.ticket.v || hw.ticket.pad[0] || hw.acc_lo.v ||
-               hw.acc_lo.pad[0] || hw.fb.v;
+  bool stale = hw.count.v || hw.count.pad[0] || hw.ticket.v || hw.ticket.pad[0] || hw.fb.v;
   for (const Line& g : hw.group) stale = stale || g.v || g.pad[0];
   for (const Line& g : hw.cls) stale = stale || g.v || g.pad[0];
   for (const Line& g : hw.node) stale = stale || g.v || g.pad[0];
