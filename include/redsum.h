@@ -354,7 +354,10 @@ int red_get_plan(int dtype, int acc, int64_t n, red_plan *plan);
 /* Time candidate plans on the caller's data (x, n; out is overwritten) and
  * install the fastest for the (dtype, acc, n) bucket; writes it to *best and
  * its median time in microseconds to *best_us (either may be NULL).
- * Synchronous.  `budget` bounds the number of candidates timed (0 = all). */
+ * Synchronous.  `budget` bounds the number of candidates timed (0 = all,
+ * followed by finals: the best shape under the relaunch, atomic-ticket and
+ * persistent plain-launch variants, timed again in 5 interleaved rounds,
+ * the lowest median winning). */
 int red_autotune(int dtype, int acc, const void *x, int64_t n, void *out, void *stream, int budget,
                  red_plan *best, double *best_us);
 
