@@ -946,16 +946,17 @@ const SegTable& seg_table() {
 // published by device-scope atomic stores it is one kernel and 1 to 4 %
 // faster than the relaunch fix-up's two (768-value segments, every slice
 // boundary a cut: 188 against 196 us; with a release fence per cut piece
-// it had taken 405 us); two 512-thread workgroups per CU, the most the
-// reduce-by-key form keeps resident; 4 loads of 16 bytes per thread per
-// tile.
+// it had taken 405 us).  Four 256-thread workgroups per CU: 16 wavefronts,
+// the most the reduce-by-key form keeps resident, which beat two 512-thread
+// workgroups by up to 8 % on 16-value segments and 2 to 4 % at 512 values
+// and on the drawn batch; 4 loads of 16 bytes per thread per tile.
 red_plan default_seg_plan(int64_t nseg, const DeviceInfo& dev) {
   (void)nseg;
   red_plan p;
   p.variant = RED_VARIANT_ATOMIC;
-  p.wg = 512;
+  p.wg = 256;
   p.ipt = 4;
-  p.grid = 2 * dev.cus;
+  p.grid = 4 * dev.cus;
   p.flags = RED_FLAG_NONTEMPORAL;
   return p;
 }

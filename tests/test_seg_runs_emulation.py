@@ -68,10 +68,12 @@ def test_small_geometries(emu, case):
 
 # The fault's geometry (2^28 values, 512-thread workgroups, grid 512) for
 # every short length up to 8, both load counts, plus drawn lengths with
-# empty segments and misaligned bases.
+# empty segments and misaligned bases; and the default plan's geometry.
 FULL = [(1 << 28, L, 0, 512, 512, ipt, 0) for L in (3, 4, 5) for ipt in (4, 2)]
 FULL += [(1 << 28, L, 0, 512, 512, 4, 0) for L in (6, 7, 8)]
 FULL += [(1 << 28, 4, 1, 512, 512, 4, 1), (1 << 28, 3, 1, 512, 512, 2, 3), ((1 << 28) - 5, 5, 0, 512, 512, 4, 2)]
+# the default plan's geometry: 256-thread workgroups, four per CU (grid 1024)
+FULL += [(1 << 28, L, 0, 1024, 256, 4, 0) for L in (3, 4, 5, 8)] + [(1 << 28, 4, 1, 1024, 256, 4, 2)]
 
 
 def test_fault_geometry_is_free_of_out_of_bounds_accesses(emu):
