@@ -68,6 +68,9 @@ int main() {
   CHECK(sync_bench_wave(9, 64, 10, &d, &e, nullptr, nullptr) == RED_EINVAL);
   CHECK(sync_bench_grid(0, 256, 10, &d, &e, nullptr, nullptr) == RED_EINVAL);
   CHECK(sync_bench_grid_r(8, 256, 0, 16, 16, 5, &d, &e, nullptr, nullptr) == RED_EINVAL);
+  CHECK(sync_bench_grid_published(8, 256, -3, 0, 0, 5, &d, &e, nullptr, nullptr) == RED_EINVAL);
+  int64_t nerr = 0;
+  CHECK(sync_check_grid_visibility_published(0, 256, 0, 10, &nerr, nullptr) == RED_EINVAL);
   CHECK(sync_bench_relaunch_ex(8, 64, 0, 4, 4, 0, 10, &d, &e, nullptr, nullptr) == RED_EINVAL);
   CHECK(sync_bench_spin(0, 8, 1, 10, &d, &e, nullptr) == RED_EINVAL);
   double wbuf[64];
