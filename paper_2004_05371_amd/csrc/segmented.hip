@@ -11,7 +11,8 @@
 //   * a slice finds its first segment by binary search in the offsets
 //     (read through the scalar cache), then streams its values as one
 //     sequence of tiles of 16-byte vectors (the next tile in flight while
-//     the current one is added into fp32 TwoSum-compensated accumulators);
+//     the current one is added into fp32 TwoSum-compensated accumulators,
+//     or, in the reduce-by-key form, into binary64 per-lane runs);
 //   * the segments are finished in one of three forms, chosen on the device
 //     from the mean segment length: a piece that ends in a tile is finished
 //     by a wavefront combine per wave, completed in batches of 64 pieces
@@ -22,10 +23,12 @@
 //   * a segment that lies inside the slice is written directly (binary64);
 //     a piece of a segment that crosses a slice boundary goes to a carry
 //     slot, and the pieces of that segment are summed in slice order in
-//     binary64 by one wavefront: in a second kernel after the launch
-//     boundary (relaunch fix-up), by the wavefront that publishes the last
-//     piece (atomic ticket per owning slice), or by the owning slice after a
-//     grid barrier (co-resident grid).
+//     binary64 by one wavefront: by the wavefront that publishes the last
+//     piece (atomic ticket per owning slice, the default), in a second
+//     kernel after the launch boundary (relaunch fix-up), or by the owning
+//     slice after a grid barrier (co-resident grid); within one launch the
+//     pieces are published with device-scope atomic stores, so neither the
+//     ticket nor the barrier needs an L2 write-back or invalidation.
 //
 // Workgroup slices keep few concurrent streams (better DRAM locality) and
 // suit long segments; wavefront slices let every wave walk its own pieces
