@@ -18,9 +18,11 @@
 //                 LDS with a halo of K values on each side.  It runs K steps
 //                 on the shrinking valid range (redundantly recomputing the
 //                 halo, so neighbours need no exchange inside the K steps),
-//                 then publishes its first and last K values, meets the
-//                 other workgroups at a grid barrier and reads its
-//                 neighbours' values into its halo.  One barrier per K steps;
+//                 then publishes its first and last K values (device-scope
+//                 atomic stores), meets the other workgroups at a grid
+//                 barrier that neither writes back nor invalidates an L2,
+//                 and reads its neighbours' values into its halo (device-
+//                 scope atomic loads).  One barrier per K steps;
 //                 HBM is touched only at the start, at the end and for the
 //                 2 K boundary values per workgroup and barrier.
 #include <algorithm>
