@@ -321,8 +321,10 @@ int red_sum_segmented_loop(const float *x, const int64_t *host_offsets, int64_t 
  *            RED_VARIANT_PERSISTENT  one launch holding the time loop: each
  *                                    workgroup keeps its block and halos in
  *                                    LDS and exchanges boundary values with
- *                                    its neighbours through u / scratch at a
- *                                    grid barrier every steps_per_sync steps;
+ *                                    its neighbours through u / scratch
+ *                                    (device-scope atomic stores and loads)
+ *                                    at a grid barrier every steps_per_sync
+ *                                    steps;
  *            RED_VARIANT_AUTO        persistent when the array fits the
  *                                    co-resident workgroups' LDS, else
  *                                    relaunch.
