@@ -679,16 +679,26 @@ static int time_plan(int dtype, int acc, const red_plan& plan, const void* x, in
   hipEvent_t a, b;
   RED_HIP(hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
   RED_HIP(hipEventCreateWithFlags(&b, hipEventDisableSystemFence));
+  // Samples of k calls back to back between one event pair: the rate of a
+  // stream of calls, as a caller's loop sees it (one call per sample would
+  // time an isolated call's launch from an idle stream, which decides the
+  // ranking of small inputs).  k makes a sample last about 200 us (1 to 32
+  // calls, from the first warm sample's time); the median of 7 samples
+  // after the warm ones, per call.
   std::vector<double> t;
   int rc = RED_OK;
-  for (int i = 0; i < 13 && rc == RED_OK; ++i) {
+  int k = 1;
+  for (int i = 0; i < 10 && rc == RED_OK; ++i) {
     if (hipEventRecord(a, s) != hipSuccess) rc = set_error(RED_EHIP, "hipEventRecord");
-    if (!rc) rc = red_sum_ex(dtype, x, n, out, s, &o);
+    for (int j = 0; j < k && !rc; ++j) rc = red_sum_ex(dtype, x, n, out, s, &o);
     if (!rc && hipEventRecord(b, s) != hipSuccess) rc = set_error(RED_EHIP, "hipEventRecord");
     if (!rc && hipEventSynchronize(b) != hipSuccess) rc = set_error(RED_EHIP, "hipEventSynchronize");
     float ms = 0;
     if (!rc && hipEventElapsedTime(&ms, a, b) != hipSuccess) rc = set_error(RED_EHIP, "hipEventElapsedTime");
-    if (!rc && i >= 3) t.push_back(ms * 1e3);
+    if (rc) break;
+    const double per = ms * 1e3 / k;
+    if (i == 1) k = (int)std::min(32.0, std::max(1.0, 200.0 / std::max(per, 1e-3)));
+    if (i >= 3) t.push_back(per);
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
@@ -779,7 +789,7 @@ int red_autotune_search(int dtype, int64_t n, int cus, int nxcc, int allow_xcd, 
 }
 
 namespace {
-// Cost of a candidate on the GPU: the median of 10 timed calls on the
+// Cost of a candidate on the GPU: the median of 7 timed samples of calls on the
 // caller's data (a persistent candidate's grid capped at co-residency).
 struct GpuCost {
   int dtype, acc;
