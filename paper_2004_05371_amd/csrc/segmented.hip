@@ -351,15 +351,36 @@ __device__ __forceinline__ void seg_wave_slices(const SegArgs& a) {
   }
 }
 
+// f(integral_constant<B>), ..., f(integral_constant<E - 1>); the _while
+// form stops after the first call that returns false.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for_while(F&& f) {
+  if constexpr (B < E) {
+    if (f(std::integral_constant<int, B>{})) static_for_while<B + 1, E>(f);
+  }
+}
+
 // Reduce-by-key form of the wavefront slices, for very short segments.
 //
 // Each tile of 64 x IPT 16-byte vectors (256 IPT contiguous values) is
-// transposed through LDS so that lane l holds the run of RL = 4 IPT
-// consecutive values that starts at value RL l of the tile.  The starts of
-// the segments that follow the open one come from a ring of the offsets
-// held in LDS (kRing entries ahead of the walk, refilled a tile ahead).
-// When fewer than 64 segments start in the tile and no run holds two
-// starts:
+// walked in parts of RS rows (fewer rows when the mean segment is short),
+// and in each part lane l holds the run of RL = 4 RS consecutive values
+// that starts at value RL l of the part.  The tile comes into LDS by
+// direct-to-LDS loads, each lane fetching the vector that the run reads
+// expect at its position, so the loads hold no registers while in flight;
+// a part's rows are loaded for the next tile as soon as the part has been
+// read.  The starts of the segments that follow the open one come from a
+// ring of the offsets held in LDS (kRing entries ahead of the walk,
+// refilled a tile ahead).  When fewer than 64 segments start in a part and
+// no run holds two starts:
 //   * each lane sums its run in binary64, cut at the start it holds (if
 //     any) into a head, the end of the segment open on its left, and a
 //     tail;
@@ -368,13 +389,15 @@ __device__ __forceinline__ void seg_wave_slices(const SegArgs& a) {
 //     the partial of the segment open at its right end;
 //   * a lane that holds a start completes the segment that ends there (its
 //     head plus the scan of the lane on its left): it writes the sum when
-//     the segment began in the tile, and the first start of the tile closes
-//     the segment that was open, which may have begun before the slice and
-//     goes through finish_piece.
-// Other tiles (an empty segment, two starts in one run, 64 starts or more)
-// are finished piece by piece as in seg_wave_slices, the open partial
-// carried in binary64 between the two.
-constexpr int kRing = 384;  // offsets entries held in LDS per wavefront
+//     the segment began in the part, and the first start of the part
+//     closes the segment that was open, which may have begun before the
+//     slice and goes through finish_piece.
+// Other parts (an empty segment, two starts in one run, 64 starts or more)
+// and the rest of their tile are finished piece by piece as in
+// seg_wave_slices, the open partial carried in binary64 between the two.
+constexpr int kRing = 384;        // offsets entries held in LDS per wavefront
+constexpr int kCpolNT = 2;        // the nontemporal bit of a load's cache policy
+constexpr int kWaitLds = 0xC07F;  // s_waitcnt lgkmcnt(0): LDS reads returned, other counters free
 
 struct RunLds {
   v4f tile[kWave * 4];   // one tile of up to 4 rows, swizzled
@@ -412,25 +435,60 @@ __device__ __forceinline__ T lds_get(LdsPtr<T> p, int i) {
   return v;
 }
 
-// Position of vector i of the transposition buffer: within each group of 16
-// vectors the low bits are XOR-ed so that both the row writes (lane l, vector
-// 64 u + l) and the run reads (lane l, vector IPT l + j) of 16 consecutive
-// lanes fall in distinct 16-byte bank groups.
-template <int IPT>
-__device__ __forceinline__ int run_swz(int i) {
-  return i ^ ((i >> 4) & (IPT - 1));
+// The same accesses while a direct-to-LDS load fills another LDS region.
+// The compiler cannot tell the regions apart, so before any LDS access it
+// would wait for every load in flight.  Written as inline assembly, which
+// its wait insertion does not treat as a memory access, each access waits
+// only for itself (lgkmcnt(0) in the same block, so no register is read or
+// reused before the LDS has answered).
+template <class T>
+__device__ __forceinline__ unsigned lds_addr(LdsPtr<T> p, int i) {
+  return (unsigned)(uintptr_t)(p + i);
 }
 
+__device__ __forceinline__ void lds_put_u32_now(LdsPtr<unsigned> p, int i, unsigned v) {
+  asm volatile("ds_write_b32 %0, %1\n\ts_waitcnt lgkmcnt(0)" : : "v"(lds_addr(p, i)), "v"(v) : "memory");
+}
+
+__device__ __forceinline__ unsigned lds_get_u32_now(LdsPtr<unsigned> p, int i) {
+  unsigned v;
+  asm volatile("ds_read_b32 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(v) : "v"(lds_addr(p, i)) : "memory");
+  return v;
+}
+
+__device__ __forceinline__ int64_t lds_get_i64_now(LdsPtr<int64_t> p, int i) {
+  int64_t v;
+  asm volatile("ds_read_b64 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(v) : "v"(lds_addr(p, i)) : "memory");
+  return v;
+}
+
+// Position in the tile buffer of the part's vector i (parts of RS rows):
+// within each group of 16 vectors the low bits are XOR-ed so that the run
+// reads (lane l, vector RS l + j) of 16 consecutive lanes fall in distinct
+// 16-byte bank groups.  The map is its own inverse and keeps each vector in
+// its row, so the load that fills position 64 u + l fetches vector
+// run_swz(64 u + l) and each load instruction still reads one contiguous
+// KB.
+template <int RS>
+__device__ __forceinline__ int run_swz(int i) {
+  return i ^ ((i >> 4) & (RS - 1));
+}
+
+// The values and the wavefront's three LDS regions come in as distinct
+// restrict pointers: the compiler then knows that the ring and slot
+// accesses cannot touch the tile that a direct-to-LDS load is filling, and
+// does not wait for that load before them.
 template <int IPT, bool NT, int FIX>
-__device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all) {
+__device__ static void seg_wave_runs_in(const SegArgs& a, const float* __restrict__ x,
+                                        const LdsPtr<v4f> __restrict__ tile,
+                                                 const LdsPtr<unsigned> __restrict__ slot,
+                                                 const LdsPtr<int64_t> __restrict__ ring) {
   // Barrier fix-up: thread 0 holds the barrier generation of this launch.
   unsigned gen = FIX == kFixBarrier ? grid_barrier_gen(a.words) : 0u;
   static_assert(IPT <= 4, "runs of at most 16 values");
-  using M = ModeF32Comp;
   const int nwaves = blockDim.x / kWave;
   const int lane = __lane_id();
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  RunLds& L = lds_all[wv];
   const int64_t w = (int64_t)blockIdx.x * nwaves + wv;
   const int64_t W = (int64_t)gridDim.x * nwaves;
   const int64_t nseg = a.nseg;
@@ -449,8 +507,8 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
   bool have = seek_segment(a, s, hi, E, end_slice, sa, sb, lane == 0);
   double C = 0.0;  // partial of segment s over [max(sa, lo), current position)
 
-  const int shift = (int)((reinterpret_cast<uintptr_t>(a.x) & 15) >> 2);
-  const v4f* xa = reinterpret_cast<const v4f*>(a.x - shift);
+  const int shift = (int)((reinterpret_cast<uintptr_t>(x) & 15) >> 2);
+  const v4f* xa = reinterpret_cast<const v4f*>(x - shift);
   const int64_t vlo = (lo + shift) >> 2;
   const int64_t vhi = (hi + shift + 3) >> 2;
   constexpr int64_t T = kWave * IPT;
@@ -463,7 +521,6 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
   // many as fit without overwriting entries from s + 1 on.  A (sub-)tile
   // reads entries s + 1 .. s + 64, those that are in the ring.
   auto off_entry = [&](int64_t i) -> int64_t { return i <= nseg ? a.offsets[i] : INT64_MAX; };
-  const LdsPtr<int64_t> ring = lds_ptr(L.ring);
   int64_t fill = 0;
   int npend = 0;
   int64_t pend0 = 0, pend1 = 0, pend2 = 0;
@@ -497,197 +554,189 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
   // 32 values, quarters (4 loads per thread) under 12.
   const int nparts = (IPT >= 4 && E < 12 * nseg) ? 4 : (IPT >= 2 && E < 32 * nseg) ? 2 : 1;
 
-  v4f cur[IPT], nxt[IPT];
-  auto load_tile = [&](v4f* v, int64_t t) {
-    const int64_t v0 = vlo + t * T + lane;
-    if (vlo + (t + 1) * T <= vhi) {
+  // Tiles arrive by direct-to-LDS loads, so no registers are held while a
+  // tile is in flight.  Load instruction u writes lane i's vector at tile
+  // position 64 u + i, and lane i fetches the tile vector that the run
+  // reads expect there (run_swz is its own inverse, and it permutes within
+  // groups of 16 vectors, so each instruction still reads 1 KB in one
+  // piece).  Positions past the slice's last vector fetch that vector
+  // again; the values they hold lie at or past hi and are masked out.
+  const int rows = IPT / nparts;  // rows per part
+  auto issue_rows = [&](int64_t t, int u0, int nrows) {
+    const int64_t vb = vlo + t * T;
 #pragma unroll
-      for (int u = 0; u < IPT; ++u) v[u] = load_vec<NT>(xa + v0 + u * kWave);
-    } else {
-#pragma unroll
-      for (int u = 0; u < IPT; ++u)
-        v[u] = v0 + u * kWave < vhi ? load_vec<NT>(xa + v0 + u * kWave) : v4f{0, 0, 0, 0};
+    for (int u = u0; u < u0 + nrows; ++u) {
+      const int pos = u * kWave + lane;
+      const int64_t g = std::min<int64_t>(vb + (pos ^ ((pos >> 4) & (rows - 1))), vhi - 1);  // run_swz<rows>(pos)
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(xa + g),
+                                       (LdsPtr<void>)(tile + u * kWave), 16, 0,
+                                       NT ? kCpolNT : 0);
     }
   };
 
   int64_t own_fix = -1;
-  if (ntiles > 0) load_tile(cur, 0);
-  for (int64_t t = 0; t < ntiles; ++t) {
-    // Every load has completed here (see seg_wave_slices), so the window
-    // blocks move without a wait.
-    __builtin_amdgcn_s_waitcnt(0);
-    if (have) refill();
-    if (t + 1 < ntiles) load_tile(nxt, t + 1);
-    __builtin_amdgcn_sched_barrier(0);
-    const int64_t e0 = 4 * (vlo + t * T) - shift;
-    const int64_t e1 = 4 * (vlo + (t + 1) * T) - shift;
-
-    // Reduce-by-key walk over rows [Q RS, Q RS + RS) of the tile (values
-    // [f0, f1)); returns false, having changed nothing, when the rows need
-    // the per-piece walk.
-    auto try_runs = [&](auto rs_tag, auto q_tag) -> bool {
-      constexpr int RS = decltype(rs_tag)::value;
-      constexpr int Q = decltype(q_tag)::value;
-      constexpr int RL = 4 * RS;  // values per lane run
-      const int64_t f0 = e0 + (int64_t)kWave * RL * Q;
-      const int64_t f1 = f0 + (int64_t)kWave * RL;
-      // Entries s + 1 .. s + vis are in the ring; a view of fewer than 64
-      // must end past the rows to show every start in them.
-      const int vis = (int)std::min<int64_t>(kWave, fill - (s + 1));
-      if (vis <= 0) return false;
-      const int64_t O = lane < vis ? lds_get(ring, ring_pos(s + 1)) : INT64_MAX;  // start of segment s + 1 + lane
-      const bool valid = O < std::min(f1, hi);
-      const int m = __popcll(__ballot(valid));  // the valid lanes are 0 .. m-1
-      if (m >= vis) return false;
-      const int rel = valid ? (int)(O - f0) : 0;
-      const int r = rel / RL;  // lane whose run holds start `lane`
-      const int rn = __builtin_amdgcn_ds_bpermute(((lane + 1) & (kWave - 1)) << 2, r);
-      const bool clash = valid && lane + 1 < m && rn == r;
-      if (__ballot(clash) != 0) return false;
-      // Start k (lane k) tells lane r_k where it lies.
-      const LdsPtr<unsigned> slot = lds_ptr(L.slot);
-      lds_put(slot, lane, 0u);
-      if (valid) lds_put(slot, r, ((unsigned)(lane + 1) << 16) | (unsigned)rel);
-      const unsigned word = lds_get(slot, lane);
-      // Transpose: row u of the rows in, a run of RL values out.
+  if (ntiles > 0) issue_rows(0, 0, IPT);
+  // The tiles walked in parts of RS rows: part q's values are
+  // [e0 + 256 RS q, e0 + 256 RS (q + 1)), and lane l holds their run
+  // [256 RS q + 4 RS l, + 4 RS) as xr[4 RS q .. 4 RS q + 4 RS).  The loop
+  // over the tiles is instantiated per part size, so that the registers
+  // one layout keeps across the loop are not added to another's.
+  auto walk = [&](auto rs_tag) {
+    constexpr int RS = decltype(rs_tag)::value;
+    constexpr int NP = IPT / RS;
+    constexpr int RL = 4 * RS;  // values per lane run
+    constexpr int64_t P = (int64_t)kWave * RL;
+    for (int64_t t = 0; t < ntiles; ++t) {
+      // Tile t is in LDS and every offsets load has completed here.
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      __builtin_amdgcn_s_waitcnt(0);
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      if (!have) break;  // the slice is finished, and no load is in flight
+      refill();
+      const int64_t e0 = 4 * (vlo + t * T) - shift;
+      const int64_t e1 = 4 * (vlo + (t + 1) * T) - shift;
+      float xr[4 * IPT];
+      // Reads part Q's runs.  Its rows then hold nothing else that is still
+      // to be read, so the same rows of the next tile go in flight: a part
+      // holds only its own runs in registers while it is walked.
+      auto take = [&](auto q_tag) {
+        constexpr int Q = decltype(q_tag)::value;
 #pragma unroll
-      for (int u = 0; u < RS; ++u) L.tile[run_swz<RS>(u * kWave + lane)] = cur[Q * RS + u];
-      __builtin_amdgcn_wave_barrier();
-      float xr[RL];
-#pragma unroll
-      for (int jj = 0; jj < RS; ++jj) {
-        const v4f y = L.tile[run_swz<RS>(lane * RS + jj)];
-        xr[4 * jj] = y.x;
-        xr[4 * jj + 1] = y.y;
-        xr[4 * jj + 2] = y.z;
-        xr[4 * jj + 3] = y.w;
-      }
-      __builtin_amdgcn_wave_barrier();
-      if (f0 < lo || f1 > hi) {  // values outside the slice are not its own
-        const int64_t p = f0 + (int64_t)RL * lane;
-#pragma unroll
-        for (int i = 0; i < RL; ++i) xr[i] = (p + i >= lo && p + i < hi) ? xr[i] : 0.0f;
-      }
-      const bool has = word != 0u;
-      const int b = has ? (int)(word & 0xFFFFu) - RL * lane : RL;  // the start's place in the run
-      // The run's head and tail in binary64: an fp32 value widens exactly,
-      // and each of the at most RL - 1 additions rounds once, at 2^-53.
-      double run = 0.0, head = 0.0;
-#pragma unroll
-      for (int i = 0; i < RL; ++i) {
-        if (i > 0) {
-          const bool at = i == b;
-          head = at ? run : head;
-          run = at ? 0.0 : run;
+        for (int jj = 0; jj < RS; ++jj) {
+          const v4f y = tile[run_swz<RS>(Q * kWave * RS + lane * RS + jj)];
+          xr[Q * RL + 4 * jj] = y.x;
+          xr[Q * RL + 4 * jj + 1] = y.y;
+          xr[Q * RL + 4 * jj + 2] = y.z;
+          xr[Q * RL + 4 * jj + 3] = y.w;
         }
-        run += (double)xr[i];
-      }
-      double v = run;
-      int f = has ? 1 : 0;
-      wave_segscan(v, f);
-      if (!f) v = C + v;  // lanes 0 .. l hold no start: the open segment continues
-      const double left = bpermute_move(v, (lane - 1) & (kWave - 1));
-      const double total = (lane == 0 ? C : left) + head;
-      const int k = (int)(word >> 16) - 1;
-      if (has && k > 0 && k < m) a.out[s + k] = total;  // segment s + k lies in the rows
-      const double c_next = read_lane(v, kWave - 1);
-      if (m > 0) {
-        const int r0 = __builtin_amdgcn_readfirstlane(r);
-        const int64_t o0 = read_lane(O, 0);
-        finish_piece<FIX>(a, s, sa, o0, read_lane(total, r0), lo, hi, w, chunk, &own_fix);
-        sa = read_lane(O, m - 1);
-        sb = read_lane(O, m);
-        s += m;
-      }
-      C = c_next;
-      return true;
-    };
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(kWaitLds);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if (t + 1 < ntiles) issue_rows(t + 1, Q * RS, RS);
+      };
 
-    // Piece by piece, as in seg_wave_slices, over the tile's values from p0
-    // on, with the open partial C.
-    auto pieces_from = [&](int64_t p0) {
-      CompF32 acc[IPT];
+      // Reduce-by-key walk over part Q (values [f0, f1)); returns false,
+      // having changed nothing, when the part needs the per-piece walk.
+      auto try_runs = [&](auto q_tag) -> bool {
+        constexpr int Q = decltype(q_tag)::value;
+        const int64_t f0 = e0 + (int64_t)kWave * RL * Q;
+        const int64_t f1 = f0 + (int64_t)kWave * RL;
+        // Entries s + 1 .. s + vis are in the ring; a view of fewer than 64
+        // must end past the part to show every start in it.
+        const int vis = (int)std::min<int64_t>(kWave, fill - (s + 1));
+        if (vis <= 0) return false;
+        const int64_t O = lane < vis ? lds_get_i64_now(ring, ring_pos(s + 1)) : INT64_MAX;  // start of segment s + 1 + lane
+        const bool valid = O < std::min(f1, hi);
+        const int m = __popcll(__ballot(valid));  // the valid lanes are 0 .. m-1
+        if (m >= vis) return false;
+        const int rel = valid ? (int)(O - f0) : 0;
+        const int r = rel / RL;  // lane whose run holds start `lane`
+        const int rn = __builtin_amdgcn_ds_bpermute(((lane + 1) & (kWave - 1)) << 2, r);
+        const bool clash = valid && lane + 1 < m && rn == r;
+        if (__ballot(clash) != 0) return false;
+        // Start k (lane k) tells lane r_k where it lies.
+        lds_put_u32_now(slot, lane, 0u);
+        if (valid) lds_put_u32_now(slot, r, ((unsigned)(lane + 1) << 16) | (unsigned)rel);
+        const unsigned word = lds_get_u32_now(slot, lane);
+        float xv[RL];
 #pragma unroll
-      for (int u = 0; u < IPT; ++u) acc[u] = M::zero();
-      auto relp = [&](int64_t e) { return (int)std::min(std::max(e - e0, (int64_t)0), 4 * T); };
-      int64_t A = std::max(std::max(sa, lo), p0), B = std::min(sb, hi);
-      while (have && B <= e1) {
-        add_masked<IPT>(acc, cur, kWave, lane, relp(A), relp(B));
-        CompF32 tot = acc[0];
+        for (int i = 0; i < RL; ++i) xv[i] = xr[Q * RL + i];
+        if (f0 < lo || f1 > hi) {  // values outside the slice are not its own
+          const int64_t p = f0 + (int64_t)RL * lane;
 #pragma unroll
-        for (int u = 1; u < IPT; ++u) tot = OpComp::add(tot, acc[u]);
-#pragma unroll
-        for (int u = 0; u < IPT; ++u) acc[u] = M::zero();
-        tot = wave_reduce_dpp<OpComp>(tot);
-        finish_piece<FIX>(a, s, sa, sb, C + comp_to_double(tot), lo, hi, w, chunk, &own_fix);
-        C = 0.0;
-        ++s;
-        have = seek_segment(a, s, hi, E, end_slice, sa, sb, lane == 0);
-        A = std::max(sa, lo);
-        B = std::min(sb, hi);
-      }
-      if (have) {
-        if (A <= e0 && vlo + (t + 1) * T <= vhi) {
-#pragma unroll
-          for (int u = 0; u < IPT; ++u) M::add_vec(acc[u], cur[u]);
-        } else {
-          add_masked<IPT>(acc, cur, kWave, lane, relp(A), relp(B));
+          for (int i = 0; i < RL; ++i) xv[i] = (p + i >= lo && p + i < hi) ? xv[i] : 0.0f;
         }
-        CompF32 tot = acc[0];
+        const bool has = word != 0u;
+        const int b = has ? (int)(word & 0xFFFFu) - RL * lane : RL;  // the start's place in the run
+        // The run's head and tail in binary64: an fp32 value widens exactly,
+        // and each of the at most RL - 1 additions rounds once, at 2^-53.
+        double run = 0.0, head = 0.0;
 #pragma unroll
-        for (int u = 1; u < IPT; ++u) tot = OpComp::add(tot, acc[u]);
-#pragma unroll
-        for (int u = 0; u < IPT; ++u) acc[u] = M::zero();
-        C += comp_to_double(wave_reduce_dpp<OpComp>(tot));
-      }
-    };
+        for (int i = 0; i < RL; ++i) {
+          if (i > 0) {
+            const bool at = i == b;
+            head = at ? run : head;
+            run = at ? 0.0 : run;
+          }
+          run += (double)xv[i];
+        }
+        double v = run;
+        int f = has ? 1 : 0;
+        wave_segscan(v, f);
+        if (!f) v = C + v;  // lanes 0 .. l hold no start: the open segment continues
+        const double left = bpermute_move(v, (lane - 1) & (kWave - 1));
+        const double total = (lane == 0 ? C : left) + head;
+        const int k = (int)(word >> 16) - 1;
+        if (has && k > 0 && k < m) a.out[s + k] = total;  // segment s + k lies in the part
+        const double c_next = read_lane(v, kWave - 1);
+        if (m > 0) {
+          const int r0 = __builtin_amdgcn_readfirstlane(r);
+          const int64_t o0 = read_lane(O, 0);
+          finish_piece<FIX>(a, s, sa, o0, read_lane(total, r0), lo, hi, w, chunk, &own_fix);
+          sa = read_lane(O, m - 1);
+          sb = read_lane(O, m);
+          s += m;
+        }
+        C = c_next;
+        return true;
+      };
 
-    if (have) {
-      using Q0 = std::integral_constant<int, 0>;
-      using Q1 = std::integral_constant<int, 1>;
-      using Q2 = std::integral_constant<int, 2>;
-      using Q3 = std::integral_constant<int, 3>;
-      // Parts of RS rows in order; the first part that cannot take the
-      // reduce-by-key walk, and the rest of the tile, go piece by piece.
-      auto one = [&](auto rs) {
-        if (!try_runs(rs, Q0{})) pieces_from(e0);
+      // Piece by piece, as in seg_wave_slices, over the tile's values from
+      // part Q0 on, with the open partial C: each lane adds its values of a
+      // piece (tile positions [ra, rb)) by compensated fp32 adds, then the
+      // wavefront combine.  Parts Q0 + 1 .. NP - 1 are read first.
+      auto pieces_from = [&](auto q_tag) {
+        constexpr int Q0 = decltype(q_tag)::value;
+        static_for<Q0 + 1, NP>(take);
+        auto relp = [&](int64_t e) { return (int)std::min(std::max(e - e0, (int64_t)0), 4 * T); };
+        auto piece_sum = [&](int ra, int rb) {
+          const unsigned wd = (unsigned)(rb - ra);
+          CompF32 acc = ModeF32Comp::zero();
+#pragma unroll
+          for (int q = Q0; q < NP; ++q) {
+            if (q * kWave * RL >= rb || (q + 1) * kWave * RL <= ra) continue;
+            const unsigned r = (unsigned)(q * kWave * RL + RL * lane - ra);
+#pragma unroll
+            for (int i = 0; i < RL; ++i) ModeF32Comp::add_elem(acc, r + i < wd ? xr[q * RL + i] : 0.0f);
+          }
+          return comp_to_double(wave_reduce_dpp<OpComp>(acc));
+        };
+        int64_t A = std::max(std::max(sa, lo), e0 + Q0 * P), B = std::min(sb, hi);
+        while (have && B <= e1) {
+          finish_piece<FIX>(a, s, sa, sb, C + piece_sum(relp(A), relp(B)), lo, hi, w, chunk, &own_fix);
+          C = 0.0;
+          ++s;
+          have = seek_segment(a, s, hi, E, end_slice, sa, sb, lane == 0);
+          A = std::max(sa, lo);
+          B = std::min(sb, hi);
+        }
+        if (have) C += piece_sum(relp(A), relp(B));
       };
-      auto two = [&](auto rs) {
-        constexpr int64_t P = (int64_t)kWave * 4 * decltype(rs)::value;
-        if (!try_runs(rs, Q0{}))
-          pieces_from(e0);
-        else if (!try_runs(rs, Q1{}))
-          pieces_from(e0 + P);
-      };
-      auto four = [&](auto rs) {
-        constexpr int64_t P = (int64_t)kWave * 4 * decltype(rs)::value;
-        if (!try_runs(rs, Q0{}))
-          pieces_from(e0);
-        else if (!try_runs(rs, Q1{}))
-          pieces_from(e0 + P);
-        else if (!try_runs(rs, Q2{}))
-          pieces_from(e0 + 2 * P);
-        else if (!try_runs(rs, Q3{}))
-          pieces_from(e0 + 3 * P);
-      };
-      if constexpr (IPT == 4) {
-        if (nparts == 4)
-          four(std::integral_constant<int, 1>{});
-        else if (nparts == 2)
-          two(std::integral_constant<int, 2>{});
-        else
-          one(std::integral_constant<int, 4>{});
-      } else if constexpr (IPT == 2) {
-        if (nparts == 2)
-          two(std::integral_constant<int, 1>{});
-        else
-          one(std::integral_constant<int, 2>{});
-      } else {
-        one(std::integral_constant<int, 1>{});
-      }
+
+      // Parts in order; the first part that cannot take the reduce-by-key
+      // walk, and the rest of the tile, go piece by piece.
+      static_for_while<0, NP>([&](auto q_tag) -> bool {
+        take(q_tag);
+        if (try_runs(q_tag)) return true;
+        pieces_from(q_tag);
+        return false;
+      });
     }
-#pragma unroll
-    for (int u = 0; u < IPT; ++u) cur[u] = nxt[u];
+  };
+  if constexpr (IPT == 4) {
+    if (nparts == 4)
+      walk(std::integral_constant<int, 1>{});
+    else if (nparts == 2)
+      walk(std::integral_constant<int, 2>{});
+    else
+      walk(std::integral_constant<int, 4>{});
+  } else if constexpr (IPT == 2) {
+    if (nparts == 2)
+      walk(std::integral_constant<int, 1>{});
+    else
+      walk(std::integral_constant<int, 2>{});
+  } else {
+    walk(std::integral_constant<int, 1>{});
   }
   if (have) {  // the segment open at the slice's end ends at or after hi
     finish_piece<FIX>(a, s, sa, sb, C, lo, hi, w, chunk, &own_fix);
@@ -704,6 +753,12 @@ __device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all)
       if (lane == 0) a.out[own_fix] = v;
     }
   }
+}
+
+template <int IPT, bool NT, int FIX>
+__device__ __forceinline__ void seg_wave_runs(const SegArgs& a, RunLds* lds_all) {
+  RunLds& L = lds_all[__builtin_amdgcn_readfirstlane(threadIdx.x / kWave)];
+  seg_wave_runs_in<IPT, NT, FIX>(a, a.x, lds_ptr(L.tile), lds_ptr(L.slot), lds_ptr(L.ring));
 }
 
 // Workgroup-granular slices (long segments: few streams, little per-piece

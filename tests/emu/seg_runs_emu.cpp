@@ -6,7 +6,8 @@
 // The emulation restates the kernel's steps for one wavefront at a time,
 // with every per-lane value held as an array of 64 and every cross-lane
 // operation (ballot, readlane, ds_bpermute, the DPP row shifts and row
-// broadcasts of the segmented scan, the LDS transposition) written out.  It
+// broadcasts of the segmented scan) written out, and the tile buffer that
+// direct-to-LDS loads fill row by row modelled with the rows in flight.  It
 // checks:
 //   * every global access: the 16-byte vectors of the values (each must
 //     overlap the array), offsets[i] (0 <= i <= nseg), out[s] (s < nseg),
@@ -14,22 +15,27 @@
 //     capacity), and readlane indexes (< 64);
 //   * every LDS access: offsets-ring positions (< 384), the ring entry read
 //     is the one the walk asks for (a shadow of each slot's index), the
-//     start slots (< 64) and the transposition buffer (< 256 vectors);
+//     start slots (< 64), the tile buffer (< 64 x loads per lane vectors),
+//     each tile position read holds the vector the read expects, no row is
+//     read or loaded again while its load is in flight;
 //   * the kernel's own invariants: the valid lanes of a window form a
 //     prefix, each start lies in the part, masked ranges are not inverted,
-//     each carry slot read by the fix-up was written by this launch;
+//     the piece walk reads only parts taken from the tile, each carry slot
+//     read by the fix-up was written by this launch;
 //   * the results: every segment written exactly once, equal to the exact
 //     integer sum of its values (the values are small integers, so every
 //     partial is exact and the sums are compared for equality).
 // A failed check prints the access that failed and exits with status 1.
 //
-// Built with -DMUTATION=k (k = 1..6) the emulation carries one planted
+// Built with -DMUTATION=k (k = 1..8) the emulation carries one planted
 // mistake of a kind the checks must catch (the test builds each one and
 // expects a failure): 1 the next segment's end read from the wrong lane,
 // 2 a prefetched ring block written one block off, 3 no check for two
 // starts in one run, 4 a part with as many starts as visible ring entries
 // taken by the reduce-by-key walk, 5 a cut segment's piece count one short,
-// 6 no mask for the values outside the slice.
+// 6 no mask for the values outside the slice, 7 tile vectors fetched in row
+// order instead of the order the run reads expect, 8 the piece walk not
+// reading the tile's remaining parts first.
 //
 // Usage: seg_runs_emu E L layout grid wg ipt shift seed
 //   E        values in the batch
@@ -248,38 +254,72 @@ void wave_runs(Machine& M, int64_t w) {
   };
   const int nparts = (IPT >= 4 && E < 12 * nseg) ? 4 : (IPT >= 2 && E < 32 * nseg) ? 2 : 1;
 
-  // cur[u][lane][j]: value j of the vector of row u held by `lane`
-  std::vector<int64_t> cur((size_t)IPT * kWave * 4), nxt((size_t)IPT * kWave * 4);
-  auto load_tile = [&](std::vector<int64_t>& v, int64_t t) {
-    for (int u = 0; u < IPT; ++u)
+  // The tile buffer (LDS): direct-to-LDS load instruction u writes lane l's
+  // vector at position 64 u + l (row u); lane l fetches tile vector
+  // run_swz(64 u + l) of the tile, clamped to the slice's last vector.
+  // tile_vec shadows which vector of the batch each position holds.  A row's
+  // load stays in flight until the wait at the top of the next tile;
+  // reading a row with a load in flight, or issuing a load over one, fails.
+  const int rows = IPT / nparts;
+  std::vector<int64_t> tile((size_t)kWave * 4 * 4, 0), pend_tile((size_t)kWave * 4 * 4, 0);
+  std::vector<int64_t> tile_vec((size_t)kWave * 4, -1), pend_vec((size_t)kWave * 4, -1);
+  bool row_pending[4] = {false, false, false, false};
+  auto issue_rows = [&](int64_t t, int u0, int n) {
+    const int64_t vb = vlo + t * T;
+    for (int u = u0; u < u0 + n; ++u) {
+      if (u < 0 || u >= IPT) fail("tile row out of bounds", u);
+      if (row_pending[u]) fail("tile row load issued over one in flight", t, u);
       for (int l = 0; l < kWave; ++l) {
-        const int64_t vi = vlo + t * T + l + (int64_t)u * kWave;
-        int64_t* d = &v[((size_t)u * kWave + l) * 4];
-        if (vi < vhi)
-          M.load_vec(vi, d);
-        else
-          d[0] = d[1] = d[2] = d[3] = 0;
+        const int pos = u * kWave + l;
+        const int swz = MUTATION == 7 ? pos : run_swz(pos, rows);
+        const int64_t g = std::min(vb + swz, vhi - 1);
+        M.load_vec(g, &pend_tile[(size_t)pos * 4]);
+        pend_vec[pos] = g;
+      }
+      row_pending[u] = true;
+    }
+  };
+  auto wait_all = [&]() {
+    for (int u = 0; u < 4; ++u)
+      if (row_pending[u]) {
+        for (int l = 0; l < kWave; ++l) {
+          const size_t pos = (size_t)u * kWave + l;
+          for (int j = 0; j < 4; ++j) tile[pos * 4 + j] = pend_tile[pos * 4 + j];
+          tile_vec[pos] = pend_vec[pos];
+        }
+        row_pending[u] = false;
       }
   };
-  // Sum of the tile-relative values [ra, rb) (the masked adds of the
-  // per-piece walk; every row the range meets is added with a mask).
-  auto masked_sum = [&](const std::vector<int64_t>& v, int ra, int rb) -> int64_t {
-    if (ra > rb) fail("masked range inverted", ra, rb);
-    if (ra < 0 || rb > 4 * T) fail("masked range outside the tile", ra, rb);
-    int64_t sum = 0;
-    for (int e = ra; e < rb; ++e) {
-      const int u = e / (4 * kWave), l = (e / 4) % kWave, j = e % 4;
-      sum += v[((size_t)u * kWave + l) * 4 + j];
-    }
-    return sum;
-  };
 
-  if (ntiles > 0) load_tile(cur, 0);
+  if (ntiles > 0) issue_rows(0, 0, IPT);
   for (int64_t t = 0; t < ntiles; ++t) {
-    if (have) refill();
-    if (t + 1 < ntiles) load_tile(nxt, t + 1);
+    wait_all();
+    if (!have) break;
+    refill();
     const int64_t e0 = 4 * (vlo + t * T) - shift;
     const int64_t e1 = 4 * (vlo + (t + 1) * T) - shift;
+    const int RSw = rows, NP = IPT / rows, RLw = 4 * rows;
+    // xr[l][q RL + i]: value i of lane l's run in part q.  take(q) reads
+    // part q at run_swz(q 64 RS + RS l + jj), each position holding the
+    // tile vector the read expects (or the slice's last vector, past it),
+    // then puts the same rows of the next tile in flight.
+    std::vector<int64_t> xr((size_t)kWave * 4 * IPT, 0);
+    bool taken[4] = {false, false, false, false};
+    auto take = [&](int q) {
+      if (q < 0 || q >= NP || taken[q]) fail("part read twice or out of range", q);
+      taken[q] = true;
+      for (int l = 0; l < kWave; ++l)
+        for (int jj = 0; jj < RSw; ++jj) {
+          const int want = q * kWave * RSw + l * RSw + jj;
+          const int pos = run_swz(want, RSw);
+          if (pos < 0 || pos >= kWave * IPT) fail("tile read out of bounds", pos);
+          if (row_pending[pos / kWave]) fail("tile read of a row with a load in flight", t, pos);
+          const int64_t expect = std::min(vlo + t * T + want, vhi - 1);
+          if (tile_vec[pos] != expect) fail("tile position holds another vector", pos, tile_vec[pos], expect);
+          for (int j = 0; j < 4; ++j) xr[(size_t)l * 4 * IPT + q * RLw + 4 * jj + j] = tile[(size_t)pos * 4 + j];
+        }
+      if (t + 1 < ntiles) issue_rows(t + 1, q * RSw, RSw);
+    };
 
     auto try_runs = [&](int RS, int Q) -> bool {
       const int RL = 4 * RS;
@@ -324,29 +364,15 @@ void wave_runs(Machine& M, int64_t w) {
         }
       Lanes<unsigned> word;
       for (int l = 0; l < kWave; ++l) word[l] = slot[l];
-      // transposition through LDS: rows in, runs of RL values out
-      std::vector<int64_t> tile((size_t)kWave * 4 * 4, 0);
-      std::vector<uint8_t> tile_set((size_t)kWave * 4, 0);
-      for (int u = 0; u < RS; ++u)
-        for (int l = 0; l < kWave; ++l) {
-          const int i = run_swz(u * kWave + l, RS);
-          if (i < 0 || i >= kWave * 4) fail("transposition write out of bounds", i);
-          for (int j = 0; j < 4; ++j) tile[(size_t)i * 4 + j] = cur[(((size_t)(Q * RS + u)) * kWave + l) * 4 + j];
-          tile_set[i] = 1;
-        }
-      std::vector<int64_t> xr((size_t)kWave * RL);
+      // lane l's run of this part
+      std::vector<int64_t> xv((size_t)kWave * RL);
       for (int l = 0; l < kWave; ++l)
-        for (int jj = 0; jj < RS; ++jj) {
-          const int i = run_swz(l * RS + jj, RS);
-          if (i < 0 || i >= kWave * 4) fail("transposition read out of bounds", i);
-          if (!tile_set[i]) fail("transposition read of an unwritten vector", i);
-          for (int j = 0; j < 4; ++j) xr[(size_t)l * RL + 4 * jj + j] = tile[(size_t)i * 4 + j];
-        }
+        for (int i = 0; i < RL; ++i) xv[(size_t)l * RL + i] = xr[(size_t)l * 4 * IPT + Q * RL + i];
       if (MUTATION != 6 && (f0 < lo || f1 > hi))
         for (int l = 0; l < kWave; ++l) {
           const int64_t p = f0 + (int64_t)RL * l;
           for (int i = 0; i < RL; ++i)
-            if (!(p + i >= lo && p + i < hi)) xr[(size_t)l * RL + i] = 0;
+            if (!(p + i >= lo && p + i < hi)) xv[(size_t)l * RL + i] = 0;
         }
       Lanes<int64_t> v, head;
       Lanes<int> f;
@@ -360,7 +386,7 @@ void wave_runs(Machine& M, int64_t w) {
             hd = run;
             run = 0;
           }
-          run += xr[(size_t)l * RL + i];
+          run += xv[(size_t)l * RL + i];
         }
         v[l] = run;
         head[l] = hd;
@@ -411,56 +437,48 @@ void wave_runs(Machine& M, int64_t w) {
       return true;
     };
 
-    auto pieces_from = [&](int64_t p0) {
+    // per-piece walk over the runs: the value xr[l][q RL + i] lies at tile
+    // position q 64 RL + RL l + i
+    auto masked_sum = [&](int ra, int rb) -> int64_t {
+      if (ra > rb) fail("masked range inverted", ra, rb);
+      if (ra < 0 || rb > 4 * T) fail("masked range outside the tile", ra, rb);
+      int64_t sum = 0;
+      for (int q = 0; q < NP; ++q)
+        for (int l = 0; l < kWave; ++l)
+          for (int i = 0; i < RLw; ++i) {
+            const int k = q * kWave * RLw + RLw * l + i;
+            if (k < ra || k >= rb) continue;
+            if (!taken[q]) fail("piece walk reads a part not read from the tile", q, k);
+            sum += xr[(size_t)l * 4 * IPT + q * RLw + i];
+          }
+      return sum;
+    };
+    auto pieces_from = [&](int q0) {
       ++M.parts_pieces;
+      for (int q = q0 + 1; q < NP && MUTATION != 8; ++q) take(q);
+      const int64_t p0 = e0 + (int64_t)q0 * kWave * RLw;
       auto relp = [&](int64_t e) { return (int)std::min(std::max(e - e0, (int64_t)0), 4 * T); };
-      int64_t acc = 0;
       int64_t A = std::max(std::max(sa, lo), p0), Bb = std::min(sb, hi);
       while (have && Bb <= e1) {
-        acc += masked_sum(cur, relp(A), relp(Bb));
-        finish_piece(M, s, sa, sb, C + acc, lo, hi, w, chunk);
-        acc = 0;
+        finish_piece(M, s, sa, sb, C + masked_sum(relp(A), relp(Bb)), lo, hi, w, chunk);
         C = 0;
         ++s;
         have = seek_segment(M, s, hi, E, end_slice, sa, sb);
         A = std::max(sa, lo);
         Bb = std::min(sb, hi);
       }
-      if (have) {
-        if (A <= e0 && vlo + (t + 1) * T <= vhi)
-          acc += masked_sum(cur, 0, (int)(4 * T));
-        else
-          acc += masked_sum(cur, relp(A), relp(Bb));
-        C += acc;
-      }
+      if (have) C += masked_sum(relp(A), relp(Bb));
     };
 
-    if (have) {
-      auto parts = [&](int RS, int np) {
-        const int64_t P = (int64_t)kWave * 4 * RS;
-        for (int q = 0; q < np; ++q)
-          if (!try_runs(RS, q)) {
-            pieces_from(e0 + q * P);
-            return;
-          }
-      };
-      if (IPT == 4) {
-        if (nparts == 4)
-          parts(1, 4);
-        else if (nparts == 2)
-          parts(2, 2);
-        else
-          parts(4, 1);
-      } else if (IPT == 2) {
-        if (nparts == 2)
-          parts(1, 2);
-        else
-          parts(2, 1);
-      } else {
-        parts(1, 1);
+    {
+      for (int q = 0; q < NP; ++q) {
+        take(q);
+        if (!try_runs(RSw, q)) {
+          pieces_from(q);
+          break;
+        }
       }
     }
-    std::swap(cur, nxt);
   }
   if (have) {
     finish_piece(M, s, sa, sb, C, lo, hi, w, chunk);

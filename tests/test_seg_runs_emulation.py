@@ -93,7 +93,7 @@ MUTATION_CASES = [(1_000_003, 5, 0, 8, 512, 4, 1), (1_000_003, 16, 1, 8, 512, 4,
                   (1_000_003, 200, 1, 16, 256, 4, 1)]
 
 
-@pytest.mark.parametrize("mutation", range(1, 7))
+@pytest.mark.parametrize("mutation", range(1, 9))
 def test_planted_mistakes_are_caught(tmp_path, mutation):
     exe = build(str(tmp_path), mutation)
     recs = [run(exe, *c) for c in MUTATION_CASES]
