@@ -511,6 +511,68 @@ def np_split(x, k):
     return np.array_split(x, k)
 
 
+def other_configs(R, dev, stream, sh, plans, inputs):
+    """One figure for each of the other workloads, with the cached plans:
+    fp32 U[-1,1] and int32 U[-1000,1000] sums of 2^20 values (us per sum,
+    back to back), the int32 2^26 sum through every synchronization variant
+    (each checked bit for bit against numpy's int64 sum), and bf16 / fp16
+    sums of 2^29 N(0,1) values drawn on the device from a fixed seed."""
+    import numpy as np
+    import torch
+    res = {}
+    for kind, x in (("f32", inputs.uniform_f32(1 << 20)), ("i32", inputs.uniform_i32(1 << 20))):
+        t = torch.from_numpy(x).to("cuda")
+        code = R.RED_F32 if kind == "f32" else R.RED_I32
+        out = torch.empty((), dtype=torch.float64 if kind == "f32" else torch.int64, device="cuda")
+        plan = plans.sum_plan(t, out, R.RED_ACC_COMPENSATED, sh)
+        o = R.opts_from_plan(plan)
+        fn = lambda: R.red_sum_ex(code, t.data_ptr(), t.numel(), out.data_ptr(), sh, o)
+        for _ in range(20):
+            fn()
+        us = statistics.median(time_loop(fn, 32, stream) for _ in range(7)) * 1e3
+        res["%s_2p20_us_per_sum" % kind] = round(us, 2)
+        res["%s_2p20_plan" % kind] = plan.as_dict()
+        if kind == "i32":
+            res["i32_2p20_bit_exact"] = out.item() == int(x.astype(np.int64).sum())
+    x = inputs.uniform_i32(1 << 26)
+    t = torch.from_numpy(x).to("cuda")
+    out = torch.empty((), dtype=torch.int64, device="cuda")
+    plan = plans.sum_plan(t, out, R.RED_ACC_COMPENSATED, sh)
+    res["i32_2p26_plan"] = plan.as_dict()
+    res["i32_2p26_GBps"] = variant_table(R, plan, R.RED_I32, t, t.numel(), out, sh, stream, dev)
+    want = int(x.astype(np.int64).sum())
+    exact = {}
+    for v in (1, 2, 3):
+        R.red_sum_ex(R.RED_I32, t.data_ptr(), t.numel(), out.data_ptr(), sh,
+                     R.make_opts(variant=v, wg=plan.wg, ipt=plan.ipt,
+                                 grid=min(plan.grid or 1024, R.red_max_coresident(plan.wg))))
+        torch.cuda.synchronize()
+        exact[R.VARIANT_NAMES[v]] = out.item() == want
+    res["i32_2p26_bit_exact"] = exact
+    del t
+    g = torch.Generator(device="cuda")
+    for kind, tdt, code in (("bf16", torch.bfloat16, R.RED_BF16), ("f16", torch.float16, R.RED_F16)):
+        g.manual_seed(2004 if kind == "bf16" else 5371)
+        t = torch.randn(1 << 29, device="cuda", generator=g).to(tdt)
+        out = torch.empty((), dtype=torch.float64, device="cuda")
+        plan = plans.sum_plan(t, out, R.RED_ACC_COMPENSATED, sh)
+        o = R.opts_from_plan(plan, acc=R.RED_ACC_COMPENSATED)
+        fn = lambda: R.red_sum_ex(code, t.data_ptr(), t.numel(), out.data_ptr(), sh, o)
+        for _ in range(3):
+            fn()
+        tt, _ = time_steps(fn, 30, stream)
+        torch.cuda.synchronize()
+        ref = float(t.double().sum())
+        res["%s_2p29_GBps" % kind] = gbps(t.numel() * 2, statistics.median(tt))
+        res["%s_2p29_plan" % kind] = plan.as_dict()
+        res["%s_2p29_rel_diff_vs_torch_f64_sum" % kind] = abs(out.item() - ref) / max(abs(ref), 1e-300)
+        del t
+        torch.cuda.empty_cache()
+    if R.red_check_error(sh) != R.RED_OK:
+        raise RuntimeError("other configurations: " + R.last_error())
+    return res
+
+
 def stencil_configs(R, dev, stream, emit, timed):
     """Microseconds per step of the 1D Jacobi stencil: relaunch (one kernel
     per step, u and scratch through the caches / HBM every step) and the
@@ -1137,6 +1199,7 @@ def headline(args, R, dev, stream, sh, plans, inputs):
         extra["stencil_4M"] = st
         del u, sc
         torch.cuda.empty_cache()
+        extra["other_configs"] = other_configs(R, dev, stream, sh, plans, inputs)
 
     # ---- CPU baseline: the oracle on the same input (and the result's error)
     cpu = None
