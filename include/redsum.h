@@ -312,31 +312,34 @@ int red_sum_segmented_loop(const float *x, const int64_t *host_offsets, int64_t 
  *   steps_per_sync  persistent form: steps between grid barriers, which
  *            is also the halo width each workgroup keeps (1 = a barrier
  *            every step); 0 = chosen by the library: the widest halo up to
- *            128 that the LDS window holds beside the block (the block
+ *            128 that the window holds beside the block (the block
  *            length is set as for 8).  Any value gives the same result.
  *   opts     NULL or plan.variant:
  *            RED_VARIANT_RELAUNCH    one kernel launch per step (the
  *                                    implicit barrier), u and scratch
  *                                    alternating;
  *            RED_VARIANT_PERSISTENT  one launch holding the time loop: each
- *                                    workgroup keeps its block and halos in
- *                                    LDS and exchanges boundary values with
- *                                    its neighbours through u / scratch
+ *                                    workgroup keeps its block and halos
+ *                                    (at most 16384 values) in its threads'
+ *                                    registers and exchanges boundary values
+ *                                    with its neighbours through u / scratch
  *                                    (device-scope atomic stores and loads)
  *                                    at a grid barrier every steps_per_sync
  *                                    steps;
- *            RED_VARIANT_AUTO        persistent when the array fits the
- *                                    co-resident workgroups' LDS, else
+ *            RED_VARIANT_AUTO        persistent when the array's windows fit
+ *                                    the co-resident workgroups, else
  *                                    relaunch.
- *            plan.wg (default: 1024 when one 64 KB LDS window per CU
- *            holds the array and n >= 4096 x CUs, else 512), plan.grid
- *            (default one workgroup per CU, or as many 64 KB LDS windows
- *            as the array needs rounded up to a whole number per CU,
- *            capped at the co-resident limit) and flags
+ *            plan.wg (persistent default: the fewest values per thread, 2
+ *            to 32, whose workgroup stays within 1024 threads and is
+ *            co-resident with the grid; relaunch default 512; a caller's
+ *            size holds at most 32 values per thread), plan.grid (default
+ *            one workgroup per CU, or as many 16 K-value windows as the
+ *            array needs rounded up to a whole number per CU) and flags
  *            RED_FLAG_PLAIN_LAUNCH / RED_FLAG_XCD as for red_sum.
  * Asynchronous on `stream`.  RED_EINVAL for bad arguments, overlapping
- * arrays, or a persistent request whose block does not fit one LDS window;
- * a grid-barrier watchdog timeout is reported by red_check_error. */
+ * arrays, or a persistent request whose windows do not fit the co-resident
+ * workgroups; a grid-barrier watchdog timeout is reported by
+ * red_check_error. */
 int stencil_jacobi_1d(float *u, float *scratch, int64_t n, int32_t steps, float r, int32_t steps_per_sync,
                       void *stream, const red_opts *opts);
 

@@ -81,7 +81,7 @@ def test_binomial_impulse(lib):
 
 def test_large_persistent_and_auto_fallback(lib):
     """A million values for 200 steps in one persistent launch; an array
-    larger than the co-resident LDS windows is refused by the persistent
+    larger than the co-resident windows is refused by the persistent
     form and run by one launch per step under AUTO."""
     x = inputs.normal_f32((1 << 20) + 5, sub=63)
     want = oracle.jacobi_1d_f32(x, 200, 0.4)
