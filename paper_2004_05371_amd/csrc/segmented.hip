@@ -625,7 +625,8 @@ __device__ static void seg_wave_runs_in(const SegArgs& a, const float* __restric
         // must end past the part to show every start in it.
         const int vis = (int)std::min<int64_t>(kWave, fill - (s + 1));
         if (vis <= 0) return false;
-        const int64_t O = lane < vis ? lds_get_i64_now(ring, ring_pos(s + 1)) : INT64_MAX;  // start of segment s + 1 + lane
+        // O: the start of segment s + 1 + lane
+        const int64_t O = lane < vis ? lds_get_i64_now(ring, ring_pos(s + 1)) : INT64_MAX;
         const bool valid = O < std::min(f1, hi);
         const int m = __popcll(__ballot(valid));  // the valid lanes are 0 .. m-1
         if (m >= vis) return false;
