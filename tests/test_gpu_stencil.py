@@ -50,6 +50,19 @@ def test_small_sizes_bit_exact(lib, form):
             assert np.array_equal(got, want), (f, n, steps, np.flatnonzero(got != want)[:5])
 
 
+@pytest.mark.parametrize("n,wg,grid", [(1000, 512, 0), (9_001, 128, 4), (100_003, 512, 16), (100_003, 1024, 16),
+                                        ((1 << 20) + 3, 256, 256), (4099, 64, 4)])
+def test_caller_workgroup_sizes(lib, n, wg, grid):
+    """A caller's workgroup size sets the values each thread holds (4 to 32
+    here: the fewest that cover the window), bit for bit for the library's
+    halo and a short one."""
+    x = inputs.normal_f32(n, sub=67)
+    for spsync in (0, 7):
+        want = oracle.jacobi_1d_f32(x, 40, 0.3)
+        got = run(lib, x, 40, 0.3, variant=PERSISTENT, spsync=spsync, wg=wg, grid=grid)
+        assert np.array_equal(got, want), (n, wg, grid, spsync, np.flatnonzero(got != want)[:5])
+
+
 def test_no_op_cases(lib):
     for n in (0, 1, 2):
         x = np.arange(n, dtype=np.float32)
