@@ -398,6 +398,8 @@ __device__ __forceinline__ void static_for_while(F&& f) {
 constexpr int kRing = 384;        // offsets entries held in LDS per wavefront
 constexpr int kCpolNT = 2;        // the nontemporal bit of a load's cache policy
 constexpr int kWaitLds = 0xC07F;  // s_waitcnt lgkmcnt(0): LDS reads returned, other counters free
+constexpr int kWaveShl1 = 0x130;  // DPP wave_shl:1: lane l receives lane l + 1 (lane 63 receives 0)
+constexpr int kWaveShr1 = 0x138;  // DPP wave_shr:1: lane l receives lane l - 1 (lane 0 receives 0)
 
 struct RunLds {
   v4f tile[kWave * 4];   // one tile of up to 4 rows, swizzled
@@ -632,7 +634,7 @@ __device__ static void seg_wave_runs_in(const SegArgs& a, const float* __restric
         if (m >= vis) return false;
         const int rel = valid ? (int)(O - f0) : 0;
         const int r = rel / RL;  // lane whose run holds start `lane`
-        const int rn = __builtin_amdgcn_ds_bpermute(((lane + 1) & (kWave - 1)) << 2, r);
+        const int rn = dpp_move<kWaveShl1, 0xF, 0xF>(r);  // lane + 1's run (lane 63: unused)
         const bool clash = valid && lane + 1 < m && rn == r;
         if (__ballot(clash) != 0) return false;
         // Start k (lane k) tells lane r_k where it lies.
@@ -665,7 +667,7 @@ __device__ static void seg_wave_runs_in(const SegArgs& a, const float* __restric
         int f = has ? 1 : 0;
         wave_segscan(v, f);
         if (!f) v = C + v;  // lanes 0 .. l hold no start: the open segment continues
-        const double left = bpermute_move(v, (lane - 1) & (kWave - 1));
+        const double left = dpp_move<kWaveShr1, 0xF, 0xF>(v);  // lane - 1's scan (lane 0: unused)
         const double total = (lane == 0 ? C : left) + head;
         const int k = (int)(word >> 16) - 1;
         if (has && k > 0 && k < m) a.out[s + k] = total;  // segment s + k lies in the part

@@ -5,7 +5,7 @@
 // Test infrastructure only: nothing of the library is linked or included.
 // The emulation restates the kernel's steps for one wavefront at a time,
 // with every per-lane value held as an array of 64 and every cross-lane
-// operation (ballot, readlane, ds_bpermute, the DPP row shifts and row
+// operation (ballot, readlane, the DPP wave and row shifts and row
 // broadcasts of the segmented scan) written out, and the tile buffer that
 // direct-to-LDS loads fill row by row modelled with the rows in flight.  It
 // checks:
@@ -351,7 +351,7 @@ void wave_runs(Machine& M, int64_t w) {
         r[l] = rel[l] / RL;
       }
       for (int l = 0; l < kWave; ++l) {
-        const int rn = r[(l + 1) & (kWave - 1)];  // ds_bpermute from lane + 1
+        const int rn = r[(l + 1) & (kWave - 1)];  // DPP wave shift: lane + 1 (lane 63 unused)
         if (MUTATION != 3 && valid[l] && l + 1 < m && rn == r[l]) return false;
       }
       // start slots (LDS)
@@ -415,7 +415,7 @@ void wave_runs(Machine& M, int64_t w) {
         if (!f[l]) v[l] = C + v[l];
       Lanes<int64_t> total;
       for (int l = 0; l < kWave; ++l) {
-        const int64_t left = v[(l - 1) & (kWave - 1)];  // ds_bpermute from lane - 1
+        const int64_t left = v[(l - 1) & (kWave - 1)];  // DPP wave shift: lane - 1 (lane 0 unused)
         total[l] = (l == 0 ? C : left) + head[l];
       }
       for (int l = 0; l < kWave; ++l) {
