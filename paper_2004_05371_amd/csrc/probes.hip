@@ -344,6 +344,12 @@ double mean(const std::vector<double>& v) {
   return s / v.size();
 }
 
+double median_of(std::vector<double> v) {
+  std::sort(v.begin(), v.end());
+  const size_t n = v.size();
+  return n % 2 ? v[n / 2] : 0.5 * (v[n / 2 - 1] + v[n / 2]);
+}
+
 double sdev(const std::vector<double>& v) {
   const double m = mean(v);
   double s = 0;
@@ -719,7 +725,9 @@ int sync_bench_relaunch_ex(int n_wg, int wg_size, int cooperative, int i, int j,
     *null_kernel_ns = red_eq7_latency(mean(lb), mean(ls), kBig, kSmall);
   } else if (null_kernel_ns) {
     // Section IV: host clock around 1 launch and around 5 launches of a
-    // null kernel, each followed by a device synchronization.
+    // null kernel, each followed by a device synchronization; the median
+    // over the repetitions, because a host-side stall of a few us in one
+    // repetition moves the mean by more than the figure itself.
     ticks = 0;
     auto one = [&]() { return launch(fn, n_wg, wg_size, args, s, coop); };
     auto five = [&]() {
@@ -742,7 +750,7 @@ int sync_bench_relaunch_ex(int n_wg, int wg_size, int cooperative, int i, int j,
       const double b = std::chrono::duration<double, std::nano>(t3 - t2).count();
       tot.push_back((b - a) / 4.0);
     }
-    *null_kernel_ns = mean(tot);
+    *null_kernel_ns = median_of(tot);
   }
   return RED_OK;
 }
