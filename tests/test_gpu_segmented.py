@@ -368,6 +368,39 @@ def test_full_size_uniform_segments(lib, L):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("L,shift", [(7, 1), (16, 3), (33, 2)])
+def test_full_size_misaligned_reduce_by_key(lib, L, shift):
+    """Close to 2^28 values at a base 4 to 12 bytes past a 16-byte boundary,
+    in segments of 7, 16 and 33 values (reduce-by-key parts of 1, 2 and 4
+    rows), the total not a whole number of tiles: the direct-to-LDS tile
+    loads start before the first value and clamp at each slice's last
+    vector.  Every segment within 1e-12 of its sum of magnitudes of a
+    binary64 row sum, 1000 sampled against the oracle's exact sums."""
+    nseg = ((1 << 28) - 5) // L
+    n = nseg * L
+    x = inputs.normal_f32(n, sub=21)
+    buf = torch.zeros(n + 8, dtype=torch.float32, device="cuda")
+    xt = buf[shift:shift + n]
+    xt.copy_(torch.from_numpy(x))
+    ot = torch.arange(0, n + 1, L, dtype=torch.int64, device="cuda")
+    out = torch.full((nseg,), float("nan"), dtype=torch.float64, device="cuda")
+    say("full-size misaligned segments", L, shift, nseg)
+    lib.red_sum_segmented_ex(xt.data_ptr(), ot.data_ptr(), nseg, out.data_ptr(), lib.current_stream(),
+                             lib.make_opts(flags=lib.FLAG_NONTEMPORAL | lib.FLAG_SEG_RUNS))
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    rows = x.reshape(nseg, L)
+    approx = rows.astype(np.float64).sum(axis=1)
+    mag = np.abs(rows).astype(np.float64).sum(axis=1)
+    bad = np.nonzero(~(np.abs(got - approx) <= 1e-12 * mag))[0]
+    assert bad.size == 0, (int(bad[0]), got[bad[0]], approx[bad[0]])
+    for k in np.random.default_rng(900 + L).choice(nseg, 1000, replace=False):
+        ex = oracle.exact_sum(rows[k], "f32")
+        assert oracle.rel_err(float(got[k]), ex) <= BOUND, (k, got[k], ex.value)
+    del buf, xt, ot, out
+    torch.cuda.empty_cache()
+
+
 def test_graph_cache_eviction(lib):
     """More distinct batches than the graph cache holds (64): the oldest
     graphs are evicted (after their stream drains) and rebuilt on reuse;
