@@ -397,7 +397,7 @@ int red_get_segmented_plan(int64_t nseg, red_plan *plan);
  * install the best plan for batches with the same nseg bit length.  The
  * search times the default plan with and without the nontemporal hint,
  * then every fix-up variant (RELAUNCH, ATOMIC) x wg {128, 256, 512} x ipt
- * {2, 4, 8} x grid {1, 2, 3, 4, 6, 8} x CUs (8 back-to-back launches each,
+ * {2, 4, 8} x grid {1, 2, 3, 4, 5, 6, 8} x CUs (8 back-to-back launches each,
  * median), and re-times the best 4 in 3 interleaved rounds.  budget > 0
  * caps the number of candidates timed in the first pass. */
 int red_autotune_segmented(const float *x, const int64_t *offsets, int64_t nseg, double *out,

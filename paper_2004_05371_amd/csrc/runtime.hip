@@ -1163,7 +1163,7 @@ int red_autotune_segmented(const float* x, const int64_t* offsets, int64_t nseg,
   for (int v : {RED_VARIANT_RELAUNCH, RED_VARIANT_ATOMIC})
     for (int wg : {128, 256, 512})
       for (int ipt : {2, 4, 8})
-        for (int m : {1, 2, 3, 4, 6, 8})
+        for (int m : {1, 2, 3, 4, 5, 6, 8})
           if (!rc) rc = consider(red_plan{v, wg, ipt, std::min(m * dev->cus, RED_MAX_GRID), nt_flag});
   if (rc) return rc;
   if (timed_plans.empty()) return set_error(RED_EINVAL, "no plan timed (budget 0?)");
