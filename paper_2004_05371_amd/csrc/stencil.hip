@@ -104,22 +104,30 @@ __global__ __launch_bounds__(1024) void k_jacobi_persistent(StencilArgs a) {
     x[i] = (j0 + i < len && e >= 0 && e < n) ? a.u[e] : 0.0f;
   }
 
+  // Window positions of the array's end points, which never change (-1 or
+  // len when the window does not hold them).
+  const int jz = (int)std::max<int64_t>(std::min<int64_t>(-base, len), -1);
+  const int jn = (int)std::max<int64_t>(std::min<int64_t>(n - 1 - base, len), -1);
+  const bool holds_end = (jz >= j0 && jz < j0 + VPT) || (jn >= j0 && jn < j0 + VPT);
+
   int sync = 0, buf = 0;
   for (int step = 0; step < a.steps;) {
     const int kk = std::min(k, a.steps - step);
     for (int s = 1; s <= kk; ++s) {
-      // Window values still valid after this step: [jlo, jhi), i.e. the
-      // elements [lo - k + s, hi + k - s); the array's end points never
-      // change.  Values outside keep their old value.
-      const int jlo = (int)(std::max<int64_t>(base + s, 1) - base);
-      const int jhi = (int)(std::min<int64_t>(hi + k - s, n - 1) - base);
+      // After step s only the window values of the elements
+      // [lo - k + s, hi + k - s) are valid: the range shrinks by one value
+      // on each side per step, so no valid value depends on one outside it.
+      // The values outside (the halo being used up, and positions past the
+      // array's ends) are updated too and never read for a valid one; the
+      // halo is reloaded at the next exchange.  Only the array's end points
+      // keep their value.
       float* eb = edge + 2 * bs * buf;
       eb[tid] = x[0];
       eb[bs + tid] = x[VPT - 1];
       __syncthreads();
       // Window value j0 - 1 is the left neighbour's last, j0 + VPT the right
-      // neighbour's first (values outside the window are never used: jlo >= 1
-      // and jhi <= len - 1).
+      // neighbour's first (thread 0 and the last thread read a value that
+      // only feeds positions outside the valid range).
       const float left = tid > 0 ? eb[bs + tid - 1] : 0.0f;
       const float right = tid + 1 < bs ? eb[tid + 1] : 0.0f;
       float y[VPT];
@@ -127,12 +135,12 @@ __global__ __launch_bounds__(1024) void k_jacobi_persistent(StencilArgs a) {
 #pragma unroll
       for (int i = 1; i < VPT - 1; ++i) y[i] = jacobi_point(x[i - 1], x[i], x[i + 1], a.r);
       y[VPT - 1] = jacobi_point(x[VPT - 2], x[VPT - 1], right, a.r);
-      if (j0 >= jlo && j0 + VPT <= jhi) {
+      if (!holds_end) {
 #pragma unroll
         for (int i = 0; i < VPT; ++i) x[i] = y[i];
-      } else {  // a run at an edge of the valid range, or past the window
+      } else {  // the run that holds element 0 or n - 1
 #pragma unroll
-        for (int i = 0; i < VPT; ++i) x[i] = (j0 + i >= jlo && j0 + i < jhi) ? y[i] : x[i];
+        for (int i = 0; i < VPT; ++i) x[i] = (j0 + i == jz || j0 + i == jn) ? x[i] : y[i];
       }
       buf ^= 1;
     }
