@@ -288,8 +288,9 @@ def summarize_configs(paths, out_dir):
                 "| Launch | Workgroups | Overhead ns (Eq. 6) | sigma ns | Null kernel ns |", "|---|---|---|---|---|"]
         out += ["| %s | %d | %.1f | %.1f | %.1f |" % (r["launch"], r["n_wg"], r["overhead_ns"], r["sigma_ns"],
                                                   r["null_kernel_total_ns"]) for r in rl]
-        out += ["", "Null kernel: the Section IV host-clock formula for ordinary and cooperative launches; for the graph "
-                "type, the Eq. 7 differential between graphs of 40 and 5 null kernels.", ""]
+        out += ["", "Null kernel: the Section IV host-clock formula for ordinary and cooperative launches (median over "
+                "the repetitions); for the graph type, the Eq. 7 differential between graphs of 40 and 5 null "
+                "kernels.", ""]
         ordinary = {r["n_wg"]: r["overhead_ns"] for r in rl if r["launch"] == "ordinary"}
         if ordinary and g:
             out += ["## Grid barrier against a kernel boundary", "",
